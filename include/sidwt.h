@@ -1,0 +1,165 @@
+/*
+ * sidwt.h -- C ABI of libsidwt, multiresolution correlation of complex
+ * radar signals in the shift-invariant DWT (SIDWT) domain on AMD MI355X
+ * (gfx950).
+ *
+ * Method: C. Bhattacharya and P.R. Mahapatra, "A Novel Application of
+ * Lifting Scheme for Multiresolution Correlation of Complex Radar Signals".
+ *
+ * What one call computes (notation of the paper, Sec. II and IV):
+ *   N = 2^J * ceil(n / 2^J); the reference x (length m <= N) and the
+ *   received pulse y (length n) are zero-padded to N and treated as
+ *   circular.  For every scale j = 0..J-1 and every lag s = 0..N-1
+ *
+ *       R_j[s] = sum_k conj(a~_{j+1,k}^{(s)}) c_{j+1,k}
+ *              + sum_k conj(b~_{j+1,k}^{(s)}) d_{j+1,k}
+ *
+ *   (eq. (15), eq. (20)/(20a)): a~, b~ are the level-(j+1) approximation
+ *   and detail coefficients of x delayed by s, obtained by lifting with the
+ *   analysis matrix P~(z^-1); c, d those of y, obtained by lifting with the
+ *   dual analysis matrix P^T(z^-1) (eq. (13)).  By shift-circulance (Sec. II)
+ *   a~^{(s)} is a circular shift of one of 2^{j+1} stored phase vectors, so
+ *   the plan stores those phases once (Fig. 5 tree) and each call lifts y
+ *   (Fig. 7) and correlates.  For float filters R_j equals, up to rounding,
+ *   the plain circular correlation of the level-j approximations; plane 0 is
+ *   the matched-filter output  R_0[s] = sum_n conj(x[n - s]) y[n].
+ *
+ * Conventions for every entry point:
+ *   - Return value: SIDWT_OK (0) or a negative SIDWT_E_* code.  Argument
+ *     errors are detected on the host and returned before anything is
+ *     enqueued; nothing is written in that case.
+ *   - Device pointers are plain HIP device addresses (for instance a
+ *     PyTorch tensor's data_ptr()); the caller owns them.  Host pointers are
+ *     read during the call only.
+ *   - Work is enqueued asynchronously on the plan's stream (default: the
+ *     null stream) and the call returns; results are ready when the stream
+ *     is synchronised.  Faults of earlier device work surface as
+ *     SIDWT_E_DEVICE.
+ *   - A plan is immutable after creation: concurrent calls with one plan on
+ *     different streams are safe.  sidwt_set_stream is the one mutator and
+ *     must not race with calls on the same plan.
+ *
+ * Data types:
+ *   - Float filters (SIDWT_LEGALL53, SIDWT_CDF97, SIDWT_D4_CAUSAL): the
+ *     reference (host) and received pulses (device) are complex64,
+ *     interleaved (re, im) float32.  Output: complex64 [J][N], plane-major.
+ *   - Integer filter (SIDWT_LEGALL53_INT): reference (host) and received
+ *     pulses (device) are int16 interleaved (I, Q).  Output: int64
+ *     [J][N][2] (re, im).  Results are exact (no rounding beyond the
+ *     integer lifting itself).
+ */
+#ifndef SIDWT_H
+#define SIDWT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sidwt_plan sidwt_plan;
+
+/* Lifting factorisations (Sec. III).
+ * SIDWT_LEGALL53:     5/3 in dual analysis bases, Sec. III-C Case I.
+ * SIDWT_CDF97:        9/7 with the rational Table I constants, Case II.
+ * SIDWT_D4_CAUSAL:    causal Daubechies-4, eq. (17); both sides (Sec. III-B).
+ * SIDWT_LEGALL53_INT: reversible integer-to-integer 5/3 (Sec. I, V-B cite
+ *                     integer lifting; the rounding rule used is
+ *                     x-side  o -= (e[k]+e[k+1])>>1, e += (o[k-1]+o[k]+2)>>2;
+ *                     y-side  e += (o[k-1]+o[k]+1)>>1, o -= (e[k]+e[k+1]+2)>>2,
+ *                     detail scalings 1/2 and 2 dropped as they cancel). */
+typedef enum {
+  SIDWT_LEGALL53 = 1,
+  SIDWT_CDF97 = 2,
+  SIDWT_D4_CAUSAL = 3,
+  SIDWT_LEGALL53_INT = 4
+} sidwt_filter;
+
+enum {
+  SIDWT_OK = 0,
+  SIDWT_E_INVAL = -1,   /* NULL pointer, n<1, m<1, J<1 or J>16, N/2^J<2,
+                           unknown filter, bad count                      */
+  SIDWT_E_SIZE = -2,    /* m > N; integer plan support would wrap at this N;
+                           or a size beyond the library's limits          */
+  SIDWT_E_NOMEM = -3,   /* device allocation failed                       */
+  SIDWT_E_DEVICE = -4,  /* a HIP runtime error (including earlier faults) */
+  SIDWT_E_UNSUPPORTED = -5 /* valid request this build does not handle    */
+};
+
+#define SIDWT_MAX_LEVELS 16
+
+/* Create a plan: copies the host reference (m samples, type per filter),
+ * builds on the current device the even/odd shift-circulant phase pyramid
+ * of the reference, a~_l^{(r)} and b~_l^{(r)} for l = 1..J and
+ * r = 0..2^l-1 (Sec. II "even and odd shifts"; Fig. 5), on their linear
+ * support.  The plan owns its device memory until sidwt_free.  The call is
+ * synchronous.  *out is set only on success. */
+int sidwt_plan_create(int filter, int J, const void *ref, int64_t m,
+                      sidwt_plan **out);
+
+/* Release a plan (waits for the plan's device memory to be idle).  NULL is a
+ * no-op. */
+void sidwt_free(sidwt_plan *p);
+
+/* Number of output elements (complex values) for a pulse of n samples:
+ * J * N with N = 2^J * ceil(n / 2^J); -1 if p is NULL or n < 1. */
+int64_t sidwt_out_len(const sidwt_plan *p, int64_t n);
+
+/* Stream for the plan's subsequent calls (a hipStream_t; NULL = null
+ * stream). */
+int sidwt_set_stream(sidwt_plan *p, void *hip_stream);
+
+/* One pulse: rx (device, n samples) -> out (device, sidwt_out_len
+ * elements).  Fused kernel: y-side lifting of all J levels in LDS, each
+ * level correlated against the plan's phases as soon as it exists
+ * (eq. (20)/(20a)). */
+int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out);
+
+/* A uniform batch in one launch: `count` pulses of n samples each, pulse i
+ * at rx + i * rx_stride samples; its planes at out + i * out_stride
+ * elements (elements are complex64 or int64 pairs).  rx_stride >= n and
+ * out_stride >= sidwt_out_len(p, n). */
+int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n,
+                         int64_t count, int64_t rx_stride, void *out,
+                         int64_t out_stride);
+
+/* Lifting only (a1 + a2 of the path, for bandwidth measurement and for
+ * callers that correlate elsewhere): `count` pulses of n samples, pulse i
+ * at rx + i*rx_stride; writes the critical y-side pyramid of each pulse,
+ * N elements at pyr + i*N in the order  d_1 | d_2 | ... | d_J | c_J
+ * (lengths N/2, N/4, ..., N/2^J, N/2^J).  Element type = output element
+ * type of the lifting (complex64 for float filters, int32 pairs for the
+ * integer filter). */
+int sidwt_lift_many(int filter, int J, const void *rx, int64_t n,
+                    int64_t count, int64_t rx_stride, void *pyr,
+                    void *hip_stream);
+
+/* Uneven batch: `count` pulses with their own plans (filters and J may
+ * differ), lengths n[i], device pointers rx[i] and out[i] (host arrays of
+ * pointers).  All work goes through one persistent launch on `hip_stream`
+ * that pulls (pulse, plane, lag-tile) items from a device work list sorted
+ * by cost.  Device scratch is owned by the library and reused across calls
+ * on the same stream. */
+int sidwt_correlate_batch(const sidwt_plan *const *plans,
+                          const void *const *rx, const int64_t *n,
+                          void *const *out, int count, void *hip_stream);
+
+/* Introspection for tests: copy phase r of band b (0 = approximation,
+ * 1 = detail) at level l (1..J) to host memory.  Writes *lo (first index of
+ * the stored linear support) and *len; dst must hold *len elements of the
+ * plan's coefficient type (complex64, or int32 pairs for the integer
+ * filter).  With dst == NULL only lo and len are returned. */
+int sidwt_plan_phase(const sidwt_plan *p, int level, int band, int r,
+                     int32_t *lo, int32_t *len, void *dst);
+
+/* Short description of an error code (static string). */
+const char *sidwt_strerror(int code);
+
+/* Library version string. */
+const char *sidwt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIDWT_H */

@@ -1,0 +1,82 @@
+"""ctypes binding of libsidwt.so (the C ABI in include/sidwt.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  If the library is missing the import of this module raises; there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsidwt.so")
+
+SIDWT_OK = 0
+SIDWT_E_INVAL = -1
+SIDWT_E_SIZE = -2
+SIDWT_E_NOMEM = -3
+SIDWT_E_DEVICE = -4
+SIDWT_E_UNSUPPORTED = -5
+
+FILTERS = {"legall53": 1, "cdf97": 2, "d4": 3, "legall53_int": 4}
+
+_lib = None
+
+
+class SidwtError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = lib().sidwt_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{what}: {msg} (code {code})" if what else f"{msg} (code {code})")
+
+
+def _declare(L):
+    c = ctypes
+    vp, i64, i32 = c.c_void_p, c.c_int64, c.c_int
+    L.sidwt_plan_create.argtypes = [i32, i32, vp, i64, c.POINTER(vp)]
+    L.sidwt_plan_create.restype = i32
+    L.sidwt_free.argtypes = [vp]
+    L.sidwt_free.restype = None
+    L.sidwt_out_len.argtypes = [vp, i64]
+    L.sidwt_out_len.restype = i64
+    L.sidwt_set_stream.argtypes = [vp, vp]
+    L.sidwt_set_stream.restype = i32
+    L.sidwt_correlate.argtypes = [vp, vp, i64, vp]
+    L.sidwt_correlate.restype = i32
+    L.sidwt_correlate_many.argtypes = [vp, vp, i64, i64, i64, vp, i64]
+    L.sidwt_correlate_many.restype = i32
+    L.sidwt_lift_many.argtypes = [i32, i32, vp, i64, i64, i64, vp, vp]
+    L.sidwt_lift_many.restype = i32
+    L.sidwt_correlate_batch.argtypes = [c.POINTER(vp), c.POINTER(vp), c.POINTER(i64),
+                                        c.POINTER(vp), i32, vp]
+    L.sidwt_correlate_batch.restype = i32
+    L.sidwt_plan_phase.argtypes = [vp, i32, i32, i32, c.POINTER(c.c_int32),
+                                   c.POINTER(c.c_int32), vp]
+    L.sidwt_plan_phase.restype = i32
+    L.sidwt_strerror.argtypes = [i32]
+    L.sidwt_strerror.restype = c.c_char_p
+    L.sidwt_version.argtypes = []
+    L.sidwt_version.restype = c.c_char_p
+    for name in ("sidwt_bank_create", "sidwt_bank_correlate", "sidwt_bank_free",
+                 "sidwt_bank_info", "sidwt_batch_plan_create", "sidwt_batch_run",
+                 "sidwt_batch_free", "sidwt_batch_info"):
+        if hasattr(L, name):
+            getattr(L, name).restype = i32
+    return L
+
+
+def lib():
+    """Load libsidwt.so (HIP runtime is shared with PyTorch when torch is
+    imported first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libsidwt.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def check(code: int, what: str = ""):
+    if code != SIDWT_OK:
+        raise SidwtError(code, what)

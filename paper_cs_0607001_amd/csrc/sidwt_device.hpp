@@ -1,0 +1,191 @@
+// Device-side building blocks of libsidwt (gfx950).
+//
+// Lifting factorisations of Sec. III of Bhattacharya & Mahapatra,
+// "A Novel Application of Lifting Scheme for Multiresolution Correlation of
+// Complex Radar Signals":
+//   - LeGall 5/3, x-side P~(z^-1) and dual analysis P^T(z^-1)  (Sec. III-C, Case I)
+//   - CDF 9/7 with Table I constants, both sides               (Sec. III-C, Case II)
+//   - causal Daubechies-4, eq. (17), same matrix on both sides (Sec. III-B)
+//   - reversible integer 5/3 (integer lifting with floor shifts)
+// A factor matrix acting on the polyphase pair [e; o] is applied right-most
+// first; "z e" is e[k+1], "z^-1 o" is o[k-1].  Pairs are (u[2k], u[2k+1]),
+// except for the causal D4 form whose pairs are (u[2k], u[2k-1]).
+// Real filters act on I and Q independently (Sec. IV).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sidwt {
+
+enum FilterId : int { F_LEGALL53 = 1, F_CDF97 = 2, F_D4 = 3, F_LEGALL53_INT = 4 };
+
+constexpr int kMaxLevels = 16;
+
+// Per level l (1..J) and band b (0 = approximation a~, 1 = detail b~): the
+// stored linear support [lo, lo+len) of every phase, and the element offset
+// of phase 0 in the plan's coefficient buffer (phases are contiguous, each
+// `len` elements long).
+struct LevelDesc {
+  int lo[2];
+  int len[2];
+  long long off[2];
+};
+
+struct PlanDesc {
+  const void *coef;  // float2 (float filters) or int2 (integer filter)
+  int filter;
+  int J;
+  int m;
+  int pad_;
+  LevelDesc lv[kMaxLevels + 1];  // index 1..J
+};
+
+// LDS layout of the fused kernel for one transform length N, computed on the
+// host.  Offsets and sizes count 8-byte complex elements.
+struct FusedLayout {
+  int N;
+  int J;
+  int region_off[kMaxLevels + 1];  // level-l bands: c at region_off, d after c
+  int halo[kMaxLevels + 1];        // circular copy appended to each band
+  int T[kMaxLevels + 1];           // Toeplitz blocking of the lag axis
+  int U[kMaxLevels + 1][2];        // lag-window length per band (even)
+  int V[kMaxLevels + 1][2];        // staged weight row length per band
+  int pc[kMaxLevels + 1];          // phases staged per chunk
+  int w_off;                       // weight staging area
+  int total;                       // total LDS elements
+};
+
+// ---------------------------------------------------------------------------
+// Table I (t = 5/4) and the causal D4 constants of eq. (17).
+// ---------------------------------------------------------------------------
+struct C97 {
+  static constexpr float a = -1.5f;
+  static constexpr float b = -0.0625f;
+  static constexpr float g = 0.8f;
+  static constexpr float d = 0.46875f;
+  static constexpr float xi = 1.13137084989847604f;      // 4 sqrt2 / 5
+  static constexpr float inv_xi = 0.883883476483184406f; // 5 / (4 sqrt2)
+};
+struct CD4 {
+  static constexpr float s3 = 1.73205080756887729f;          // sqrt3
+  static constexpr float u0 = 0.433012701892219323f;         // sqrt3 / 4
+  static constexpr float u1 = -0.0669872981077806766f;       // (sqrt3 - 2) / 4
+  static constexpr float ka = 1.93185165257813657f;          // (sqrt3 + 1) / sqrt2
+  static constexpr float kb = 0.517638090205041524f;         // (sqrt3 - 1) / sqrt2
+};
+
+// ---------------------------------------------------------------------------
+// Lane neighbours inside a 64-wide wavefront (lane-1 / lane+1).  Lanes at the
+// edge get their own value back; the window schedule never uses those.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float2 lane_prev(float2 v) {
+  return make_float2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
+}
+__device__ __forceinline__ float2 lane_next(float2 v) {
+  return make_float2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+}
+__device__ __forceinline__ int2 lane_prev(int2 v) {
+  return make_int2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
+}
+__device__ __forceinline__ int2 lane_next(int2 v) {
+  return make_int2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+}
+
+__device__ __forceinline__ float2 fma2(float s, float2 a, float2 c) {
+  return make_float2(fmaf(s, a.x, c.x), fmaf(s, a.y, c.y));
+}
+__device__ __forceinline__ float2 add2(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 scale2(float s, float2 a) {
+  return make_float2(s * a.x, s * a.y);
+}
+
+// ---------------------------------------------------------------------------
+// y-side (dual analysis, P^T(z^-1)) lifting of one level, one pair per lane.
+// HL/HR: lanes at the window edges whose results are incomplete.
+// On return e holds c (approximation), o holds d (detail).
+// ---------------------------------------------------------------------------
+template <int F> struct YLift;
+
+template <> struct YLift<F_LEGALL53> {
+  // Sec. III-C Case I: P^T(z^-1) = diag(1,2) [1 0; -(1+z)/4 1] [1 (1+z^-1)/2; 0 1]
+  static constexpr int HL = 1, HR = 1;
+  static constexpr bool kOddBefore = false;
+  using V = float2;
+  __device__ __forceinline__ static void run(float2 &e, float2 &o) {
+    e = fma2(0.5f, add2(lane_prev(o), o), e);
+    o = fma2(-0.25f, add2(e, lane_next(e)), o);
+    o = scale2(2.0f, o);
+  }
+};
+
+template <> struct YLift<F_CDF97> {
+  // Sec. III-C Case II: P^T(z^-1) = diag(1/x, x) [1 0; -d(1+z) 1]
+  //   [1 -g(1+z^-1); 0 1] [1 0; -b(1+z) 1] [1 -a(1+z^-1); 0 1]
+  static constexpr int HL = 2, HR = 2;
+  static constexpr bool kOddBefore = false;
+  using V = float2;
+  __device__ __forceinline__ static void run(float2 &e, float2 &o) {
+    e = fma2(-C97::a, add2(lane_prev(o), o), e);
+    o = fma2(-C97::b, add2(e, lane_next(e)), o);
+    e = fma2(-C97::g, add2(lane_prev(o), o), e);
+    o = fma2(-C97::d, add2(e, lane_next(e)), o);
+    e = scale2(C97::inv_xi, e);
+    o = scale2(C97::xi, o);
+  }
+};
+
+template <> struct YLift<F_D4> {
+  // Sec. III-B eq. (17): diag(ka, kb) [1 0; 1 z^-1] [1 u0 + u1 z^-1; 0 1] [1 0; -sqrt3 1]
+  // on pairs (e, o) = (u[2k], u[2k-1]); the same matrix serves both sides.
+  static constexpr int HL = 1, HR = 0;
+  static constexpr bool kOddBefore = true;
+  using V = float2;
+  __device__ __forceinline__ static void run(float2 &e, float2 &o) {
+    float2 o1 = fma2(-CD4::s3, e, o);
+    float2 o1p = lane_prev(o1);
+    float2 e1 = fma2(CD4::u1, o1p, fma2(CD4::u0, o1, e));
+    float2 o2 = add2(e1, o1p);
+    e = scale2(CD4::ka, e1);
+    o = scale2(CD4::kb, o2);
+  }
+};
+
+template <> struct YLift<F_LEGALL53_INT> {
+  // Reversible integer 5/3, dual-analysis (update-first) order:
+  //   e += (o[k-1] + o[k] + 1) >> 1 ;  o -= (e[k] + e[k+1] + 2) >> 2
+  static constexpr int HL = 1, HR = 1;
+  static constexpr bool kOddBefore = false;
+  using V = int2;
+  __device__ __forceinline__ static void run(int2 &e, int2 &o) {
+    int2 op = lane_prev(o);
+    e.x += (op.x + o.x + 1) >> 1;
+    e.y += (op.y + o.y + 1) >> 1;
+    int2 en = lane_next(e);
+    o.x -= (e.x + en.x + 2) >> 2;
+    o.y -= (e.y + en.y + 2) >> 2;
+  }
+};
+
+template <int F> struct ElemOf { using T = float2; };
+template <> struct ElemOf<F_LEGALL53_INT> { using T = int2; };
+
+// Tap reach of the x-side analysis bands: out[k] depends on u[2k+i] for
+// i in [lo, hi].  Used by the host to size the stored phase supports.
+struct TapRange { int lo, hi; };
+
+__host__ __device__ inline int floor_div(int a, int b) {
+  int q = a / b;
+  return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+__host__ __device__ inline int pos_mod(int a, int b) {
+  int r = a % b;
+  return r < 0 ? r + b : r;
+}
+
+// MFMA operand/accumulator vector types.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+}  // namespace sidwt

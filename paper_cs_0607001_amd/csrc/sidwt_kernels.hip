@@ -1,0 +1,573 @@
+// HIP kernels of libsidwt for gfx950.
+//
+//   ref_tree_level<F>   x-side lifting of the reference phase tree (plan).
+//   fused_correlate<F>  one workgroup per pulse: y-side lifting of all J
+//                       levels in LDS, each level correlated against the
+//                       plan's stored phases with MFMA as soon as it exists.
+//   lift_many<F>        y-side lifting only, pyramid written to HBM.
+//
+// Method references (Bhattacharya & Mahapatra): shift-circulant phases
+// Sec. II; dual analysis lifting Sec. III; per-scale correlation eq. (15),
+// (20), (20a); the Fig. 5 even/odd tree; Fig. 7 lifting of the received
+// signal.
+#include "sidwt_device.hpp"
+
+namespace sidwt {
+
+// ===========================================================================
+// Reference phase tree (plan creation).
+//
+// Level l, phase r < 2^l: the input is phase r' = r mod 2^(l-1) of level l-1
+// delayed by one sample when r >= 2^(l-1) (shift-circulance, Sec. II; the
+// even/odd tree of Fig. 5).  Lifting runs on a zero-extended linear buffer
+// of pairs that covers the output supports with a margin.
+// ===========================================================================
+
+template <int F> struct XStepsLDS;
+
+template <> struct XStepsLDS<F_LEGALL53> {
+  // Sec. III-C Case I: P~(z^-1) = diag(1, 1/2) [1 (1+z^-1)/4; 0 1] [1 0; -(1+z)/2 1]
+  __device__ static void run(float2 *e, float2 *o, float2 *, int np, int tid, int nt) {
+    for (int k = tid; k < np; k += nt) {
+      float2 en = (k + 1 < np) ? e[k + 1] : make_float2(0.f, 0.f);
+      o[k] = fma2(-0.5f, add2(e[k], en), o[k]);
+    }
+    __syncthreads();
+    for (int k = tid; k < np; k += nt) {
+      float2 op = (k > 0) ? o[k - 1] : make_float2(0.f, 0.f);
+      e[k] = fma2(0.25f, add2(op, o[k]), e[k]);
+    }
+    __syncthreads();
+    for (int k = tid; k < np; k += nt) o[k] = scale2(0.5f, o[k]);
+    __syncthreads();
+  }
+};
+
+template <> struct XStepsLDS<F_CDF97> {
+  // Sec. III-C Case II: P~(z^-1) = diag(x, 1/x) [1 d(1+z^-1); 0 1]
+  //   [1 0; g(1+z) 1] [1 b(1+z^-1); 0 1] [1 0; a(1+z) 1]
+  __device__ static void pred(float2 *e, float2 *o, int np, int tid, int nt, float c) {
+    for (int k = tid; k < np; k += nt) {
+      float2 en = (k + 1 < np) ? e[k + 1] : make_float2(0.f, 0.f);
+      o[k] = fma2(c, add2(e[k], en), o[k]);
+    }
+    __syncthreads();
+  }
+  __device__ static void upd(float2 *e, float2 *o, int np, int tid, int nt, float c) {
+    for (int k = tid; k < np; k += nt) {
+      float2 op = (k > 0) ? o[k - 1] : make_float2(0.f, 0.f);
+      e[k] = fma2(c, add2(op, o[k]), e[k]);
+    }
+    __syncthreads();
+  }
+  __device__ static void run(float2 *e, float2 *o, float2 *, int np, int tid, int nt) {
+    pred(e, o, np, tid, nt, C97::a);
+    upd(e, o, np, tid, nt, C97::b);
+    pred(e, o, np, tid, nt, C97::g);
+    upd(e, o, np, tid, nt, C97::d);
+    for (int k = tid; k < np; k += nt) {
+      e[k] = scale2(C97::xi, e[k]);
+      o[k] = scale2(C97::inv_xi, o[k]);
+    }
+    __syncthreads();
+  }
+};
+
+template <> struct XStepsLDS<F_D4> {
+  // Sec. III-B eq. (17) on pairs (u[2k], u[2k-1]).  `tmp` is a third pair
+  // buffer for the step that reads o[k-1] while replacing o.
+  __device__ static void run(float2 *e, float2 *o, float2 *tmp, int np, int tid, int nt) {
+    for (int k = tid; k < np; k += nt) o[k] = fma2(-CD4::s3, e[k], o[k]);
+    __syncthreads();
+    for (int k = tid; k < np; k += nt) {
+      float2 op = (k > 0) ? o[k - 1] : make_float2(0.f, 0.f);
+      e[k] = fma2(CD4::u1, op, fma2(CD4::u0, o[k], e[k]));
+    }
+    __syncthreads();
+    // [1 0; 1 z^-1]: o[k] <- e[k] + o[k-1]
+    for (int k = tid; k < np; k += nt) {
+      float2 op = (k > 0) ? o[k - 1] : make_float2(0.f, 0.f);
+      tmp[k] = add2(e[k], op);
+    }
+    __syncthreads();
+    for (int k = tid; k < np; k += nt) {
+      e[k] = scale2(CD4::ka, e[k]);
+      o[k] = scale2(CD4::kb, tmp[k]);
+    }
+    __syncthreads();
+  }
+};
+
+template <> struct XStepsLDS<F_LEGALL53_INT> {
+  // reversible 5/3, x-side:  o -= (e[k]+e[k+1])>>1 ;  e += (o[k-1]+o[k]+2)>>2
+  __device__ static void run(int2 *e, int2 *o, int2 *, int np, int tid, int nt) {
+    for (int k = tid; k < np; k += nt) {
+      int2 en = (k + 1 < np) ? e[k + 1] : make_int2(0, 0);
+      o[k].x -= (e[k].x + en.x) >> 1;
+      o[k].y -= (e[k].y + en.y) >> 1;
+    }
+    __syncthreads();
+    for (int k = tid; k < np; k += nt) {
+      int2 op = (k > 0) ? o[k - 1] : make_int2(0, 0);
+      e[k].x += (op.x + o[k].x + 2) >> 2;
+      e[k].y += (op.y + o[k].y + 2) >> 2;
+    }
+    __syncthreads();
+  }
+};
+
+template <int F> struct XOddBefore { static constexpr bool v = false; };
+template <> struct XOddBefore<F_D4> { static constexpr bool v = true; };
+
+// One block per phase r.  `in` holds 2^(l-1) phases of in_len elements each
+// (level 1: the reference itself, a single "phase").  Pair buffer covers
+// k in [k0, k0 + np).
+template <int F>
+__global__ __launch_bounds__(256) void ref_tree_level(
+    const typename ElemOf<F>::T *__restrict__ in, int in_lo, int in_len, int level,
+    int k0, int np, typename ElemOf<F>::T *__restrict__ outA, int loA, int lenA,
+    typename ElemOf<F>::T *__restrict__ outB, int loB, int lenB) {
+  using V = typename ElemOf<F>::T;
+  extern __shared__ __align__(16) char smem_tree[];
+  V *e = reinterpret_cast<V *>(smem_tree);
+  V *o = e + np;
+  V *tmp = o + np;
+  const int r = blockIdx.x;
+  const int half = 1 << (level - 1);
+  const int rp = (level == 1) ? 0 : (r & (half - 1));
+  const int delay = r >> (level - 1);
+  const V *src = in + (long long)rp * in_len;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  auto sample = [&](int t) -> V {
+    int i = t - delay - in_lo;
+    V z;
+    if (i >= 0 && i < in_len) return src[i];
+    z.x = 0; z.y = 0;
+    return z;
+  };
+  for (int kk = tid; kk < np; kk += nt) {
+    int k = k0 + kk;
+    e[kk] = sample(2 * k);
+    o[kk] = XOddBefore<F>::v ? sample(2 * k - 1) : sample(2 * k + 1);
+  }
+  __syncthreads();
+  XStepsLDS<F>::run(e, o, tmp, np, tid, nt);
+  for (int t = tid; t < lenA; t += nt) outA[(long long)r * lenA + t] = e[loA + t - k0];
+  for (int t = tid; t < lenB; t += nt) outB[(long long)r * lenB + t] = o[loB + t - k0];
+}
+
+// ===========================================================================
+// y-side lifting of one level across the workgroup (Fig. 7).  Each wave
+// takes windows of 64 consecutive pairs; HL/HR edge lanes only feed their
+// neighbours (shuffles), the remaining lanes own their pair.  `load(kc, e,
+// o)` fetches pair kc (0 <= kc < np) of the level input; `store(k, c, d)`
+// receives the owned outputs.
+// ===========================================================================
+template <int F, int UNROLL, class Load, class Store>
+__device__ __forceinline__ void lift_level(int np, Load load, Store store) {
+  using L = YLift<F>;
+  using V = typename L::V;
+  constexpr int OWN = 64 - L::HL - L::HR;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int nwin = (np + OWN - 1) / OWN;
+  for (int w0 = wave * UNROLL; w0 < nwin; w0 += nw * UNROLL) {
+    V e[UNROLL], o[UNROLL];
+    int kk[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      int k = (w0 + u) * OWN - L::HL + lane;
+      kk[u] = k;
+      load(pos_mod(k, np), e[u], o[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) L::run(e[u], o[u]);
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      int k = kk[u];
+      if (lane >= L::HL && lane < 64 - L::HR && k < np && (w0 + u) < nwin) store(k, e[u], o[u]);
+    }
+  }
+}
+
+// Pair kc of a circular sequence of length 2*np held in `src` (LDS or
+// global); for the causal D4 form the odd member is u[2k-1].
+template <bool ODD_BEFORE, class V>
+__device__ __forceinline__ void pair_at(const V *src, int kc, int np, V &e, V &o) {
+  e = src[2 * kc];
+  o = ODD_BEFORE ? src[kc == 0 ? 2 * np - 1 : 2 * kc - 1] : src[2 * kc + 1];
+}
+
+// Level-1 input from the caller's pulse: complex64, or int16 I/Q widened to
+// int32.  Samples at index >= n are the zero padding up to N.
+__device__ __forceinline__ float2 rx_sample(const float2 *rx, long long n, int i) {
+  return (i < n) ? rx[i] : make_float2(0.f, 0.f);
+}
+__device__ __forceinline__ int2 rx_sample(const short2 *rx, long long n, int i) {
+  if (i < n) {
+    short2 s = rx[i];
+    return make_int2(s.x, s.y);
+  }
+  return make_int2(0, 0);
+}
+
+template <int F> struct RxOf { using T = float2; using Out = float; };
+template <> struct RxOf<F_LEGALL53_INT> { using T = short2; using Out = long long; };
+
+// ===========================================================================
+// Per-scale correlation of one level against the stored phases (eq. (20),
+// (20a)): plane j = l-1, P = 2^l phases, L = N/2^l lags per phase.
+//
+//   R[P p + r] = sum_t conj(w_r[t]) c[(p + t) mod L] + same for (w~, d)
+//
+// as a real GEMM on MFMA 16x16x4: rows = lag blocks p1 (p = p1*T + p0),
+// columns = (p0, r, re/im) with T*P = 8 for P < 8 (Toeplitz blocking of
+// the lag axis) or 8 phases per tile for P >= 8, K = (lag offset u, re/im).
+// The complex product conj(w) c is the 2x2 real embedding
+// [re; im] = [w.re w.im; -w.im w.re] [c.re; c.im].
+// ===========================================================================
+template <bool INT> struct CorrTypes;
+template <> struct CorrTypes<false> {
+  using V = float2;
+  using S = float;
+  using A = float;
+  using Acc = f32x4;
+  __device__ static Acc mma(A a, A b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static A cvt(float v) { return v; }
+  // v_mfma_f32_16x16x4_f32: accumulator register i of lane l holds row
+  // 4*(l/16) + i, column l%16.
+  __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
+template <> struct CorrTypes<true> {
+  using V = int2;
+  using S = int;
+  using A = double;
+  using Acc = f64x4;
+  __device__ static Acc mma(A a, A b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static A cvt(int v) { return (double)v; }
+  // v_mfma_f64_16x16x4_f64: accumulator register i of lane l holds row
+  // 4*i + l/16, column l%16.
+  __device__ static int row_of(int lane, int i) { return 4 * i + (lane >> 4); }
+};
+
+template <bool INT, class OutT>
+__device__ void correlate_level(const PlanDesc &plan, const FusedLayout &lay, int l,
+                                typename CorrTypes<INT>::V *sm, OutT *__restrict__ outp) {
+  using CT = CorrTypes<INT>;
+  using V = typename CT::V;
+  using S = typename CT::S;
+  const int N = lay.N;
+  const int P = 1 << l;
+  const int L = N >> l;
+  const int T = lay.T[l];
+  const int Mrows = (L + T - 1) / T;
+  const int mtiles = (Mrows + 15) / 16;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const V *bands[2];
+  bands[0] = sm + lay.region_off[l];
+  bands[1] = bands[0] + L + lay.halo[l];
+  V *W = sm + lay.w_off;
+  const V *coef = reinterpret_cast<const V *>(plan.coef);
+  const LevelDesc &ld = plan.lv[l];
+  const int pc = lay.pc[l];
+  const int V0 = lay.V[l][0], V1 = lay.V[l][1];
+
+  // Lane roles (MFMA 16x16x4: A[row][k], B[k][col], lane = 16*k + row|col).
+  const int row = lane & 15;
+  const int kq = lane >> 4;
+  const int du = kq >> 1;
+  const int ci = kq & 1;
+  const int col = lane & 15;
+  const int co = col & 1;
+  const int cc = col >> 1;
+  const bool neg = (ci == 0) && (co == 1);
+
+  for (int r0 = 0; r0 < P; r0 += pc) {
+    const int pcc = min(pc, P - r0);
+    // Stage weights of phases r0..r0+pcc-1, both bands, zero padded so that
+    // v = u + du - p0 + T - 1 indexes w[v - (T-1)].
+    {
+      const int tot0 = pcc * V0, tot = tot0 + pcc * V1;
+      for (int i = tid; i < tot; i += nt) {
+        const int b = i >= tot0;
+        const int j = b ? i - tot0 : i;
+        const int Vb = b ? V1 : V0;
+        const int rr = j / Vb;
+        const int v = j - rr * Vb;
+        const int t = v - (T - 1);
+        V w;
+        w.x = 0; w.y = 0;
+        if (t >= 0 && t < ld.len[b]) w = coef[ld.off[b] + (long long)(r0 + rr) * ld.len[b] + t];
+        W[i] = w;
+      }
+    }
+    __syncthreads();
+    const int ntn = (T > 1) ? 1 : (pcc >> 3);
+    const int ntiles = mtiles * ntn;
+    int r_local, p0;
+    if (T > 1) {
+      r_local = cc & (P - 1);
+      p0 = cc >> l;
+    }
+    for (int tile = wave; tile < ntiles; tile += nw) {
+      const int mt = tile % mtiles;
+      const int ntile = tile / mtiles;
+      if (T == 1) {
+        r_local = ntile * 8 + cc;
+        p0 = 0;
+      }
+      const int p1 = mt * 16 + row;
+      typename CT::Acc acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int Ub = lay.U[l][b];
+        const int base = pos_mod(p1 * T + ld.lo[b], L);
+        const S *ap = reinterpret_cast<const S *>(bands[b]) + 2 * (base + du) + ci;
+        const S *wp = reinterpret_cast<const S *>(W + (b ? pcc * V0 : 0) + r_local * (b ? V1 : V0)) +
+                      2 * (du - p0 + T - 1) + (ci ^ co);
+#pragma unroll 4
+        for (int u = 0; u < Ub; u += 2) {
+          S a = ap[2 * u];
+          S w = wp[2 * u];
+          if (neg) w = -w;
+          acc = CT::mma(CT::cvt(a), CT::cvt(w), acc);
+        }
+      }
+      // Output element (row CT::row_of(lane, i), column col) of this tile.
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int pp1 = mt * 16 + CT::row_of(lane, i);
+        const int p = pp1 * T + p0;
+        if (pp1 < Mrows && p < L) {
+          const long long s = (long long)P * p + r0 + r_local;
+          if constexpr (INT) {
+            outp[2 * s + co] = (long long)acc[i];
+          } else {
+            __builtin_nontemporal_store(acc[i], &outp[2 * s + co]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ===========================================================================
+// Fused kernel: one workgroup per pulse.
+// LDS: level-l bands c_l | d_l at region_off[l] (odd and even levels in
+// alternating halves, so level l+1 can be lifted from c_l while nothing
+// else is live), each band followed by a circular halo copy so that the
+// correlation's lag windows never wrap; then the weight staging area.
+// ===========================================================================
+template <int F>
+__global__ __launch_bounds__(256) void fused_correlate(PlanDesc plan, FusedLayout lay,
+                                                       const void *__restrict__ rx_all, long long n,
+                                                       long long rx_stride,
+                                                       void *__restrict__ out_all,
+                                                       long long out_stride) {
+  constexpr bool INT = (F == F_LEGALL53_INT);
+  using V = typename ElemOf<F>::T;
+  using RxT = typename RxOf<F>::T;
+  using OutT = typename RxOf<F>::Out;
+  constexpr bool OB = YLift<F>::kOddBefore;
+  extern __shared__ __align__(16) char smem_fused[];
+  V *sm = reinterpret_cast<V *>(smem_fused);
+  const long long pulse = blockIdx.x;
+  const RxT *rx = reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride;
+  OutT *out = reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2;
+  const int N = lay.N;
+
+  // Level 1 straight from HBM (pairs split at load, zero padding n..N-1).
+  {
+    const int np = N >> 1;
+    V *c1 = sm + lay.region_off[1];
+    V *d1 = c1 + np + lay.halo[1];
+    const int halo = lay.halo[1];
+    lift_level<F, 2>(
+        np,
+        [&](int kc, V &e, V &o) {
+          e = rx_sample(rx, n, 2 * kc);
+          o = rx_sample(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
+        },
+        [&](int k, V c, V d) {
+          for (int kk = k; kk < np + halo; kk += np) {
+            c1[kk] = c;
+            d1[kk] = d;
+          }
+        });
+  }
+  __syncthreads();
+
+  for (int l = 1; l <= lay.J; ++l) {
+    correlate_level<INT>(plan, lay, l, sm, out + 2LL * (l - 1) * N);
+    if (l < lay.J) {
+      const int np = N >> (l + 1);
+      const V *cin = sm + lay.region_off[l];
+      V *c2 = sm + lay.region_off[l + 1];
+      V *d2 = c2 + np + lay.halo[l + 1];
+      const int halo = lay.halo[l + 1];
+      lift_level<F, 1>(
+          np, [&](int kc, V &e, V &o) { pair_at<OB>(cin, kc, np, e, o); },
+          [&](int k, V c, V d) {
+            for (int kk = k; kk < np + halo; kk += np) {
+              c2[kk] = c;
+              d2[kk] = d;
+            }
+          });
+    }
+    __syncthreads();
+  }
+}
+
+// ===========================================================================
+// Lifting only: pyramid d_1 | ... | d_J | c_J written to HBM.
+// LDS holds the current approximation (odd levels at [0, N/2), even levels
+// at [N/2, 3N/4)).
+// ===========================================================================
+template <int F>
+__global__ __launch_bounds__(256) void lift_many(int J, int N, const void *__restrict__ rx_all,
+                                                 long long n, long long rx_stride,
+                                                 void *__restrict__ pyr_all) {
+  using V = typename ElemOf<F>::T;
+  using RxT = typename RxOf<F>::T;
+  constexpr bool OB = YLift<F>::kOddBefore;
+  extern __shared__ __align__(16) char smem_lift[];
+  V *sm = reinterpret_cast<V *>(smem_lift);
+  const long long pulse = blockIdx.x;
+  const RxT *rx = reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride;
+  V *pyr = reinterpret_cast<V *>(pyr_all) + pulse * (long long)N;
+  for (int l = 1; l <= J; ++l) {
+    const int np = N >> l;
+    V *dg = pyr + (N - (N >> (l - 1)));               // d_l
+    V *cl = (l == J) ? pyr + (N - np) : sm + ((l & 1) ? 0 : (N >> 1));
+    if (l == 1) {
+      lift_level<F, 4>(
+          np,
+          [&](int kc, V &e, V &o) {
+            e = rx_sample(rx, n, 2 * kc);
+            o = rx_sample(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
+          },
+          [&](int k, V c, V d) {
+            cl[k] = c;
+            dg[k] = d;
+          });
+    } else {
+      const V *cin = sm + (((l - 1) & 1) ? 0 : (N >> 1));
+      lift_level<F, 2>(
+          np, [&](int kc, V &e, V &o) { pair_at<OB>(cin, kc, np, e, o); },
+          [&](int k, V c, V d) {
+            cl[k] = c;
+            dg[k] = d;
+          });
+    }
+    __syncthreads();
+  }
+}
+
+// Explicit instantiations are produced by the launch helpers below.
+#define SIDWT_FOR_FILTERS(X) X(F_LEGALL53) X(F_CDF97) X(F_D4) X(F_LEGALL53_INT)
+
+}  // namespace sidwt
+
+// ---------------------------------------------------------------------------
+// Launch helpers with C++ linkage, used by the host API (sidwt_api.cpp).
+// ---------------------------------------------------------------------------
+namespace sidwt {
+
+template <int F>
+static hipError_t launch_tree_t(const void *in, int in_lo, int in_len, int level, int k0, int np,
+                                void *outA, int loA, int lenA, void *outB, int loB, int lenB,
+                                hipStream_t st) {
+  using V = typename ElemOf<F>::T;
+  size_t shm = 3ull * np * sizeof(V);
+  if (shm > 65536) {
+    hipError_t e = hipFuncSetAttribute((const void *)ref_tree_level<F>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(ref_tree_level<F>, dim3(1u << level), dim3(256), shm, st,
+                     reinterpret_cast<const V *>(in), in_lo, in_len, level, k0, np,
+                     reinterpret_cast<V *>(outA), loA, lenA, reinterpret_cast<V *>(outB), loB, lenB);
+  return hipGetLastError();
+}
+
+hipError_t launch_tree(int filter, const void *in, int in_lo, int in_len, int level, int k0,
+                       int np, void *outA, int loA, int lenA, void *outB, int loB, int lenB,
+                       hipStream_t st) {
+  switch (filter) {
+#define X(F) \
+  case F:    \
+    return launch_tree_t<F>(in, in_lo, in_len, level, k0, np, outA, loA, lenA, outB, loB, lenB, st);
+    SIDWT_FOR_FILTERS(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int F>
+static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, const void *rx,
+                                 long long n, long long count, long long rx_stride, void *out,
+                                 long long out_stride, hipStream_t st) {
+  size_t shm = (size_t)lay.total * 8;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)fused_correlate<F>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(fused_correlate<F>, dim3((unsigned)count), dim3(256), shm, st, plan, lay, rx,
+                     n, rx_stride, out, out_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_fused(const PlanDesc &plan, const FusedLayout &lay, const void *rx, long long n,
+                        long long count, long long rx_stride, void *out, long long out_stride,
+                        hipStream_t st) {
+  switch (plan.filter) {
+#define X(F) \
+  case F:    \
+    return launch_fused_t<F>(plan, lay, rx, n, count, rx_stride, out, out_stride, st);
+    SIDWT_FOR_FILTERS(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int F>
+static hipError_t launch_lift_t(int J, int N, const void *rx, long long n, long long count,
+                                long long rx_stride, void *pyr, hipStream_t st) {
+  size_t shm = (size_t)(N / 2 + N / 4 + 1) * 8;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)lift_many<F>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(lift_many<F>, dim3((unsigned)count), dim3(256), shm, st, J, N, rx, n,
+                     rx_stride, pyr);
+  return hipGetLastError();
+}
+
+hipError_t launch_lift(int filter, int J, int N, const void *rx, long long n, long long count,
+                       long long rx_stride, void *pyr, hipStream_t st) {
+  switch (filter) {
+#define X(F) \
+  case F:    \
+    return launch_lift_t<F>(J, N, rx, n, count, rx_stride, pyr, st);
+    SIDWT_FOR_FILTERS(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace sidwt

@@ -1,0 +1,71 @@
+"""CPU-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sidwt.h")
+LIB = os.path.join(ROOT, "paper_cs_0607001_amd", "libsidwt.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sidwt_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(LIB):
+        pytest.skip("libsidwt.so not built")
+    from paper_cs_0607001_amd._lib import lib
+    return lib()
+
+
+def test_header_declares_the_core_api():
+    names = declared_functions()
+    for want in ("sidwt_plan_create", "sidwt_correlate", "sidwt_free", "sidwt_out_len",
+                 "sidwt_set_stream", "sidwt_correlate_batch", "sidwt_strerror"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    raw = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(raw, n)]
+    assert not missing, missing
+
+
+def test_strerror_and_version(L):
+    assert L.sidwt_strerror(0) == b"ok"
+    assert L.sidwt_strerror(-1) == b"invalid argument"
+    assert L.sidwt_strerror(-2).startswith(b"size")
+    assert L.sidwt_version().startswith(b"sidwt")
+
+
+def test_invalid_arguments_are_rejected_on_the_host(L):
+    vp = ctypes.c_void_p
+    h = vp()
+    ref = (ctypes.c_float * 8)()
+    # unknown filter, NULL ref, NULL out, bad J, bad m
+    assert L.sidwt_plan_create(9, 3, ctypes.cast(ref, vp), 4, ctypes.byref(h)) == -1
+    assert L.sidwt_plan_create(1, 3, None, 4, ctypes.byref(h)) == -1
+    assert L.sidwt_plan_create(1, 3, ctypes.cast(ref, vp), 4, None) == -1
+    assert L.sidwt_plan_create(1, 0, ctypes.cast(ref, vp), 4, ctypes.byref(h)) == -1
+    assert L.sidwt_plan_create(1, 17, ctypes.cast(ref, vp), 4, ctypes.byref(h)) == -1
+    assert L.sidwt_plan_create(1, 3, ctypes.cast(ref, vp), 0, ctypes.byref(h)) == -1
+    assert L.sidwt_plan_create(1, 3, ctypes.cast(ref, vp), 1 << 20, ctypes.byref(h)) == -2
+    assert h.value is None
+    # NULL plan everywhere
+    assert L.sidwt_correlate(None, vp(16), 8, vp(16)) == -1
+    assert L.sidwt_correlate_many(None, vp(16), 8, 1, 8, vp(16), 8) == -1
+    assert L.sidwt_out_len(None, 8) == -1
+    assert L.sidwt_set_stream(None, None) == -1
+    L.sidwt_free(None)  # no-op
+    # lifting-only entry: NULL pointers, bad filter, N/2^J < 2, stride < n
+    assert L.sidwt_lift_many(1, 3, None, 64, 1, 64, vp(16), None) == -1
+    assert L.sidwt_lift_many(7, 3, vp(16), 64, 1, 64, vp(16), None) == -1
+    assert L.sidwt_lift_many(1, 3, vp(16), 8, 1, 8, vp(16), None) == -1
+    assert L.sidwt_lift_many(1, 3, vp(16), 64, 1, 32, vp(16), None) == -1

@@ -1,0 +1,226 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Float filters: relative L2 error per plane <= 1e-5 (FP32 lifting and FP32
+MFMA accumulation against the FP64 definition).  Integer filter: bit-exact.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0607001_amd as S
+    S._lib.lib()  # loud failure if the library is missing
+    return torch, S
+
+
+def crandn(rng, n):
+    return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def run_float(dev, filt, J, ref, rx):
+    torch, S = dev
+    print(f"[case] filter={filt} J={J} m={len(ref)} n={len(rx)}", flush=True)
+    with S.plan_create(filt, J, ref) as plan:
+        x = torch.from_numpy(np.asarray(rx, np.complex64)).cuda()
+        out = S.correlate(plan, x)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+
+def assert_planes_close(got, want, tol=TOL):
+    assert got.shape == want.shape
+    for j in range(want.shape[0]):
+        e = rel_l2(got[j].astype(np.complex128), want[j])
+        assert e <= tol, f"plane {j}: rel L2 {e:.3e}"
+
+
+# ---------------------------------------------------------------------------
+# Single pulses, every float filter, ragged lengths, several tiles
+# ---------------------------------------------------------------------------
+
+def test_single_chirp_legall53_j3(dev):
+    w = W.single_chirp(seed=1)
+    got = run_float(dev, w.filter, w.J, w.ref, w.rx)
+    want = O.correlate_direct(w.filter, w.J, w.ref, w.rx)
+    assert_planes_close(got, want)
+    assert int(np.argmax(np.abs(got[0]))) == w.delay
+
+
+@pytest.mark.parametrize("filt,J,m,n", [
+    ("legall53", 3, 37, 200),     # N = 200 (ragged, 25 * 8)
+    ("legall53", 5, 120, 1000),   # N = 1024
+    ("cdf97", 5, 100, 640),
+    ("cdf97", 4, 300, 1500),      # N = 1504
+    ("cdf97", 2, 16, 40),
+    ("d4", 4, 50, 300),           # N = 304
+    ("d4", 6, 64, 1024),
+    ("d4", 1, 5, 9),              # N = 10
+])
+def test_float_filters_random(dev, filt, J, m, n):
+    rng = np.random.default_rng(hash((filt, J, m, n)) & 0xffff)
+    ref, rx = crandn(rng, m), crandn(rng, n)
+    got = run_float(dev, filt, J, ref, rx)
+    want = O.correlate_direct(filt, J, ref, rx)
+    assert_planes_close(got, want)
+
+
+def test_reference_as_long_as_the_transform(dev):
+    rng = np.random.default_rng(5)
+    ref, rx = crandn(rng, 64), crandn(rng, 64)
+    got = run_float(dev, "cdf97", 3, ref, rx)
+    assert_planes_close(got, O.correlate_direct("cdf97", 3, ref, rx))
+
+
+def test_dc_and_delta_special_cases(dev):
+    rng = np.random.default_rng(6)
+    x = crandn(rng, 21)
+    got = run_float(dev, "cdf97", 4, x, np.ones(128))
+    assert np.abs(got - np.conj(x.sum())).max() < 1e-5 * abs(x.sum())
+    y = crandn(rng, 96)
+    got = run_float(dev, "d4", 3, np.array([1.0 + 0j]), y)
+    assert np.abs(got[0] - y).max() < 1e-5 * np.abs(y).max()
+
+
+# ---------------------------------------------------------------------------
+# Reference phase pyramid (plan) against the oracle's directly computed phases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("filt", ["legall53", "cdf97", "d4", "legall53_int"])
+def test_plan_phases_match_direct_computation(dev, filt):
+    torch, S = dev
+    rng = np.random.default_rng(7)
+    J, m, N = 4, 23, 512
+    if filt == "legall53_int":
+        ref = rng.integers(-2047, 2048, size=(m, 2)).astype(np.int16)
+    else:
+        ref = crandn(rng, m).astype(np.complex64)
+    with S.plan_create(filt, J, ref) as plan:
+        for lvl in range(1, J + 1):
+            L = N >> lvl
+            for r in range(1 << lvl):
+                want = O.reference_phase(filt, ref, N, lvl, r)
+                for b in (0, 1):
+                    lo, c = S.plan_phase(plan, lvl, b, r)
+                    if filt == "legall53_int":
+                        c = c[:, 0] + 1j * c[:, 1]
+                    circ = np.zeros(L, complex)
+                    np.add.at(circ, (lo + np.arange(len(c))) % L, c)
+                    tol = 0 if filt == "legall53_int" else 1e-5 * np.abs(want[b]).max()
+                    assert np.abs(circ - want[b]).max() <= tol, (lvl, r, b)
+
+
+# ---------------------------------------------------------------------------
+# Lifting-only kernel against the oracle's lifting
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("filt,J,n", [("legall53", 3, 1000), ("cdf97", 5, 8192), ("d4", 4, 300)])
+def test_lift_many_float(dev, filt, J, n):
+    torch, S = dev
+    rng = np.random.default_rng(8)
+    count = 3
+    rx = np.stack([crandn(rng, n) for _ in range(count)])
+    pyr = S.lift_many(filt, J, torch.from_numpy(rx.astype(np.complex64)).cuda())
+    torch.cuda.synchronize()
+    pyr = pyr.cpu().numpy()
+    N = O.transform_length(n, J)
+    _, _, ylo, yhi = O.TAPS[filt]
+    for i in range(count):
+        c = O.zero_pad(rx[i], N)
+        parts = []
+        for _ in range(J):
+            c, d = O.analyze(c, ylo), O.analyze(c, yhi)
+            parts.append(d)
+        want = np.concatenate(parts + [c])
+        assert rel_l2(pyr[i].astype(complex), want) < 1e-6
+
+
+def test_lift_many_integer(dev):
+    torch, S = dev
+    J, n, count = 6, 4096, 2
+    rx = np.stack([W.int_pulse(3, i, n=n) for i in range(count)])
+    pyr = S.lift_many("legall53_int", J, torch.from_numpy(rx).cuda())
+    torch.cuda.synchronize()
+    pyr = pyr.cpu().numpy().astype(np.int64)
+    for i in range(count):
+        re, im = rx[i, :, 0].astype(np.int64), rx[i, :, 1].astype(np.int64)
+        parts = []
+        for _ in range(J):
+            (re, dre), (im, dim) = O.i2i_lift_y(re), O.i2i_lift_y(im)
+            parts.append(np.stack([dre, dim], -1))
+        want = np.concatenate(parts + [np.stack([re, im], -1)])
+        assert np.array_equal(pyr[i], want)
+
+
+# ---------------------------------------------------------------------------
+# Integer path: bit-exact
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("J,m,n", [(3, 40, 200), (6, 64, 1024), (4, 31, 230)])
+def test_integer_path_bit_exact(dev, J, m, n):
+    torch, S = dev
+    rng = np.random.default_rng(J * 1000 + m)
+    ref = rng.integers(-2047, 2048, size=(m, 2)).astype(np.int16)
+    rx = rng.integers(-2048, 2048, size=(n, 2)).astype(np.int16)
+    print(f"[case] int J={J} m={m} n={n}", flush=True)
+    with S.plan_create("legall53_int", J, ref) as plan:
+        out = S.correlate(plan, torch.from_numpy(rx).cuda())
+        torch.cuda.synchronize()
+    want = O.correlate_int(J, ref, rx)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_integer_support_wrap_is_rejected(dev):
+    torch, S = dev
+    ref = np.ones((60, 2), np.int16)
+    with S.plan_create("legall53_int", 3, ref) as plan:
+        rx = torch.zeros((64, 2), dtype=torch.int16, device="cuda")
+        with pytest.raises(S.SidwtError) as e:
+            S.correlate(plan, rx)
+        assert e.value.code == -2
+
+
+# ---------------------------------------------------------------------------
+# Error paths through the ABI with a real plan
+# ---------------------------------------------------------------------------
+
+def test_size_errors(dev):
+    torch, S = dev
+    rng = np.random.default_rng(9)
+    with S.plan_create("cdf97", 3, crandn(rng, 40)) as plan:
+        with pytest.raises(S.SidwtError) as e:      # m > N
+            S.correlate(plan, torch.zeros(32, dtype=torch.complex64, device="cuda"))
+        assert e.value.code == -2
+        with pytest.raises(S.SidwtError) as e:      # N / 2^J < 2
+            S.correlate(plan, torch.zeros(8, dtype=torch.complex64, device="cuda"))
+        assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------
+# Uniform batch in one launch: every pulse equals its own single launch and
+# the oracle (small batch, full planes)
+# ---------------------------------------------------------------------------
+
+def test_correlate_many_matches_oracle(dev):
+    torch, S = dev
+    b = W.batched_uniform(seed=21, count=5, n=1024, m=128, J=4)
+    with S.plan_create(b.filter, b.J, b.ref) as plan:
+        out = S.correlate_many(plan, torch.from_numpy(b.rx).cuda())
+        torch.cuda.synchronize()
+        out = out.cpu().numpy()
+    for i in range(5):
+        assert_planes_close(out[i], O.correlate_direct(b.filter, b.J, b.ref, b.rx[i]))

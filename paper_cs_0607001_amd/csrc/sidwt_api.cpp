@@ -96,8 +96,10 @@ int make_layout(const sidwt_plan *p, int64_t N64, FusedLayout *lay) {
     lay->T[l] = T;
     int halo = 0;
     for (int b = 0; b < 2; ++b) {
+      // lag offsets u in [0, U): K of the per-scale GEMM, in groups of 8
+      // (four 16x16x4 MFMAs of two offsets each)
       int U = p->desc.lv[l].len[b] + T - 1;
-      U = (U + 1) & ~1;
+      U = (U + 7) & ~7;
       lay->U[l][b] = U;
       lay->V[l][b] = (U + T) | 1;  // odd row length spreads phases over LDS banks
       halo = std::max(halo, U);

@@ -20,6 +20,9 @@ namespace sidwt {
 enum FilterId : int { F_LEGALL53 = 1, F_CDF97 = 2, F_D4 = 3, F_LEGALL53_INT = 4 };
 
 constexpr int kMaxLevels = 16;
+// Threads per workgroup of the fused kernel (8 waves: two workgroups per CU
+// give four waves per SIMD to hide LDS latency behind the MFMA pipe).
+constexpr int kFusedThreads = 512;
 
 // Per level l (1..J) and band b (0 = approximation a~, 1 = detail b~): the
 // stored linear support [lo, lo+len) of every phase, and the element offset

@@ -311,47 +311,77 @@ __device__ void correlate_level(const PlanDesc &plan, const FusedLayout &lay, in
     }
     __syncthreads();
     const int ntn = (T > 1) ? 1 : (pcc >> 3);
-    const int ntiles = mtiles * ntn;
-    int r_local, p0;
+    // Each wave computes two vertically adjacent 16x16 tiles that share the
+    // weight (B) operand; K runs in groups of 4 MFMAs (8 lag offsets) with
+    // the next group's LDS reads issued before the current MFMAs.
+    const int mpairs = (mtiles + 1) >> 1;
+    const int ntiles = mpairs * ntn;
+    int r_local = 0, p0 = 0;
     if (T > 1) {
       r_local = cc & (P - 1);
       p0 = cc >> l;
     }
     for (int tile = wave; tile < ntiles; tile += nw) {
-      const int mt = tile % mtiles;
-      const int ntile = tile / mtiles;
-      if (T == 1) {
-        r_local = ntile * 8 + cc;
-        p0 = 0;
-      }
-      const int p1 = mt * 16 + row;
-      typename CT::Acc acc = {0, 0, 0, 0};
+      const int mp = tile % mpairs;
+      const int ntile = tile / mpairs;
+      if (T == 1) r_local = ntile * 8 + cc;
+      const int p1a = (2 * mp) * 16 + row;
+      const int p1b = p1a + 16;
+      typename CT::Acc acc0 = {0, 0, 0, 0};
+      typename CT::Acc acc1 = {0, 0, 0, 0};
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int Ub = lay.U[l][b];
-        const int base = pos_mod(p1 * T + ld.lo[b], L);
-        const S *ap = reinterpret_cast<const S *>(bands[b]) + 2 * (base + du) + ci;
+        const int G = lay.U[l][b] >> 3;
+        const S *band = reinterpret_cast<const S *>(bands[b]);
+        const S *apa = band + 2 * (pos_mod(p1a * T + ld.lo[b], L) + du) + ci;
+        const S *apb = band + 2 * (pos_mod(p1b * T + ld.lo[b], L) + du) + ci;
         const S *wp = reinterpret_cast<const S *>(W + (b ? pcc * V0 : 0) + r_local * (b ? V1 : V0)) +
                       2 * (du - p0 + T - 1) + (ci ^ co);
-#pragma unroll 4
-        for (int u = 0; u < Ub; u += 2) {
-          S a = ap[2 * u];
-          S w = wp[2 * u];
-          if (neg) w = -w;
-          acc = CT::mma(CT::cvt(a), CT::cvt(w), acc);
+        S a0[4], a1[4], w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          a0[q] = apa[4 * q];
+          a1[q] = apb[4 * q];
+          w[q] = wp[4 * q];
+        }
+        for (int g = 0; g < G; ++g) {
+          S na0[4], na1[4], nw_[4];
+          const int nx = (g + 1 < G) ? 16 * (g + 1) : 16 * g;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            na0[q] = apa[nx + 4 * q];
+            na1[q] = apb[nx + 4 * q];
+            nw_[q] = wp[nx + 4 * q];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const S wq = neg ? -w[q] : w[q];
+            acc0 = CT::mma(CT::cvt(a0[q]), CT::cvt(wq), acc0);
+            acc1 = CT::mma(CT::cvt(a1[q]), CT::cvt(wq), acc1);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            a0[q] = na0[q];
+            a1[q] = na1[q];
+            w[q] = nw_[q];
+          }
         }
       }
-      // Output element (row CT::row_of(lane, i), column col) of this tile.
+      // Output element (row CT::row_of(lane, i), column col) of each tile.
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int pp1 = mt * 16 + CT::row_of(lane, i);
-        const int p = pp1 * T + p0;
-        if (pp1 < Mrows && p < L) {
-          const long long s = (long long)P * p + r0 + r_local;
-          if constexpr (INT) {
-            outp[2 * s + co] = (long long)acc[i];
-          } else {
-            __builtin_nontemporal_store(acc[i], &outp[2 * s + co]);
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int pp1 = (2 * mp + h) * 16 + CT::row_of(lane, i);
+          const int p = pp1 * T + p0;
+          const auto v = h ? acc1[i] : acc0[i];
+          if (pp1 < Mrows && p < L) {
+            const long long s = (long long)P * p + r0 + r_local;
+            if constexpr (INT) {
+              outp[2 * s + co] = (long long)v;
+            } else {
+              __builtin_nontemporal_store(v, &outp[2 * s + co]);
+            }
           }
         }
       }
@@ -368,7 +398,7 @@ __device__ void correlate_level(const PlanDesc &plan, const FusedLayout &lay, in
 // correlation's lag windows never wrap; then the weight staging area.
 // ===========================================================================
 template <int F>
-__global__ __launch_bounds__(256) void fused_correlate(PlanDesc plan, FusedLayout lay,
+__global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, FusedLayout lay,
                                                        const void *__restrict__ rx_all, long long n,
                                                        long long rx_stride,
                                                        void *__restrict__ out_all,
@@ -524,7 +554,7 @@ static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, c
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(fused_correlate<F>, dim3((unsigned)count), dim3(256), shm, st, plan, lay, rx,
+  hipLaunchKernelGGL(fused_correlate<F>, dim3((unsigned)count), dim3(kFusedThreads), shm, st, plan, lay, rx,
                      n, rx_stride, out, out_stride);
   return hipGetLastError();
 }

@@ -8,7 +8,7 @@
 #include <vector>
 
 #include "../../include/sidwt.h"
-#include "sidwt_device.hpp"
+#include "sidwt_host.hpp"
 
 namespace sidwt {
 hipError_t launch_tree(int filter, const void *in, int in_lo, int in_len, int level, int k0,
@@ -37,119 +37,14 @@ struct sidwt_plan {
 
 namespace {
 
-constexpr int64_t kMaxRef = 8192;              // longest reference accepted (tree LDS)
-constexpr int64_t kMaxN = int64_t(1) << 30;     // longest circular length
-constexpr int kLdsElems = 160 * 1024 / 8;       // LDS per workgroup, 8-byte elements
-constexpr int kLdsTwoPerCu = 80 * 1024 / 8;     // budget that keeps two workgroups per CU
+using namespace sidwt::host;
 
 bool valid_filter(int f) { return f >= SIDWT_LEGALL53 && f <= SIDWT_LEGALL53_INT; }
-
-// x-side analysis reach: band b at output k depends on u[2k+i], i in [lo, hi]
-// (5/3: h~ spans -2..2, g~ spans 0..2; 9/7: -4..4 and -2..4; causal D4: -3..0).
-sidwt::TapRange tap_range(int filter, int band) {
-  switch (filter) {
-    case SIDWT_LEGALL53:
-    case SIDWT_LEGALL53_INT:
-      return band == 0 ? sidwt::TapRange{-2, 2} : sidwt::TapRange{0, 2};
-    case SIDWT_CDF97:
-      return band == 0 ? sidwt::TapRange{-4, 4} : sidwt::TapRange{-2, 4};
-    default:
-      return sidwt::TapRange{-3, 0};
-  }
-}
-
-int ceil_div_i(int a, int b) { return -sidwt::floor_div(-a, b); }
-
-int64_t transform_length(int64_t n, int J) {
-  int64_t q = int64_t(1) << J;
-  return q * ((n + q - 1) / q);
-}
 
 int map_err(hipError_t e) {
   if (e == hipSuccess) return SIDWT_OK;
   if (e == hipErrorOutOfMemory) return SIDWT_E_NOMEM;
   return SIDWT_E_DEVICE;
-}
-
-// Integer plans hold linear-support phases; they equal the circular
-// integer lifting at length N only if no level's input support (plus the
-// one-sample delay and the +-2 reach of the 5/3 steps) wraps around.
-bool int_support_fits(const sidwt_plan *p, int64_t N) {
-  int64_t in_len = p->m;
-  for (int l = 1; l <= p->J; ++l) {
-    if (in_len + 5 > (N >> (l - 1))) return false;
-    in_len = p->desc.lv[l].len[0];
-  }
-  return true;
-}
-
-// LDS layout of the fused kernel (see FusedLayout).
-int make_layout(const sidwt_plan *p, int64_t N64, FusedLayout *lay) {
-  std::memset(lay, 0, sizeof(*lay));
-  if (N64 > kLdsElems) return SIDWT_E_UNSUPPORTED;
-  const int N = (int)N64, J = p->J;
-  lay->N = N;
-  lay->J = J;
-  for (int l = 1; l <= J; ++l) {
-    const int P = 1 << l;
-    const int T = P < 8 ? 8 / P : 1;
-    lay->T[l] = T;
-    int halo = 0;
-    for (int b = 0; b < 2; ++b) {
-      // lag offsets u in [0, U): K of the per-scale GEMM, in groups of 8
-      // (four 16x16x4 MFMAs of two offsets each)
-      int U = p->desc.lv[l].len[b] + T - 1;
-      U = (U + 7) & ~7;
-      lay->U[l][b] = U;
-      lay->V[l][b] = (U + T) | 1;  // odd row length spreads phases over LDS banks
-      halo = std::max(halo, U);
-    }
-    lay->halo[l] = halo;
-  }
-  // Odd levels at 0, even levels after the largest odd-level c band.
-  int even_off = 0;
-  for (int l = 1; l <= J; l += 2) even_off = std::max(even_off, (N >> l) + lay->halo[l]);
-  int total = 0;
-  for (int l = 1; l <= J; ++l) {
-    const int L = N >> l;
-    const int sz = 2 * (L + lay->halo[l]);
-    if (l & 1) {
-      lay->region_off[l] = 0;
-      if (l >= 3 && sz > even_off) return SIDWT_E_UNSUPPORTED;
-    } else {
-      lay->region_off[l] = even_off;
-    }
-    total = std::max(total, lay->region_off[l] + sz);
-  }
-  total = (total + 1) & ~1;
-  lay->w_off = total;
-  // Weight staging: all phases when P < 8 (one Toeplitz tile spans them),
-  // otherwise chunks of 8k phases within the budget.
-  int budget = std::max(0, kLdsTwoPerCu - total);
-  int need_min = 0;
-  for (int l = 1; l <= J; ++l) {
-    const int P = 1 << l;
-    const int row = lay->V[l][0] + lay->V[l][1];
-    need_min = std::max(need_min, (P < 8 ? P : 8) * row);
-  }
-  if (need_min > budget) budget = kLdsElems - total;
-  if (need_min > budget) return SIDWT_E_UNSUPPORTED;
-  int cap = 0;
-  for (int l = 1; l <= J; ++l) {
-    const int P = 1 << l;
-    const int row = lay->V[l][0] + lay->V[l][1];
-    int pc;
-    if (P < 8) {
-      pc = P;
-    } else {
-      pc = std::min(P, (budget / row) / 8 * 8);
-      pc = std::max(pc, 8);
-    }
-    lay->pc[l] = pc;
-    cap = std::max(cap, pc * row);
-  }
-  lay->total = total + cap;
-  return lay->total <= kLdsElems ? SIDWT_OK : SIDWT_E_UNSUPPORTED;
 }
 
 int check_pulse(const sidwt_plan *p, int64_t n, int64_t *N_out) {
@@ -158,7 +53,7 @@ int check_pulse(const sidwt_plan *p, int64_t n, int64_t *N_out) {
   if (N > kMaxN) return SIDWT_E_SIZE;
   if ((N >> p->J) < 2) return SIDWT_E_INVAL;
   if (p->m > N) return SIDWT_E_SIZE;
-  if (p->filter == SIDWT_LEGALL53_INT && !int_support_fits(p, N)) return SIDWT_E_SIZE;
+  if (p->filter == SIDWT_LEGALL53_INT && !int_support_fits(p->desc, N)) return SIDWT_E_SIZE;
   *N_out = N;
   return SIDWT_OK;
 }
@@ -201,23 +96,7 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
   d.filter = filter;
   d.J = J;
   d.m = (int)m;
-  // Stored supports, level by level (input support includes the one-sample
-  // delay of the odd branch).
-  long long off = 0;
-  int in_lo = 0, in_len = (int)m;
-  for (int l = 1; l <= J; ++l) {
-    for (int b = 0; b < 2; ++b) {
-      sidwt::TapRange tr = tap_range(filter, b);
-      int k_first = ceil_div_i(in_lo - tr.hi, 2);
-      int k_last = sidwt::floor_div(in_lo + in_len - tr.lo, 2);
-      d.lv[l].lo[b] = k_first;
-      d.lv[l].len[b] = k_last - k_first + 1;
-      d.lv[l].off[b] = off;
-      off += (long long)d.lv[l].len[b] << l;
-    }
-    in_lo = d.lv[l].lo[0];
-    in_len = d.lv[l].len[0];
-  }
+  const long long off = plan_windows(filter, J, (int)m, &d);
   const size_t elem = 8;  // float2 or int2
   p->coef_bytes = (size_t)off * elem;
   hipError_t e = hipMalloc(&p->coef, p->coef_bytes);
@@ -237,8 +116,8 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
   void *ref_dev = nullptr;
   e = hipMalloc(&ref_dev, 8 * (size_t)m);
   if (e == hipSuccess) e = hipMemcpy(ref_dev, host.data(), 8 * (size_t)m, hipMemcpyHostToDevice);
-  in_lo = 0;
-  in_len = (int)m;
+  int in_lo = 0;
+  int in_len = (int)m;
   const char *base = static_cast<const char *>(p->coef);
   for (int l = 1; l <= J && e == hipSuccess; ++l) {
     const sidwt::LevelDesc &lv = d.lv[l];
@@ -291,8 +170,7 @@ int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t
   if (rc) return rc;
   if (rx_stride < n || out_stride < (int64_t)p->J * N) return SIDWT_E_INVAL;
   FusedLayout lay;
-  rc = make_layout(p, N, &lay);
-  if (rc) return rc;
+  if (make_layout(p->desc, N, &lay) != 0) return SIDWT_E_UNSUPPORTED;
   return map_err(sidwt::launch_fused(p->desc, lay, rx, n, count, rx_stride, out, out_stride,
                                      p->stream));
 }
@@ -309,7 +187,7 @@ int sidwt_lift_many(int filter, int J, const void *rx, int64_t n, int64_t count,
     return SIDWT_E_INVAL;
   const int64_t N = transform_length(n, J);
   if ((N >> J) < 2) return SIDWT_E_INVAL;
-  if (N / 2 + N / 4 + 1 > kLdsElems) return SIDWT_E_UNSUPPORTED;
+  if (2 * (N / 2 + N / 4 + 1) > kLdsWords) return SIDWT_E_UNSUPPORTED;
   return map_err(sidwt::launch_lift(filter, J, (int)N, rx, n, count, rx_stride, pyr,
                                     static_cast<hipStream_t>(hip_stream)));
 }

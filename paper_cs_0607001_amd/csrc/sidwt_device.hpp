@@ -44,18 +44,34 @@ struct PlanDesc {
 };
 
 // LDS layout of the fused kernel for one transform length N, computed on the
-// host.  Offsets and sizes count 8-byte complex elements.
+// host.  All offsets and sizes count 4-byte words.
+//
+// Level l (1..J) holds its approximation band c_l (b = 0) and detail band
+// d_l (b = 1) of length L = N/2^l, each followed by a circular halo copy so
+// the correlation's lag windows never wrap: element q < ext = L + halo is
+// c[q mod L].  A band is two planes (re, im); a plane is T polyphase
+// sub-sequences (element q lives in sub-sequence q mod T at index q / T,
+// sub-sequences Ls words apart), so the rows of an MFMA tile, which step
+// through the lag axis T elements apart, read consecutive words.
 struct FusedLayout {
   int N;
   int J;
-  int region_off[kMaxLevels + 1];  // level-l bands: c at region_off, d after c
-  int halo[kMaxLevels + 1];        // circular copy appended to each band
-  int T[kMaxLevels + 1];           // Toeplitz blocking of the lag axis
-  int U[kMaxLevels + 1][2];        // lag-window length per band (even)
-  int V[kMaxLevels + 1][2];        // staged weight row length per band
-  int pc[kMaxLevels + 1];          // phases staged per chunk
-  int w_off;                       // weight staging area
-  int total;                       // total LDS elements
+  int region_off[kMaxLevels + 1];    // start of level l (band 0, re plane)
+  int band_size[kMaxLevels + 1];     // words per band (both planes)
+  int plane_stride[kMaxLevels + 1];  // re plane -> im plane
+  int Ls[kMaxLevels + 1];            // sub-sequence stride
+  int ext[kMaxLevels + 1];           // valid elements per band incl. halo
+  int T[kMaxLevels + 1];             // Toeplitz blocking of the lag axis
+  int logT[kMaxLevels + 1];
+  int lo[kMaxLevels + 1][2];         // lag-window start, aligned down to T
+  int F[kMaxLevels + 1][2];          // front zero pad of the staged weights
+  int U[kMaxLevels + 1][2];          // lag-window length (GEMM K per re/im)
+  int V[kMaxLevels + 1][2];          // staged weight row length (complex)
+  int pc[kMaxLevels + 1];            // phases staged per chunk
+  int w_at[kMaxLevels + 1];          // weight staging area of level l (outside
+                                     // the level's bands; 16-byte aligned)
+  int w_off;                         // end of the band regions
+  int total;                         // words of LDS
 };
 
 // ---------------------------------------------------------------------------
@@ -187,8 +203,14 @@ __host__ __device__ inline int pos_mod(int a, int b) {
   return r < 0 ? r + b : r;
 }
 
+// Word offset of element q inside one plane of a band (see FusedLayout).
+__device__ __forceinline__ int poly_off(int q, int logT, int Ls) {
+  return (q & ((1 << logT) - 1)) * Ls + (q >> logT);
+}
+
 // MFMA operand/accumulator vector types.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 }  // namespace sidwt

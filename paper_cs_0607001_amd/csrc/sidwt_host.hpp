@@ -1,0 +1,220 @@
+// Host-side planning of libsidwt: stored phase supports of a plan and the
+// LDS layout of the fused kernel, plus a bounds audit of that layout.
+// Pure host C++ (no device calls), shared by the C ABI implementation and
+// the CPU-side layout checker.
+#pragma once
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+
+#include "sidwt_device.hpp"
+
+namespace sidwt {
+namespace host {
+
+constexpr int64_t kMaxRef = 8192;              // longest reference (tree kernel LDS)
+constexpr int64_t kMaxN = int64_t(1) << 30;     // longest circular length
+constexpr int kLdsWords = 160 * 1024 / 4;       // LDS per workgroup (gfx950)
+constexpr int kLdsWordsTwoPerCu = 80 * 1024 / 4; // two workgroups per CU
+
+inline bool is_int_filter(int f) { return f == F_LEGALL53_INT; }
+
+// x-side analysis reach: band b at output k depends on u[2k+i], i in [lo, hi]
+// (5/3: h~ spans -2..2, g~ spans 0..2; 9/7: -4..4 and -2..4; causal D4:
+// -3..0).  The integer 5/3 has the reach of the float 5/3.
+inline TapRange tap_range(int filter, int band) {
+  switch (filter) {
+    case F_LEGALL53:
+    case F_LEGALL53_INT:
+      return band == 0 ? TapRange{-2, 2} : TapRange{0, 2};
+    case F_CDF97:
+      return band == 0 ? TapRange{-4, 4} : TapRange{-2, 4};
+    default:
+      return TapRange{-3, 0};
+  }
+}
+
+inline int ceil_div_i(int a, int b) { return -floor_div(-a, b); }
+
+inline int64_t transform_length(int64_t n, int J) {
+  int64_t q = int64_t(1) << J;
+  return q * ((n + q - 1) / q);
+}
+
+// Stored linear supports of the phase pyramid, level by level.  The input
+// support of level l includes the one-sample delay of the odd branch
+// (shift-circulant tree).  Returns the number of complex elements.
+inline long long plan_windows(int filter, int J, int m, PlanDesc *d) {
+  long long off = 0;
+  int in_lo = 0, in_len = m;
+  for (int l = 1; l <= J; ++l) {
+    for (int b = 0; b < 2; ++b) {
+      TapRange tr = tap_range(filter, b);
+      int k_first = ceil_div_i(in_lo - tr.hi, 2);
+      int k_last = floor_div(in_lo + in_len - tr.lo, 2);
+      d->lv[l].lo[b] = k_first;
+      d->lv[l].len[b] = k_last - k_first + 1;
+      d->lv[l].off[b] = off;
+      off += (long long)d->lv[l].len[b] << l;
+    }
+    in_lo = d->lv[l].lo[0];
+    in_len = d->lv[l].len[0];
+  }
+  return off;
+}
+
+// Integer plans hold linear-support phases; they equal the circular
+// integer lifting at length N only if no level's input support (plus the
+// one-sample delay and the +-2 reach of the 5/3 steps) wraps around.
+inline bool int_support_fits(const PlanDesc &d, int64_t N) {
+  int64_t in_len = d.m;
+  for (int l = 1; l <= d.J; ++l) {
+    if (in_len + 5 > (N >> (l - 1))) return false;
+    in_len = d.lv[l].len[0];
+  }
+  return true;
+}
+
+// Output columns per MFMA tile, in complex values: 16 for the FP32 32x32x2
+// tiles, 8 for the FP64 16x16x4 tiles of the integer path.
+inline int tile_cols(bool is_int) { return is_int ? 8 : 16; }
+
+// LDS layout of the fused kernel (see FusedLayout); sizes in 4-byte words.
+// Returns 0, or -5 (unsupported) when the pulse does not fit one workgroup.
+inline int make_layout(const PlanDesc &d, int64_t N64, FusedLayout *lay) {
+  std::memset(lay, 0, sizeof(*lay));
+  if (N64 > kLdsWords) return -5;
+  const bool is_int = is_int_filter(d.filter);
+  const int N = (int)N64, J = d.J;
+  const int ncol = tile_cols(is_int);
+  lay->N = N;
+  lay->J = J;
+  for (int l = 1; l <= J; ++l) {
+    const int P = 1 << l, L = N >> l;
+    int T = P < ncol ? ncol / P : 1;
+    while (L % T) T >>= 1;  // lag blocks must tile L exactly
+    int logT = 0;
+    while ((1 << logT) < T) ++logT;
+    lay->T[l] = T;
+    lay->logT[l] = logT;
+    int halo = 0;
+    for (int b = 0; b < 2; ++b) {
+      const int lo = d.lv[l].lo[b], len = d.lv[l].len[b];
+      const int delta = pos_mod(lo, T);  // window start aligned down to T
+      lay->lo[l][b] = lo - delta;
+      lay->F[l][b] = T - 1 + delta;
+      int U = len + delta + T - 1;
+      U = is_int ? (U + 1) & ~1 : (U + 3) & ~3;  // FP32: groups of 4 offsets
+      lay->U[l][b] = U;
+      // staged row >= U + T - 1 complex, an odd multiple of T (the phases of
+      // one tile then fall on disjoint LDS banks)
+      int k = (U + T - 1 + T - 1) / T;
+      if ((k & 1) == 0) ++k;
+      lay->V[l][b] = k * T;
+      // rows start at multiples of T below L and read U offsets
+      halo = std::max(halo, U - T + 1);
+    }
+    lay->ext[l] = L + halo;
+    const int lsub = (lay->ext[l] + T - 1) / T;
+    // integer tiles read two neighbouring sub-sequences at once: Ls = 16 mod
+    // 64 puts them on different LDS banks
+    lay->Ls[l] = is_int ? lsub + ((16 - lsub % 64) + 64) % 64 : lsub;
+    lay->plane_stride[l] = ((T * lay->Ls[l] + 63) / 64) * 64 + 32;  // = 32 mod 64
+    lay->band_size[l] = 2 * lay->plane_stride[l];
+  }
+  // Level l is lifted from c_{l-1} while it is written, so its region must
+  // miss that band: at offset 0 when it fits below, else right after it.
+  int total = 0;
+  for (int l = 1; l <= J; ++l) {
+    if (l == 1) {
+      lay->region_off[l] = 0;
+    } else {
+      const int cstart = lay->region_off[l - 1];
+      lay->region_off[l] = (2 * lay->band_size[l] <= cstart) ? 0 : cstart + lay->band_size[l - 1];
+    }
+    total = std::max(total, lay->region_off[l] + 2 * lay->band_size[l]);
+  }
+  total = (total + 3) & ~3;
+  lay->w_off = total;
+  // Weight staging (complex = 2 words): all phases when P < ncol (one tile's
+  // columns span them), otherwise chunks of k*ncol phases within budget.
+  int budget = std::max(0, kLdsWordsTwoPerCu - total);
+  int need_min = 0;
+  for (int l = 1; l <= J; ++l) {
+    const int P = 1 << l;
+    const int row = 2 * (lay->V[l][0] + lay->V[l][1]);
+    need_min = std::max(need_min, (P < ncol ? P : ncol) * row);
+  }
+  if (need_min > budget) budget = kLdsWords - total;
+  if (need_min > budget) return -5;
+  // While plane l-1 is correlated only level l's bands are live, so its
+  // staged weights may reuse any other part of the band area; only what
+  // does not fit there goes after it.
+  int end = total;
+  for (int l = 1; l <= J; ++l) {
+    const int P = 1 << l;
+    const int row = 2 * (lay->V[l][0] + lay->V[l][1]);
+    int pc = P;
+    if (P >= ncol) pc = std::max(ncol, std::min(P, (budget / row) / ncol * ncol));
+    lay->pc[l] = pc;
+    const int need = pc * row;
+    const int r0 = lay->region_off[l], r1 = r0 + 2 * lay->band_size[l];
+    const int after = (r1 + 3) & ~3;
+    if (need <= r0) {
+      lay->w_at[l] = 0;
+    } else if (after + need <= total) {
+      lay->w_at[l] = after;
+    } else {
+      lay->w_at[l] = total;
+      end = std::max(end, total + need);
+    }
+  }
+  lay->total = end;
+  return lay->total <= kLdsWords ? 0 : -5;
+}
+
+// Audit of a layout against the index ranges the fused kernel touches.
+// Returns 0 if every access is inside its region and regions that are live
+// together are disjoint; otherwise a positive code naming the failed check.
+inline int layout_violation(const PlanDesc &d, const FusedLayout &lay) {
+  const bool is_int = is_int_filter(d.filter);
+  const int ncol = tile_cols(is_int);
+  const int N = lay.N;
+  for (int l = 1; l <= lay.J; ++l) {
+    const int L = N >> l, T = lay.T[l], Ls = lay.Ls[l], P = 1 << l;
+    if (T < 1 || (1 << lay.logT[l]) != T || L % T) return 1;
+    // element q < ext: plane offset (q%T)*Ls + q/T must stay below T*Ls
+    if ((lay.ext[l] + T - 1) / T > Ls) return 2;
+    if (T * Ls + 32 > lay.plane_stride[l]) return 3;
+    if (lay.band_size[l] != 2 * lay.plane_stride[l]) return 4;
+    if (lay.region_off[l] + 2 * lay.band_size[l] > lay.w_off) return 5;
+    if (l > 1) {  // level l must miss c_{l-1}
+      const int a0 = lay.region_off[l], a1 = a0 + 2 * lay.band_size[l];
+      const int b0 = lay.region_off[l - 1], b1 = b0 + lay.band_size[l - 1];
+      if (a0 < b1 && b0 < a1) return 6;
+    }
+    for (int b = 0; b < 2; ++b) {
+      // correlation rows start at q in [0, L-T] (multiples of T), offsets
+      // u < U; the next level reads q < L
+      if ((L - T) + lay.U[l][b] - 1 >= lay.ext[l]) return 7;
+      // weight lookup v = u (+du) - p0 + T - 1 in [0, U + T - 2] < V
+      if (lay.U[l][b] + T - 2 >= lay.V[l][b]) return 8;
+      if (lay.F[l][b] < T - 1 || lay.F[l][b] > 2 * T - 2) return 9;
+      // every tap t < len reachable for every p0 < T: u = t + p0 + F - (T-1) < U
+      if (lay.U[l][b] < d.lv[l].len[b] + lay.F[l][b]) return 10;
+      if (is_int ? (lay.U[l][b] & 1) : (lay.U[l][b] & 3)) return 11;
+    }
+    const int row = 2 * (lay.V[l][0] + lay.V[l][1]);
+    const int pc = lay.pc[l];
+    if (P < ncol ? pc != P : (pc % ncol || pc < ncol)) return 12;
+    const int w0 = lay.w_at[l], w1 = w0 + std::min(pc, P) * row;
+    if ((w0 & 3) || w0 < 0 || w1 > lay.total) return 13;
+    const int r0 = lay.region_off[l], r1 = r0 + 2 * lay.band_size[l];
+    if (w0 < r1 && r0 < w1) return 15;
+  }
+  if (lay.total > kLdsWords || (lay.w_off & 3)) return 14;
+  return 0;
+}
+
+}  // namespace host
+}  // namespace sidwt

@@ -10,6 +10,8 @@
 // Sec. II; dual analysis lifting Sec. III; per-scale correlation eq. (15),
 // (20), (20a); the Fig. 5 even/odd tree; Fig. 7 lifting of the received
 // signal.
+#include <type_traits>
+
 #include "sidwt_device.hpp"
 
 namespace sidwt {
@@ -217,147 +219,129 @@ template <> struct RxOf<F_LEGALL53_INT> { using T = short2; using Out = long lon
 
 // ===========================================================================
 // Per-scale correlation of one level against the stored phases (eq. (20),
-// (20a)): plane j = l-1, P = 2^l phases, L = N/2^l lags per phase.
+// (20a)): plane j = l-1, P = 2^l phases, L = N/2^l lags per phase,
 //
-//   R[P p + r] = sum_t conj(w_r[t]) c[(p + t) mod L] + same for (w~, d)
+//   R[P p + r] = sum_t conj(a_r[t]) c[(p + t) mod L] + conj(b_r[t]) d[(p + t) mod L]
 //
-// as a real GEMM on MFMA 16x16x4: rows = lag blocks p1 (p = p1*T + p0),
-// columns = (p0, r, re/im) with T*P = 8 for P < 8 (Toeplitz blocking of
-// the lag axis) or 8 phases per tile for P >= 8, K = (lag offset u, re/im).
-// The complex product conj(w) c is the 2x2 real embedding
-// [re; im] = [w.re w.im; -w.im w.re] [c.re; c.im].
+// computed as a real GEMM.  Rows: lag blocks p1 (p = p1*T + p0).  Columns:
+// (p0, r, re/im out) -- Toeplitz blocking of the lag axis, T*P columns of
+// complex outputs per tile when P is small, plain phases when T = 1.
+// K: lag offset u (data element q = p1*T + lo + u) times re/im in.  The
+// complex product conj(w) c is the 2x2 real embedding
+//   [out.re; out.im] = [w.re  w.im; -w.im  w.re] [c.re; c.im].
+// FP32 path: v_mfma_f32_32x32x2_f32 (one lag offset per MFMA, T*P = 16).
+// Integer path: v_mfma_f64_16x16x4_f64 on int32 data and phases, exact
+// because every product and partial sum is an integer below 2^53.
 // ===========================================================================
-template <bool INT> struct CorrTypes;
-template <> struct CorrTypes<false> {
-  using V = float2;
-  using S = float;
-  using A = float;
-  using Acc = f32x4;
-  __device__ static Acc mma(A a, A b, Acc c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-  __device__ static A cvt(float v) { return v; }
-  // v_mfma_f32_16x16x4_f32: accumulator register i of lane l holds row
-  // 4*(l/16) + i, column l%16.
-  __device__ static int row_of(int lane, int i) { return 4 * (lane >> 4) + i; }
-};
-template <> struct CorrTypes<true> {
-  using V = int2;
-  using S = int;
-  using A = double;
-  using Acc = f64x4;
-  __device__ static Acc mma(A a, A b, Acc c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-  __device__ static A cvt(int v) { return (double)v; }
-  // v_mfma_f64_16x16x4_f64: accumulator register i of lane l holds row
-  // 4*i + l/16, column l%16.
-  __device__ static int row_of(int lane, int i) { return 4 * i + (lane >> 4); }
-};
 
-template <bool INT, class OutT>
-__device__ void correlate_level(const PlanDesc &plan, const FusedLayout &lay, int l,
-                                typename CorrTypes<INT>::V *sm, OutT *__restrict__ outp) {
-  using CT = CorrTypes<INT>;
-  using V = typename CT::V;
-  using S = typename CT::S;
-  const int N = lay.N;
-  const int P = 1 << l;
-  const int L = N >> l;
-  const int T = lay.T[l];
-  const int Mrows = (L + T - 1) / T;
-  const int mtiles = (Mrows + 15) / 16;
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const V *bands[2];
-  bands[0] = sm + lay.region_off[l];
-  bands[1] = bands[0] + L + lay.halo[l];
-  V *W = sm + lay.w_off;
+// Stage phases r0..r0+pcc-1 of both bands as complex rows W[b][rr][v] with
+// W[v] = w[v - F] (zero outside the stored support).
+template <class V>
+__device__ __forceinline__ void stage_weights(const PlanDesc &plan, const FusedLayout &lay, int l,
+                                              int r0, int pcc, V *W) {
   const V *coef = reinterpret_cast<const V *>(plan.coef);
   const LevelDesc &ld = plan.lv[l];
-  const int pc = lay.pc[l];
   const int V0 = lay.V[l][0], V1 = lay.V[l][1];
+  const int tot0 = pcc * V0, tot = tot0 + pcc * V1;
+  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+    const int b = i >= tot0;
+    const int j = b ? i - tot0 : i;
+    const int Vb = b ? V1 : V0;
+    const int rr = j / Vb;
+    const int t = j - rr * Vb - lay.F[l][b];
+    V w;
+    w.x = 0;
+    w.y = 0;
+    if (t >= 0 && t < ld.len[b]) w = coef[ld.off[b] + (long long)(r0 + rr) * ld.len[b] + t];
+    W[i] = w;
+  }
+}
 
-  // Lane roles (MFMA 16x16x4: A[row][k], B[k][col], lane = 16*k + row|col).
-  const int row = lane & 15;
-  const int kq = lane >> 4;
-  const int du = kq >> 1;
-  const int ci = kq & 1;
-  const int col = lane & 15;
-  const int co = col & 1;
-  const int cc = col >> 1;
+__device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// FP32 correlation of level l (32x32x2 tiles, two row tiles per wave that
+// share the weight operand).
+__device__ void correlate_level_f32(const PlanDesc &plan, const FusedLayout &lay, int l,
+                                    float *smf, float *__restrict__ outp) {
+  const int N = lay.N, P = 1 << l, L = N >> l;
+  const int T = lay.T[l], logT = lay.logT[l], Ls = lay.Ls[l];
+  const int Mrows = L >> logT;
+  const int mtiles = (Mrows + 31) >> 5;
+  const int mpairs = (mtiles + 1) >> 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  float2 *W = reinterpret_cast<float2 *>(smf + lay.w_at[l]);
+  const int V0 = lay.V[l][0], V1 = lay.V[l][1];
+  const int row = lane & 31;
+  const int ci = lane >> 5;
+  const int co = lane & 1;
+  const int cc = (lane & 31) >> 1;
   const bool neg = (ci == 0) && (co == 1);
-
-  for (int r0 = 0; r0 < P; r0 += pc) {
-    const int pcc = min(pc, P - r0);
-    // Stage weights of phases r0..r0+pcc-1, both bands, zero padded so that
-    // v = u + du - p0 + T - 1 indexes w[v - (T-1)].
-    {
-      const int tot0 = pcc * V0, tot = tot0 + pcc * V1;
-      for (int i = tid; i < tot; i += nt) {
-        const int b = i >= tot0;
-        const int j = b ? i - tot0 : i;
-        const int Vb = b ? V1 : V0;
-        const int rr = j / Vb;
-        const int v = j - rr * Vb;
-        const int t = v - (T - 1);
-        V w;
-        w.x = 0; w.y = 0;
-        if (t >= 0 && t < ld.len[b]) w = coef[ld.off[b] + (long long)(r0 + rr) * ld.len[b] + t];
-        W[i] = w;
-      }
-    }
+  for (int r0 = 0; r0 < P; r0 += lay.pc[l]) {
+    const int pcc = min(lay.pc[l], P - r0);
+    stage_weights(plan, lay, l, r0, pcc, W);
     __syncthreads();
-    const int ntn = (T > 1) ? 1 : (pcc >> 3);
-    // Each wave computes two vertically adjacent 16x16 tiles that share the
-    // weight (B) operand; K runs in groups of 4 MFMAs (8 lag offsets) with
-    // the next group's LDS reads issued before the current MFMAs.
-    const int mpairs = (mtiles + 1) >> 1;
+    // P < 16: one column tile holds all (p0, r) pairs, p0 < T; otherwise
+    // T = 1 and each column tile holds 16 phases.
+    const int ntn = (P < 16) ? 1 : (pcc >> 4);
     const int ntiles = mpairs * ntn;
-    int r_local = 0, p0 = 0;
-    if (T > 1) {
-      r_local = cc & (P - 1);
-      p0 = cc >> l;
-    }
     for (int tile = wave; tile < ntiles; tile += nw) {
       const int mp = tile % mpairs;
       const int ntile = tile / mpairs;
-      if (T == 1) r_local = ntile * 8 + cc;
-      const int p1a = (2 * mp) * 16 + row;
-      const int p1b = p1a + 16;
-      typename CT::Acc acc0 = {0, 0, 0, 0};
-      typename CT::Acc acc1 = {0, 0, 0, 0};
+      int r, p0;
+      bool colok;
+      if (P < 16) {
+        r = cc & (P - 1);
+        p0 = cc >> l;
+        colok = p0 < T;
+        if (!colok) p0 = 0;
+      } else {
+        r = ntile * 16 + cc;
+        p0 = 0;
+        colok = true;
+      }
+      const int p1a = mp * 64 + row;
+      const int p1b = p1a + 32;
+      f32x16 acc0, acc1;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        acc0[i] = 0.f;
+        acc1[i] = 0.f;
+      }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int G = lay.U[l][b] >> 3;
-        const S *band = reinterpret_cast<const S *>(bands[b]);
-        const S *apa = band + 2 * (pos_mod(p1a * T + ld.lo[b], L) + du) + ci;
-        const S *apb = band + 2 * (pos_mod(p1b * T + ld.lo[b], L) + du) + ci;
-        const S *wp = reinterpret_cast<const S *>(W + (b ? pcc * V0 : 0) + r_local * (b ? V1 : V0)) +
-                      2 * (du - p0 + T - 1) + (ci ^ co);
-        S a0[4], a1[4], w[4];
+        const int G = lay.U[l][b] >> 2;
+        const float *pl = smf + lay.region_off[l] + b * lay.band_size[l] + ci * lay.plane_stride[l];
+        const float *pa = pl + (pos_mod(p1a * T + lay.lo[l][b], L) >> logT);
+        const float *pb = pl + (pos_mod(p1b * T + lay.lo[l][b], L) >> logT);
+        const float *wp = reinterpret_cast<const float *>(W + (b ? pcc * V0 : 0) + r * (b ? V1 : V0)) +
+                          2 * (T - 1 - p0) + (ci ^ co);
+        float a0[4], a1[4], w[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          a0[q] = apa[4 * q];
-          a1[q] = apb[4 * q];
-          w[q] = wp[4 * q];
+          const int off = (q & (T - 1)) * Ls + (q >> logT);
+          a0[q] = pa[off];
+          a1[q] = pb[off];
+          w[q] = wp[2 * q];
         }
         for (int g = 0; g < G; ++g) {
-          S na0[4], na1[4], nw_[4];
-          const int nx = (g + 1 < G) ? 16 * (g + 1) : 16 * g;
+          float na0[4], na1[4], nw_[4];
+          const int un = (g + 1 < G) ? 4 * (g + 1) : 4 * g;
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            na0[q] = apa[nx + 4 * q];
-            na1[q] = apb[nx + 4 * q];
-            nw_[q] = wp[nx + 4 * q];
+            const int u = un + q;
+            const int off = (u & (T - 1)) * Ls + (u >> logT);
+            na0[q] = pa[off];
+            na1[q] = pb[off];
+            nw_[q] = wp[2 * u];
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const S wq = neg ? -w[q] : w[q];
-            acc0 = CT::mma(CT::cvt(a0[q]), CT::cvt(wq), acc0);
-            acc1 = CT::mma(CT::cvt(a1[q]), CT::cvt(wq), acc1);
+            float wq = neg ? -w[q] : w[q];
+            wq = colok ? wq : 0.f;
+            acc0 = mfma32(a0[q], wq, acc0);
+            acc1 = mfma32(a1[q], wq, acc1);
           }
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
@@ -367,20 +351,16 @@ __device__ void correlate_level(const PlanDesc &plan, const FusedLayout &lay, in
           }
         }
       }
-      // Output element (row CT::row_of(lane, i), column col) of each tile.
+      if (colok) {
+        // register i of lane l: row 8*(i/4) + 4*(l/32) + i%4, column l%32
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int pp1 = (2 * mp + h) * 16 + CT::row_of(lane, i);
-          const int p = pp1 * T + p0;
-          const auto v = h ? acc1[i] : acc0[i];
-          if (pp1 < Mrows && p < L) {
-            const long long s = (long long)P * p + r0 + r_local;
-            if constexpr (INT) {
-              outp[2 * s + co] = (long long)v;
-            } else {
-              __builtin_nontemporal_store(v, &outp[2 * s + co]);
+          for (int i = 0; i < 16; ++i) {
+            const int pp1 = mp * 64 + h * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+            if (pp1 < Mrows) {
+              const long long s = (long long)P * (pp1 * T + p0) + r0 + r;
+              __builtin_nontemporal_store(h ? acc1[i] : acc0[i], &outp[2 * s + co]);
             }
           }
         }
@@ -390,68 +370,167 @@ __device__ void correlate_level(const PlanDesc &plan, const FusedLayout &lay, in
   }
 }
 
+// Integer correlation of level l (FP64 16x16x4 tiles, two row tiles per
+// wave sharing the weight operand).
+__device__ void correlate_level_int(const PlanDesc &plan, const FusedLayout &lay, int l,
+                                    int *smi, long long *__restrict__ outp) {
+  const int N = lay.N, P = 1 << l, L = N >> l;
+  const int T = lay.T[l], logT = lay.logT[l], Ls = lay.Ls[l];
+  const int Mrows = L >> logT;
+  const int mtiles = (Mrows + 15) >> 4;
+  const int mpairs = (mtiles + 1) >> 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int2 *W = reinterpret_cast<int2 *>(smi + lay.w_at[l]);
+  const int V0 = lay.V[l][0], V1 = lay.V[l][1];
+  const int row = lane & 15;
+  const int kq = lane >> 4;
+  const int du = kq >> 1;
+  const int ci = kq & 1;
+  const int co = lane & 1;
+  const int cc = (lane & 15) >> 1;
+  const bool neg = (ci == 0) && (co == 1);
+  for (int r0 = 0; r0 < P; r0 += lay.pc[l]) {
+    const int pcc = min(lay.pc[l], P - r0);
+    stage_weights(plan, lay, l, r0, pcc, W);
+    __syncthreads();
+    const int ntn = (P < 8) ? 1 : (pcc >> 3);
+    const int ntiles = mpairs * ntn;
+    for (int tile = wave; tile < ntiles; tile += nw) {
+      const int mp = tile % mpairs;
+      const int ntile = tile / mpairs;
+      int r, p0;
+      bool colok;
+      if (P < 8) {
+        r = cc & (P - 1);
+        p0 = cc >> l;
+        colok = p0 < T;
+        if (!colok) p0 = 0;
+      } else {
+        r = ntile * 8 + cc;
+        p0 = 0;
+        colok = true;
+      }
+      const int p1a = mp * 32 + row;
+      const int p1b = p1a + 16;
+      f64x4 acc0 = {0, 0, 0, 0};
+      f64x4 acc1 = {0, 0, 0, 0};
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int steps = lay.U[l][b] >> 1;
+        const int *pl = smi + lay.region_off[l] + b * lay.band_size[l] + ci * lay.plane_stride[l];
+        const int qa = pos_mod(p1a * T + lay.lo[l][b], L);
+        const int qb = pos_mod(p1b * T + lay.lo[l][b], L);
+        const int *wp = reinterpret_cast<const int *>(W + (b ? pcc * V0 : 0) + r * (b ? V1 : V0)) +
+                        2 * (du - p0 + T - 1) + (ci ^ co);
+        for (int st = 0; st < steps; ++st) {
+          const int u = 2 * st + du;
+          const int a0 = pl[poly_off(qa + u, logT, Ls)];
+          const int a1 = pl[poly_off(qb + u, logT, Ls)];
+          int wv = wp[4 * st];
+          wv = neg ? -wv : wv;
+          wv = colok ? wv : 0;
+          const double wd = (double)wv;
+          acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a0, wd, acc0, 0, 0, 0);
+          acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a1, wd, acc1, 0, 0, 0);
+        }
+      }
+      if (colok) {
+        // register i of lane l: row 4*i + l/16, column l%16
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int pp1 = mp * 32 + h * 16 + 4 * i + (lane >> 4);
+            if (pp1 < Mrows) {
+              const long long s = (long long)P * (pp1 * T + p0) + r0 + r;
+              outp[2 * s + co] = (long long)(h ? acc1[i] : acc0[i]);
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Store one lifted pair of level l (c into band 0, d into band 1) with its
+// halo copies.
+template <class V, class S>
+__device__ __forceinline__ void store_pair(S *sm, const FusedLayout &lay, int l, int k, V c, V d) {
+  const int L = lay.N >> l;
+  S *b0 = sm + lay.region_off[l];
+  S *b1 = b0 + lay.band_size[l];
+  const int ps = lay.plane_stride[l];
+  for (int q = k; q < lay.ext[l]; q += L) {
+    const int o = poly_off(q, lay.logT[l], lay.Ls[l]);
+    b0[o] = c.x;
+    b0[o + ps] = c.y;
+    b1[o] = d.x;
+    b1[o + ps] = d.y;
+  }
+}
+
+template <class V, class S>
+__device__ __forceinline__ V load_elem(const S *sm, const FusedLayout &lay, int l, int q) {
+  const S *b0 = sm + lay.region_off[l];
+  const int o = poly_off(q, lay.logT[l], lay.Ls[l]);
+  V v;
+  v.x = b0[o];
+  v.y = b0[o + lay.plane_stride[l]];
+  return v;
+}
+
 // ===========================================================================
-// Fused kernel: one workgroup per pulse.
-// LDS: level-l bands c_l | d_l at region_off[l] (odd and even levels in
-// alternating halves, so level l+1 can be lifted from c_l while nothing
-// else is live), each band followed by a circular halo copy so that the
-// correlation's lag windows never wrap; then the weight staging area.
+// Fused kernel: one workgroup per pulse.  Level 1 is lifted straight from
+// HBM; every level's bands are correlated as soon as they exist, then the
+// next level is lifted from c_l.  Odd and even levels live in alternating
+// LDS regions so that c_l stays intact while level l+1 is written.
 // ===========================================================================
 template <int F>
 __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, FusedLayout lay,
-                                                       const void *__restrict__ rx_all, long long n,
-                                                       long long rx_stride,
-                                                       void *__restrict__ out_all,
-                                                       long long out_stride) {
+                                                                const void *__restrict__ rx_all,
+                                                                long long n, long long rx_stride,
+                                                                void *__restrict__ out_all,
+                                                                long long out_stride) {
   constexpr bool INT = (F == F_LEGALL53_INT);
   using V = typename ElemOf<F>::T;
+  using S = typename std::conditional<INT, int, float>::type;
   using RxT = typename RxOf<F>::T;
   using OutT = typename RxOf<F>::Out;
   constexpr bool OB = YLift<F>::kOddBefore;
   extern __shared__ __align__(16) char smem_fused[];
-  V *sm = reinterpret_cast<V *>(smem_fused);
+  S *sm = reinterpret_cast<S *>(smem_fused);
   const long long pulse = blockIdx.x;
   const RxT *rx = reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride;
   OutT *out = reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2;
   const int N = lay.N;
 
   // Level 1 straight from HBM (pairs split at load, zero padding n..N-1).
-  {
-    const int np = N >> 1;
-    V *c1 = sm + lay.region_off[1];
-    V *d1 = c1 + np + lay.halo[1];
-    const int halo = lay.halo[1];
-    lift_level<F, 2>(
-        np,
-        [&](int kc, V &e, V &o) {
-          e = rx_sample(rx, n, 2 * kc);
-          o = rx_sample(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
-        },
-        [&](int k, V c, V d) {
-          for (int kk = k; kk < np + halo; kk += np) {
-            c1[kk] = c;
-            d1[kk] = d;
-          }
-        });
-  }
+  lift_level<F, 2>(
+      N >> 1,
+      [&](int kc, V &e, V &o) {
+        e = rx_sample(rx, n, 2 * kc);
+        o = rx_sample(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
+      },
+      [&](int k, V c, V d) { store_pair(sm, lay, 1, k, c, d); });
   __syncthreads();
 
   for (int l = 1; l <= lay.J; ++l) {
-    correlate_level<INT>(plan, lay, l, sm, out + 2LL * (l - 1) * N);
+    if constexpr (INT) {
+      correlate_level_int(plan, lay, l, sm, out + 2LL * (l - 1) * N);
+    } else {
+      correlate_level_f32(plan, lay, l, sm, out + 2LL * (l - 1) * N);
+    }
     if (l < lay.J) {
       const int np = N >> (l + 1);
-      const V *cin = sm + lay.region_off[l];
-      V *c2 = sm + lay.region_off[l + 1];
-      V *d2 = c2 + np + lay.halo[l + 1];
-      const int halo = lay.halo[l + 1];
+      const int Lin = N >> l;
       lift_level<F, 1>(
-          np, [&](int kc, V &e, V &o) { pair_at<OB>(cin, kc, np, e, o); },
-          [&](int k, V c, V d) {
-            for (int kk = k; kk < np + halo; kk += np) {
-              c2[kk] = c;
-              d2[kk] = d;
-            }
-          });
+          np,
+          [&](int kc, V &e, V &o) {
+            e = load_elem<V>(sm, lay, l, 2 * kc);
+            o = load_elem<V>(sm, lay, l, OB ? (kc == 0 ? Lin - 1 : 2 * kc - 1) : 2 * kc + 1);
+          },
+          [&](int k, V c, V d) { store_pair(sm, lay, l + 1, k, c, d); });
     }
     __syncthreads();
   }
@@ -546,7 +625,7 @@ template <int F>
 static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, const void *rx,
                                  long long n, long long count, long long rx_stride, void *out,
                                  long long out_stride, hipStream_t st) {
-  size_t shm = (size_t)lay.total * 8;
+  size_t shm = (size_t)lay.total * 4;
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)fused_correlate<F>,

@@ -87,15 +87,42 @@ def algorithmic_flops_per_pulse(S, plan, N):
     return total
 
 
+PROFILE = os.path.join(ROOT, "profiles", "fused_correlate_cdf97_4096x8192_J5.md")
+KERNEL_SOURCES = ["sidwt_kernels.hip", "sidwt_device.hpp", "sidwt_host.hpp"]
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter summary, or None if the kernel sources changed since."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_cs_0607001_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    if h.hexdigest()[:16] not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return int(line.split(":")[1])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--count", type=int, default=4096)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run an elementwise kernel that reads and writes 256 MiB "
+                         "(calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -171,6 +198,15 @@ def main():
     lift_gbs = lift_bytes / (lift_ms * 1e-3) / 1e9
     log(f"lifting only: {lift_ms * 1e3:.1f} us, {lift_gbs:.0f} GB/s")
 
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x elementwise kernels reading and writing 256 MiB each")
+        del src, dst
+
     cpu = None
     if args.cpu:
         log("timing the CPU oracle on a bounded sample")
@@ -195,7 +231,8 @@ def main():
                    "pulses": args.count, "n": args.n, "ref_len": m, "filter": "cdf97", "J": J},
         "roofline": {"bound": "mfma", "achieved": achieved_tflops,
                      "peak": PEAK_FP32_MATRIX_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
+                     "frac": achieved_tflops / PEAK_FP32_MATRIX_TFLOPS,
+                     "traffic": profiled_traffic() if (args.count, args.n) == (4096, 8192) else None,
                      "kernel": "fused_correlate<CDF97>"},
         "lifting_roofline": {"bound": "hbm", "achieved": lift_gbs, "peak": PEAK_HBM_GBS,
                              "unit": "GB/s", "frac": lift_gbs / PEAK_HBM_GBS,

@@ -134,12 +134,52 @@ int sidwt_lift_many(int filter, int J, const void *rx, int64_t n,
                     int64_t count, int64_t rx_stride, void *pyr,
                     void *hip_stream);
 
-/* Uneven batch: `count` pulses with their own plans (filters and J may
- * differ), lengths n[i], device pointers rx[i] and out[i] (host arrays of
- * pointers).  All work goes through one persistent launch on `hip_stream`
- * that pulls (pulse, plane, lag-tile) items from a device work list sorted
- * by cost.  Device scratch is owned by the library and reused across calls
- * on the same stream. */
+/* ---- Uneven batches (one persistent launch) ------------------------------
+ * A batch fixes `count` pulses, each with its own plan (float filters; the
+ * filter and J may differ per pulse) and length n[i].  Short pulses are
+ * processed whole in LDS; long ones are lifted level by level into a
+ * library-owned HBM scratch pyramid and split into lag tiles of one level.
+ * All items are sorted by estimated cost (largest first) and pulled from a
+ * device work counter by one persistent kernel.  The launch sequence
+ * (counter reset, per-level lifting of long pulses, persistent kernel) is
+ * captured in a HIP graph on first run and replayed afterwards; a run only
+ * uploads the pulse / output pointers.  Plans must outlive the batch.
+ * Calls that use one batch object must not overlap (they share its
+ * descriptors, scratch and counter); different batch objects are
+ * independent. */
+typedef struct sidwt_batch sidwt_batch;
+
+/* plans[i], n[i] for i < count (host arrays).  Builds descriptors and
+ * allocates device scratch; synchronous.  SIDWT_E_UNSUPPORTED for the
+ * integer filter. */
+int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int count,
+                       sidwt_batch **out);
+
+/* Enqueue one pass on `hip_stream`: rx[i] (device, n[i] complex64 samples)
+ * -> out[i] (device, J_i x N_i complex64).  rx and out are host arrays of
+ * device pointers, read during the call. */
+int sidwt_batch_run(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream);
+
+/* Autotuner: times candidate (fused_max_N, tile_rows) pairs by running the
+ * batch on these buffers (events on `hip_stream`), keeps the fastest.  The
+ * outputs hold a valid result afterwards.  Synchronous. */
+int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream);
+
+/* Set the split explicitly: pulses with N <= fused_max_N run whole in LDS
+ * (when their layout fits); tiles of long pulses span tile_rows lag blocks
+ * (32..4096).  Synchronous. */
+int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_rows);
+
+/* values[0..nvalues): fused_max_N, tile_rows, items, whole-pulse items,
+ * tile items, LDS bytes per workgroup, persistent grid size, scratch
+ * bytes, tuned (0/1), best tuned time in microseconds. */
+int sidwt_batch_info(const sidwt_batch *b, int64_t *values, int nvalues);
+
+/* NULL is a no-op; waits for the device to be idle. */
+void sidwt_batch_free(sidwt_batch *b);
+
+/* One-shot form: builds a temporary batch, runs it without graph capture,
+ * synchronises `hip_stream` and frees the batch before returning. */
 int sidwt_correlate_batch(const sidwt_plan *const *plans,
                           const void *const *rx, const int64_t *n,
                           void *const *out, int count, void *hip_stream);

@@ -21,7 +21,8 @@ import numpy as np
 from ._lib import FILTERS, SidwtError, check, lib  # noqa: F401
 
 __all__ = ["Plan", "plan_create", "correlate", "correlate_many", "lift_many", "out_len",
-           "transform_length", "plan_phase", "SidwtError", "FILTERS", "version"]
+           "transform_length", "plan_phase", "Batch", "correlate_batch", "SidwtError",
+           "FILTERS", "version"]
 
 
 def transform_length(n: int, J: int) -> int:
@@ -182,3 +183,106 @@ def plan_phase(plan: Plan, level: int, band: int, r: int):
 
 def version() -> str:
     return lib().sidwt_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# Uneven batches
+# ---------------------------------------------------------------------------
+
+BATCH_INFO_KEYS = ("fused_max_N", "tile_rows", "items", "whole_pulse_items", "tile_items",
+                   "lds_bytes", "grid", "scratch_bytes", "tuned", "tuned_us")
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p
+    return arr
+
+
+def batch_outputs(plans, ns, device):
+    """Allocate (J, N) complex64 outputs for each pulse of a batch."""
+    torch = _torch()
+    return [torch.empty((p.J, transform_length(n, p.J)), dtype=torch.complex64, device=device)
+            for p, n in zip(plans, ns)]
+
+
+class Batch:
+    """Owns a sidwt_batch: pulses of uneven lengths with their own plans,
+    one persistent launch (replayed from a HIP graph) per run."""
+
+    def __init__(self, plans, ns):
+        _torch()
+        self.plans = list(plans)
+        self.ns = [int(n) for n in ns]
+        if len(self.plans) != len(self.ns) or not self.plans:
+            raise ValueError("plans and lengths must be non-empty and of equal length")
+        h = ctypes.c_void_p()
+        plan_arr = _ptr_array([p.handle.value for p in self.plans])
+        n_arr = (ctypes.c_int64 * len(self.ns))(*self.ns)
+        check(lib().sidwt_batch_create(plan_arr, n_arr, len(self.ns), ctypes.byref(h)),
+              "sidwt_batch_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("batch already freed")
+        return self._h
+
+    def _arrays(self, rx, out):
+        if len(rx) != len(self.ns) or len(out) != len(self.ns):
+            raise ValueError("one input and one output per pulse")
+        for x, n in zip(rx, self.ns):
+            if not x.is_cuda or x.dtype != _torch().complex64 or x.numel() < n or \
+                    not x.is_contiguous():
+                raise ValueError("pulses must be contiguous complex64 device tensors")
+        return _ptr_array([x.data_ptr() for x in rx]), _ptr_array([o.data_ptr() for o in out])
+
+    def run(self, rx, out, stream=None):
+        a, b = self._arrays(rx, out)
+        check(lib().sidwt_batch_run(self.handle, a, b, _stream_ptr(stream)), "sidwt_batch_run")
+        return out
+
+    def tune(self, rx, out, stream=None):
+        a, b = self._arrays(rx, out)
+        check(lib().sidwt_batch_tune(self.handle, a, b, _stream_ptr(stream)), "sidwt_batch_tune")
+        return self.info()
+
+    def config(self, fused_max_N: int, tile_rows: int):
+        check(lib().sidwt_batch_config(self.handle, fused_max_N, tile_rows), "sidwt_batch_config")
+
+    def info(self) -> dict:
+        v = (ctypes.c_int64 * len(BATCH_INFO_KEYS))()
+        check(lib().sidwt_batch_info(self.handle, v, len(BATCH_INFO_KEYS)), "sidwt_batch_info")
+        return dict(zip(BATCH_INFO_KEYS, list(v)))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sidwt_batch_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def correlate_batch(plans, rx, out=None, stream=None):
+    """One-shot uneven batch (synchronises the stream before returning)."""
+    ns = [int(x.numel()) for x in rx]
+    if out is None:
+        out = batch_outputs(plans, ns, rx[0].device)
+    plan_arr = _ptr_array([p.handle.value for p in plans])
+    n_arr = (ctypes.c_int64 * len(ns))(*ns)
+    check(lib().sidwt_correlate_batch(plan_arr, _ptr_array([x.data_ptr() for x in rx]), n_arr,
+                                      _ptr_array([o.data_ptr() for o in out]), len(ns),
+                                      _stream_ptr(stream)), "sidwt_correlate_batch")
+    return out

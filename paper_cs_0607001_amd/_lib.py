@@ -58,11 +58,19 @@ def _declare(L):
     L.sidwt_strerror.restype = c.c_char_p
     L.sidwt_version.argtypes = []
     L.sidwt_version.restype = c.c_char_p
-    for name in ("sidwt_bank_create", "sidwt_bank_correlate", "sidwt_bank_free",
-                 "sidwt_bank_info", "sidwt_batch_plan_create", "sidwt_batch_run",
-                 "sidwt_batch_free", "sidwt_batch_info"):
-        if hasattr(L, name):
-            getattr(L, name).restype = i32
+    pp = c.POINTER(vp)
+    L.sidwt_batch_create.argtypes = [pp, c.POINTER(i64), i32, pp]
+    L.sidwt_batch_create.restype = i32
+    L.sidwt_batch_run.argtypes = [vp, pp, pp, vp]
+    L.sidwt_batch_run.restype = i32
+    L.sidwt_batch_tune.argtypes = [vp, pp, pp, vp]
+    L.sidwt_batch_tune.restype = i32
+    L.sidwt_batch_config.argtypes = [vp, i64, i32]
+    L.sidwt_batch_config.restype = i32
+    L.sidwt_batch_info.argtypes = [vp, c.POINTER(i64), i32]
+    L.sidwt_batch_info.restype = i32
+    L.sidwt_batch_free.argtypes = [vp]
+    L.sidwt_batch_free.restype = None
     return L
 
 

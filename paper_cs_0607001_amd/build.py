@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsidwt.so")
-SOURCES = ["sidwt_kernels.hip", "sidwt_api.cpp"]
+SOURCES = ["sidwt_kernels.hip", "sidwt_api.cpp", "sidwt_batch.cpp"]
 ARCH = "gfx950"
 
 

@@ -60,6 +60,10 @@ int check_pulse(const sidwt_plan *p, int64_t n, int64_t *N_out) {
 
 }  // namespace
 
+// Descriptor of a plan for the batch module (C++ linkage, not exported in
+// the header).
+const sidwt::PlanDesc *sidwt_plan_desc(const sidwt_plan *p) { return p ? &p->desc : nullptr; }
+
 extern "C" {
 
 const char *sidwt_strerror(int code) {
@@ -190,12 +194,6 @@ int sidwt_lift_many(int filter, int J, const void *rx, int64_t n, int64_t count,
   if (2 * (N / 2 + N / 4 + 1) > kLdsWords) return SIDWT_E_UNSUPPORTED;
   return map_err(sidwt::launch_lift(filter, J, (int)N, rx, n, count, rx_stride, pyr,
                                     static_cast<hipStream_t>(hip_stream)));
-}
-
-int sidwt_correlate_batch(const sidwt_plan *const *plans, const void *const *rx,
-                          const int64_t *n, void *const *out, int count, void *hip_stream) {
-  (void)plans; (void)rx; (void)n; (void)out; (void)count; (void)hip_stream;
-  return SIDWT_E_UNSUPPORTED;
 }
 
 int sidwt_plan_phase(const sidwt_plan *p, int level, int band, int r, int32_t *lo, int32_t *len,

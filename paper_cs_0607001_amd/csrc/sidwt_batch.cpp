@@ -1,0 +1,453 @@
+// Uneven batches of pulses through one persistent launch (C ABI part of
+// libsidwt; declarations in include/sidwt.h).
+//
+// A batch object fixes the plans and pulse lengths.  Building it:
+//   - short pulses (transform length N <= fused_max_N whose fused LDS
+//     layout fits) become one "whole pulse" work item each (lifting and all
+//     planes in LDS);
+//   - long pulses are lifted level by level into an HBM scratch pyramid and
+//     split into lag tiles (rows of one level) of `tile_rows` lag blocks;
+//   - items are ordered by estimated cost, largest first, and pulled by a
+//     persistent kernel from an atomic counter.
+// The launch sequence (counter reset, per-level lifting, persistent kernel)
+// is captured once in a HIP graph and replayed; each run only uploads the
+// caller's pulse and output pointers.  sidwt_batch_tune times candidate
+// (fused_max_N, tile_rows) pairs on the caller's buffers and keeps the best.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sidwt.h"
+#include "sidwt_host.hpp"
+
+namespace sidwt {
+hipError_t batch_set_lds(size_t bytes);
+hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_batch(const PlanDesc *plans, const FusedLayout *lays, const BatchPulse *pulses,
+                        const BatchItem *items, int nitems, int *counter, float2 *scratch,
+                        const LiftChunk *const *chunks, const int *nchunks, int Jmax, int grid,
+                        size_t lds_bytes, hipStream_t st);
+}  // namespace sidwt
+
+// The plan object is defined in sidwt_api.cpp; the batch only needs its
+// descriptor, which that file exposes through this accessor.
+extern "C++" const sidwt::PlanDesc *sidwt_plan_desc(const sidwt_plan *p);
+
+using namespace sidwt;
+using namespace sidwt::host;
+
+namespace {
+
+constexpr int kLiftChunkPairs = 4096;
+
+int map_err(hipError_t e) {
+  if (e == hipSuccess) return SIDWT_OK;
+  if (e == hipErrorOutOfMemory) return SIDWT_E_NOMEM;
+  return SIDWT_E_DEVICE;
+}
+
+template <class T>
+int upload(T **dptr, size_t *cap, const std::vector<T> &v) {
+  const size_t need = std::max<size_t>(1, v.size());
+  if (*cap < need) {
+    if (*dptr) (void)hipFree(*dptr);
+    *dptr = nullptr;
+    *cap = 0;
+    hipError_t e = hipMalloc(dptr, need * sizeof(T));
+    if (e != hipSuccess) return map_err(e);
+    *cap = need;
+  }
+  if (!v.empty()) {
+    hipError_t e = hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return map_err(e);
+  }
+  return SIDWT_OK;
+}
+
+}  // namespace
+
+struct sidwt_batch {
+  int count = 0;
+  std::vector<PlanDesc> plans;       // distinct plans
+  std::vector<int> pulse_plan;       // per pulse: index into plans
+  std::vector<int64_t> n, N;
+  std::vector<int> J;
+  // configuration
+  int fused_max_N = 8192;
+  int tile_rows = 256;
+  int tuned = 0;
+  double tuned_us = 0;
+  // derived
+  std::vector<FusedLayout> lays;
+  std::vector<BatchPulse> pulses;
+  std::vector<BatchItem> items;
+  std::vector<LiftChunk> chunks;     // all levels, grouped by level
+  int chunk_off[kMaxLevels + 2] = {0};
+  int nchunks[kMaxLevels + 2] = {0};
+  int Jmax = 0, n_fused = 0, n_tiles = 0, grid = 0;
+  size_t lds_bytes = 0;
+  long long scratch_elems = 0;
+  // device
+  PlanDesc *d_plans = nullptr;
+  size_t c_plans = 0;
+  FusedLayout *d_lays = nullptr;
+  size_t c_lays = 0;
+  BatchPulse *d_pulses = nullptr;
+  size_t c_pulses = 0;
+  BatchItem *d_items = nullptr;
+  size_t c_items = 0;
+  LiftChunk *d_chunks = nullptr;
+  size_t c_chunks = 0;
+  int *d_counter = nullptr;
+  float2 *d_scratch = nullptr;
+  long long scratch_cap = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+};
+
+namespace {
+
+void drop_graph(sidwt_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+double item_cost(const PlanDesc &d, const BatchItem &it, int N, const FusedLayout &lay) {
+  if (it.kind == 0) {
+    double c = 0;
+    for (int l = 1; l <= d.J; ++l) c += 8.0 * N * (d.lv[l].len[0] + d.lv[l].len[1]);
+    return c;
+  }
+  const int l = it.level;
+  return 8.0 * it.rows * lay.T[l] * (1 << l) * (d.lv[l].len[0] + d.lv[l].len[1]);
+}
+
+// Rebuild work list, layouts and device descriptors for the current
+// configuration.
+int build(sidwt_batch *b) {
+  drop_graph(b);
+  b->lays.clear();
+  b->pulses.assign(b->count, BatchPulse{});
+  b->items.clear();
+  b->chunks.clear();
+  std::vector<std::vector<LiftChunk>> per_level(kMaxLevels + 1);
+  std::map<std::tuple<int, long long, int>, int> lay_index;  // (plan, N, kind)
+  long long scratch = 0;
+  size_t lds_words = 0;
+  b->Jmax = 0;
+  b->n_fused = b->n_tiles = 0;
+  std::vector<std::pair<double, BatchItem>> costed;
+  for (int i = 0; i < b->count; ++i) {
+    const int pi = b->pulse_plan[i];
+    const PlanDesc &d = b->plans[pi];
+    const long long N = b->N[i];
+    BatchPulse &p = b->pulses[i];
+    p.n = b->n[i];
+    p.N = (int)N;
+    p.J = d.J;
+    p.plan = pi;
+    p.scratch = 0;
+    b->Jmax = std::max(b->Jmax, d.J);
+    FusedLayout lay;
+    bool fused = N <= b->fused_max_N && make_layout(d, N, &lay) == 0;
+    const int kind = fused ? 0 : 1;
+    auto key = std::make_tuple(pi, N, kind);
+    auto itl = lay_index.find(key);
+    if (itl == lay_index.end()) {
+      if (!fused && make_tile_layout(d, N, b->tile_rows, &lay) != 0) return SIDWT_E_UNSUPPORTED;
+      lay_index[key] = (int)b->lays.size();
+      b->lays.push_back(lay);
+      lds_words = std::max<size_t>(lds_words, lay.total);
+      itl = lay_index.find(key);
+    }
+    p.layout = itl->second;
+    const FusedLayout &L = b->lays[p.layout];
+    if (fused) {
+      BatchItem it{};
+      it.kind = 0;
+      it.pulse = i;
+      costed.push_back({item_cost(d, it, (int)N, L), it});
+      ++b->n_fused;
+    } else {
+      p.scratch = scratch;
+      scratch += 2 * N;
+      for (int l = 1; l <= d.J; ++l) {
+        const int rows_l = (int)((N >> l) / L.T[l]);
+        for (int r0 = 0; r0 < rows_l; r0 += b->tile_rows) {
+          BatchItem it{};
+          it.kind = 1;
+          it.pulse = i;
+          it.level = l;
+          it.row0 = r0;
+          it.rows = std::min(b->tile_rows, rows_l - r0);
+          costed.push_back({item_cost(d, it, (int)N, L), it});
+          ++b->n_tiles;
+        }
+        const int np = (int)(N >> l);
+        for (int k0 = 0; k0 < np; k0 += kLiftChunkPairs)
+          per_level[l].push_back(LiftChunk{i, k0, std::min(np, k0 + kLiftChunkPairs), 0});
+      }
+    }
+  }
+  std::stable_sort(costed.begin(), costed.end(),
+                   [](const std::pair<double, BatchItem> &x, const std::pair<double, BatchItem> &y) {
+                     return x.first > y.first;
+                   });
+  for (auto &c : costed) b->items.push_back(c.second);
+  for (int l = 0; l <= kMaxLevels + 1; ++l) b->chunk_off[l] = b->nchunks[l] = 0;
+  for (int l = 1; l <= kMaxLevels; ++l) {
+    b->chunk_off[l] = (int)b->chunks.size();
+    b->nchunks[l] = (int)per_level[l].size();
+    b->chunks.insert(b->chunks.end(), per_level[l].begin(), per_level[l].end());
+  }
+  b->scratch_elems = scratch;
+  b->lds_bytes = std::max<size_t>(lds_words * 4, 1024);
+  // device side
+  int rc = upload(&b->d_plans, &b->c_plans, b->plans);
+  if (!rc) rc = upload(&b->d_lays, &b->c_lays, b->lays);
+  if (!rc) rc = upload(&b->d_pulses, &b->c_pulses, b->pulses);
+  if (!rc) rc = upload(&b->d_items, &b->c_items, b->items);
+  if (!rc) rc = upload(&b->d_chunks, &b->c_chunks, b->chunks);
+  if (rc) return rc;
+  if (b->scratch_cap < std::max<long long>(1, scratch)) {
+    if (b->d_scratch) (void)hipFree(b->d_scratch);
+    b->d_scratch = nullptr;
+    b->scratch_cap = 0;
+    hipError_t e = hipMalloc(&b->d_scratch, (size_t)std::max<long long>(1, scratch) * sizeof(float2));
+    if (e != hipSuccess) return map_err(e);
+    b->scratch_cap = std::max<long long>(1, scratch);
+  }
+  hipError_t e = batch_set_lds(b->lds_bytes);
+  if (e != hipSuccess) return map_err(e);
+  int per_cu = 0, cus = 0, dev = 0;
+  e = batch_occupancy(b->lds_bytes, &per_cu);
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return map_err(e);
+  if (per_cu < 1) return SIDWT_E_UNSUPPORTED;
+  b->grid = std::max(1, std::min<int>(per_cu * cus, (int)b->items.size()));
+  return SIDWT_OK;
+}
+
+int enqueue(sidwt_batch *b, hipStream_t st) {
+  const LiftChunk *chunk_ptr[kMaxLevels + 2];
+  for (int l = 0; l <= kMaxLevels + 1; ++l) chunk_ptr[l] = b->d_chunks + b->chunk_off[l];
+  return map_err(launch_batch(b->d_plans, b->d_lays, b->d_pulses, b->d_items, (int)b->items.size(),
+                              b->d_counter, b->d_scratch, chunk_ptr, b->nchunks, b->Jmax, b->grid,
+                              b->lds_bytes, st));
+}
+
+int ensure_graph(sidwt_batch *b) {
+  if (b->exec) return SIDWT_OK;
+  if (!b->cap_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return map_err(e);
+  }
+  hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return map_err(e);
+  int rc = enqueue(b, b->cap_stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->cap_stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return map_err(e);
+  b->graph = g;
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(b);
+    return map_err(e);
+  }
+  return SIDWT_OK;
+}
+
+int set_pointers(sidwt_batch *b, const void *const *rx, void *const *out, hipStream_t st) {
+  for (int i = 0; i < b->count; ++i) {
+    if (!rx[i] || !out[i]) return SIDWT_E_INVAL;
+    b->pulses[i].rx = rx[i];
+    b->pulses[i].out = out[i];
+  }
+  // pageable source: the runtime stages it before returning
+  return map_err(hipMemcpyAsync(b->d_pulses, b->pulses.data(), b->pulses.size() * sizeof(BatchPulse),
+                                hipMemcpyHostToDevice, st));
+}
+
+int run(sidwt_batch *b, const void *const *rx, void *const *out, hipStream_t st, bool use_graph) {
+  int rc = set_pointers(b, rx, out, st);
+  if (rc) return rc;
+  if (!use_graph) return enqueue(b, st);
+  rc = ensure_graph(b);
+  if (rc) return rc;
+  return map_err(hipGraphLaunch(b->exec, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int count,
+                       sidwt_batch **out) {
+  if (!plans || !n || !out || count < 1) return SIDWT_E_INVAL;
+  sidwt_batch *b = new (std::nothrow) sidwt_batch();
+  if (!b) return SIDWT_E_NOMEM;
+  b->count = count;
+  std::map<const sidwt_plan *, int> idx;
+  for (int i = 0; i < count; ++i) {
+    const PlanDesc *d = plans[i] ? sidwt_plan_desc(plans[i]) : nullptr;
+    if (!d || n[i] < 1) {
+      delete b;
+      return SIDWT_E_INVAL;
+    }
+    if (is_int_filter(d->filter)) {
+      delete b;
+      return SIDWT_E_UNSUPPORTED;
+    }
+    const int64_t N = transform_length(n[i], d->J);
+    if ((N >> d->J) < 2) {
+      delete b;
+      return SIDWT_E_INVAL;
+    }
+    if (d->m > N || N > (int64_t(1) << 26)) {
+      delete b;
+      return SIDWT_E_SIZE;
+    }
+    auto it = idx.find(plans[i]);
+    if (it == idx.end()) {
+      it = idx.emplace(plans[i], (int)b->plans.size()).first;
+      b->plans.push_back(*d);
+    }
+    b->pulse_plan.push_back(it->second);
+    b->n.push_back(n[i]);
+    b->N.push_back(N);
+    b->J.push_back(d->J);
+  }
+  hipError_t e = hipMalloc(&b->d_counter, sizeof(int));
+  int rc = map_err(e);
+  if (!rc) rc = build(b);
+  if (rc) {
+    sidwt_batch_free(b);
+    return rc;
+  }
+  *out = b;
+  return SIDWT_OK;
+}
+
+void sidwt_batch_free(sidwt_batch *b) {
+  if (!b) return;
+  (void)hipDeviceSynchronize();
+  drop_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  (void)hipFree(b->d_plans);
+  (void)hipFree(b->d_lays);
+  (void)hipFree(b->d_pulses);
+  (void)hipFree(b->d_items);
+  (void)hipFree(b->d_chunks);
+  (void)hipFree(b->d_counter);
+  (void)hipFree(b->d_scratch);
+  delete b;
+}
+
+int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_rows) {
+  if (!b || fused_max_N < 0 || tile_rows < 32 || tile_rows > 4096) return SIDWT_E_INVAL;
+  (void)hipDeviceSynchronize();
+  b->fused_max_N = (int)std::min<int64_t>(fused_max_N, 1 << 20);
+  b->tile_rows = tile_rows;
+  return build(b);
+}
+
+int sidwt_batch_run(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream) {
+  if (!b || !rx || !out) return SIDWT_E_INVAL;
+  return run(b, rx, out, static_cast<hipStream_t>(hip_stream), true);
+}
+
+int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream) {
+  if (!b || !rx || !out) return SIDWT_E_INVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return SIDWT_E_DEVICE;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SIDWT_E_DEVICE;
+  }
+  auto time_cfg = [&](int fmax, int rows, double *us) -> int {
+    b->fused_max_N = fmax;
+    b->tile_rows = rows;
+    int rc = build(b);
+    if (rc) return rc;
+    rc = run(b, rx, out, st, true);  // warm-up (also builds the graph)
+    if (rc) return rc;
+    if (hipEventRecord(e0, st) != hipSuccess) return SIDWT_E_DEVICE;
+    for (int k = 0; k < 2 && !rc; ++k) rc = run(b, rx, out, st, true);
+    if (rc) return rc;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return SIDWT_E_DEVICE;
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SIDWT_E_DEVICE;
+    *us = 1e3 * ms / 2;
+    return SIDWT_OK;
+  };
+  // Tile size first (with the default split), then the fused/tiled split.
+  const int rows_c[] = {64, 128, 256, 512};
+  const int fmax_c[] = {0, 4096, 8192, 16384};
+  int best_rows = b->tile_rows, best_fmax = b->fused_max_N;
+  double best = 1e300;
+  int rc = SIDWT_OK;
+  for (int rows : rows_c) {
+    double us;
+    int r = time_cfg(8192, rows, &us);
+    if (r == SIDWT_E_UNSUPPORTED) continue;
+    if (r) { rc = r; break; }
+    if (us < best) { best = us; best_rows = rows; best_fmax = 8192; }
+  }
+  for (int fmax : fmax_c) {
+    if (rc || fmax == 8192) continue;
+    double us;
+    int r = time_cfg(fmax, best_rows, &us);
+    if (r == SIDWT_E_UNSUPPORTED) continue;
+    if (r) { rc = r; break; }
+    if (us < best) { best = us; best_fmax = fmax; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  b->fused_max_N = best_fmax;
+  b->tile_rows = best_rows;
+  b->tuned = 1;
+  b->tuned_us = best;
+  return build(b);
+}
+
+int sidwt_batch_info(const sidwt_batch *b, int64_t *v, int nv) {
+  if (!b || !v || nv < 1) return SIDWT_E_INVAL;
+  const int64_t vals[] = {b->fused_max_N, b->tile_rows, (int64_t)b->items.size(), b->n_fused,
+                          b->n_tiles, (int64_t)b->lds_bytes, b->grid,
+                          b->scratch_elems * (int64_t)sizeof(float2), b->tuned,
+                          (int64_t)(b->tuned_us + 0.5)};
+  const int k = (int)(sizeof(vals) / sizeof(vals[0]));
+  for (int i = 0; i < nv; ++i) v[i] = i < k ? vals[i] : 0;
+  return SIDWT_OK;
+}
+
+int sidwt_correlate_batch(const sidwt_plan *const *plans, const void *const *rx, const int64_t *n,
+                          void *const *out, int count, void *hip_stream) {
+  if (!rx || !out) return SIDWT_E_INVAL;
+  sidwt_batch *b = nullptr;
+  int rc = sidwt_batch_create(plans, n, count, &b);
+  if (rc) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  rc = run(b, rx, out, st, false);
+  if (!rc) rc = map_err(hipStreamSynchronize(st));
+  sidwt_batch_free(b);
+  return rc;
+}
+
+}  // extern "C"

@@ -74,6 +74,35 @@ struct FusedLayout {
   int total;                         // words of LDS
 };
 
+// Uneven-batch descriptors (host builds them, the persistent kernel reads them).
+struct BatchPulse {
+  const void *rx;       // caller's pulse (complex64), n samples
+  void *out;            // caller's planes, J x N complex64
+  long long n;
+  long long scratch;    // complex offset of this pulse's pyramid (long pulses)
+  int N, J, plan, layout;
+};
+
+struct BatchItem {
+  int kind;             // 0: whole pulse (fused), 1: lag tile of a long pulse
+  int pulse;
+  int level;            // kind 1: level l (plane l-1)
+  int row0, rows;       // kind 1: lag-block rows [row0, row0 + rows)
+  int pad_[3];
+};
+
+struct LiftChunk {
+  int pulse;
+  int k0, k1;           // pairs [k0, k1) of the level
+  int pad_;
+};
+
+// Offset (complex elements) of c_l inside a pulse's scratch pyramid; d_l
+// follows c_l.
+__host__ __device__ inline long long scratch_level_off(int N, int l) {
+  return 2LL * N - 4LL * (N >> l);
+}
+
 // ---------------------------------------------------------------------------
 // Table I (t = 5/4) and the causal D4 constants of eq. (17).
 // ---------------------------------------------------------------------------

@@ -173,6 +173,93 @@ inline int make_layout(const PlanDesc &d, int64_t N64, FusedLayout *lay) {
   return lay->total <= kLdsWords ? 0 : -5;
 }
 
+// Per-level geometry shared by the fused and tile layouts: Toeplitz block T
+// (T | L), aligned lag windows, staged row lengths.
+inline void level_geometry(const PlanDesc &d, int N, int l, bool is_int, FusedLayout *lay) {
+  const int ncol = tile_cols(is_int);
+  const int P = 1 << l, L = N >> l;
+  int T = P < ncol ? ncol / P : 1;
+  while (L % T) T >>= 1;
+  int logT = 0;
+  while ((1 << logT) < T) ++logT;
+  lay->T[l] = T;
+  lay->logT[l] = logT;
+  for (int b = 0; b < 2; ++b) {
+    const int lo = d.lv[l].lo[b], len = d.lv[l].len[b];
+    const int delta = pos_mod(lo, T);
+    lay->lo[l][b] = lo - delta;
+    lay->F[l][b] = T - 1 + delta;
+    int U = len + delta + T - 1;
+    U = is_int ? (U + 1) & ~1 : (U + 3) & ~3;
+    lay->U[l][b] = U;
+    int k = (U + T - 1 + T - 1) / T;
+    if ((k & 1) == 0) ++k;
+    lay->V[l][b] = k * T;
+  }
+}
+
+// Tile layout of a long pulse (float filters): for each level, LDS holds a
+// window of `rows` lag-block rows (rounded up to 64) of both bands as
+// polyphase re/im planes (band 0 at word 0, band 1 at 2*plane_stride) and the
+// staged weights at w_at.  Returns 0 or -5.
+inline int make_tile_layout(const PlanDesc &d, int64_t N64, int rows, FusedLayout *lay) {
+  std::memset(lay, 0, sizeof(*lay));
+  if (is_int_filter(d.filter) || rows < 1 || N64 > (int64_t(1) << 28)) return -5;
+  const int N = (int)N64, J = d.J, ncol = tile_cols(false);
+  lay->N = N;
+  lay->J = J;
+  int total = 0;
+  for (int l = 1; l <= J; ++l) {
+    level_geometry(d, N, l, false, lay);
+    const int P = 1 << l, L = N >> l, T = lay->T[l];
+    const int rows_l = std::min(rows, L / T);
+    const int rows64 = (rows_l + 63) & ~63;
+    const int W = rows64 * T + std::max(lay->U[l][0], lay->U[l][1]);
+    lay->ext[l] = W;
+    lay->Ls[l] = (W + T - 1) / T;
+    lay->plane_stride[l] = ((T * lay->Ls[l] + 63) / 64) * 64 + 32;
+    lay->band_size[l] = 2 * lay->plane_stride[l];
+    lay->region_off[l] = 0;
+    lay->w_at[l] = 2 * lay->band_size[l];
+    const int row = 2 * (lay->V[l][0] + lay->V[l][1]);
+    int pc = P;
+    if (P >= ncol) {
+      int avail = kLdsWordsTwoPerCu - lay->w_at[l];
+      if (avail < ncol * row) avail = kLdsWords - lay->w_at[l];
+      pc = std::max(ncol, std::min(P, (avail / row) / ncol * ncol));
+    }
+    lay->pc[l] = pc;
+    total = std::max(total, lay->w_at[l] + std::min(pc, P) * row);
+  }
+  lay->w_off = 0;
+  lay->total = total;
+  return total <= kLdsWords ? 0 : -5;
+}
+
+// Audit of a tile layout against the ranges tile items touch.
+inline int tile_layout_violation(const PlanDesc &d, const FusedLayout &lay, int rows) {
+  const int N = lay.N;
+  for (int l = 1; l <= lay.J; ++l) {
+    const int L = N >> l, T = lay.T[l], P = 1 << l;
+    if (T < 1 || (1 << lay.logT[l]) != T || L % T) return 21;
+    const int rows_l = std::min(rows, L / T);
+    const int rows64 = (rows_l + 63) & ~63;
+    for (int b = 0; b < 2; ++b) {
+      // window elements q < rows64*T + U (the last row pair of a tile reads them)
+      if ((rows64 * T + lay.U[l][b] + T - 1) / T > lay.Ls[l]) return 22;
+      if (lay.U[l][b] + T - 2 >= lay.V[l][b]) return 23;
+      if (lay.U[l][b] < d.lv[l].len[b] + lay.F[l][b]) return 24;
+    }
+    if (T * lay.Ls[l] + 32 > lay.plane_stride[l]) return 25;
+    if (lay.w_at[l] < 4 * lay.plane_stride[l] || (lay.w_at[l] & 3)) return 26;
+    const int row = 2 * (lay.V[l][0] + lay.V[l][1]);
+    const int pc = lay.pc[l];
+    if (P < 16 ? pc != P : (pc % 16 || pc < 16)) return 27;
+    if (lay.w_at[l] + std::min(pc, P) * row > lay.total) return 28;
+  }
+  return lay.total > kLdsWords ? 29 : 0;
+}
+
 // Audit of a layout against the index ranges the fused kernel touches.
 // Returns 0 if every access is inside its region and regions that are live
 // together are disjoint; otherwise a positive code naming the failed check.

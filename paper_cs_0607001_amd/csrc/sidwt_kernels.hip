@@ -166,20 +166,20 @@ __global__ __launch_bounds__(256) void ref_tree_level(
 // receives the owned outputs.
 // ===========================================================================
 template <int F, int UNROLL, class Load, class Store>
-__device__ __forceinline__ void lift_level(int np, Load load, Store store) {
+__device__ __forceinline__ void lift_level_range(int np, int k0, int k1, Load load, Store store) {
   using L = YLift<F>;
   using V = typename L::V;
   constexpr int OWN = 64 - L::HL - L::HR;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
-  const int nwin = (np + OWN - 1) / OWN;
+  const int nwin = (k1 - k0 + OWN - 1) / OWN;
   for (int w0 = wave * UNROLL; w0 < nwin; w0 += nw * UNROLL) {
     V e[UNROLL], o[UNROLL];
     int kk[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
-      int k = (w0 + u) * OWN - L::HL + lane;
+      int k = k0 + (w0 + u) * OWN - L::HL + lane;
       kk[u] = k;
       load(pos_mod(k, np), e[u], o[u]);
     }
@@ -188,9 +188,14 @@ __device__ __forceinline__ void lift_level(int np, Load load, Store store) {
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       int k = kk[u];
-      if (lane >= L::HL && lane < 64 - L::HR && k < np && (w0 + u) < nwin) store(k, e[u], o[u]);
+      if (lane >= L::HL && lane < 64 - L::HR && k < k1 && (w0 + u) < nwin) store(k, e[u], o[u]);
     }
   }
+}
+
+template <int F, int UNROLL, class Load, class Store>
+__device__ __forceinline__ void lift_level(int np, Load load, Store store) {
+  lift_level_range<F, UNROLL>(np, 0, np, load, store);
 }
 
 // Pair kc of a circular sequence of length 2*np held in `src` (LDS or
@@ -234,21 +239,60 @@ template <> struct RxOf<F_LEGALL53_INT> { using T = short2; using Out = long lon
 // because every product and partial sum is an integer below 2^53.
 // ===========================================================================
 
+// One level as the correlation engine sees it: where the two bands sit in
+// LDS (polyphase planes, see FusedLayout), the lag windows, the staged
+// weight geometry, and the range of lag-block rows p1 to produce.
+struct LevelView {
+  int l, P, L, T, logT, Ls, plane_stride;
+  int base[2];          // word offset of band b's re plane
+  int lo[2];            // lag-window start (aligned to T)
+  int U[2], V[2], F[2];
+  int pc, w_at;
+  int wrap;             // 1: band holds the whole level (+halo), row p1 starts at
+                        //    element (p1*T + lo) mod L; 0: band holds a window
+                        //    whose element 0 is row row_begin's first element
+  int row_begin, row_end;
+};
+
+__device__ __forceinline__ LevelView fused_view(const FusedLayout &lay, int l) {
+  LevelView v;
+  v.l = l;
+  v.P = 1 << l;
+  v.L = lay.N >> l;
+  v.T = lay.T[l];
+  v.logT = lay.logT[l];
+  v.Ls = lay.Ls[l];
+  v.plane_stride = lay.plane_stride[l];
+  for (int b = 0; b < 2; ++b) {
+    v.base[b] = lay.region_off[l] + b * lay.band_size[l];
+    v.lo[b] = lay.lo[l][b];
+    v.U[b] = lay.U[l][b];
+    v.V[b] = lay.V[l][b];
+    v.F[b] = lay.F[l][b];
+  }
+  v.pc = lay.pc[l];
+  v.w_at = lay.w_at[l];
+  v.wrap = 1;
+  v.row_begin = 0;
+  v.row_end = v.L >> v.logT;
+  return v;
+}
+
 // Stage phases r0..r0+pcc-1 of both bands as complex rows W[b][rr][v] with
 // W[v] = w[v - F] (zero outside the stored support).
 template <class V>
-__device__ __forceinline__ void stage_weights(const PlanDesc &plan, const FusedLayout &lay, int l,
-                                              int r0, int pcc, V *W) {
+__device__ __forceinline__ void stage_weights(const PlanDesc &plan, const LevelView &lv, int r0,
+                                              int pcc, V *W) {
   const V *coef = reinterpret_cast<const V *>(plan.coef);
-  const LevelDesc &ld = plan.lv[l];
-  const int V0 = lay.V[l][0], V1 = lay.V[l][1];
+  const LevelDesc &ld = plan.lv[lv.l];
+  const int V0 = lv.V[0], V1 = lv.V[1];
   const int tot0 = pcc * V0, tot = tot0 + pcc * V1;
   for (int i = threadIdx.x; i < tot; i += blockDim.x) {
     const int b = i >= tot0;
     const int j = b ? i - tot0 : i;
     const int Vb = b ? V1 : V0;
     const int rr = j / Vb;
-    const int t = j - rr * Vb - lay.F[l][b];
+    const int t = j - rr * Vb - lv.F[b];
     V w;
     w.x = 0;
     w.y = 0;
@@ -261,26 +305,30 @@ __device__ __forceinline__ f32x16 mfma32(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
 
-// FP32 correlation of level l (32x32x2 tiles, two row tiles per wave that
-// share the weight operand).
-__device__ void correlate_level_f32(const PlanDesc &plan, const FusedLayout &lay, int l,
-                                    float *smf, float *__restrict__ outp) {
-  const int N = lay.N, P = 1 << l, L = N >> l;
-  const int T = lay.T[l], logT = lay.logT[l], Ls = lay.Ls[l];
-  const int Mrows = L >> logT;
-  const int mtiles = (Mrows + 31) >> 5;
+__device__ __forceinline__ int row_start(const LevelView &v, int p1, int b) {
+  return v.wrap ? (pos_mod(p1 * v.T + v.lo[b], v.L) >> v.logT) : (p1 - v.row_begin);
+}
+
+// FP32 correlation of rows [row_begin, row_end) of one level (32x32x2
+// tiles, two row tiles per wave that share the weight operand).  outp is
+// the plane's output (complex64 as float pairs), indexed by global lag.
+__device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, float *smf,
+                                   float *__restrict__ outp) {
+  const int P = v.P, l = v.l, T = v.T, logT = v.logT, Ls = v.Ls;
+  const int nrows = v.row_end - v.row_begin;
+  const int mtiles = (nrows + 31) >> 5;
   const int mpairs = (mtiles + 1) >> 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  float2 *W = reinterpret_cast<float2 *>(smf + lay.w_at[l]);
-  const int V0 = lay.V[l][0], V1 = lay.V[l][1];
+  float2 *W = reinterpret_cast<float2 *>(smf + v.w_at);
+  const int V0 = v.V[0], V1 = v.V[1];
   const int row = lane & 31;
   const int ci = lane >> 5;
   const int co = lane & 1;
   const int cc = (lane & 31) >> 1;
   const bool neg = (ci == 0) && (co == 1);
-  for (int r0 = 0; r0 < P; r0 += lay.pc[l]) {
-    const int pcc = min(lay.pc[l], P - r0);
-    stage_weights(plan, lay, l, r0, pcc, W);
+  for (int r0 = 0; r0 < P; r0 += v.pc) {
+    const int pcc = min(v.pc, P - r0);
+    stage_weights(plan, v, r0, pcc, W);
     __syncthreads();
     // P < 16: one column tile holds all (p0, r) pairs, p0 < T; otherwise
     // T = 1 and each column tile holds 16 phases.
@@ -301,7 +349,7 @@ __device__ void correlate_level_f32(const PlanDesc &plan, const FusedLayout &lay
         p0 = 0;
         colok = true;
       }
-      const int p1a = mp * 64 + row;
+      const int p1a = v.row_begin + mp * 64 + row;
       const int p1b = p1a + 32;
       f32x16 acc0, acc1;
 #pragma unroll
@@ -311,10 +359,10 @@ __device__ void correlate_level_f32(const PlanDesc &plan, const FusedLayout &lay
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int G = lay.U[l][b] >> 2;
-        const float *pl = smf + lay.region_off[l] + b * lay.band_size[l] + ci * lay.plane_stride[l];
-        const float *pa = pl + (pos_mod(p1a * T + lay.lo[l][b], L) >> logT);
-        const float *pb = pl + (pos_mod(p1b * T + lay.lo[l][b], L) >> logT);
+        const int G = v.U[b] >> 2;
+        const float *pl = smf + v.base[b] + ci * v.plane_stride;
+        const float *pa = pl + row_start(v, p1a, b);
+        const float *pb = pl + row_start(v, p1b, b);
         const float *wp = reinterpret_cast<const float *>(W + (b ? pcc * V0 : 0) + r * (b ? V1 : V0)) +
                           2 * (T - 1 - p0) + (ci ^ co);
         float a0[4], a1[4], w[4];
@@ -357,8 +405,8 @@ __device__ void correlate_level_f32(const PlanDesc &plan, const FusedLayout &lay
         for (int h = 0; h < 2; ++h) {
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
-            const int pp1 = mp * 64 + h * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-            if (pp1 < Mrows) {
+            const int pp1 = v.row_begin + mp * 64 + h * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+            if (pp1 < v.row_end) {
               const long long s = (long long)P * (pp1 * T + p0) + r0 + r;
               __builtin_nontemporal_store(h ? acc1[i] : acc0[i], &outp[2 * s + co]);
             }
@@ -370,18 +418,17 @@ __device__ void correlate_level_f32(const PlanDesc &plan, const FusedLayout &lay
   }
 }
 
-// Integer correlation of level l (FP64 16x16x4 tiles, two row tiles per
-// wave sharing the weight operand).
-__device__ void correlate_level_int(const PlanDesc &plan, const FusedLayout &lay, int l,
-                                    int *smi, long long *__restrict__ outp) {
-  const int N = lay.N, P = 1 << l, L = N >> l;
-  const int T = lay.T[l], logT = lay.logT[l], Ls = lay.Ls[l];
-  const int Mrows = L >> logT;
+// Integer correlation of one whole level (FP64 16x16x4 tiles, two row
+// tiles per wave sharing the weight operand).
+__device__ void correlate_level_int(const PlanDesc &plan, const LevelView &v, int *smi,
+                                    long long *__restrict__ outp) {
+  const int P = v.P, l = v.l, L = v.L, T = v.T, logT = v.logT, Ls = v.Ls;
+  const int Mrows = v.row_end;
   const int mtiles = (Mrows + 15) >> 4;
   const int mpairs = (mtiles + 1) >> 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  int2 *W = reinterpret_cast<int2 *>(smi + lay.w_at[l]);
-  const int V0 = lay.V[l][0], V1 = lay.V[l][1];
+  int2 *W = reinterpret_cast<int2 *>(smi + v.w_at);
+  const int V0 = v.V[0], V1 = v.V[1];
   const int row = lane & 15;
   const int kq = lane >> 4;
   const int du = kq >> 1;
@@ -389,9 +436,9 @@ __device__ void correlate_level_int(const PlanDesc &plan, const FusedLayout &lay
   const int co = lane & 1;
   const int cc = (lane & 15) >> 1;
   const bool neg = (ci == 0) && (co == 1);
-  for (int r0 = 0; r0 < P; r0 += lay.pc[l]) {
-    const int pcc = min(lay.pc[l], P - r0);
-    stage_weights(plan, lay, l, r0, pcc, W);
+  for (int r0 = 0; r0 < P; r0 += v.pc) {
+    const int pcc = min(v.pc, P - r0);
+    stage_weights(plan, v, r0, pcc, W);
     __syncthreads();
     const int ntn = (P < 8) ? 1 : (pcc >> 3);
     const int ntiles = mpairs * ntn;
@@ -416,10 +463,10 @@ __device__ void correlate_level_int(const PlanDesc &plan, const FusedLayout &lay
       f64x4 acc1 = {0, 0, 0, 0};
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        const int steps = lay.U[l][b] >> 1;
-        const int *pl = smi + lay.region_off[l] + b * lay.band_size[l] + ci * lay.plane_stride[l];
-        const int qa = pos_mod(p1a * T + lay.lo[l][b], L);
-        const int qb = pos_mod(p1b * T + lay.lo[l][b], L);
+        const int steps = v.U[b] >> 1;
+        const int *pl = smi + v.base[b] + ci * v.plane_stride;
+        const int qa = pos_mod(p1a * T + v.lo[b], L);
+        const int qb = pos_mod(p1b * T + v.lo[b], L);
         const int *wp = reinterpret_cast<const int *>(W + (b ? pcc * V0 : 0) + r * (b ? V1 : V0)) +
                         2 * (du - p0 + T - 1) + (ci ^ co);
         for (int st = 0; st < steps; ++st) {
@@ -487,22 +534,14 @@ __device__ __forceinline__ V load_elem(const S *sm, const FusedLayout &lay, int 
 // LDS regions so that c_l stays intact while level l+1 is written.
 // ===========================================================================
 template <int F>
-__global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, FusedLayout lay,
-                                                                const void *__restrict__ rx_all,
-                                                                long long n, long long rx_stride,
-                                                                void *__restrict__ out_all,
-                                                                long long out_stride) {
+__device__ void fused_pulse(const PlanDesc &plan, const FusedLayout &lay,
+                            const typename RxOf<F>::T *__restrict__ rx, long long n,
+                            typename RxOf<F>::Out *__restrict__ out, char *smem) {
   constexpr bool INT = (F == F_LEGALL53_INT);
   using V = typename ElemOf<F>::T;
   using S = typename std::conditional<INT, int, float>::type;
-  using RxT = typename RxOf<F>::T;
-  using OutT = typename RxOf<F>::Out;
   constexpr bool OB = YLift<F>::kOddBefore;
-  extern __shared__ __align__(16) char smem_fused[];
-  S *sm = reinterpret_cast<S *>(smem_fused);
-  const long long pulse = blockIdx.x;
-  const RxT *rx = reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride;
-  OutT *out = reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2;
+  S *sm = reinterpret_cast<S *>(smem);
   const int N = lay.N;
 
   // Level 1 straight from HBM (pairs split at load, zero padding n..N-1).
@@ -517,9 +556,9 @@ __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, 
 
   for (int l = 1; l <= lay.J; ++l) {
     if constexpr (INT) {
-      correlate_level_int(plan, lay, l, sm, out + 2LL * (l - 1) * N);
+      correlate_level_int(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N);
     } else {
-      correlate_level_f32(plan, lay, l, sm, out + 2LL * (l - 1) * N);
+      correlate_rows_f32(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N);
     }
     if (l < lay.J) {
       const int np = N >> (l + 1);
@@ -534,6 +573,154 @@ __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, 
     }
     __syncthreads();
   }
+}
+
+template <int F>
+__global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, FusedLayout lay,
+                                                                const void *__restrict__ rx_all,
+                                                                long long n, long long rx_stride,
+                                                                void *__restrict__ out_all,
+                                                                long long out_stride) {
+  using RxT = typename RxOf<F>::T;
+  using OutT = typename RxOf<F>::Out;
+  extern __shared__ __align__(16) char smem_fused[];
+  const long long pulse = blockIdx.x;
+  fused_pulse<F>(plan, lay, reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride, n,
+                 reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2, smem_fused);
+}
+
+// ===========================================================================
+// Uneven batches.  Long pulses are lifted level by level into an HBM
+// scratch pyramid (c_l then d_l for l = 1..J, 2N complex per pulse); one
+// persistent kernel then pulls work items from an atomic counter: whole
+// short pulses (fused path above) and lag tiles (rows of one level) of long
+// pulses, whose band windows are read from the scratch pyramid.
+// ===========================================================================
+
+template <int F>
+__device__ void lift_chunk(const BatchPulse &p, float2 *scratch, int l, int k0, int k1) {
+  constexpr bool OB = YLift<F>::kOddBefore;
+  const int N = p.N;
+  const int np = N >> l;
+  float2 *c = scratch + p.scratch + scratch_level_off(N, l);
+  float2 *d = c + np;
+  if (l == 1) {
+    const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
+    const long long n = p.n;
+    lift_level_range<F, 2>(
+        np, k0, k1,
+        [&](int kc, float2 &e, float2 &o) {
+          e = rx_sample(rx, n, 2 * kc);
+          o = rx_sample(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
+        },
+        [&](int k, float2 cv, float2 dv) {
+          c[k] = cv;
+          d[k] = dv;
+        });
+  } else {
+    const float2 *src = scratch + p.scratch + scratch_level_off(N, l - 1);
+    lift_level_range<F, 2>(
+        np, k0, k1, [&](int kc, float2 &e, float2 &o) { pair_at<OB>(src, kc, np, e, o); },
+        [&](int k, float2 cv, float2 dv) {
+          c[k] = cv;
+          d[k] = dv;
+        });
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_lift(const PlanDesc *__restrict__ plans,
+                                                  const BatchPulse *__restrict__ pulses,
+                                                  const LiftChunk *__restrict__ chunks, int l,
+                                                  float2 *__restrict__ scratch) {
+  const LiftChunk ch = chunks[blockIdx.x];
+  const BatchPulse &p = pulses[ch.pulse];
+  switch (plans[p.plan].filter) {
+    case F_LEGALL53: lift_chunk<F_LEGALL53>(p, scratch, l, ch.k0, ch.k1); break;
+    case F_CDF97: lift_chunk<F_CDF97>(p, scratch, l, ch.k0, ch.k1); break;
+    case F_D4: lift_chunk<F_D4>(p, scratch, l, ch.k0, ch.k1); break;
+    default: break;
+  }
+}
+
+// Lag tile of a long pulse: level l, rows [row0, row0 + rows).  `tl` is the
+// pulse's tile layout (per level: T, windows, staging geometry; bands start
+// at word 0, band 1 at 2*plane_stride, weights at w_at).
+__device__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const BatchPulse &p,
+                          const BatchItem &it, const float2 *__restrict__ scratch, float *smf) {
+  const int l = it.level;
+  LevelView v;
+  v.l = l;
+  v.P = 1 << l;
+  v.L = p.N >> l;
+  v.T = tl.T[l];
+  v.logT = tl.logT[l];
+  v.Ls = tl.Ls[l];
+  v.plane_stride = tl.plane_stride[l];
+  for (int b = 0; b < 2; ++b) {
+    v.base[b] = b * 2 * tl.plane_stride[l];
+    v.lo[b] = tl.lo[l][b];
+    v.U[b] = tl.U[l][b];
+    v.V[b] = tl.V[l][b];
+    v.F[b] = tl.F[l][b];
+  }
+  v.pc = tl.pc[l];
+  v.w_at = tl.w_at[l];
+  v.wrap = 0;
+  v.row_begin = it.row0;
+  v.row_end = min(it.row0 + it.rows, v.L >> v.logT);
+  // Band windows: element q of band b is c_l / d_l at (row0*T + lo + q) mod L,
+  // for q below (rows rounded up to 64)*T + U (the last row pair reads them).
+  const int rows64 = (it.rows + 63) & ~63;
+  const float2 *src0 = scratch + p.scratch + scratch_level_off(p.N, l);
+  for (int b = 0; b < 2; ++b) {
+    const float2 *src = src0 + (b ? v.L : 0);
+    const int Wb = rows64 * v.T + v.U[b];
+    const int e0 = it.row0 * v.T + v.lo[b];
+    float *pl = smf + v.base[b];
+    for (int q = threadIdx.x; q < Wb; q += blockDim.x) {
+      const float2 x = src[pos_mod(e0 + q, v.L)];
+      const int o = poly_off(q, v.logT, v.Ls);
+      pl[o] = x.x;
+      pl[o + v.plane_stride] = x.y;
+    }
+  }
+  __syncthreads();
+  correlate_rows_f32(plan, v, smf, reinterpret_cast<float *>(p.out) + 2LL * (l - 1) * p.N);
+}
+
+__global__ __launch_bounds__(kFusedThreads) void batch_persistent(
+    const PlanDesc *__restrict__ plans, const FusedLayout *__restrict__ lays,
+    const BatchPulse *__restrict__ pulses, const BatchItem *__restrict__ items, int nitems,
+    int *__restrict__ counter, const float2 *__restrict__ scratch) {
+  extern __shared__ __align__(16) char smem_batch[];
+  __shared__ int next;
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int i = next;
+    __syncthreads();
+    if (i >= nitems) break;  // the counter only grows: every workgroup exits
+    const BatchItem it = items[i];
+    const BatchPulse &p = pulses[it.pulse];
+    const PlanDesc &plan = plans[p.plan];
+    const FusedLayout &lay = lays[p.layout];
+    if (it.kind == 0) {
+      const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
+      float *out = reinterpret_cast<float *>(p.out);
+      switch (plan.filter) {
+        case F_LEGALL53: fused_pulse<F_LEGALL53>(plan, lay, rx, p.n, out, smem_batch); break;
+        case F_CDF97: fused_pulse<F_CDF97>(plan, lay, rx, p.n, out, smem_batch); break;
+        case F_D4: fused_pulse<F_D4>(plan, lay, rx, p.n, out, smem_batch); break;
+        default: break;
+      }
+    } else {
+      tile_item(plan, lay, p, it, scratch, reinterpret_cast<float *>(smem_batch));
+    }
+  }
+}
+
+__global__ void batch_reset(int *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
 // ===========================================================================
@@ -677,6 +864,37 @@ hipError_t launch_lift(int filter, int J, int N, const void *rx, long long n, lo
 #undef X
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t batch_set_lds(size_t bytes) {
+  return hipFuncSetAttribute((const void *)batch_persistent,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent,
+                                                      kFusedThreads, lds_bytes);
+}
+
+hipError_t launch_batch(const PlanDesc *plans, const FusedLayout *lays, const BatchPulse *pulses,
+                        const BatchItem *items, int nitems, int *counter, float2 *scratch,
+                        const LiftChunk *const *chunks, const int *nchunks, int Jmax, int grid,
+                        size_t lds_bytes, hipStream_t st) {
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, counter);
+  hipError_t e = hipGetLastError();
+  for (int l = 1; l <= Jmax && e == hipSuccess; ++l) {
+    if (nchunks[l] == 0) continue;
+    hipLaunchKernelGGL(batch_lift, dim3(nchunks[l]), dim3(256), 0, st, plans, pulses, chunks[l], l,
+                       scratch);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  if (nitems > 0) {
+    hipLaunchKernelGGL(batch_persistent, dim3(grid), dim3(kFusedThreads), lds_bytes, st, plans,
+                       lays, pulses, items, nitems, counter, scratch);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace sidwt

@@ -20,8 +20,23 @@ static int check(int filter, int J, int m, long long n, bool verbose, long long 
   const long long N = transform_length(n, J);
   if ((N >> J) < 2 || m > N) return 0;
   if (filter == F_LEGALL53_INT && !int_support_fits(d, N)) return 0;
+  int bad = 0;
+  if (filter != F_LEGALL53_INT) {
+    for (int rows : {32, 64, 100, 256, 512}) {
+      FusedLayout tl;
+      if (make_tile_layout(d, N, rows, &tl) != 0) continue;
+      const int v = tile_layout_violation(d, tl, rows);
+      if (v) {
+        std::printf("TILE VIOLATION %d: filter=%d J=%d m=%d n=%lld rows=%d\n", v, filter, J, m, n,
+                    rows);
+        bad = 1;
+      } else {
+        ++*n_ok;
+      }
+    }
+  }
   FusedLayout lay;
-  if (make_layout(d, N, &lay) != 0) return 0;  // handled elsewhere (unsupported)
+  if (make_layout(d, N, &lay) != 0) return bad;  // long pulse: tiles only
   const int v = layout_violation(d, lay);
   if (v) {
     std::printf("VIOLATION %d: filter=%d J=%d m=%d n=%lld\n", v, filter, J, m, n);
@@ -31,7 +46,7 @@ static int check(int filter, int J, int m, long long n, bool verbose, long long 
   if (verbose)
     std::printf("filter=%d J=%d m=%d n=%lld N=%lld: LDS %d bytes (%s per CU)\n", filter, J, m, n,
                 N, lay.total * 4, lay.total <= kLdsWordsTwoPerCu ? "2" : "1");
-  return 0;
+  return bad;
 }
 
 int main() {
@@ -49,7 +64,7 @@ int main() {
   for (int f : filters)
     for (int J = 1; J <= 13; ++J)
       for (int m : ms)
-        for (long long n = 2; n <= 40000; n = n * 5 / 4 + 7) bad += check(f, J, m, n, false, &ok);
+        for (long long n = 2; n <= 70000; n = n * 5 / 4 + 7) bad += check(f, J, m, n, false, &ok);
   std::printf("layouts checked: %lld, violations: %d\n", ok, bad);
   return bad ? 1 : 0;
 }

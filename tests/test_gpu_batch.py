@@ -1,0 +1,136 @@
+"""Uneven batches through the persistent kernel: parity with the oracle for
+whole-pulse and tiled pulses, agreement between work splits, graph replay."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0607001_amd as S
+    S._lib.lib()
+    return torch, S
+
+
+LENGTHS = [300, 517, 1500, 2100, 5000, 9000, 17000, 33000, 65536]
+
+
+def make_batch(S, torch, seed=41):
+    rng = np.random.default_rng(seed)
+    refs = W.reference_set(seed, count=5, m_lo=40, m_hi=600)
+    plans, rx, meta = [], [], []
+    cache = {}
+    for i, n in enumerate(LENGTHS):
+        J = W.levels_for(n)
+        filt = "d4" if i % 2 else "cdf97"
+        elig = [k for k, r in enumerate(refs) if len(r) <= n // 2]
+        k = elig[i % len(elig)]
+        key = (k, filt, J)
+        if key not in cache:
+            cache[key] = S.plan_create(filt, J, refs[k])
+        plans.append(cache[key])
+        y = W.echoes(n, refs[k], rng)
+        rx.append(torch.from_numpy(y.astype(np.complex64)).cuda())
+        meta.append((filt, J, refs[k], y))
+    return plans, rx, meta, cache
+
+
+def check_against_oracle(got, meta, full_max_N=2200, nlags=24):
+    rng = np.random.default_rng(5)
+    for o, (filt, J, ref, y) in zip(got, meta):
+        N = O.transform_length(len(y), J)
+        g = o.cpu().numpy().astype(np.complex128)
+        assert g.shape == (J, N)
+        if N <= full_max_N:
+            want = O.correlate_direct(filt, J, ref, y)
+            for j in range(J):
+                e = np.linalg.norm(g[j] - want[j]) / np.linalg.norm(want[j])
+                assert e <= 1e-5, (len(y), j, e)
+        else:
+            for j in range(J):
+                lags = np.concatenate([[0, N - 1], rng.integers(0, N, nlags)])
+                want = O.correlate_at(filt, J, ref, y, j, lags)
+                e = np.linalg.norm(g[j, lags] - want) / np.linalg.norm(want)
+                assert e <= 1e-5, (len(y), j, e)
+
+
+def test_uneven_batch_matches_oracle(dev):
+    torch, S = dev
+    plans, rx, meta, cache = make_batch(S, torch)
+    print("[case] uneven batch", LENGTHS, flush=True)
+    with S.Batch(plans, [x.numel() for x in rx]) as b:
+        b.config(4096, 128)
+        info = b.info()
+        assert info["whole_pulse_items"] > 0 and info["tile_items"] > 0
+        out = S.batch_outputs(plans, [x.numel() for x in rx], rx[0].device)
+        b.run(rx, out)
+        torch.cuda.synchronize()
+        check_against_oracle(out, meta)
+    for p in cache.values():
+        p.free()
+
+
+def test_work_splits_agree_and_graph_replays(dev):
+    torch, S = dev
+    plans, rx, meta, cache = make_batch(S, torch, seed=43)
+    ns = [x.numel() for x in rx]
+    results = []
+    with S.Batch(plans, ns) as b:
+        for fmax, rows in [(0, 64), (16384, 512), (4096, 256)]:
+            print(f"[case] split fused_max_N={fmax} tile_rows={rows}", flush=True)
+            b.config(fmax, rows)
+            out = S.batch_outputs(plans, ns, rx[0].device)
+            b.run(rx, out)
+            torch.cuda.synchronize()
+            results.append([o.clone() for o in out])
+            # replay of the captured graph gives the same bits
+            b.run(rx, out)
+            torch.cuda.synchronize()
+            for o, r in zip(out, results[-1]):
+                assert torch.equal(o, r)
+    for r in results[1:]:
+        for a, c in zip(results[0], r):
+            d = (a - c).abs().max().item()
+            assert d <= 1e-6 * max(1.0, a.abs().max().item()), d
+    one_shot = S.correlate_batch(plans, rx)
+    torch.cuda.synchronize()
+    for a, c in zip(results[0], one_shot):
+        assert (a - c).abs().max().item() <= 1e-6 * max(1.0, a.abs().max().item())
+    for p in cache.values():
+        p.free()
+
+
+def test_autotuner_picks_a_valid_split(dev):
+    torch, S = dev
+    plans, rx, meta, cache = make_batch(S, torch, seed=47)
+    ns = [x.numel() for x in rx]
+    with S.Batch(plans, ns) as b:
+        out = S.batch_outputs(plans, ns, rx[0].device)
+        info = b.tune(rx, out)
+        print("[case] tuned", info, flush=True)
+        assert info["tuned"] == 1 and info["tuned_us"] > 0
+        assert info["tile_rows"] in (64, 128, 256, 512)
+        assert info["fused_max_N"] in (0, 4096, 8192, 16384)
+        b.run(rx, out)
+        torch.cuda.synchronize()
+        check_against_oracle(out, meta, full_max_N=600, nlags=8)
+    for p in cache.values():
+        p.free()
+
+
+def test_batch_rejects_integer_plans(dev):
+    torch, S = dev
+    ref = np.ones((16, 2), np.int16)
+    with S.plan_create("legall53_int", 3, ref) as p:
+        with pytest.raises(S.SidwtError) as e:
+            S.Batch([p], [256])
+        assert e.value.code == -5

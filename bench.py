@@ -123,20 +123,32 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run an elementwise kernel that reads and writes 256 MiB "
                          "(calibrates the HBM byte counters)")
+    ap.add_argument("--workload", default="batched_uniform",
+                    choices=["batched_uniform", "uneven", "integer", "single", "serving"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(pulses are independent; see DESIGN.md for how the work would shard).",
+        print("bench.py measures one GPU only: there is no multi-GPU path in this library "
+              "(pulses are independent; a multi-GPU run would shard the pulse list).",
               file=sys.stderr)
         sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    fn = {"batched_uniform": bench_batched_uniform, "uneven": bench_uneven,
+          "integer": bench_integer, "single": bench_single}.get(args.workload)
+    if fn is None:
+        from bench_serving import bench_serving  # noqa: E402
+        fn = bench_serving
+    rec = fn(args)
+    print(json.dumps(rec), flush=True)
 
+
+def bench_batched_uniform(args):
     import numpy as np
     import torch
 
     import paper_cs_0607001_amd as S
     import workloads as W
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     J, m = 5, 512
     log(f"generating {args.count} x {args.n} pulses")
@@ -239,8 +251,249 @@ def main():
                              "us_per_launch": lift_ms * 1e3, "kernel": "lift_many<CDF97>"},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(rec), flush=True)
     plan.free()
+    return rec
+
+
+# ---------------------------------------------------------------------------
+# Other workloads (not the default line)
+# ---------------------------------------------------------------------------
+
+def _time_steps(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _oracle_lag_sample(args):
+    """CPU time of the oracle on `k` lags per plane of one pulse, scaled to
+    all N lags (the direct form costs the same per lag)."""
+    filt, J, ref, rx, k = args
+    import numpy as np
+    import oracle
+    N = oracle.transform_length(len(rx), J)
+    lags = np.linspace(0, N - 1, k).astype(np.int64)
+    t0 = time.perf_counter()
+    for j in range(J):
+        oracle.correlate_at(filt, J, ref, rx, j, lags)
+    return (time.perf_counter() - t0) * N / k
+
+
+def cpu_baseline_lags(items, k=64, max_workers=32):
+    """items: list of (filter, J, ref, rx); returns samples/s over the pool."""
+    import multiprocessing as mp
+    os.environ["OMP_NUM_THREADS"] = "1"
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(cores, max_workers, len(items)))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_warm, range(workers))
+        secs = pool.map(_oracle_lag_sample, [it + (k,) for it in items])
+    samples = sum(len(it[3]) for it in items)
+    # work spread over `workers` processes
+    return samples / (sum(secs) / workers), workers, cores
+
+
+def pulse_flops(plan_desc_lens, N):
+    return 8 * N * sum(plan_desc_lens)
+
+
+def plan_lens(S, plan):
+    import ctypes
+    lens = []
+    for lvl in range(1, plan.J + 1):
+        for band in (0, 1):
+            lo, ln = ctypes.c_int32(), ctypes.c_int32()
+            S._lib.check(S._lib.lib().sidwt_plan_phase(plan.handle, lvl, band, 0, ctypes.byref(lo),
+                                                       ctypes.byref(ln), None))
+            lens.append(ln.value)
+    return lens
+
+
+def bench_uneven(args):
+    """10^4 pulses, lengths log-uniform in [512, 65536], 16 references
+    (LFM / Barker-13 / polyphase, 64..2048 samples), D4 and 9/7 mixed,
+    J = floor(log2(n/16)); one persistent launch per step from a HIP graph,
+    split chosen by the autotuner."""
+    import numpy as np
+    import torch
+
+    import paper_cs_0607001_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    count = 10000 if args.count == 4096 else args.count
+    log(f"generating {count} uneven pulses")
+    refs, reqs = W.uneven_batch(seed=4, count=count)
+    ns = [r.n for r in reqs]
+    total = sum(ns)
+    flat = np.empty(total, np.complex64)
+    offs = np.cumsum([0] + ns)
+    for r, o in zip(reqs, offs):
+        flat[o:o + r.n] = r.rx
+    rx_all = torch.from_numpy(flat).to(dev)
+    rx = [rx_all[o:o + n] for o, n in zip(offs, ns)]
+    plans, cache, flops = [], {}, 0
+    for r in reqs:
+        key = (r.ref_index, r.filter, r.J)
+        if key not in cache:
+            p = S.plan_create(r.filter, r.J, refs[r.ref_index])
+            cache[key] = (p, plan_lens(S, p))
+        plans.append(cache[key][0])
+        flops += pulse_flops(cache[key][1], S.transform_length(r.n, r.J))
+    out_sizes = [p.J * S.transform_length(n, p.J) for p, n in zip(plans, ns)]
+    out_all = torch.empty(sum(out_sizes), dtype=torch.complex64, device=dev)
+    oo = np.cumsum([0] + out_sizes)
+    out = [out_all[o:o + sz].view(p.J, -1) for o, sz, p in zip(oo, out_sizes, plans)]
+    log(f"{count} pulses, {total / 1e6:.1f} M samples, {len(cache)} plans, "
+        f"{out_all.numel() * 8 / 1e9:.1f} GB of planes")
+    stream = torch.cuda.current_stream()
+    b = S.Batch(plans, ns)
+    info = b.tune(rx, out)
+    log(f"autotuned: {info}")
+    ms = _time_steps(lambda: b.run(rx, out), args.steps, args.warmup, stream)
+    value = total / (ms * 1e-3)
+    tflops = flops / (ms * 1e-3) / 1e12
+    log(f"uneven: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s")
+    cpu = None
+    if args.cpu:
+        idx = np.argsort(ns)[np.linspace(0, count - 1, 32).astype(int)]
+        items = [(reqs[i].filter, reqs[i].J, refs[reqs[i].ref_index], reqs[i].rx) for i in idx]
+        v, workers, cores = cpu_baseline_lags(items)
+        cpu = {"value": v, "unit": "complex samples/s", "cores": workers, "kind": "oracle",
+               "sample": f"32 pulses stratified by length, 64 lags per plane each, oracle time "
+                         f"scaled to all N lags; host has {cores} cores"}
+    b.free()
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT correlate",
+        "value": value, "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"uneven batch: {count} pulses, n log-uniform in [512, 65536], "
+                               f"16 references 64..2048, D4 / CDF 9/7, J=floor(log2(n/16)), "
+                               f"one persistent graph-replayed launch", "samples": total,
+                   "batch": info},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
+                     "kernel": "batch_persistent"},
+        "cpu_baseline": cpu,
+    }
+
+
+def bench_integer(args):
+    """16384 x 4096 int16 I/Q pulses, reversible 5/3, J = 6, exact int64
+    planes (FP64 MFMA accumulation of integer products)."""
+    import numpy as np
+    import torch
+
+    import paper_cs_0607001_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    count = 16384 if args.count == 4096 else args.count
+    n, J = 4096, 6
+    log(f"generating {count} x {n} int16 pulses")
+    ib = W.integer_batch(seed=3, count=count, n=n, m=512, J=J)
+    rx = torch.from_numpy(ib.rx_iq).to(dev)
+    plan = S.plan_create("legall53_int", J, ib.ref_iq)
+    out = torch.empty((count, J, n, 2), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    ms = _time_steps(lambda: S.correlate_many(plan, rx, out=out), args.steps, args.warmup, stream)
+    flops = pulse_flops(plan_lens(S, plan), n) * count
+    value = count * n / (ms * 1e-3)
+    tflops = flops / (ms * 1e-3) / 1e12
+    log(f"integer: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s (FP64 MFMA)")
+    cpu = None
+    if args.cpu:
+        items = [("legall53_int", J, ib.ref_iq, ib.rx_iq[i]) for i in range(16)]
+        v, workers, cores = cpu_baseline_lags_int(items)
+        cpu = {"value": v, "unit": "complex samples/s", "cores": workers, "kind": "oracle",
+               "sample": f"16 pulses, 64 lags per plane each, int64 oracle time scaled to all "
+                         f"N lags; host has {cores} cores"}
+    plan.free()
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT correlate",
+        "value": value, "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32 lifting, int64 planes", "data": "synthetic",
+        "config": {"workload": f"integer: {count} x {n} int16 I/Q, reversible 5/3, J={J}, "
+                               f"bit-exact int64 planes"},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": 78.6, "unit": "TFLOP/s",
+                     "frac": tflops / 78.6, "traffic": None, "kernel": "fused_correlate<INT53>"},
+        "cpu_baseline": cpu,
+    }
+
+
+def _oracle_lag_sample_int(args):
+    filt, J, ref, rx, k = args
+    import numpy as np
+    import oracle
+    N = oracle.transform_length(len(rx), J)
+    lags = np.linspace(0, N - 1, k).astype(np.int64)
+    t0 = time.perf_counter()
+    for j in range(J):
+        oracle.correlate_int_at(J, ref, rx, j, lags)
+    return (time.perf_counter() - t0) * N / k
+
+
+def cpu_baseline_lags_int(items, k=64, max_workers=32):
+    import multiprocessing as mp
+    os.environ["OMP_NUM_THREADS"] = "1"
+    cores = len(os.sched_getaffinity(0))
+    workers = max(1, min(cores, max_workers, len(items)))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        pool.map(_warm, range(workers))
+        secs = pool.map(_oracle_lag_sample_int, [it + (k,) for it in items])
+    samples = sum(len(it[3]) for it in items)
+    return samples / (sum(secs) / workers), workers, cores
+
+
+def bench_single(args):
+    """One 1024-sample pulse per request (5/3, J = 3): per-request latency
+    (launch to completion, host clock) over seeded requests."""
+    import numpy as np
+    import torch
+
+    import paper_cs_0607001_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    reqs = [W.single_chirp(seed=s) for s in range(1, 1001)]
+    rx = [torch.from_numpy(w.rx.astype(np.complex64)).to(dev) for w in reqs]
+    plan = S.plan_create("legall53", 3, reqs[0].ref)
+    out = torch.empty((3, 1024), dtype=torch.complex64, device=dev)
+    for x in rx[:50]:
+        S.correlate(plan, x, out=out)
+    torch.cuda.synchronize()
+    lat = []
+    for x in rx:
+        t0 = time.perf_counter()
+        S.correlate(plan, x, out=out)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat)
+    p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+    plan.free()
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT correlate; p50/p99 request latency",
+        "value": 1024 / p50, "unit": "complex samples/s", "n_gpus": 1, "steps": len(lat),
+        "warmup": 50, "ms_per_step": p50 * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "single correlation: 1024-sample pulse, 256-sample chirp "
+                               "(TBP 64), 10 dB, 5/3, J=3, one request at a time",
+                   "p50_us": p50 * 1e6, "p99_us": p99 * 1e6},
+        "roofline": None, "cpu_baseline": None,
+    }
 
 
 if __name__ == "__main__":

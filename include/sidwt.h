@@ -160,17 +160,18 @@ int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int cou
  * device pointers, read during the call. */
 int sidwt_batch_run(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream);
 
-/* Autotuner: times candidate (fused_max_N, tile_rows) pairs by running the
+/* Autotuner: times candidate (fused_max_N, tile_window) pairs by running the
  * batch on these buffers (events on `hip_stream`), keeps the fastest.  The
  * outputs hold a valid result afterwards.  Synchronous. */
 int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream);
 
 /* Set the split explicitly: pulses with N <= fused_max_N run whole in LDS
- * (when their layout fits); tiles of long pulses span tile_rows lag blocks
- * (32..4096).  Synchronous. */
-int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_rows);
+ * (when their layout fits); a tile of a long pulse's level covers as many
+ * lag-block rows (a multiple of 64, at least 64) as keep its band window
+ * near tile_window elements (64..32768).  Synchronous. */
+int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_window);
 
-/* values[0..nvalues): fused_max_N, tile_rows, items, whole-pulse items,
+/* values[0..nvalues): fused_max_N, tile_window, items, whole-pulse items,
  * tile items, LDS bytes per workgroup, persistent grid size, scratch
  * bytes, tuned (0/1), best tuned time in microseconds. */
 int sidwt_batch_info(const sidwt_batch *b, int64_t *values, int nvalues);

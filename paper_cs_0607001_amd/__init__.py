@@ -189,7 +189,7 @@ def version() -> str:
 # Uneven batches
 # ---------------------------------------------------------------------------
 
-BATCH_INFO_KEYS = ("fused_max_N", "tile_rows", "items", "whole_pulse_items", "tile_items",
+BATCH_INFO_KEYS = ("fused_max_N", "tile_window", "items", "whole_pulse_items", "tile_items",
                    "lds_bytes", "grid", "scratch_bytes", "tuned", "tuned_us")
 
 
@@ -249,8 +249,8 @@ class Batch:
         check(lib().sidwt_batch_tune(self.handle, a, b, _stream_ptr(stream)), "sidwt_batch_tune")
         return self.info()
 
-    def config(self, fused_max_N: int, tile_rows: int):
-        check(lib().sidwt_batch_config(self.handle, fused_max_N, tile_rows), "sidwt_batch_config")
+    def config(self, fused_max_N: int, tile_window: int):
+        check(lib().sidwt_batch_config(self.handle, fused_max_N, tile_window), "sidwt_batch_config")
 
     def info(self) -> dict:
         v = (ctypes.c_int64 * len(BATCH_INFO_KEYS))()

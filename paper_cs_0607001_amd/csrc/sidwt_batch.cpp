@@ -6,16 +6,19 @@
 //     layout fits) become one "whole pulse" work item each (lifting and all
 //     planes in LDS);
 //   - long pulses are lifted level by level into an HBM scratch pyramid and
-//     split into lag tiles (rows of one level) of `tile_rows` lag blocks;
+//     split into lag tiles (rows of one level) whose band windows hold about
+//     `tile_window` elements;
 //   - items are ordered by estimated cost, largest first, and pulled by a
 //     persistent kernel from an atomic counter.
 // The launch sequence (counter reset, per-level lifting, persistent kernel)
 // is captured once in a HIP graph and replayed; each run only uploads the
 // caller's pulse and output pointers.  sidwt_batch_tune times candidate
-// (fused_max_N, tile_rows) pairs on the caller's buffers and keeps the best.
+// (fused_max_N, tile_window) pairs on the caller's buffers and keeps the best.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -45,8 +48,10 @@ namespace {
 
 constexpr int kLiftChunkPairs = 4096;
 
-int map_err(hipError_t e) {
+int map_err(hipError_t e, const char *what = nullptr) {
   if (e == hipSuccess) return SIDWT_OK;
+  if (what && std::getenv("SIDWT_DEBUG"))
+    std::fprintf(stderr, "sidwt batch: %s: %s\n", what, hipGetErrorString(e));
   if (e == hipErrorOutOfMemory) return SIDWT_E_NOMEM;
   return SIDWT_E_DEVICE;
 }
@@ -59,12 +64,12 @@ int upload(T **dptr, size_t *cap, const std::vector<T> &v) {
     *dptr = nullptr;
     *cap = 0;
     hipError_t e = hipMalloc(dptr, need * sizeof(T));
-    if (e != hipSuccess) return map_err(e);
+    if (e != hipSuccess) return map_err(e, "hipMalloc (descriptors)");
     *cap = need;
   }
   if (!v.empty()) {
     hipError_t e = hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-    if (e != hipSuccess) return map_err(e);
+    if (e != hipSuccess) return map_err(e, "hipMemcpy (descriptors)");
   }
   return SIDWT_OK;
 }
@@ -79,7 +84,7 @@ struct sidwt_batch {
   std::vector<int> J;
   // configuration
   int fused_max_N = 8192;
-  int tile_rows = 256;
+  int tile_window = 3072;       // band-window budget of a tile, elements
   int tuned = 0;
   double tuned_us = 0;
   // derived
@@ -162,7 +167,7 @@ int build(sidwt_batch *b) {
     auto key = std::make_tuple(pi, N, kind);
     auto itl = lay_index.find(key);
     if (itl == lay_index.end()) {
-      if (!fused && make_tile_layout(d, N, b->tile_rows, &lay) != 0) return SIDWT_E_UNSUPPORTED;
+      if (!fused && make_tile_layout(d, N, b->tile_window, &lay) != 0) return SIDWT_E_UNSUPPORTED;
       lay_index[key] = (int)b->lays.size();
       b->lays.push_back(lay);
       lds_words = std::max<size_t>(lds_words, lay.total);
@@ -181,13 +186,13 @@ int build(sidwt_batch *b) {
       scratch += 2 * N;
       for (int l = 1; l <= d.J; ++l) {
         const int rows_l = (int)((N >> l) / L.T[l]);
-        for (int r0 = 0; r0 < rows_l; r0 += b->tile_rows) {
+        for (int r0 = 0; r0 < rows_l; r0 += L.rows[l]) {
           BatchItem it{};
           it.kind = 1;
           it.pulse = i;
           it.level = l;
           it.row0 = r0;
-          it.rows = std::min(b->tile_rows, rows_l - r0);
+          it.rows = std::min(L.rows[l], rows_l - r0);
           costed.push_back({item_cost(d, it, (int)N, L), it});
           ++b->n_tiles;
         }
@@ -222,16 +227,16 @@ int build(sidwt_batch *b) {
     b->d_scratch = nullptr;
     b->scratch_cap = 0;
     hipError_t e = hipMalloc(&b->d_scratch, (size_t)std::max<long long>(1, scratch) * sizeof(float2));
-    if (e != hipSuccess) return map_err(e);
+    if (e != hipSuccess) return map_err(e, "hipMalloc (scratch)");
     b->scratch_cap = std::max<long long>(1, scratch);
   }
   hipError_t e = batch_set_lds(b->lds_bytes);
-  if (e != hipSuccess) return map_err(e);
+  if (e != hipSuccess) return map_err(e, "hipFuncSetAttribute (LDS)");
   int per_cu = 0, cus = 0, dev = 0;
   e = batch_occupancy(b->lds_bytes, &per_cu);
   if (e == hipSuccess) e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return map_err(e);
+  if (e != hipSuccess) return map_err(e, "occupancy query");
   if (per_cu < 1) return SIDWT_E_UNSUPPORTED;
   b->grid = std::max(1, std::min<int>(per_cu * cus, (int)b->items.size()));
   return SIDWT_OK;
@@ -242,7 +247,8 @@ int enqueue(sidwt_batch *b, hipStream_t st) {
   for (int l = 0; l <= kMaxLevels + 1; ++l) chunk_ptr[l] = b->d_chunks + b->chunk_off[l];
   return map_err(launch_batch(b->d_plans, b->d_lays, b->d_pulses, b->d_items, (int)b->items.size(),
                               b->d_counter, b->d_scratch, chunk_ptr, b->nchunks, b->Jmax, b->grid,
-                              b->lds_bytes, st));
+                              b->lds_bytes, st),
+                 "kernel launch");
 }
 
 int ensure_graph(sidwt_batch *b) {
@@ -252,7 +258,7 @@ int ensure_graph(sidwt_batch *b) {
     if (e != hipSuccess) return map_err(e);
   }
   hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return map_err(e);
+  if (e != hipSuccess) return map_err(e, "hipStreamBeginCapture");
   int rc = enqueue(b, b->cap_stream);
   hipGraph_t g = nullptr;
   e = hipStreamEndCapture(b->cap_stream, &g);
@@ -260,12 +266,12 @@ int ensure_graph(sidwt_batch *b) {
     if (g) (void)hipGraphDestroy(g);
     return rc;
   }
-  if (e != hipSuccess) return map_err(e);
+  if (e != hipSuccess) return map_err(e, "hipStreamEndCapture");
   b->graph = g;
   e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     drop_graph(b);
-    return map_err(e);
+    return map_err(e, "hipGraphInstantiate");
   }
   return SIDWT_OK;
 }
@@ -278,7 +284,8 @@ int set_pointers(sidwt_batch *b, const void *const *rx, void *const *out, hipStr
   }
   // pageable source: the runtime stages it before returning
   return map_err(hipMemcpyAsync(b->d_pulses, b->pulses.data(), b->pulses.size() * sizeof(BatchPulse),
-                                hipMemcpyHostToDevice, st));
+                                hipMemcpyHostToDevice, st),
+                 "hipMemcpyAsync (pointers)");
 }
 
 int run(sidwt_batch *b, const void *const *rx, void *const *out, hipStream_t st, bool use_graph) {
@@ -287,7 +294,7 @@ int run(sidwt_batch *b, const void *const *rx, void *const *out, hipStream_t st,
   if (!use_graph) return enqueue(b, st);
   rc = ensure_graph(b);
   if (rc) return rc;
-  return map_err(hipGraphLaunch(b->exec, st));
+  return map_err(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
 }
 
 }  // namespace
@@ -356,11 +363,11 @@ void sidwt_batch_free(sidwt_batch *b) {
   delete b;
 }
 
-int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_rows) {
-  if (!b || fused_max_N < 0 || tile_rows < 32 || tile_rows > 4096) return SIDWT_E_INVAL;
+int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_window) {
+  if (!b || fused_max_N < 0 || tile_window < 64 || tile_window > 32768) return SIDWT_E_INVAL;
   (void)hipDeviceSynchronize();
   b->fused_max_N = (int)std::min<int64_t>(fused_max_N, 1 << 20);
-  b->tile_rows = tile_rows;
+  b->tile_window = tile_window;
   return build(b);
 }
 
@@ -378,9 +385,9 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
     (void)hipEventDestroy(e0);
     return SIDWT_E_DEVICE;
   }
-  auto time_cfg = [&](int fmax, int rows, double *us) -> int {
+  auto time_cfg = [&](int fmax, int window, double *us) -> int {
     b->fused_max_N = fmax;
-    b->tile_rows = rows;
+    b->tile_window = window;
     int rc = build(b);
     if (rc) return rc;
     rc = run(b, rx, out, st, true);  // warm-up (also builds the graph)
@@ -388,30 +395,31 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
     if (hipEventRecord(e0, st) != hipSuccess) return SIDWT_E_DEVICE;
     for (int k = 0; k < 2 && !rc; ++k) rc = run(b, rx, out, st, true);
     if (rc) return rc;
-    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-      return SIDWT_E_DEVICE;
+    hipError_t er = hipEventRecord(e1, st);
+    if (er == hipSuccess) er = hipEventSynchronize(e1);
+    if (er != hipSuccess) return map_err(er, "tuning run");
     float ms = 0;
     if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return SIDWT_E_DEVICE;
     *us = 1e3 * ms / 2;
     return SIDWT_OK;
   };
-  // Tile size first (with the default split), then the fused/tiled split.
-  const int rows_c[] = {64, 128, 256, 512};
-  const int fmax_c[] = {0, 4096, 8192, 16384};
-  int best_rows = b->tile_rows, best_fmax = b->fused_max_N;
+  // Tile window first (with the default split), then the fused/tiled split.
+  const int win_c[] = {1024, 2048, 3072, 4096, 6144};
+  const int fmax_c[] = {0, 2048, 4096, 8192, 16384};
+  int best_win = b->tile_window, best_fmax = b->fused_max_N;
   double best = 1e300;
   int rc = SIDWT_OK;
-  for (int rows : rows_c) {
+  for (int win : win_c) {
     double us;
-    int r = time_cfg(8192, rows, &us);
+    int r = time_cfg(4096, win, &us);
     if (r == SIDWT_E_UNSUPPORTED) continue;
     if (r) { rc = r; break; }
-    if (us < best) { best = us; best_rows = rows; best_fmax = 8192; }
+    if (us < best) { best = us; best_win = win; best_fmax = 4096; }
   }
   for (int fmax : fmax_c) {
-    if (rc || fmax == 8192) continue;
+    if (rc || fmax == 4096) continue;
     double us;
-    int r = time_cfg(fmax, best_rows, &us);
+    int r = time_cfg(fmax, best_win, &us);
     if (r == SIDWT_E_UNSUPPORTED) continue;
     if (r) { rc = r; break; }
     if (us < best) { best = us; best_fmax = fmax; }
@@ -420,7 +428,7 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   b->fused_max_N = best_fmax;
-  b->tile_rows = best_rows;
+  b->tile_window = best_win;
   b->tuned = 1;
   b->tuned_us = best;
   return build(b);
@@ -428,7 +436,7 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
 
 int sidwt_batch_info(const sidwt_batch *b, int64_t *v, int nv) {
   if (!b || !v || nv < 1) return SIDWT_E_INVAL;
-  const int64_t vals[] = {b->fused_max_N, b->tile_rows, (int64_t)b->items.size(), b->n_fused,
+  const int64_t vals[] = {b->fused_max_N, b->tile_window, (int64_t)b->items.size(), b->n_fused,
                           b->n_tiles, (int64_t)b->lds_bytes, b->grid,
                           b->scratch_elems * (int64_t)sizeof(float2), b->tuned,
                           (int64_t)(b->tuned_us + 0.5)};

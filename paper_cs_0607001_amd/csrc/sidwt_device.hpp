@@ -68,6 +68,7 @@ struct FusedLayout {
   int U[kMaxLevels + 1][2];          // lag-window length (GEMM K per re/im)
   int V[kMaxLevels + 1][2];          // staged weight row length (complex)
   int pc[kMaxLevels + 1];            // phases staged per chunk
+  int rows[kMaxLevels + 1];          // tile layouts: lag-block rows per tile
   int w_at[kMaxLevels + 1];          // weight staging area of level l (outside
                                      // the level's bands; 16-byte aligned)
   int w_off;                         // end of the band regions

@@ -14,7 +14,9 @@ namespace host {
 
 constexpr int64_t kMaxRef = 8192;              // longest reference (tree kernel LDS)
 constexpr int64_t kMaxN = int64_t(1) << 30;     // longest circular length
-constexpr int kLdsWords = 160 * 1024 / 4;       // LDS per workgroup (gfx950)
+// LDS per workgroup on gfx950 is 160 KB; 256 bytes stay free for the
+// kernels' static shared variables.
+constexpr int kLdsWords = (160 * 1024 - 256) / 4;
 constexpr int kLdsWordsTwoPerCu = 80 * 1024 / 4; // two workgroups per CU
 
 inline bool is_int_filter(int f) { return f == F_LEGALL53_INT; }
@@ -198,13 +200,14 @@ inline void level_geometry(const PlanDesc &d, int N, int l, bool is_int, FusedLa
   }
 }
 
-// Tile layout of a long pulse (float filters): for each level, LDS holds a
-// window of `rows` lag-block rows (rounded up to 64) of both bands as
-// polyphase re/im planes (band 0 at word 0, band 1 at 2*plane_stride) and the
-// staged weights at w_at.  Returns 0 or -5.
-inline int make_tile_layout(const PlanDesc &d, int64_t N64, int rows, FusedLayout *lay) {
+// Tile layout of a long pulse (float filters).  A tile of level l covers
+// rows[l] lag-block rows (a multiple of 64), chosen so that its band window
+// rows*T + U stays near `window` elements (at least 64 rows); LDS holds the
+// window of both bands as polyphase re/im planes (band 0 at word 0, band 1
+// at 2*plane_stride) and the staged weights at w_at.  Returns 0 or -5.
+inline int make_tile_layout(const PlanDesc &d, int64_t N64, int window, FusedLayout *lay) {
   std::memset(lay, 0, sizeof(*lay));
-  if (is_int_filter(d.filter) || rows < 1 || N64 > (int64_t(1) << 28)) return -5;
+  if (is_int_filter(d.filter) || window < 1 || N64 > (int64_t(1) << 28)) return -5;
   const int N = (int)N64, J = d.J, ncol = tile_cols(false);
   lay->N = N;
   lay->J = J;
@@ -212,9 +215,18 @@ inline int make_tile_layout(const PlanDesc &d, int64_t N64, int rows, FusedLayou
   for (int l = 1; l <= J; ++l) {
     level_geometry(d, N, l, false, lay);
     const int P = 1 << l, L = N >> l, T = lay->T[l];
-    const int rows_l = std::min(rows, L / T);
-    const int rows64 = (rows_l + 63) & ~63;
-    const int W = rows64 * T + std::max(lay->U[l][0], lay->U[l][1]);
+    const int Umax = std::max(lay->U[l][0], lay->U[l][1]);
+    const int rows_total = L / T;
+    // With fewer than 16 phases a level has one column tile, so its rows are
+    // the only parallel axis: keep them a multiple of 512 (one 64-row pair
+    // per wave of a 512-thread workgroup).  Otherwise column tiles of 16
+    // phases spread the work and 64-row granularity suffices.
+    const int gran = P < ncol ? 512 : 64;
+    int rows = ((window - Umax) / T) / gran * gran;
+    rows = std::max(gran, rows);
+    rows = std::min(rows, (rows_total + 63) & ~63);
+    lay->rows[l] = rows;
+    const int W = rows * T + Umax;
     lay->ext[l] = W;
     lay->Ls[l] = (W + T - 1) / T;
     lay->plane_stride[l] = ((T * lay->Ls[l] + 63) / 64) * 64 + 32;
@@ -237,16 +249,16 @@ inline int make_tile_layout(const PlanDesc &d, int64_t N64, int rows, FusedLayou
 }
 
 // Audit of a tile layout against the ranges tile items touch.
-inline int tile_layout_violation(const PlanDesc &d, const FusedLayout &lay, int rows) {
+inline int tile_layout_violation(const PlanDesc &d, const FusedLayout &lay) {
   const int N = lay.N;
   for (int l = 1; l <= lay.J; ++l) {
     const int L = N >> l, T = lay.T[l], P = 1 << l;
     if (T < 1 || (1 << lay.logT[l]) != T || L % T) return 21;
-    const int rows_l = std::min(rows, L / T);
-    const int rows64 = (rows_l + 63) & ~63;
+    const int rows = lay.rows[l];
+    if (rows < 64 || (rows & 63)) return 30;
     for (int b = 0; b < 2; ++b) {
-      // window elements q < rows64*T + U (the last row pair of a tile reads them)
-      if ((rows64 * T + lay.U[l][b] + T - 1) / T > lay.Ls[l]) return 22;
+      // window elements q < rows*T + U (the last row pair of a tile reads them)
+      if ((rows * T + lay.U[l][b] + T - 1) / T > lay.Ls[l]) return 22;
       if (lay.U[l][b] + T - 2 >= lay.V[l][b]) return 23;
       if (lay.U[l][b] < d.lv[l].len[b] + lay.F[l][b]) return 24;
     }

@@ -669,19 +669,23 @@ __device__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const Bat
   v.row_begin = it.row0;
   v.row_end = min(it.row0 + it.rows, v.L >> v.logT);
   // Band windows: element q of band b is c_l / d_l at (row0*T + lo + q) mod L,
-  // for q below (rows rounded up to 64)*T + U (the last row pair reads them).
+  // for q below (rows rounded up to 64)*T + U (the last row pair reads them;
+  // rows never exceeds the layout's tile rows, a multiple of 64).
   const int rows64 = (it.rows + 63) & ~63;
   const float2 *src0 = scratch + p.scratch + scratch_level_off(p.N, l);
   for (int b = 0; b < 2; ++b) {
     const float2 *src = src0 + (b ? v.L : 0);
     const int Wb = rows64 * v.T + v.U[b];
-    const int e0 = it.row0 * v.T + v.lo[b];
     float *pl = smf + v.base[b];
+    int e = pos_mod(it.row0 * v.T + v.lo[b] + (int)threadIdx.x, v.L);
+    const int step = pos_mod((int)blockDim.x, v.L);
     for (int q = threadIdx.x; q < Wb; q += blockDim.x) {
-      const float2 x = src[pos_mod(e0 + q, v.L)];
+      const float2 x = src[e];
       const int o = poly_off(q, v.logT, v.Ls);
       pl[o] = x.x;
       pl[o + v.plane_stride] = x.y;
+      e += step;
+      if (e >= v.L) e -= v.L;
     }
   }
   __syncthreads();

@@ -22,13 +22,13 @@ static int check(int filter, int J, int m, long long n, bool verbose, long long 
   if (filter == F_LEGALL53_INT && !int_support_fits(d, N)) return 0;
   int bad = 0;
   if (filter != F_LEGALL53_INT) {
-    for (int rows : {32, 64, 100, 256, 512}) {
+    for (int window : {100, 1024, 2048, 3072, 4096, 8192}) {
       FusedLayout tl;
-      if (make_tile_layout(d, N, rows, &tl) != 0) continue;
-      const int v = tile_layout_violation(d, tl, rows);
+      if (make_tile_layout(d, N, window, &tl) != 0) continue;
+      const int v = tile_layout_violation(d, tl);
       if (v) {
-        std::printf("TILE VIOLATION %d: filter=%d J=%d m=%d n=%lld rows=%d\n", v, filter, J, m, n,
-                    rows);
+        std::printf("TILE VIOLATION %d: filter=%d J=%d m=%d n=%lld window=%d\n", v, filter, J, m,
+                    n, window);
         bad = 1;
       } else {
         ++*n_ok;

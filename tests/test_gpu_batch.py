@@ -68,7 +68,7 @@ def test_uneven_batch_matches_oracle(dev):
     plans, rx, meta, cache = make_batch(S, torch)
     print("[case] uneven batch", LENGTHS, flush=True)
     with S.Batch(plans, [x.numel() for x in rx]) as b:
-        b.config(4096, 128)
+        b.config(4096, 1024)
         info = b.info()
         assert info["whole_pulse_items"] > 0 and info["tile_items"] > 0
         out = S.batch_outputs(plans, [x.numel() for x in rx], rx[0].device)
@@ -85,8 +85,8 @@ def test_work_splits_agree_and_graph_replays(dev):
     ns = [x.numel() for x in rx]
     results = []
     with S.Batch(plans, ns) as b:
-        for fmax, rows in [(0, 64), (16384, 512), (4096, 256)]:
-            print(f"[case] split fused_max_N={fmax} tile_rows={rows}", flush=True)
+        for fmax, rows in [(0, 512), (16384, 6144), (4096, 2048)]:
+            print(f"[case] split fused_max_N={fmax} tile_window={rows}", flush=True)
             b.config(fmax, rows)
             out = S.batch_outputs(plans, ns, rx[0].device)
             b.run(rx, out)
@@ -118,8 +118,8 @@ def test_autotuner_picks_a_valid_split(dev):
         info = b.tune(rx, out)
         print("[case] tuned", info, flush=True)
         assert info["tuned"] == 1 and info["tuned_us"] > 0
-        assert info["tile_rows"] in (64, 128, 256, 512)
-        assert info["fused_max_N"] in (0, 4096, 8192, 16384)
+        assert info["tile_window"] in (1024, 2048, 3072, 4096, 6144)
+        assert info["fused_max_N"] in (0, 2048, 4096, 8192, 16384)
         b.run(rx, out)
         torch.cuda.synchronize()
         check_against_oracle(out, meta, full_max_N=600, nlags=8)

@@ -185,6 +185,53 @@ int sidwt_correlate_batch(const sidwt_plan *const *plans,
                           const void *const *rx, const int64_t *n,
                           void *const *out, int count, void *hip_stream);
 
+/* ---- Reference banks (16-bit MFMA with hi+lo correction) -----------------
+ * A bank holds `count` references of one float filter, in ascending length
+ * m[0] <= m[1] <= ..., each with a phase pyramid of Jmax levels.  For a pulse
+ * of n samples the eligible references are those with m <= n (a prefix).
+ * One request computes, for every eligible reference e, the same planes as
+ * sidwt_correlate with that reference's plan: out = E x J x N complex64
+ * (reference-major, then plane, then lag).  The dense step (eq. (20)/(20a)
+ * for all references at once, a GEMM whose data operand is shared) runs on
+ * v_mfma_f32_32x32x16_{f16,bf16}: every operand x is split into
+ * hi = h(x s), lo = h(x s - hi) with power-of-two scales s and a product is
+ * accumulated in FP32 as hi*hi + hi*lo + lo*hi.  Relative error against the
+ * exact planes: about 1e-6 (FP16) or 1e-5 (BF16) per plane.
+ * Calls on one bank reuse its device descriptors and scratch: issue them on
+ * one stream (or synchronise in between). */
+typedef struct sidwt_bank sidwt_bank;
+
+enum { SIDWT_BANK_FP16 = 1, SIDWT_BANK_BF16 = 2 };
+
+/* refs[e]: host complex64 arrays of m[e] samples (ascending m).  Builds one
+ * plan per reference and the split weights; synchronous.
+ * SIDWT_E_UNSUPPORTED for the integer filter; SIDWT_E_INVAL if m is not
+ * ascending. */
+int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64_t *m,
+                      int count, int precision, sidwt_bank **out);
+
+/* `count` requests: rx[i] (device, n[i] complex64), J[i] <= Jmax scales,
+ * out[i] (device, sidwt_bank_out_len(bank, n[i], J[i]) complex64).  All
+ * requests go through one lifting pass and one GEMM launch on `hip_stream`. */
+int sidwt_bank_correlate(sidwt_bank *bank, const void *const *rx, const int64_t *n,
+                         const int *J, void *const *out, int count, void *hip_stream);
+
+/* Eligible references for a pulse of n samples (-1 on bad arguments). */
+int64_t sidwt_bank_eligible(const sidwt_bank *bank, int64_t n);
+
+/* Output elements for one request: eligible(n) * J * N (-1 on bad arguments). */
+int64_t sidwt_bank_out_len(const sidwt_bank *bank, int64_t n, int J);
+
+/* The bank's FP32 plan of reference e (owned by the bank; Jmax levels). */
+const sidwt_plan *sidwt_bank_plan(const sidwt_bank *bank, int e);
+
+/* values[0..nvalues): references, Jmax, precision, weight bytes, longest
+ * padded lag window. */
+int sidwt_bank_info(const sidwt_bank *bank, int64_t *values, int nvalues);
+
+/* NULL is a no-op; waits for the device to be idle. */
+void sidwt_bank_free(sidwt_bank *bank);
+
 /* Introspection for tests: copy phase r of band b (0 = approximation,
  * 1 = detail) at level l (1..J) to host memory.  Writes *lo (first index of
  * the stored linear support) and *len; dst must hold *len elements of the

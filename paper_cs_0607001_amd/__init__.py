@@ -21,8 +21,8 @@ import numpy as np
 from ._lib import FILTERS, SidwtError, check, lib  # noqa: F401
 
 __all__ = ["Plan", "plan_create", "correlate", "correlate_many", "lift_many", "out_len",
-           "transform_length", "plan_phase", "Batch", "correlate_batch", "SidwtError",
-           "FILTERS", "version"]
+           "transform_length", "plan_phase", "Batch", "correlate_batch", "Bank",
+           "SidwtError", "FILTERS", "version"]
 
 
 def transform_length(n: int, J: int) -> int:
@@ -44,8 +44,18 @@ def _stream_ptr(stream=None):
 class Plan:
     """Owns a sidwt_plan (device phase pyramid of one reference)."""
 
+    @classmethod
+    def borrowed(cls, handle, filt: str, J: int, m: int):
+        """A view of a plan owned by someone else (freeing it is a no-op)."""
+        p = cls.__new__(cls)
+        p.filter, p.J, p.m, p._ref = filt, J, m, None
+        p._h = ctypes.c_void_p(handle)
+        p._borrowed = True
+        return p
+
     def __init__(self, filt: str, J: int, ref):
         _torch()
+        self._borrowed = False
         self.filter = filt
         self.J = J
         if filt not in FILTERS:
@@ -76,7 +86,8 @@ class Plan:
 
     def free(self):
         if getattr(self, "_h", None) is not None:
-            lib().sidwt_free(self._h)
+            if not getattr(self, "_borrowed", False):
+                lib().sidwt_free(self._h)
             self._h = None
 
     def __enter__(self):
@@ -286,3 +297,89 @@ def correlate_batch(plans, rx, out=None, stream=None):
                                       _ptr_array([o.data_ptr() for o in out]), len(ns),
                                       _stream_ptr(stream)), "sidwt_correlate_batch")
     return out
+
+
+# ---------------------------------------------------------------------------
+# Reference banks (16-bit MFMA, hi+lo correction)
+# ---------------------------------------------------------------------------
+
+BANK_PRECISION = {"fp16": 1, "bf16": 2}
+BANK_INFO_KEYS = ("references", "Jmax", "precision", "weight_bytes", "max_window")
+
+
+class Bank:
+    """Owns a sidwt_bank: references of ascending length, one float filter."""
+
+    def __init__(self, filt: str, Jmax: int, refs, precision: str = "fp16"):
+        _torch()
+        if filt not in FILTERS or precision not in BANK_PRECISION:
+            raise ValueError("unknown filter or precision")
+        self.filter, self.Jmax, self.precision = filt, Jmax, precision
+        self._refs = [np.ascontiguousarray(np.asarray(r, np.complex64).reshape(-1)) for r in refs]
+        self.m = [len(r) for r in self._refs]
+        ptrs = _ptr_array([r.ctypes.data for r in self._refs])
+        ms = (ctypes.c_int64 * len(self.m))(*self.m)
+        h = ctypes.c_void_p()
+        check(lib().sidwt_bank_create(FILTERS[filt], Jmax, ptrs, ms, len(self.m),
+                                      BANK_PRECISION[precision], ctypes.byref(h)),
+              "sidwt_bank_create")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("bank already freed")
+        return self._h
+
+    def eligible(self, n: int) -> int:
+        return lib().sidwt_bank_eligible(self.handle, n)
+
+    def out_shape(self, n: int, J: int):
+        return (self.eligible(n), J, transform_length(n, J))
+
+    def plan(self, e: int) -> Plan:
+        """The bank's FP32 plan of reference e (borrowed)."""
+        h = lib().sidwt_bank_plan(self.handle, e)
+        if not h:
+            raise IndexError(e)
+        return Plan.borrowed(h, self.filter, self.Jmax, self.m[e])
+
+    def correlate(self, rx, J, out=None, stream=None):
+        """rx: list of complex64 device pulses; J: list of scale counts.
+        Returns a list of (E_i, J_i, N_i) complex64 tensors."""
+        torch = _torch()
+        ns = [int(x.numel()) for x in rx]
+        if out is None:
+            out = [torch.empty(self.out_shape(n, j), dtype=torch.complex64, device=x.device)
+                   for x, n, j in zip(rx, ns, J)]
+        for x in rx:
+            if not x.is_cuda or x.dtype != torch.complex64 or not x.is_contiguous():
+                raise ValueError("pulses must be contiguous complex64 device tensors")
+        n_arr = (ctypes.c_int64 * len(ns))(*ns)
+        j_arr = (ctypes.c_int32 * len(ns))(*[int(j) for j in J])
+        check(lib().sidwt_bank_correlate(self.handle, _ptr_array([x.data_ptr() for x in rx]), n_arr,
+                                         j_arr, _ptr_array([o.data_ptr() for o in out]), len(ns),
+                                         _stream_ptr(stream)), "sidwt_bank_correlate")
+        return out
+
+    def info(self) -> dict:
+        v = (ctypes.c_int64 * len(BANK_INFO_KEYS))()
+        check(lib().sidwt_bank_info(self.handle, v, len(BANK_INFO_KEYS)), "sidwt_bank_info")
+        return dict(zip(BANK_INFO_KEYS, list(v)))
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sidwt_bank_free(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

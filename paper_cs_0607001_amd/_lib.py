@@ -71,6 +71,20 @@ def _declare(L):
     L.sidwt_batch_info.restype = i32
     L.sidwt_batch_free.argtypes = [vp]
     L.sidwt_batch_free.restype = None
+    L.sidwt_bank_create.argtypes = [i32, i32, pp, c.POINTER(i64), i32, i32, pp]
+    L.sidwt_bank_create.restype = i32
+    L.sidwt_bank_correlate.argtypes = [vp, pp, c.POINTER(i64), c.POINTER(i32), pp, i32, vp]
+    L.sidwt_bank_correlate.restype = i32
+    L.sidwt_bank_eligible.argtypes = [vp, i64]
+    L.sidwt_bank_eligible.restype = i64
+    L.sidwt_bank_out_len.argtypes = [vp, i64, i32]
+    L.sidwt_bank_out_len.restype = i64
+    L.sidwt_bank_plan.argtypes = [vp, i32]
+    L.sidwt_bank_plan.restype = vp
+    L.sidwt_bank_info.argtypes = [vp, c.POINTER(i64), i32]
+    L.sidwt_bank_info.restype = i32
+    L.sidwt_bank_free.argtypes = [vp]
+    L.sidwt_bank_free.restype = None
     return L
 
 

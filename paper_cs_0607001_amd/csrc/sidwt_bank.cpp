@@ -1,0 +1,371 @@
+// Reference banks (C ABI part of libsidwt; declarations in include/sidwt.h).
+//
+// A bank holds E references (ascending length) of one float filter with a
+// phase pyramid of Jmax levels each.  At creation every stored phase
+// coefficient w of reference e and level l is scaled by a power of two s
+// (the largest |w| of that reference and level maps below 2^14) and split
+// into 16-bit hi = h(w s) and lo = h(w s - hi), in two column variants
+// (re-out: (w.re, w.im), im-out: (-w.im, w.re)) so the MFMA weight operand
+// needs no sign handling.  A request lifts its pulse into an HBM scratch
+// pyramid and runs one GEMM work item per (level, 256 lags, 64
+// reference-phase pairs).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sidwt.h"
+#include "sidwt_host.hpp"
+
+namespace sidwt {
+hipError_t launch_bank(bool bf16, const BankReq *reqs, const BankItem *items, int nitems,
+                       const BankRefLevel *rl, int Jmax, const int *lo_lb, const unsigned *wts,
+                       const float2 *scratch, int Wmax, hipStream_t st);
+hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
+                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
+                              float2 *scratch, hipStream_t st);
+}  // namespace sidwt
+
+extern "C++" const sidwt::PlanDesc *sidwt_plan_desc(const sidwt_plan *p);
+
+using namespace sidwt;
+using namespace sidwt::host;
+
+namespace {
+
+constexpr int kRows = 256, kPairs = 64, kChunk = 4096;
+
+int map_err(hipError_t e, const char *what = nullptr) {
+  if (e == hipSuccess) return SIDWT_OK;
+  if (what && std::getenv("SIDWT_DEBUG"))
+    std::fprintf(stderr, "sidwt bank: %s: %s\n", what, hipGetErrorString(e));
+  if (e == hipErrorOutOfMemory) return SIDWT_E_NOMEM;
+  return SIDWT_E_DEVICE;
+}
+
+// 16-bit encodings (round to nearest even).
+unsigned short to_f16(float x) {
+  _Float16 h = (_Float16)x;
+  unsigned short u;
+  std::memcpy(&u, &h, 2);
+  return u;
+}
+float from_f16(unsigned short u) {
+  _Float16 h;
+  std::memcpy(&h, &u, 2);
+  return (float)h;
+}
+unsigned short to_bf16(float x) {
+  unsigned u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)(u >> 16);  // inf / nan
+  const unsigned rounding = 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)((u + rounding) >> 16);
+}
+float from_bf16(unsigned short h) {
+  unsigned u = (unsigned)h << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+template <class T>
+int grow(T **p, size_t *cap, size_t need) {
+  need = std::max<size_t>(need, 1);
+  if (*cap >= need) return SIDWT_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  *cap = 0;
+  hipError_t e = hipMalloc(p, need * sizeof(T));
+  if (e != hipSuccess) return map_err(e, "hipMalloc");
+  *cap = need;
+  return SIDWT_OK;
+}
+
+}  // namespace
+
+struct sidwt_bank {
+  int filter = 0, Jmax = 0, E = 0, precision = 1;
+  std::vector<int64_t> m;
+  std::vector<sidwt_plan *> plans;   // one per reference (FP32 path, tests)
+  PlanDesc desc0;                    // windows are shared by all references
+  std::vector<BankRefLevel> rl;      // [e * (Jmax + 1) + l]
+  std::vector<int> lo_lb;            // [2 l + b]
+  int Umax = 0;
+  long long weight_words = 0;
+  // device
+  unsigned *d_w = nullptr;
+  BankRefLevel *d_rl = nullptr;
+  int *d_lo = nullptr;
+  PlanDesc *d_plan = nullptr;
+  // per-call buffers (calls on one bank are stream-ordered by the caller)
+  BankReq *d_reqs = nullptr;
+  size_t c_reqs = 0;
+  BankItem *d_items = nullptr;
+  size_t c_items = 0;
+  BatchPulse *d_pulses = nullptr;
+  size_t c_pulses = 0;
+  LiftChunk *d_chunks = nullptr;
+  size_t c_chunks = 0;
+  float2 *d_scratch = nullptr;
+  size_t c_scratch = 0;
+};
+
+extern "C" {
+
+int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64_t *m, int count,
+                      int precision, sidwt_bank **out) {
+  if (!refs || !m || !out || count < 1 || Jmax < 1 || Jmax > SIDWT_MAX_LEVELS ||
+      (precision != SIDWT_BANK_FP16 && precision != SIDWT_BANK_BF16))
+    return SIDWT_E_INVAL;
+  if (filter != SIDWT_LEGALL53 && filter != SIDWT_CDF97 && filter != SIDWT_D4_CAUSAL)
+    return filter == SIDWT_LEGALL53_INT ? SIDWT_E_UNSUPPORTED : SIDWT_E_INVAL;
+  for (int e = 0; e < count; ++e) {
+    if (!refs[e] || m[e] < 1) return SIDWT_E_INVAL;
+    if (e > 0 && m[e] < m[e - 1]) return SIDWT_E_INVAL;  // ascending length
+  }
+  sidwt_bank *bk = new (std::nothrow) sidwt_bank();
+  if (!bk) return SIDWT_E_NOMEM;
+  bk->filter = filter;
+  bk->Jmax = Jmax;
+  bk->E = count;
+  bk->precision = precision;
+  const bool bf16 = precision == SIDWT_BANK_BF16;
+  int rc = SIDWT_OK;
+  std::vector<unsigned> words;
+  bk->rl.assign((size_t)count * (Jmax + 1), BankRefLevel{});
+  for (int e = 0; e < count && !rc; ++e) {
+    sidwt_plan *p = nullptr;
+    rc = sidwt_plan_create(filter, Jmax, refs[e], m[e], &p);
+    if (rc) break;
+    bk->plans.push_back(p);
+    bk->m.push_back(m[e]);
+    const PlanDesc &d = *sidwt_plan_desc(p);
+    if (e == 0) bk->desc0 = d;
+    long long total = 0;
+    for (int l = 1; l <= Jmax; ++l) total += ((long long)d.lv[l].len[0] + d.lv[l].len[1]) << l;
+    std::vector<float> coef(2 * (size_t)total);
+    hipError_t he = hipMemcpy(coef.data(), d.coef, coef.size() * 4, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) { rc = map_err(he, "hipMemcpy (phases)"); break; }
+    for (int l = 1; l <= Jmax; ++l) {
+      float mx = 0.f;
+      for (int b = 0; b < 2; ++b) {
+        const size_t o = 2 * (size_t)d.lv[l].off[b], cnt = 2 * ((size_t)d.lv[l].len[b] << l);
+        for (size_t i = 0; i < cnt; ++i) mx = std::max(mx, std::fabs(coef[o + i]));
+      }
+      int ex = 0;
+      std::frexp(mx, &ex);
+      const float s = mx > 0.f ? std::ldexp(1.f, 14 - ex) : 1.f;
+      BankRefLevel &R = bk->rl[(size_t)e * (Jmax + 1) + l];
+      R.inv_scale = 1.f / s;
+      for (int b = 0; b < 2; ++b) {
+        const int len = d.lv[l].len[b];
+        const int U = (len + 7) & ~7;
+        R.U[b] = U;
+        R.off[b] = (long long)words.size();
+        bk->Umax = std::max(bk->Umax, U);
+        for (int r = 0; r < (1 << l); ++r) {
+          unsigned arr[4];
+          const size_t base = words.size();
+          words.resize(base + 4 * (size_t)U, 0u);
+          for (int u = 0; u < len; ++u) {
+            const size_t c = 2 * ((size_t)d.lv[l].off[b] + (size_t)r * len + u);
+            const float wr = coef[c] * s, wi = coef[c + 1] * s;
+            // column variants: re-out (wr, wi), im-out (-wi, wr); hi then lo
+            const float v[2][2] = {{wr, wi}, {-wi, wr}};
+            for (int co = 0; co < 2; ++co) {
+              unsigned short h0, h1, l0, l1;
+              if (bf16) {
+                h0 = to_bf16(v[co][0]);
+                h1 = to_bf16(v[co][1]);
+                l0 = to_bf16(v[co][0] - from_bf16(h0));
+                l1 = to_bf16(v[co][1] - from_bf16(h1));
+              } else {
+                h0 = to_f16(v[co][0]);
+                h1 = to_f16(v[co][1]);
+                l0 = to_f16(v[co][0] - from_f16(h0));
+                l1 = to_f16(v[co][1] - from_f16(h1));
+              }
+              arr[co] = (unsigned)h0 | ((unsigned)h1 << 16);
+              arr[2 + co] = (unsigned)l0 | ((unsigned)l1 << 16);
+            }
+            for (int a = 0; a < 4; ++a) words[base + (size_t)a * U + u] = arr[a];
+          }
+        }
+      }
+    }
+  }
+  if (!rc) {
+    bk->lo_lb.assign(2 * (Jmax + 1), 0);
+    for (int l = 1; l <= Jmax; ++l)
+      for (int b = 0; b < 2; ++b) bk->lo_lb[2 * l + b] = bk->desc0.lv[l].lo[b];
+    bk->weight_words = (long long)words.size();
+    hipError_t he = hipMalloc(&bk->d_w, std::max<size_t>(1, words.size()) * 4);
+    if (he == hipSuccess && !words.empty())
+      he = hipMemcpy(bk->d_w, words.data(), words.size() * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMalloc(&bk->d_rl, bk->rl.size() * sizeof(BankRefLevel));
+    if (he == hipSuccess)
+      he = hipMemcpy(bk->d_rl, bk->rl.data(), bk->rl.size() * sizeof(BankRefLevel),
+                     hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMalloc(&bk->d_lo, bk->lo_lb.size() * sizeof(int));
+    if (he == hipSuccess)
+      he = hipMemcpy(bk->d_lo, bk->lo_lb.data(), bk->lo_lb.size() * sizeof(int),
+                     hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMalloc(&bk->d_plan, sizeof(PlanDesc));
+    if (he == hipSuccess)
+      he = hipMemcpy(bk->d_plan, &bk->desc0, sizeof(PlanDesc), hipMemcpyHostToDevice);
+    rc = map_err(he, "bank upload");
+  }
+  if (rc) {
+    sidwt_bank_free(bk);
+    return rc;
+  }
+  *out = bk;
+  return SIDWT_OK;
+}
+
+void sidwt_bank_free(sidwt_bank *bk) {
+  if (!bk) return;
+  (void)hipDeviceSynchronize();
+  for (sidwt_plan *p : bk->plans) sidwt_free(p);
+  (void)hipFree(bk->d_w);
+  (void)hipFree(bk->d_rl);
+  (void)hipFree(bk->d_lo);
+  (void)hipFree(bk->d_plan);
+  (void)hipFree(bk->d_reqs);
+  (void)hipFree(bk->d_items);
+  (void)hipFree(bk->d_pulses);
+  (void)hipFree(bk->d_chunks);
+  (void)hipFree(bk->d_scratch);
+  delete bk;
+}
+
+int64_t sidwt_bank_eligible(const sidwt_bank *bk, int64_t n) {
+  if (!bk || n < 1) return -1;
+  return (int64_t)(std::upper_bound(bk->m.begin(), bk->m.end(), n) - bk->m.begin());
+}
+
+int64_t sidwt_bank_out_len(const sidwt_bank *bk, int64_t n, int J) {
+  if (!bk || n < 1 || J < 1 || J > bk->Jmax) return -1;
+  return sidwt_bank_eligible(bk, n) * J * transform_length(n, J);
+}
+
+const sidwt_plan *sidwt_bank_plan(const sidwt_bank *bk, int e) {
+  if (!bk || e < 0 || e >= bk->E) return nullptr;
+  return bk->plans[e];
+}
+
+int sidwt_bank_info(const sidwt_bank *bk, int64_t *v, int nv) {
+  if (!bk || !v || nv < 1) return SIDWT_E_INVAL;
+  const int64_t vals[] = {bk->E, bk->Jmax, bk->precision, bk->weight_words * 4, bk->Umax};
+  const int k = (int)(sizeof(vals) / sizeof(vals[0]));
+  for (int i = 0; i < nv; ++i) v[i] = i < k ? vals[i] : 0;
+  return SIDWT_OK;
+}
+
+int sidwt_bank_correlate(sidwt_bank *bk, const void *const *rx, const int64_t *n, const int *J,
+                         void *const *out, int count, void *hip_stream) {
+  if (!bk || !rx || !n || !J || !out || count < 1) return SIDWT_E_INVAL;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  std::vector<BankReq> reqs(count);
+  std::vector<BatchPulse> pulses(count);
+  std::vector<BankItem> items;
+  std::vector<std::vector<LiftChunk>> per_level(kMaxLevels + 1);
+  long long scratch = 0;
+  int Jmax = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!rx[i] || !out[i] || n[i] < 1 || J[i] < 1 || J[i] > bk->Jmax) return SIDWT_E_INVAL;
+    const int64_t N = transform_length(n[i], J[i]);
+    if ((N >> J[i]) < 2) return SIDWT_E_INVAL;
+    if (N > (int64_t(1) << 26)) return SIDWT_E_SIZE;
+    const int E = (int)sidwt_bank_eligible(bk, n[i]);
+    BankReq &q = reqs[i];
+    q.rx = rx[i];
+    q.out = out[i];
+    q.n = n[i];
+    q.N = (int)N;
+    q.J = J[i];
+    q.E = E;
+    q.scratch = scratch;
+    BatchPulse &p = pulses[i];
+    p = BatchPulse{};
+    p.rx = rx[i];
+    p.n = n[i];
+    p.N = (int)N;
+    p.J = J[i];
+    p.plan = 0;
+    p.scratch = scratch;
+    scratch += 2 * N;
+    Jmax = std::max(Jmax, J[i]);
+    if (E == 0) continue;
+    for (int l = 1; l <= J[i]; ++l) {
+      const int L = (int)(N >> l), P = 1 << l;
+      for (int k0 = 0; k0 < L; k0 += kChunk)
+        per_level[l].push_back(LiftChunk{i, k0, std::min(L, k0 + kChunk), 0});
+      const int pairs = E * P;
+      for (int c0 = 0; c0 < pairs; c0 += kPairs) {
+        BankItem it{};
+        it.req = i;
+        it.level = l;
+        it.pair0 = c0;
+        it.npairs = std::min(kPairs, pairs - c0);
+        const int e_lo = c0 >> l, e_hi = (c0 + it.npairs - 1) >> l;
+        for (int b = 0; b < 2; ++b) {
+          int U = 0;
+          for (int e = e_lo; e <= e_hi; ++e)
+            U = std::max(U, bk->rl[(size_t)e * (bk->Jmax + 1) + l].U[b]);
+          it.U[b] = U;
+        }
+        for (int r0 = 0; r0 < L; r0 += kRows) {
+          it.row0 = r0;
+          it.rows = std::min(kRows, L - r0);
+          items.push_back(it);
+        }
+      }
+    }
+  }
+  // Largest windows first (they take longest).
+  std::stable_sort(items.begin(), items.end(), [](const BankItem &a, const BankItem &b) {
+    return (long long)(a.U[0] + a.U[1]) * a.rows > (long long)(b.U[0] + b.U[1]) * b.rows;
+  });
+  std::vector<LiftChunk> chunks;
+  int off[kMaxLevels + 2] = {0}, nch[kMaxLevels + 2] = {0};
+  for (int l = 1; l <= kMaxLevels; ++l) {
+    off[l] = (int)chunks.size();
+    nch[l] = (int)per_level[l].size();
+    chunks.insert(chunks.end(), per_level[l].begin(), per_level[l].end());
+  }
+  int rc = grow(&bk->d_reqs, &bk->c_reqs, reqs.size());
+  if (!rc) rc = grow(&bk->d_items, &bk->c_items, items.size());
+  if (!rc) rc = grow(&bk->d_pulses, &bk->c_pulses, pulses.size());
+  if (!rc) rc = grow(&bk->d_chunks, &bk->c_chunks, chunks.size());
+  if (!rc) rc = grow(&bk->d_scratch, &bk->c_scratch, (size_t)scratch);
+  if (rc) return rc;
+  // pageable sources: the runtime stages them before returning
+  hipError_t e = hipMemcpyAsync(bk->d_reqs, reqs.data(), reqs.size() * sizeof(BankReq),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !items.empty())
+    e = hipMemcpyAsync(bk->d_items, items.data(), items.size() * sizeof(BankItem),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(bk->d_pulses, pulses.data(), pulses.size() * sizeof(BatchPulse),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !chunks.empty())
+    e = hipMemcpyAsync(bk->d_chunks, chunks.data(), chunks.size() * sizeof(LiftChunk),
+                       hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return map_err(e, "descriptor upload");
+  const LiftChunk *cp[kMaxLevels + 2];
+  for (int l = 0; l <= kMaxLevels + 1; ++l) cp[l] = bk->d_chunks + off[l];
+  e = launch_lift_levels(bk->d_plan, bk->d_pulses, cp, nch, Jmax, bk->d_scratch, st);
+  if (e != hipSuccess) return map_err(e, "lifting");
+  e = launch_bank(bk->precision == SIDWT_BANK_BF16, bk->d_reqs, bk->d_items, (int)items.size(),
+                  bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w, bk->d_scratch, kRows + bk->Umax, st);
+  return map_err(e, "bank kernel");
+}
+
+}  // extern "C"

@@ -104,6 +104,31 @@ __host__ __device__ inline long long scratch_level_off(int N, int l) {
   return 2LL * N - 4LL * (N >> l);
 }
 
+// Reference-bank descriptors.
+struct BankReq {
+  const void *rx;       // caller's pulse (complex64), n samples
+  void *out;            // caller's output, E x J x N complex64
+  long long n;
+  long long scratch;    // complex offset of the pulse's pyramid in scratch
+  int N, J, E, pad_;    // E: eligible references (the first E of the bank)
+};
+
+struct BankItem {
+  int req, level;
+  int row0, rows;       // lags [row0, row0 + rows) of every phase (rows <= 256)
+  int pair0, npairs;    // (reference, phase) pairs e*P + r, npairs <= 64
+  int U[2];             // lag-window length per band (max over the pairs' references)
+};
+
+// Per (reference e, level l): where its split weights start (in 4-byte
+// units, per band), the padded window per band and 1 / weight scale.
+struct BankRefLevel {
+  long long off[2];
+  int U[2];
+  float inv_scale;
+  int pad_;
+};
+
 // ---------------------------------------------------------------------------
 // Table I (t = 5/4) and the causal D4 constants of eq. (17).
 // ---------------------------------------------------------------------------

@@ -901,4 +901,17 @@ hipError_t launch_batch(const PlanDesc *plans, const FusedLayout *lays, const Ba
   return e;
 }
 
+hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
+                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
+                              float2 *scratch, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int l = 1; l <= Jmax && e == hipSuccess; ++l) {
+    if (nchunks[l] == 0) continue;
+    hipLaunchKernelGGL(batch_lift, dim3(nchunks[l]), dim3(256), 0, st, plans, pulses, chunks[l], l,
+                       scratch);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
 }  // namespace sidwt

@@ -1,0 +1,101 @@
+"""Reference bank on 16-bit MFMA with hi+lo correction: every eligible
+reference's planes against the oracle (and the FP32 plain path)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# relative L2 error per plane against the FP64 oracle
+TOL = {"fp16": 1e-5, "bf16": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0607001_amd as S
+    S._lib.lib()
+    return torch, S
+
+
+def bank_refs(seed=7, count=6):
+    return W.reference_set(seed, count=count, m_lo=24, m_hi=400)
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+@pytest.mark.parametrize("filt", ["cdf97", "d4"])
+def test_bank_matches_oracle(dev, filt, precision):
+    torch, S = dev
+    refs = bank_refs()
+    rng = np.random.default_rng(3)
+    Jmax = 10
+    print(f"[case] bank {filt} {precision} m={[len(r) for r in refs]}", flush=True)
+    with S.Bank(filt, Jmax, refs, precision) as bank:
+        ns = [200, 700, 3000, 16000]
+        Js = [W.levels_for(n) for n in ns]
+        ys = [W.echoes(n, refs[-1] if len(refs[-1]) <= n else refs[0], rng) for n in ns]
+        rx = [torch.from_numpy(y.astype(np.complex64)).cuda() for y in ys]
+        out = bank.correlate(rx, Js)
+        torch.cuda.synchronize()
+        worst = 0.0
+        for y, J, o in zip(ys, Js, out):
+            E = bank.eligible(len(y))
+            assert o.shape[0] == E == sum(len(r) <= len(y) for r in refs)
+            g = o.cpu().numpy().astype(np.complex128)
+            N = O.transform_length(len(y), J)
+            for e in range(E):
+                if N <= 1024:
+                    want = O.correlate_direct(filt, J, refs[e], y)
+                    lags = np.arange(N)
+                else:
+                    lags = np.concatenate([[0, N - 1], rng.integers(0, N, 30)])
+                    want = np.stack([O.correlate_at(filt, J, refs[e], y, j, lags)
+                                     for j in range(J)])
+                for j in range(J):
+                    err = np.linalg.norm(g[e, j, lags] - want[j]) / np.linalg.norm(want[j])
+                    worst = max(worst, err)
+                    assert err <= TOL[precision], (len(y), e, j, err)
+        print(f"[case] worst rel L2 {worst:.2e}", flush=True)
+
+
+def test_bank_equals_fp32_path_within_tolerance(dev):
+    torch, S = dev
+    refs = bank_refs(seed=9, count=4)
+    rng = np.random.default_rng(4)
+    with S.Bank("cdf97", 8, refs, "fp16") as bank:
+        n = 2048
+        J = 7
+        y = W.echoes(n, refs[1], rng)
+        x = torch.from_numpy(y.astype(np.complex64)).cuda()
+        out = bank.correlate([x], [J])[0]
+        torch.cuda.synchronize()
+        for e in range(bank.eligible(n)):
+            p = bank.plan(e)
+            # the bank plan has Jmax levels; the FP32 path with J levels uses
+            # the same phases of levels 1..J
+            ref32 = S.correlate(S.plan_create("cdf97", J, refs[e]), x)
+            torch.cuda.synchronize()
+            a = out[e].cpu().numpy()
+            b = ref32.cpu().numpy()
+            for j in range(J):
+                err = np.linalg.norm(a[j] - b[j]) / np.linalg.norm(b[j])
+                assert err <= 1e-5, (e, j, err)
+            p.free()
+
+
+def test_bank_argument_checks(dev):
+    torch, S = dev
+    refs = bank_refs(count=3)
+    with pytest.raises(S.SidwtError):
+        S.Bank("cdf97", 6, refs[::-1])          # not ascending
+    with pytest.raises(S.SidwtError):
+        S.Bank("legall53_int", 6, refs)         # integer filter
+    with S.Bank("d4", 6, refs) as bank:
+        assert bank.eligible(1) == 0
+        assert bank.eligible(10 ** 6) == 3
+        with pytest.raises(S.SidwtError):
+            bank.correlate([torch.zeros(64, dtype=torch.complex64, device="cuda")], [7])  # J > Jmax

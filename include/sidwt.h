@@ -197,8 +197,8 @@ int sidwt_correlate_batch(const sidwt_plan *const *plans,
  * hi = h(x s), lo = h(x s - hi) with power-of-two scales s and a product is
  * accumulated in FP32 as hi*hi + hi*lo + lo*hi.  Relative error against the
  * exact planes: about 1e-6 (FP16) or 1e-5 (BF16) per plane.
- * Calls on one bank reuse its device descriptors and scratch: issue them on
- * one stream (or synchronise in between). */
+ * Calls through one workspace (below) reuse its device descriptors and
+ * scratch: issue them on one stream (or synchronise in between). */
 typedef struct sidwt_bank sidwt_bank;
 
 enum { SIDWT_BANK_FP16 = 1, SIDWT_BANK_BF16 = 2 };
@@ -215,6 +215,22 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
  * requests go through one lifting pass and one GEMM launch on `hip_stream`. */
 int sidwt_bank_correlate(sidwt_bank *bank, const void *const *rx, const int64_t *n,
                          const int *J, void *const *out, int count, void *hip_stream);
+
+/* Workspaces: the device buffers of one call in flight (descriptors and the
+ * scratch pyramids, grown on demand and kept).  sidwt_bank_correlate uses
+ * the bank's own workspace; callers that overlap requests on several
+ * streams give each stream its own workspace.  A workspace must not be used
+ * by two calls that can run at the same time. */
+typedef struct sidwt_bank_ws sidwt_bank_ws;
+int sidwt_bank_ws_create(const sidwt_bank *bank, sidwt_bank_ws **out);
+void sidwt_bank_ws_free(sidwt_bank_ws *ws);   /* NULL is a no-op; waits for the device */
+int sidwt_bank_correlate_ws(sidwt_bank *bank, sidwt_bank_ws *ws, const void *const *rx,
+                            const int64_t *n, const int *J, void *const *out, int count,
+                            void *hip_stream);
+
+/* Device scratch one request needs inside a workspace (bytes; -1 on bad
+ * arguments). */
+int64_t sidwt_bank_scratch_bytes(const sidwt_bank *bank, int64_t n, int J);
 
 /* Eligible references for a pulse of n samples (-1 on bad arguments). */
 int64_t sidwt_bank_eligible(const sidwt_bank *bank, int64_t n);

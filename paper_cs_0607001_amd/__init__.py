@@ -344,7 +344,16 @@ class Bank:
             raise IndexError(e)
         return Plan.borrowed(h, self.filter, self.Jmax, self.m[e])
 
-    def correlate(self, rx, J, out=None, stream=None):
+    def workspace(self):
+        """A workspace for calls in flight on one more stream."""
+        h = ctypes.c_void_p()
+        check(lib().sidwt_bank_ws_create(self.handle, ctypes.byref(h)), "sidwt_bank_ws_create")
+        return BankWorkspace(h)
+
+    def scratch_bytes(self, n: int, J: int) -> int:
+        return lib().sidwt_bank_scratch_bytes(self.handle, n, J)
+
+    def correlate(self, rx, J, out=None, stream=None, workspace=None):
         """rx: list of complex64 device pulses; J: list of scale counts.
         Returns a list of (E_i, J_i, N_i) complex64 tensors."""
         torch = _torch()
@@ -357,9 +366,15 @@ class Bank:
                 raise ValueError("pulses must be contiguous complex64 device tensors")
         n_arr = (ctypes.c_int64 * len(ns))(*ns)
         j_arr = (ctypes.c_int32 * len(ns))(*[int(j) for j in J])
-        check(lib().sidwt_bank_correlate(self.handle, _ptr_array([x.data_ptr() for x in rx]), n_arr,
-                                         j_arr, _ptr_array([o.data_ptr() for o in out]), len(ns),
-                                         _stream_ptr(stream)), "sidwt_bank_correlate")
+        rx_p = _ptr_array([x.data_ptr() for x in rx])
+        out_p = _ptr_array([o.data_ptr() for o in out])
+        if workspace is None:
+            check(lib().sidwt_bank_correlate(self.handle, rx_p, n_arr, j_arr, out_p, len(ns),
+                                             _stream_ptr(stream)), "sidwt_bank_correlate")
+        else:
+            check(lib().sidwt_bank_correlate_ws(self.handle, workspace.handle, rx_p, n_arr, j_arr,
+                                                out_p, len(ns), _stream_ptr(stream)),
+                  "sidwt_bank_correlate_ws")
         return out
 
     def info(self) -> dict:
@@ -377,6 +392,30 @@ class Bank:
 
     def __exit__(self, *a):
         self.free()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class BankWorkspace:
+    """Device buffers of one bank call in flight (one per stream)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("workspace already freed")
+        return self._h
+
+    def free(self):
+        if getattr(self, "_h", None) is not None:
+            lib().sidwt_bank_ws_free(self._h)
+            self._h = None
 
     def __del__(self):
         try:

@@ -85,6 +85,14 @@ def _declare(L):
     L.sidwt_bank_info.restype = i32
     L.sidwt_bank_free.argtypes = [vp]
     L.sidwt_bank_free.restype = None
+    L.sidwt_bank_ws_create.argtypes = [vp, pp]
+    L.sidwt_bank_ws_create.restype = i32
+    L.sidwt_bank_ws_free.argtypes = [vp]
+    L.sidwt_bank_ws_free.restype = None
+    L.sidwt_bank_correlate_ws.argtypes = [vp, vp, pp, c.POINTER(i64), c.POINTER(i32), pp, i32, vp]
+    L.sidwt_bank_correlate_ws.restype = i32
+    L.sidwt_bank_scratch_bytes.argtypes = [vp, i64, i32]
+    L.sidwt_bank_scratch_bytes.restype = i64
     return L
 
 

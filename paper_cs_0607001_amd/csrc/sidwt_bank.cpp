@@ -89,6 +89,21 @@ int grow(T **p, size_t *cap, size_t need) {
 
 }  // namespace
 
+// Per-call device buffers: request and item descriptors, lifting chunks and
+// the scratch pyramids.  One workspace serves one stream at a time.
+struct sidwt_bank_ws {
+  BankReq *d_reqs = nullptr;
+  size_t c_reqs = 0;
+  BankItem *d_items = nullptr;
+  size_t c_items = 0;
+  BatchPulse *d_pulses = nullptr;
+  size_t c_pulses = 0;
+  LiftChunk *d_chunks = nullptr;
+  size_t c_chunks = 0;
+  float2 *d_scratch = nullptr;
+  size_t c_scratch = 0;
+};
+
 struct sidwt_bank {
   int filter = 0, Jmax = 0, E = 0, precision = 1;
   std::vector<int64_t> m;
@@ -103,17 +118,7 @@ struct sidwt_bank {
   BankRefLevel *d_rl = nullptr;
   int *d_lo = nullptr;
   PlanDesc *d_plan = nullptr;
-  // per-call buffers (calls on one bank are stream-ordered by the caller)
-  BankReq *d_reqs = nullptr;
-  size_t c_reqs = 0;
-  BankItem *d_items = nullptr;
-  size_t c_items = 0;
-  BatchPulse *d_pulses = nullptr;
-  size_t c_pulses = 0;
-  LiftChunk *d_chunks = nullptr;
-  size_t c_chunks = 0;
-  float2 *d_scratch = nullptr;
-  size_t c_scratch = 0;
+  sidwt_bank_ws *ws = nullptr;      // default workspace
 };
 
 extern "C" {
@@ -237,12 +242,32 @@ void sidwt_bank_free(sidwt_bank *bk) {
   (void)hipFree(bk->d_rl);
   (void)hipFree(bk->d_lo);
   (void)hipFree(bk->d_plan);
-  (void)hipFree(bk->d_reqs);
-  (void)hipFree(bk->d_items);
-  (void)hipFree(bk->d_pulses);
-  (void)hipFree(bk->d_chunks);
-  (void)hipFree(bk->d_scratch);
+  sidwt_bank_ws_free(bk->ws);
   delete bk;
+}
+
+int sidwt_bank_ws_create(const sidwt_bank *bk, sidwt_bank_ws **out) {
+  if (!bk || !out) return SIDWT_E_INVAL;
+  sidwt_bank_ws *w = new (std::nothrow) sidwt_bank_ws();
+  if (!w) return SIDWT_E_NOMEM;
+  *out = w;
+  return SIDWT_OK;
+}
+
+void sidwt_bank_ws_free(sidwt_bank_ws *w) {
+  if (!w) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(w->d_reqs);
+  (void)hipFree(w->d_items);
+  (void)hipFree(w->d_pulses);
+  (void)hipFree(w->d_chunks);
+  (void)hipFree(w->d_scratch);
+  delete w;
+}
+
+int64_t sidwt_bank_scratch_bytes(const sidwt_bank *bk, int64_t n, int J) {
+  if (!bk || n < 1 || J < 1 || J > bk->Jmax) return -1;
+  return 2 * transform_length(n, J) * (int64_t)sizeof(float2);
 }
 
 int64_t sidwt_bank_eligible(const sidwt_bank *bk, int64_t n) {
@@ -270,7 +295,18 @@ int sidwt_bank_info(const sidwt_bank *bk, int64_t *v, int nv) {
 
 int sidwt_bank_correlate(sidwt_bank *bk, const void *const *rx, const int64_t *n, const int *J,
                          void *const *out, int count, void *hip_stream) {
-  if (!bk || !rx || !n || !J || !out || count < 1) return SIDWT_E_INVAL;
+  if (!bk) return SIDWT_E_INVAL;
+  if (!bk->ws) {
+    int rc = sidwt_bank_ws_create(bk, &bk->ws);
+    if (rc) return rc;
+  }
+  return sidwt_bank_correlate_ws(bk, bk->ws, rx, n, J, out, count, hip_stream);
+}
+
+int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const *rx,
+                            const int64_t *n, const int *J, void *const *out, int count,
+                            void *hip_stream) {
+  if (!bk || !ws || !rx || !n || !J || !out || count < 1) return SIDWT_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   std::vector<BankReq> reqs(count);
   std::vector<BatchPulse> pulses(count);
@@ -340,31 +376,31 @@ int sidwt_bank_correlate(sidwt_bank *bk, const void *const *rx, const int64_t *n
     nch[l] = (int)per_level[l].size();
     chunks.insert(chunks.end(), per_level[l].begin(), per_level[l].end());
   }
-  int rc = grow(&bk->d_reqs, &bk->c_reqs, reqs.size());
-  if (!rc) rc = grow(&bk->d_items, &bk->c_items, items.size());
-  if (!rc) rc = grow(&bk->d_pulses, &bk->c_pulses, pulses.size());
-  if (!rc) rc = grow(&bk->d_chunks, &bk->c_chunks, chunks.size());
-  if (!rc) rc = grow(&bk->d_scratch, &bk->c_scratch, (size_t)scratch);
+  int rc = grow(&ws->d_reqs, &ws->c_reqs, reqs.size());
+  if (!rc) rc = grow(&ws->d_items, &ws->c_items, items.size());
+  if (!rc) rc = grow(&ws->d_pulses, &ws->c_pulses, pulses.size());
+  if (!rc) rc = grow(&ws->d_chunks, &ws->c_chunks, chunks.size());
+  if (!rc) rc = grow(&ws->d_scratch, &ws->c_scratch, (size_t)scratch);
   if (rc) return rc;
   // pageable sources: the runtime stages them before returning
-  hipError_t e = hipMemcpyAsync(bk->d_reqs, reqs.data(), reqs.size() * sizeof(BankReq),
+  hipError_t e = hipMemcpyAsync(ws->d_reqs, reqs.data(), reqs.size() * sizeof(BankReq),
                                 hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !items.empty())
-    e = hipMemcpyAsync(bk->d_items, items.data(), items.size() * sizeof(BankItem),
+    e = hipMemcpyAsync(ws->d_items, items.data(), items.size() * sizeof(BankItem),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(bk->d_pulses, pulses.data(), pulses.size() * sizeof(BatchPulse),
+    e = hipMemcpyAsync(ws->d_pulses, pulses.data(), pulses.size() * sizeof(BatchPulse),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !chunks.empty())
-    e = hipMemcpyAsync(bk->d_chunks, chunks.data(), chunks.size() * sizeof(LiftChunk),
+    e = hipMemcpyAsync(ws->d_chunks, chunks.data(), chunks.size() * sizeof(LiftChunk),
                        hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return map_err(e, "descriptor upload");
   const LiftChunk *cp[kMaxLevels + 2];
-  for (int l = 0; l <= kMaxLevels + 1; ++l) cp[l] = bk->d_chunks + off[l];
-  e = launch_lift_levels(bk->d_plan, bk->d_pulses, cp, nch, Jmax, bk->d_scratch, st);
+  for (int l = 0; l <= kMaxLevels + 1; ++l) cp[l] = ws->d_chunks + off[l];
+  e = launch_lift_levels(bk->d_plan, ws->d_pulses, cp, nch, Jmax, ws->d_scratch, st);
   if (e != hipSuccess) return map_err(e, "lifting");
-  e = launch_bank(bk->precision == SIDWT_BANK_BF16, bk->d_reqs, bk->d_items, (int)items.size(),
-                  bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w, bk->d_scratch, kRows + bk->Umax, st);
+  e = launch_bank(bk->precision == SIDWT_BANK_BF16, ws->d_reqs, ws->d_items, (int)items.size(),
+                  bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w, ws->d_scratch, kRows + bk->Umax, st);
   return map_err(e, "bank kernel");
 }
 

@@ -134,10 +134,8 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fn = {"batched_uniform": bench_batched_uniform, "uneven": bench_uneven,
-          "integer": bench_integer, "single": bench_single}.get(args.workload)
-    if fn is None:
-        from bench_serving import bench_serving  # noqa: E402
-        fn = bench_serving
+          "integer": bench_integer, "single": bench_single,
+          "serving": bench_serving}[args.workload]
     rec = fn(args)
     print(json.dumps(rec), flush=True)
 
@@ -492,6 +490,123 @@ def bench_single(args):
         "config": {"workload": "single correlation: 1024-sample pulse, 256-sample chirp "
                                "(TBP 64), 10 dB, 5/3, J=3, one request at a time",
                    "p50_us": p50 * 1e6, "p99_us": p99 * 1e6},
+        "roofline": None, "cpu_baseline": None,
+    }
+
+
+def bench_serving(args):
+    """Serving with a bank of 64 references (ascending length, LFM /
+    Barker-13 / polyphase, 64..2048 samples, CDF 9/7, FP16 hi+lo MFMA):
+    requests sized as the uneven workload arrive as a Poisson process at
+    rates swept relative to the measured saturation rate; p50/p99 latency
+    and samples/s per rate.  Also: the same requests through the FP32 plain
+    path (every (request, reference) pair as one pulse of an uneven batch)
+    and the bank's per-scale error against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import paper_cs_0607001_amd as S
+    import workloads as W
+    from paper_cs_0607001_amd import serving
+
+    dev = torch.device("cuda:0")
+    count = args.count
+    refs = W.reference_set(5, count=64)
+    log("building the bank (64 references, Jmax 12)")
+    bank = S.Bank("cdf97", 12, refs, "fp16")
+    rng = np.random.default_rng([5, 1])
+    pulses = []
+    for i in range(count):
+        n = W.uneven_length(rng)
+        elig = [k for k, r in enumerate(refs) if len(r) <= n // 2] or [0]
+        k = elig[int(rng.integers(0, len(elig)))]
+        pulses.append((n, W.levels_for(n), W.echoes(n, refs[k], rng).astype(np.complex64)))
+    host = [torch.from_numpy(p[2]).pin_memory() for p in pulses]
+    total_samples = sum(p[0] for p in pulses)
+
+    def reqs(times, keep=False):
+        return [serving.Request(i, float(times[i]), host[i], pulses[i][1], keep)
+                for i in range(count)]
+
+    budget = 64 << 30
+    srv = serving.Server(bank, slots=4, budget_bytes=budget, max_group=32)
+    srv.run(reqs(np.zeros(count))[:64])          # warm-up (workspaces grow)
+    log(f"saturation run: {count} requests at t = 0")
+    sat = serving.summarize(srv.run(reqs(np.zeros(count))))
+    rate_sat = sat["requests_per_s"]
+    ref_samples = sum(p[0] * bank.eligible(p[0]) for p in pulses)
+    sat["reference_samples_per_s"] = sat["samples_per_s"] * ref_samples / total_samples
+    log(f"saturation: {rate_sat:.0f} requests/s, {sat['samples_per_s'] / 1e9:.2f} G samples/s")
+    sweep = []
+    for f in (0.1, 0.2, 0.4, 0.6, 0.8, 0.9, 1.0, 1.1, 1.2):
+        rate = f * rate_sat
+        t = W.poisson_arrivals(5 + int(f * 100), rate, count)
+        rec = serving.summarize(srv.run(reqs(t - t[0])))
+        rec["rate_fraction"] = f
+        rec["offered_requests_per_s"] = rate
+        sweep.append(rec)
+        log(f"rate {f:.1f}x: p50 {rec['p50_ms']:.2f} ms, p99 {rec['p99_ms']:.2f} ms, "
+            f"{rec['samples_per_s'] / 1e9:.2f} G samples/s")
+    srv.close()
+
+    # Bank vs FP32 plain path on the same subset, raw GPU throughput.
+    sub = list(range(min(count, 200)))
+    rx = [host[i].to(dev) for i in sub]
+    Js = [pulses[i][1] for i in sub]
+    outs = bank.correlate(rx, Js)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ms_bank = _time_steps(lambda: bank.correlate(rx, Js, out=outs), 3, 1, stream)
+    plan_cache, plans, prx, pouts = {}, [], [], []
+    for i, x, J, o in zip(sub, rx, Js, outs):
+        for e in range(bank.eligible(pulses[i][0])):
+            key = (e, J)
+            if key not in plan_cache:
+                plan_cache[key] = S.plan_create("cdf97", J, refs[e])
+            plans.append(plan_cache[key])
+            prx.append(x)
+            pouts.append(o[e])
+    b32 = S.Batch(plans, [x.numel() for x in prx])
+    b32.tune(prx, pouts)
+    ms_fp32 = _time_steps(lambda: b32.run(prx, pouts), 3, 1, stream)
+    sub_samples = sum(pulses[i][0] for i in sub)
+    log(f"bank FP16 hi+lo: {ms_bank:.2f} ms, FP32 plain path: {ms_fp32:.2f} ms "
+        f"for {len(sub)} requests ({len(plans)} reference correlations)")
+    # per-scale error of the bank (FP16 hi+lo) against the oracle, sampled lags
+    outs = bank.correlate(rx, Js)
+    torch.cuda.synchronize()
+    err = {}
+    prng = np.random.default_rng(9)
+    for i in sub[:6]:
+        n, J, y = pulses[i]
+        N = S.transform_length(n, J)
+        E = bank.eligible(n)
+        for e in sorted({0, E // 2, E - 1}):
+            lags = prng.integers(0, N, 48)
+            g = outs[i][e].cpu().numpy()
+            for j in range(J):
+                want = oracle.correlate_at("cdf97", J, refs[e], y.astype(np.complex128), j, lags)
+                r = float(np.linalg.norm(g[j, lags] - want) / np.linalg.norm(want))
+                err[j] = max(err.get(j, 0.0), r)
+    b32.free()
+    for p in plan_cache.values():
+        p.free()
+    bank.free()
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT correlate; p50/p99 request latency",
+        "value": sat["samples_per_s"], "unit": "complex samples/s", "n_gpus": 1, "steps": count,
+        "warmup": 64, "ms_per_step": 1e3 / rate_sat, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp16 hi+lo MFMA, fp32 accumulate", "data": "synthetic",
+        "config": {"workload": f"serving: {count} requests per rate, n log-uniform in "
+                               f"[512, 65536], bank of 64 references (64..2048), CDF 9/7, "
+                               f"J=floor(log2(n/16)), 4 slots, {budget >> 30} GiB budget",
+                   "saturation": sat, "sweep": sweep,
+                   "bank_vs_fp32": {"requests": len(sub), "samples": sub_samples,
+                                    "bank_ms": ms_bank, "fp32_ms": ms_fp32,
+                                    "bank_samples_per_s": sub_samples / (ms_bank * 1e-3),
+                                    "fp32_samples_per_s": sub_samples / (ms_fp32 * 1e-3)},
+                   "bank_rel_l2_per_scale_max": err},
         "roofline": None, "cpu_baseline": None,
     }
 

@@ -211,8 +211,10 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
                       int count, int precision, sidwt_bank **out);
 
 /* `count` requests: rx[i] (device, n[i] complex64), J[i] <= Jmax scales,
- * out[i] (device, sidwt_bank_out_len(bank, n[i], J[i]) complex64).  All
- * requests go through one lifting pass and one GEMM launch on `hip_stream`. */
+ * out[i] (device, sidwt_bank_out_len(bank, n[i], J[i]) complex64, laid out
+ * [e][j][k] for eligible reference e, scale j, lag k; 16-byte aligned, else
+ * SIDWT_E_INVAL).  All requests go through one lifting pass and one GEMM
+ * launch on `hip_stream`; returns once both are queued. */
 int sidwt_bank_correlate(sidwt_bank *bank, const void *const *rx, const int64_t *n,
                          const int *J, void *const *out, int count, void *hip_stream);
 

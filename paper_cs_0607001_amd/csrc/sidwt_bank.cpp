@@ -6,15 +6,17 @@
 // (the largest |w| of that reference and level maps below 2^14) and split
 // into 16-bit hi = h(w s) and lo = h(w s - hi), in two column variants
 // (re-out: (w.re, w.im), im-out: (-w.im, w.re)) so the MFMA weight operand
-// needs no sign handling.  A request lifts its pulse into an HBM scratch
-// pyramid and runs one GEMM work item per (level, 256 lags, 64
-// reference-phase pairs).
+// needs no sign handling.  The split weights of a level are stored per
+// column tile of 16 (reference, phase) pairs as panels in the order the MFMA
+// lanes read them.  A request lifts its pulse into an HBM scratch pyramid and
+// runs one GEMM work item per (level, up to 256 lags, up to 16 tiles).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstdint>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -23,9 +25,10 @@
 #include "sidwt_host.hpp"
 
 namespace sidwt {
-hipError_t launch_bank(bool bf16, const BankReq *reqs, const BankItem *items, int nitems,
-                       const BankRefLevel *rl, int Jmax, const int *lo_lb, const unsigned *wts,
-                       const float2 *scratch, int Wmax, hipStream_t st);
+hipError_t launch_bank(bool bf16, const BankSeg *segs, const int *item_seg, int nitems,
+                       const BankTile *tiles, const int *tile_base, const BankRefLevel *rl,
+                       int Jmax, const int *lo_lb, const unsigned *wts, const float2 *scratch,
+                       int Wmax, hipStream_t st);
 hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
                               const LiftChunk *const *chunks, const int *nchunks, int Jmax,
                               float2 *scratch, hipStream_t st);
@@ -38,7 +41,7 @@ using namespace sidwt::host;
 
 namespace {
 
-constexpr int kRows = 256, kPairs = 64, kChunk = 4096;
+constexpr int kChunk = 4096;
 
 int map_err(hipError_t e, const char *what = nullptr) {
   if (e == hipSuccess) return SIDWT_OK;
@@ -92,10 +95,10 @@ int grow(T **p, size_t *cap, size_t need) {
 // Per-call device buffers: request and item descriptors, lifting chunks and
 // the scratch pyramids.  One workspace serves one stream at a time.
 struct sidwt_bank_ws {
-  BankReq *d_reqs = nullptr;
-  size_t c_reqs = 0;
-  BankItem *d_items = nullptr;
-  size_t c_items = 0;
+  BankSeg *d_segs = nullptr;
+  size_t c_segs = 0;
+  int *d_item_seg = nullptr;
+  size_t c_item_seg = 0;
   BatchPulse *d_pulses = nullptr;
   size_t c_pulses = 0;
   LiftChunk *d_chunks = nullptr;
@@ -111,10 +114,15 @@ struct sidwt_bank {
   PlanDesc desc0;                    // windows are shared by all references
   std::vector<BankRefLevel> rl;      // [e * (Jmax + 1) + l]
   std::vector<int> lo_lb;            // [2 l + b]
+  std::vector<BankTile> tiles;       // [tile_base[l] + T]
+  std::vector<long long> steps_pre;  // prefix sums of steps (both bands), [tile_base[l] + T + l]
+  std::vector<int> tile_base;        // [l], l = 0..Jmax
   int Umax = 0;
   long long weight_words = 0;
   // device
   unsigned *d_w = nullptr;
+  BankTile *d_tiles = nullptr;
+  int *d_tile_base = nullptr;
   BankRefLevel *d_rl = nullptr;
   int *d_lo = nullptr;
   PlanDesc *d_plan = nullptr;
@@ -142,7 +150,9 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
   bk->precision = precision;
   const bool bf16 = precision == SIDWT_BANK_BF16;
   int rc = SIDWT_OK;
-  std::vector<unsigned> words;
+  // split[e][l][b]: 4 arrays (hi re-out, hi im-out, lo re-out, lo im-out) of
+  // len words for every phase r, as [r][a][u]
+  std::vector<std::vector<unsigned>> split((size_t)count * (Jmax + 1) * 2);
   bk->rl.assign((size_t)count * (Jmax + 1), BankRefLevel{});
   for (int e = 0; e < count && !rc; ++e) {
     sidwt_plan *p = nullptr;
@@ -170,14 +180,10 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
       R.inv_scale = 1.f / s;
       for (int b = 0; b < 2; ++b) {
         const int len = d.lv[l].len[b];
-        const int U = (len + 7) & ~7;
-        R.U[b] = U;
-        R.off[b] = (long long)words.size();
-        bk->Umax = std::max(bk->Umax, U);
-        for (int r = 0; r < (1 << l); ++r) {
-          unsigned arr[4];
-          const size_t base = words.size();
-          words.resize(base + 4 * (size_t)U, 0u);
+        R.len[b] = len;
+        std::vector<unsigned> &w = split[((size_t)e * (Jmax + 1) + l) * 2 + b];
+        w.assign(((size_t)4 * len) << l, 0u);
+        for (int r = 0; r < (1 << l); ++r)
           for (int u = 0; u < len; ++u) {
             const size_t c = 2 * ((size_t)d.lv[l].off[b] + (size_t)r * len + u);
             const float wr = coef[c] * s, wi = coef[c + 1] * s;
@@ -196,12 +202,67 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
                 l0 = to_f16(v[co][0] - from_f16(h0));
                 l1 = to_f16(v[co][1] - from_f16(h1));
               }
-              arr[co] = (unsigned)h0 | ((unsigned)h1 << 16);
-              arr[2 + co] = (unsigned)l0 | ((unsigned)l1 << 16);
+              w[((size_t)r * 4 + co) * len + u] = (unsigned)h0 | ((unsigned)h1 << 16);
+              w[((size_t)r * 4 + 2 + co) * len + u] = (unsigned)l0 | ((unsigned)l1 << 16);
             }
-            for (int a = 0; a < 4; ++a) words[base + (size_t)a * U + u] = arr[a];
           }
+      }
+    }
+  }
+  // Panels: per level, per tile of 16 pairs c = e * 2^l + r, per band.
+  std::vector<unsigned> words;
+  if (!rc) {
+    bk->tile_base.assign(Jmax + 1, 0);
+    for (int l = 1; l <= Jmax; ++l) {
+      bk->tile_base[l] = (int)bk->tiles.size();
+      const int P = 1 << l;
+      const long long pairs = (long long)count * P;
+      for (long long T = 0; T * kBankTilePairs < pairs; ++T) {
+        BankTile tile{};
+        for (int b = 0; b < 2; ++b) {
+          int U = 0;
+          for (int pl = 0; pl < kBankTilePairs; ++pl) {
+            const long long c = T * kBankTilePairs + pl;
+            if (c < pairs) U = std::max(U, bk->rl[(size_t)(c >> l) * (Jmax + 1) + l].len[b]);
+          }
+          const int steps = (U + 7) / 8;
+          tile.steps[b] = steps;
+          tile.off[b] = (long long)words.size();
+          bk->Umax = std::max(bk->Umax, 8 * steps);
+          words.resize(words.size() + (size_t)steps * kBankStepWords, 0u);
+          unsigned *panel = words.data() + tile.off[b];
+          for (int st = 0; st < steps; ++st)
+            for (int hl = 0; hl < 2; ++hl)
+              for (int lane = 0; lane < 64; ++lane) {
+                const int col = lane & 31, g = lane >> 5;
+                const long long c = T * kBankTilePairs + (col >> 1);
+                if (c >= pairs) continue;
+                const int e = (int)(c >> l), r = (int)(c & (P - 1));
+                const int len = bk->rl[(size_t)e * (Jmax + 1) + l].len[b];
+                const std::vector<unsigned> &w = split[((size_t)e * (Jmax + 1) + l) * 2 + b];
+                const int a = 2 * hl + (col & 1);
+                for (int k = 0; k < 4; ++k) {
+                  const int u = 8 * st + 4 * g + k;
+                  if (u < len)
+                    panel[((size_t)(st * 2 + hl) * 64 + lane) * 4 + k] =
+                        w[((size_t)r * 4 + a) * len + u];
+                }
+              }
         }
+        bk->tiles.push_back(tile);
+      }
+    }
+  }
+  if (!rc) {
+    // per level: steps_pre[tile_base[l] + l - 1 + T] = steps of tiles [0, T)
+    bk->steps_pre.clear();
+    for (int l = 1; l <= Jmax; ++l) {
+      const int t1 = l < Jmax ? bk->tile_base[l + 1] : (int)bk->tiles.size();
+      long long acc = 0;
+      bk->steps_pre.push_back(0);
+      for (int T = bk->tile_base[l]; T < t1; ++T) {
+        acc += bk->tiles[T].steps[0] + bk->tiles[T].steps[1];
+        bk->steps_pre.push_back(acc);
       }
     }
   }
@@ -213,6 +274,14 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
     hipError_t he = hipMalloc(&bk->d_w, std::max<size_t>(1, words.size()) * 4);
     if (he == hipSuccess && !words.empty())
       he = hipMemcpy(bk->d_w, words.data(), words.size() * 4, hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMalloc(&bk->d_tiles, bk->tiles.size() * sizeof(BankTile));
+    if (he == hipSuccess)
+      he = hipMemcpy(bk->d_tiles, bk->tiles.data(), bk->tiles.size() * sizeof(BankTile),
+                     hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMalloc(&bk->d_tile_base, bk->tile_base.size() * sizeof(int));
+    if (he == hipSuccess)
+      he = hipMemcpy(bk->d_tile_base, bk->tile_base.data(), bk->tile_base.size() * sizeof(int),
+                     hipMemcpyHostToDevice);
     if (he == hipSuccess) he = hipMalloc(&bk->d_rl, bk->rl.size() * sizeof(BankRefLevel));
     if (he == hipSuccess)
       he = hipMemcpy(bk->d_rl, bk->rl.data(), bk->rl.size() * sizeof(BankRefLevel),
@@ -239,6 +308,8 @@ void sidwt_bank_free(sidwt_bank *bk) {
   (void)hipDeviceSynchronize();
   for (sidwt_plan *p : bk->plans) sidwt_free(p);
   (void)hipFree(bk->d_w);
+  (void)hipFree(bk->d_tiles);
+  (void)hipFree(bk->d_tile_base);
   (void)hipFree(bk->d_rl);
   (void)hipFree(bk->d_lo);
   (void)hipFree(bk->d_plan);
@@ -257,8 +328,8 @@ int sidwt_bank_ws_create(const sidwt_bank *bk, sidwt_bank_ws **out) {
 void sidwt_bank_ws_free(sidwt_bank_ws *w) {
   if (!w) return;
   (void)hipDeviceSynchronize();
-  (void)hipFree(w->d_reqs);
-  (void)hipFree(w->d_items);
+  (void)hipFree(w->d_segs);
+  (void)hipFree(w->d_item_seg);
   (void)hipFree(w->d_pulses);
   (void)hipFree(w->d_chunks);
   (void)hipFree(w->d_scratch);
@@ -308,26 +379,19 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
                             void *hip_stream) {
   if (!bk || !ws || !rx || !n || !J || !out || count < 1) return SIDWT_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  std::vector<BankReq> reqs(count);
   std::vector<BatchPulse> pulses(count);
-  std::vector<BankItem> items;
+  std::vector<BankSeg> segs;
+  std::vector<long long> cost;       // per item of the segment
   std::vector<std::vector<LiftChunk>> per_level(kMaxLevels + 1);
   long long scratch = 0;
   int Jmax = 0;
   for (int i = 0; i < count; ++i) {
     if (!rx[i] || !out[i] || n[i] < 1 || J[i] < 1 || J[i] > bk->Jmax) return SIDWT_E_INVAL;
+    if (reinterpret_cast<uintptr_t>(out[i]) & 15) return SIDWT_E_INVAL;
     const int64_t N = transform_length(n[i], J[i]);
     if ((N >> J[i]) < 2) return SIDWT_E_INVAL;
     if (N > (int64_t(1) << 26)) return SIDWT_E_SIZE;
     const int E = (int)sidwt_bank_eligible(bk, n[i]);
-    BankReq &q = reqs[i];
-    q.rx = rx[i];
-    q.out = out[i];
-    q.n = n[i];
-    q.N = (int)N;
-    q.J = J[i];
-    q.E = E;
-    q.scratch = scratch;
     BatchPulse &p = pulses[i];
     p = BatchPulse{};
     p.rx = rx[i];
@@ -343,32 +407,47 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
       const int L = (int)(N >> l), P = 1 << l;
       for (int k0 = 0; k0 < L; k0 += kChunk)
         per_level[l].push_back(LiftChunk{i, k0, std::min(L, k0 + kChunk), 0});
-      const int pairs = E * P;
-      for (int c0 = 0; c0 < pairs; c0 += kPairs) {
-        BankItem it{};
-        it.req = i;
-        it.level = l;
-        it.pair0 = c0;
-        it.npairs = std::min(kPairs, pairs - c0);
-        const int e_lo = c0 >> l, e_hi = (c0 + it.npairs - 1) >> l;
-        for (int b = 0; b < 2; ++b) {
-          int U = 0;
-          for (int e = e_lo; e <= e_hi; ++e)
-            U = std::max(U, bk->rl[(size_t)e * (bk->Jmax + 1) + l].U[b]);
-          it.U[b] = U;
-        }
-        for (int r0 = 0; r0 < L; r0 += kRows) {
-          it.row0 = r0;
-          it.rows = std::min(kRows, L - r0);
-          items.push_back(it);
-        }
-      }
+      BankSeg sg{};
+      sg.out = out[i];
+      sg.scratch = scratch - 2 * N;
+      sg.N = (int)N;
+      sg.J = J[i];
+      sg.E = E;
+      sg.level = l;
+      sg.L = L;
+      sg.ntiles = (E * P + kBankTilePairs - 1) / kBankTilePairs;
+      sg.nblocks = (L + 255) / 256;
+      const int last = L - 256 * (sg.nblocks - 1);
+      const int per_last = bank_tiles_per_item(last);
+      sg.g_full = (sg.ntiles + 3) / 4;
+      sg.g_last = (sg.ntiles + per_last - 1) / per_last;
+      segs.push_back(sg);
+      // cost of one item: rows x steps of its tiles (mean over the level's tiles)
+      const long long *pre = bk->steps_pre.data() + bk->tile_base[l] + (l - 1);
+      const long long st = pre[sg.ntiles];
+      cost.push_back(std::min(L, 256) * st / std::max(1, sg.nblocks > 1 ? sg.g_full : sg.g_last) +
+                     std::min(L, 256) * 8);
     }
   }
-  // Largest windows first (they take longest).
-  std::stable_sort(items.begin(), items.end(), [](const BankItem &a, const BankItem &b) {
-    return (long long)(a.U[0] + a.U[1]) * a.rows > (long long)(b.U[0] + b.U[1]) * b.rows;
-  });
+  // Segments with the costliest items first (longest-processing-time order).
+  std::vector<int> order(segs.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<BankSeg> sorted(segs.size());
+  long long nitems = 0;
+  for (size_t k = 0; k < order.size(); ++k) {
+    sorted[k] = segs[order[k]];
+    sorted[k].item0 = nitems;
+    nitems += (long long)(sorted[k].nblocks - 1) * sorted[k].g_full + sorted[k].g_last;
+  }
+  if (nitems > (1LL << 31) - 1) return SIDWT_E_SIZE;
+  std::vector<int> item_seg((size_t)nitems);
+  for (size_t k = 0; k < sorted.size(); ++k) {
+    const long long a = sorted[k].item0;
+    const long long b = k + 1 < sorted.size() ? sorted[k + 1].item0 : nitems;
+    std::fill(item_seg.begin() + a, item_seg.begin() + b, (int)k);
+  }
   std::vector<LiftChunk> chunks;
   int off[kMaxLevels + 2] = {0}, nch[kMaxLevels + 2] = {0};
   for (int l = 1; l <= kMaxLevels; ++l) {
@@ -376,17 +455,19 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
     nch[l] = (int)per_level[l].size();
     chunks.insert(chunks.end(), per_level[l].begin(), per_level[l].end());
   }
-  int rc = grow(&ws->d_reqs, &ws->c_reqs, reqs.size());
-  if (!rc) rc = grow(&ws->d_items, &ws->c_items, items.size());
+  int rc = grow(&ws->d_segs, &ws->c_segs, sorted.size());
+  if (!rc) rc = grow(&ws->d_item_seg, &ws->c_item_seg, item_seg.size());
   if (!rc) rc = grow(&ws->d_pulses, &ws->c_pulses, pulses.size());
   if (!rc) rc = grow(&ws->d_chunks, &ws->c_chunks, chunks.size());
   if (!rc) rc = grow(&ws->d_scratch, &ws->c_scratch, (size_t)scratch);
   if (rc) return rc;
   // pageable sources: the runtime stages them before returning
-  hipError_t e = hipMemcpyAsync(ws->d_reqs, reqs.data(), reqs.size() * sizeof(BankReq),
-                                hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !items.empty())
-    e = hipMemcpyAsync(ws->d_items, items.data(), items.size() * sizeof(BankItem),
+  hipError_t e = hipSuccess;
+  if (!sorted.empty())
+    e = hipMemcpyAsync(ws->d_segs, sorted.data(), sorted.size() * sizeof(BankSeg),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !item_seg.empty())
+    e = hipMemcpyAsync(ws->d_item_seg, item_seg.data(), item_seg.size() * sizeof(int),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(ws->d_pulses, pulses.data(), pulses.size() * sizeof(BatchPulse),
@@ -399,8 +480,9 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   for (int l = 0; l <= kMaxLevels + 1; ++l) cp[l] = ws->d_chunks + off[l];
   e = launch_lift_levels(bk->d_plan, ws->d_pulses, cp, nch, Jmax, ws->d_scratch, st);
   if (e != hipSuccess) return map_err(e, "lifting");
-  e = launch_bank(bk->precision == SIDWT_BANK_BF16, ws->d_reqs, ws->d_items, (int)items.size(),
-                  bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w, ws->d_scratch, kRows + bk->Umax, st);
+  e = launch_bank(bk->precision == SIDWT_BANK_BF16, ws->d_segs, ws->d_item_seg, (int)nitems,
+                  bk->d_tiles, bk->d_tile_base, bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w,
+                  ws->d_scratch, 256 + bk->Umax, st);
   return map_err(e, "bank kernel");
 }
 

@@ -74,31 +74,66 @@ __device__ __forceinline__ V8 load8(const unsigned *p) {
   return v;
 }
 
-constexpr int kBankThreads = 256;  // 4 waves; each wave owns 64 rows x 64 columns
-constexpr int kBankRows = 256;     // rows per item
-constexpr int kBankPairs = 64;     // (reference, phase) pairs per item
-constexpr int kBankKChunk = 32;    // lag offsets staged per chunk
+// 16-byte global load of a panel entry (4 words, 16-byte aligned).
+template <class V8>
+__device__ __forceinline__ V8 gload8(const unsigned *p) {
+  const uint4 w = *reinterpret_cast<const uint4 *>(p);
+  V8 v;
+  __builtin_memcpy(&v, &w, 16);
+  return v;
+}
 
-// LDS: data windows [band][hi/lo][W] words (W = kBankRows + Umax), then the
-// staged weights [pair][array: hi re-col, hi im-col, lo re-col, lo im-col][32].
+constexpr int kBankThreads = 256;  // 4 waves; a wave owns 64 rows x up to 4 column tiles
+constexpr int kStageLd = 36;       // staging row stride (floats): 32 columns + pad, 16-byte rows
+
+// LDS: data windows [band][hi/lo][Wmax] words (W = 64 rw + umax of the
+// item), then one output staging tile [64 rows][kStageLd] floats per wave.
+// Weights are read from their panels straight into registers (no LDS, no
+// barrier in the K loop); the waves of an item that share tiles read the
+// same panel lines close together in time.
 template <bool BF16>
-__global__ __launch_bounds__(kBankThreads) void bank_items(
-    const BankReq *__restrict__ reqs, const BankItem *__restrict__ items,
+__global__ __launch_bounds__(kBankThreads, 2) void bank_items(
+    const BankSeg *__restrict__ segs, const int *__restrict__ item_seg,
+    const BankTile *__restrict__ tiles, const int *__restrict__ tile_base,
     const BankRefLevel *__restrict__ rl, int Jmax, const int *__restrict__ lo_lb,
-    const unsigned *__restrict__ wts, const float2 *__restrict__ scratch, int Wmax) {
+    const unsigned *__restrict__ wts,
+    const float2 *__restrict__ scratch, int Wmax) {
   using H = Half<BF16>;
   using V8 = typename H::V8;
   extern __shared__ __align__(16) unsigned sm_bank[];
   __shared__ float s_max;
-  const BankItem it = items[blockIdx.x];
-  const BankReq &q = reqs[it.req];
-  const int l = it.level, P = 1 << l, L = q.N >> l, N = q.N;
+
+  // Item: segment, row block and tile group (uniform across the block).
+  const BankSeg sg = segs[item_seg[blockIdx.x]];
+  const BankSeg &q = sg;                         // the request's fields
+  const int l = sg.level, P = 1 << l, L = sg.L, N = q.N;
+  int k = (int)(blockIdx.x - sg.item0);
+  const int kfull = (sg.nblocks - 1) * sg.g_full;
+  int rb, grp;
+  if (k < kfull) {
+    rb = k / sg.g_full;
+    grp = k - rb * sg.g_full;
+  } else {
+    rb = sg.nblocks - 1;
+    grp = k - kfull;
+  }
+  const int row0 = 256 * rb;
+  const int rows = min(256, L - row0);
+  const int rw = rows > 128 ? 4 : rows > 64 ? 2 : 1;
+  const int per = bank_tiles_per_item(rows);
+  const int tile0 = grp * per;
+  const int ntiles = min(per, sg.ntiles - tile0);
+  const BankTile *tl = tiles + tile_base[l];
+  int umax = 0;
+  for (int t = tile0; t < tile0 + ntiles; ++t)
+    umax = max(umax, 8 * max(tl[t].steps[0], tl[t].steps[1]));
+
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int Umax = max(it.U[0], it.U[1]);
-  const int W = kBankRows + Umax;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int W = 64 * rw + umax;
   unsigned *dat = sm_bank;                      // [b][hilo][Wmax]
-  unsigned *ws = sm_bank + 4 * Wmax;            // [pair][4][32]
+  float *stg = reinterpret_cast<float *>(sm_bank + 4 * Wmax) + wave * 64 * kStageLd;
   const float2 *band0 = scratch + q.scratch + scratch_level_off(N, l);
 
   // Data windows: element i of band b is c_l / d_l at (row0 + lo + i) mod L.
@@ -107,7 +142,7 @@ __global__ __launch_bounds__(kBankThreads) void bank_items(
   float mx = 0.f;
   for (int b = 0; b < 2; ++b) {
     const float2 *src = band0 + (b ? L : 0);
-    const int e0 = it.row0 + lo_lb[2 * l + b];
+    const int e0 = row0 + lo_lb[2 * l + b];
     for (int i = tid; i < W; i += nt) {
       const float2 x = src[pos_mod(e0 + i, L)];
       mx = fmaxf(mx, fmaxf(fabsf(x.x), fabsf(x.y)));
@@ -122,7 +157,7 @@ __global__ __launch_bounds__(kBankThreads) void bank_items(
   const float inv_sd = 1.f / sd;
   for (int b = 0; b < 2; ++b) {
     const float2 *src = band0 + (b ? L : 0);
-    const int e0 = it.row0 + lo_lb[2 * l + b];
+    const int e0 = row0 + lo_lb[2 * l + b];
     unsigned *hi = dat + (2 * b) * Wmax;
     unsigned *lo = hi + Wmax;
     for (int i = tid; i < W; i += nt) {
@@ -133,13 +168,19 @@ __global__ __launch_bounds__(kBankThreads) void bank_items(
       lo[i] = pack2<BF16>(xr - unpack_lo<BF16>(h), xi - unpack_hi<BF16>(h));
     }
   }
+  __syncthreads();
 
-  // Wave roles: rows [64 wave, 64 wave + 64) of the item, all 4 column tiles.
-  const int rloc = 64 * wave + (lane & 31);      // row of the first row tile
-  const int g = lane >> 5;                        // K half: offsets 4g..4g+3
+  // Wave role: row group wr (64 rows), tile group wt (up to 4 tiles).
+  const int wr = wave % rw, wt = wave / rw;
+  const int rows_w = rows - 64 * wr;
+  const int t0 = tile0 + 4 * wt;
+  const int nt_w = min(4, tile0 + ntiles - t0);
+  if (rows_w <= 0 || nt_w <= 0) return;          // no barrier follows
+  const bool two = rows_w > 32;                  // second 32-row half in use
+  const BankTile *tb = tl + t0;
+  const int rloc = 64 * wr + (lane & 31);        // row of the first row tile
+  const int g = lane >> 5;                        // K half: offsets 4g..4g+3 of a step
   const int col = lane & 31;
-  const int co = col & 1;
-  const bool active = 64 * wave < it.rows;
   f32x16 acc[2][4];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -151,91 +192,127 @@ __global__ __launch_bounds__(kBankThreads) void bank_items(
   for (int b = 0; b < 2; ++b) {
     const unsigned *dhi = dat + (2 * b) * Wmax;
     const unsigned *dlo = dhi + Wmax;
-    for (int k0 = 0; k0 < it.U[b]; k0 += kBankKChunk) {
-      __syncthreads();
-      // stage weights of the item's pairs for offsets [k0, k0 + 32)
-      for (int x = tid; x < kBankPairs * 4 * kBankKChunk; x += nt) {
-        const int u = x & (kBankKChunk - 1);
-        const int a = (x >> 5) & 3;
-        const int pl = x >> 7;
-        unsigned w = 0;
-        if (pl < it.npairs) {
-          const int c = it.pair0 + pl;
-          const int e = c >> l, r = c & (P - 1);
-          const BankRefLevel &R = rl[e * (Jmax + 1) + l];
-          const int Ue = R.U[b];
-          if (k0 + u < Ue) w = wts[R.off[b] + ((long long)r * 4 + a) * Ue + k0 + u];
-        }
-        ws[x] = w;
+    int steps[4];
+    const unsigned *pw[4];
+    int S = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      steps[t] = t < nt_w ? tb[t].steps[b] : 0;
+      pw[t] = wts + (t < nt_w ? tb[t].off[b] : 0) + 4 * lane;
+      S = max(S, steps[t]);
+    }
+    V8 bh[4], bl[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (steps[t] > 0) {
+        bh[t] = gload8<V8>(pw[t]);
+        bl[t] = gload8<V8>(pw[t] + 256);
       }
-      __syncthreads();
-      if (active) {
-        const int steps = min(4, (it.U[b] - k0 + 7) >> 3);
-        for (int st = 0; st < steps; ++st) {
-          const int u0 = k0 + 8 * st + 4 * g;
-          V8 ahi[2], alo[2];
+    for (int s = 0; s < S; ++s) {
+      V8 nh[4], nl[4];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            ahi[h] = load8<V8>(dhi + rloc + 32 * h + u0);
-            alo[h] = load8<V8>(dlo + rloc + 32 * h + u0);
-          }
+      for (int t = 0; t < 4; ++t)
+        if (s + 1 < steps[t]) {
+          nh[t] = gload8<V8>(pw[t] + (s + 1) * kBankStepWords);
+          nl[t] = gload8<V8>(pw[t] + (s + 1) * kBankStepWords + 256);
+        }
+      const int u0 = 8 * s + 4 * g;
+      V8 ahi[2], alo[2];
+      ahi[0] = load8<V8>(dhi + rloc + u0);
+      alo[0] = load8<V8>(dlo + rloc + u0);
+      ahi[1] = load8<V8>(dhi + rloc + 32 + u0);
+      alo[1] = load8<V8>(dlo + rloc + 32 + u0);
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            const int pl = t * 16 + (col >> 1);
-            const unsigned *wb = ws + (pl * 4) * kBankKChunk + 8 * st + 4 * g;
-            const V8 bhi = load8<V8>(wb + co * kBankKChunk);
-            const V8 blo = load8<V8>(wb + (2 + co) * kBankKChunk);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              acc[h][t] = H::mma(ahi[h], bhi, acc[h][t]);
-              acc[h][t] = H::mma(ahi[h], blo, acc[h][t]);
-              acc[h][t] = H::mma(alo[h], bhi, acc[h][t]);
-            }
+      for (int t = 0; t < 4; ++t)
+        if (s < steps[t]) {
+          acc[0][t] = H::mma(ahi[0], bh[t], acc[0][t]);
+          acc[0][t] = H::mma(ahi[0], bl[t], acc[0][t]);
+          acc[0][t] = H::mma(alo[0], bh[t], acc[0][t]);
+          if (two) {
+            acc[1][t] = H::mma(ahi[1], bh[t], acc[1][t]);
+            acc[1][t] = H::mma(ahi[1], bl[t], acc[1][t]);
+            acc[1][t] = H::mma(alo[1], bh[t], acc[1][t]);
           }
         }
-      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (s + 1 < steps[t]) {
+          bh[t] = nh[t];
+          bl[t] = nl[t];
+        }
     }
   }
 
-  // register i of lane l: row 8*(i/4) + 4*(l/32) + i%4, column l%32
-  if (!active) return;
+  // Output.  Accumulator register i of lane l holds row 8*(i/4) + 4*(l/32)
+  // + i%4, column l%32 (column 2 pp + v: pair pp of the tile, v = re/im).
+  // Each tile goes through the wave's staging area and leaves as 16-byte
+  // runs (2 consecutive phases of one reference at one lag), ordered so a
+  // store instruction covers whole runs of out[e][l-1][P p + r]: per
+  // reference of the tile Q = min(P, 16) pairs, Q / 2 runs per lag.
+  // (an opaque copy of the lane index keeps this index math from being
+  // hoisted into the MFMA loop, where it would hold registers)
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
   float *out = reinterpret_cast<float *>(q.out);
+  const int pairs = q.E * P;
+  const int lq = min(l, 4);                       // log2 Q
+  const int lcpr = lq - 1;                        // log2 runs per lag
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int pl = t * 16 + (col >> 1);
-    if (pl >= it.npairs) continue;
-    const int c = it.pair0 + pl;
-    const int e = c >> l, r = c & (P - 1);
-    const float scale = inv_sd * rl[e * (Jmax + 1) + l].inv_scale;
-    float *o = out + 2 * (((long long)e * q.J + (l - 1)) * N) + 2LL * r + co;
+    if (t >= nt_w) break;
+    const int c = kBankTilePairs * (t0 + t) + ((ln & 31) >> 1);
+    const float scale =
+        c < pairs ? inv_sd * rl[(c >> l) * (Jmax + 1) + l].inv_scale : 0.f;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int lr = 64 * wave + 32 * h + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        if (lr < it.rows) {
-          const long long s = (long long)P * (it.row0 + lr);
-          __builtin_nontemporal_store(acc[h][t][i] * scale, o + 2 * s);
-        }
+      for (int i = 0; i < 16; ++i)
+        stg[(32 * h + 8 * (i >> 2) + 4 * (ln >> 5) + (i & 3)) * kStageLd + (ln & 31)] =
+            acc[h][t][i] * scale;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int kk = 64 * j + ln;
+      const int ch = kk & ((1 << lcpr) - 1);
+      const int rest = kk >> lcpr;
+      const int row = rest & 63;
+      const int pp = ((rest >> 6) << lq) + 2 * ch;
+      const int cc = kBankTilePairs * (t0 + t) + pp;
+      if (row < rows_w && cc < pairs) {
+        const f32x4 v = *reinterpret_cast<const f32x4 *>(stg + row * kStageLd + 2 * pp);
+        const int e = cc >> l, r = cc & (P - 1);
+        float *o = out + 2 * (((long long)e * q.J + (l - 1)) * N +
+                              (long long)P * (row0 + 64 * wr + row) + r);
+        __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(o));
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
-hipError_t launch_bank(bool bf16, const BankReq *reqs, const BankItem *items, int nitems,
-                       const BankRefLevel *rl, int Jmax, const int *lo_lb, const unsigned *wts,
-                       const float2 *scratch, int Wmax, hipStream_t st) {
-  const size_t lds = (size_t)(4 * Wmax + kBankPairs * 4 * kBankKChunk) * 4;
+size_t bank_lds_bytes(int Wmax) {
+  return (size_t)(4 * Wmax) * 4 + (size_t)4 * 64 * kStageLd * 4;
+}
+
+hipError_t launch_bank(bool bf16, const BankSeg *segs, const int *item_seg, int nitems,
+                       const BankTile *tiles, const int *tile_base, const BankRefLevel *rl,
+                       int Jmax, const int *lo_lb, const unsigned *wts, const float2 *scratch,
+                       int Wmax, hipStream_t st) {
+  const size_t lds = bank_lds_bytes(Wmax);
   const void *fn = bf16 ? (const void *)bank_items<true> : (const void *)bank_items<false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (nitems <= 0) return hipSuccess;
   if (bf16)
-    hipLaunchKernelGGL(bank_items<true>, dim3(nitems), dim3(kBankThreads), lds, st, reqs, items, rl,
-                       Jmax, lo_lb, wts, scratch, Wmax);
+    hipLaunchKernelGGL(bank_items<true>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
+                       item_seg, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
   else
-    hipLaunchKernelGGL(bank_items<false>, dim3(nitems), dim3(kBankThreads), lds, st, reqs, items, rl,
-                       Jmax, lo_lb, wts, scratch, Wmax);
+    hipLaunchKernelGGL(bank_items<false>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
+                       item_seg, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
   return hipGetLastError();
 }
 

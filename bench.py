@@ -124,7 +124,7 @@ def main():
                     help="also run an elementwise kernel that reads and writes 256 MiB "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "uneven", "integer", "single", "serving"])
+                    choices=["batched_uniform", "uneven", "integer", "single", "serving", "bank"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path in this library "
@@ -135,7 +135,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fn = {"batched_uniform": bench_batched_uniform, "uneven": bench_uneven,
           "integer": bench_integer, "single": bench_single,
-          "serving": bench_serving}[args.workload]
+          "serving": bench_serving, "bank": bench_bank}[args.workload]
     rec = fn(args)
     print(json.dumps(rec), flush=True)
 
@@ -494,6 +494,87 @@ def bench_single(args):
     }
 
 
+def _serving_requests(refs, count, seed=5):
+    """Requests of the serving workload: n log-uniform in [512, 65536], J =
+    floor(log2(n / 16)), an echo train of one bank reference (m <= n / 2)
+    in noise."""
+    import numpy as np
+
+    import workloads as W
+    rng = np.random.default_rng([seed, 1])
+    out = []
+    for _ in range(count):
+        n = W.uneven_length(rng)
+        elig = [k for k, r in enumerate(refs) if len(r) <= n // 2] or [0]
+        k = elig[int(rng.integers(0, len(elig)))]
+        out.append((n, W.levels_for(n), W.echoes(n, refs[k], rng).astype(np.complex64)))
+    return out
+
+
+def bench_bank(args):
+    """One bank call per step: 256 requests of the serving mix against a bank
+    of 64 references (64..2048 samples, CDF 9/7, FP16 hi+lo MFMA).  The GEMM
+    kernel's duration comes from HIP events the library records around its
+    launch on the call's stream."""
+    import torch
+
+    import paper_cs_0607001_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    count = 256 if args.count == 4096 else args.count
+    refs = W.reference_set(5, count=64)
+    bank = S.Bank("cdf97", 12, refs, "fp16")
+    reqs = _serving_requests(refs, count)
+    rx = [torch.from_numpy(y).to(dev) for _, _, y in reqs]
+    Js = [J for _, J, _ in reqs]
+    ws = bank.workspace()
+    outs = bank.correlate(rx, Js, workspace=ws)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ms = _time_steps(lambda: bank.correlate(rx, Js, out=outs, workspace=ws),
+                     args.steps, args.warmup, stream)
+    ws.timing(True)
+    lift, gemm = [], []
+    for _ in range(args.steps):
+        bank.correlate(rx, Js, out=outs, workspace=ws)
+        a, b = ws.times()
+        lift.append(a)
+        gemm.append(b)
+    ws.timing(False)
+    lift_ms, gemm_ms = sum(lift) / len(lift), sum(gemm) / len(gemm)
+    lens = [plan_lens(S, bank.plan(e)) for e in range(len(refs))]
+    flops = 0
+    samples = sum(n for n, _, _ in reqs)
+    out_bytes = sum(o.numel() * 8 for o in outs)
+    for n, J, _ in reqs:
+        N = S.transform_length(n, J)
+        for e in range(bank.eligible(n)):
+            flops += 3 * pulse_flops(lens[e][:2 * J], N)   # hi*hi + hi*lo + lo*hi
+    tflops = flops / (gemm_ms * 1e-3) / 1e12
+    value = samples / (ms * 1e-3)
+    log(f"bank: {ms:.3f} ms/step ({lift_ms:.3f} lifting + {gemm_ms:.3f} GEMM), "
+        f"{value / 1e9:.3f} G samples/s, {tflops:.0f} TFLOP/s FP16, "
+        f"planes {out_bytes / (gemm_ms * 1e-3) / 1e12:.2f} TB/s")
+    ws.free()
+    bank.free()
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT correlate",
+        "value": value, "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp16 hi+lo MFMA, fp32 accumulate", "data": "synthetic",
+        "config": {"workload": f"reference bank: {count} requests, n log-uniform in [512, 65536], "
+                               f"64 references (64..2048), CDF 9/7, J=floor(log2(n/16)), "
+                               f"all eligible references per request",
+                   "samples": samples, "plane_bytes": out_bytes,
+                   "lift_ms": lift_ms, "gemm_ms": gemm_ms},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tflops / 2500.0, "traffic": None, "kernel": "bank_items<FP16>",
+                     "hbm_write_frac": out_bytes / (gemm_ms * 1e-3) / 8e12},
+        "cpu_baseline": None,
+    }
+
+
 def bench_serving(args):
     """Serving with a bank of 64 references (ascending length, LFM /
     Barker-13 / polyphase, 64..2048 samples, CDF 9/7, FP16 hi+lo MFMA):
@@ -515,13 +596,7 @@ def bench_serving(args):
     refs = W.reference_set(5, count=64)
     log("building the bank (64 references, Jmax 12)")
     bank = S.Bank("cdf97", 12, refs, "fp16")
-    rng = np.random.default_rng([5, 1])
-    pulses = []
-    for i in range(count):
-        n = W.uneven_length(rng)
-        elig = [k for k, r in enumerate(refs) if len(r) <= n // 2] or [0]
-        k = elig[int(rng.integers(0, len(elig)))]
-        pulses.append((n, W.levels_for(n), W.echoes(n, refs[k], rng).astype(np.complex64)))
+    pulses = _serving_requests(refs, count)
     host = [torch.from_numpy(p[2]).pin_memory() for p in pulses]
     total_samples = sum(p[0] for p in pulses)
 

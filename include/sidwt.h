@@ -230,6 +230,15 @@ int sidwt_bank_correlate_ws(sidwt_bank *bank, sidwt_bank_ws *ws, const void *con
                             const int64_t *n, const int *J, void *const *out, int count,
                             void *hip_stream);
 
+/* Kernel timing of the calls through a workspace (benchmarks): with timing
+ * on, every call records HIP events on its stream before the lifting
+ * launches, between lifting and the GEMM launch, and after it.
+ * sidwt_bank_ws_times waits for the last call and returns both durations
+ * in milliseconds; SIDWT_E_INVAL if no call was timed since timing was
+ * switched on. */
+int sidwt_bank_ws_timing(sidwt_bank_ws *ws, int on);
+int sidwt_bank_ws_times(sidwt_bank_ws *ws, float *lift_ms, float *gemm_ms);
+
 /* Device scratch one request needs inside a workspace (bytes; -1 on bad
  * arguments). */
 int64_t sidwt_bank_scratch_bytes(const sidwt_bank *bank, int64_t n, int J);

@@ -406,6 +406,17 @@ class BankWorkspace:
     def __init__(self, handle):
         self._h = handle
 
+    def timing(self, on: bool = True):
+        """Record HIP events around the lifting and GEMM launches of calls."""
+        check(lib().sidwt_bank_ws_timing(self.handle, int(bool(on))), "sidwt_bank_ws_timing")
+
+    def times(self):
+        """(lifting ms, GEMM ms) of the last timed call (waits for it)."""
+        a, b = ctypes.c_float(), ctypes.c_float()
+        check(lib().sidwt_bank_ws_times(self.handle, ctypes.byref(a), ctypes.byref(b)),
+              "sidwt_bank_ws_times")
+        return a.value, b.value
+
     @property
     def handle(self):
         if self._h is None:

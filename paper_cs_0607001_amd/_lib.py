@@ -89,6 +89,10 @@ def _declare(L):
     L.sidwt_bank_ws_create.restype = i32
     L.sidwt_bank_ws_free.argtypes = [vp]
     L.sidwt_bank_ws_free.restype = None
+    L.sidwt_bank_ws_timing.argtypes = [vp, i32]
+    L.sidwt_bank_ws_timing.restype = i32
+    L.sidwt_bank_ws_times.argtypes = [vp, c.POINTER(c.c_float), c.POINTER(c.c_float)]
+    L.sidwt_bank_ws_times.restype = i32
     L.sidwt_bank_correlate_ws.argtypes = [vp, vp, pp, c.POINTER(i64), c.POINTER(i32), pp, i32, vp]
     L.sidwt_bank_correlate_ws.restype = i32
     L.sidwt_bank_scratch_bytes.argtypes = [vp, i64, i32]

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/sidwt.h"
+#include "sidwt_bank.hpp"
 #include "sidwt_host.hpp"
 
 namespace sidwt {
@@ -105,6 +106,9 @@ struct sidwt_bank_ws {
   size_t c_chunks = 0;
   float2 *d_scratch = nullptr;
   size_t c_scratch = 0;
+  bool timing = false;
+  bool timed = false;                // the last call recorded its events
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
 };
 
 struct sidwt_bank {
@@ -333,7 +337,34 @@ void sidwt_bank_ws_free(sidwt_bank_ws *w) {
   (void)hipFree(w->d_pulses);
   (void)hipFree(w->d_chunks);
   (void)hipFree(w->d_scratch);
+  for (hipEvent_t e : w->ev)
+    if (e) (void)hipEventDestroy(e);
   delete w;
+}
+
+int sidwt_bank_ws_timing(sidwt_bank_ws *ws, int on) {
+  if (!ws) return SIDWT_E_INVAL;
+  if (on)
+    for (hipEvent_t &e : ws->ev)
+      if (!e) {
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) {
+          e = nullptr;
+          return map_err(he, "hipEventCreate");
+        }
+      }
+  ws->timing = on != 0;
+  ws->timed = false;
+  return SIDWT_OK;
+}
+
+int sidwt_bank_ws_times(sidwt_bank_ws *ws, float *lift_ms, float *gemm_ms) {
+  if (!ws || !lift_ms || !gemm_ms) return SIDWT_E_INVAL;
+  if (!ws->timed) return SIDWT_E_INVAL;
+  hipError_t e = hipEventSynchronize(ws->ev[2]);
+  if (e == hipSuccess) e = hipEventElapsedTime(lift_ms, ws->ev[0], ws->ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(gemm_ms, ws->ev[1], ws->ev[2]);
+  return map_err(e, "event timing");
 }
 
 int64_t sidwt_bank_scratch_bytes(const sidwt_bank *bk, int64_t n, int J) {
@@ -478,11 +509,20 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   if (e != hipSuccess) return map_err(e, "descriptor upload");
   const LiftChunk *cp[kMaxLevels + 2];
   for (int l = 0; l <= kMaxLevels + 1; ++l) cp[l] = ws->d_chunks + off[l];
-  e = launch_lift_levels(bk->d_plan, ws->d_pulses, cp, nch, Jmax, ws->d_scratch, st);
+  ws->timed = false;
+  if (ws->timing) e = hipEventRecord(ws->ev[0], st);
+  if (e == hipSuccess)
+    e = launch_lift_levels(bk->d_plan, ws->d_pulses, cp, nch, Jmax, ws->d_scratch, st);
   if (e != hipSuccess) return map_err(e, "lifting");
+  if (ws->timing) e = hipEventRecord(ws->ev[1], st);
+  if (e != hipSuccess) return map_err(e, "event");
   e = launch_bank(bk->precision == SIDWT_BANK_BF16, ws->d_segs, ws->d_item_seg, (int)nitems,
                   bk->d_tiles, bk->d_tile_base, bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w,
                   ws->d_scratch, 256 + bk->Umax, st);
+  if (e == hipSuccess && ws->timing) {
+    e = hipEventRecord(ws->ev[2], st);
+    ws->timed = e == hipSuccess;
+  }
   return map_err(e, "bank kernel");
 }
 

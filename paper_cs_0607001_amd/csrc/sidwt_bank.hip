@@ -13,7 +13,7 @@
 // v_mfma_f32_32x32x16_{f16,bf16}; the output is divided by both scales.
 #include <type_traits>
 
-#include "sidwt_device.hpp"
+#include "sidwt_bank.hpp"
 
 namespace sidwt {
 

@@ -99,3 +99,23 @@ def test_bank_argument_checks(dev):
         assert bank.eligible(10 ** 6) == 3
         with pytest.raises(S.SidwtError):
             bank.correlate([torch.zeros(64, dtype=torch.complex64, device="cuda")], [7])  # J > Jmax
+
+
+def test_workspace_kernel_timing(dev):
+    torch, S = dev
+    refs = bank_refs(seed=11, count=3)
+    rng = np.random.default_rng(6)
+    with S.Bank("cdf97", 6, refs, "bf16") as bank:
+        ws = bank.workspace()
+        with pytest.raises(S.SidwtError):
+            ws.times()                           # nothing timed yet
+        ws.timing(True)
+        x = torch.from_numpy(W.echoes(1500, refs[0], rng).astype(np.complex64)).cuda()
+        a = bank.correlate([x], [6], workspace=ws)[0]
+        lift_ms, gemm_ms = ws.times()
+        assert lift_ms > 0 and gemm_ms > 0
+        ws.timing(False)
+        b = bank.correlate([x], [6], workspace=ws)[0]
+        torch.cuda.synchronize()
+        assert torch.equal(a, b)                 # timing changes nothing in the results
+        ws.free()

@@ -127,18 +127,26 @@ struct CD4 {
 // Lane neighbours inside a 64-wide wavefront (lane-1 / lane+1).  Lanes at the
 // edge get their own value back; the window schedule never uses those.
 // ---------------------------------------------------------------------------
+// Neighbour lanes through DPP whole-wave shifts (a register-level modifier
+// on GFX9-family parts, no LDS round trip): wave_shr:1 gives lane i the
+// value of lane i-1, wave_shl:1 that of lane i+1; the edge lane keeps its
+// own value (it only ever feeds halo lanes whose results are discarded).
+__device__ __forceinline__ int dpp_prev(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_next(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);
+}
 __device__ __forceinline__ float2 lane_prev(float2 v) {
-  return make_float2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
+  return make_float2(__int_as_float(dpp_prev(__float_as_int(v.x))),
+                     __int_as_float(dpp_prev(__float_as_int(v.y))));
 }
 __device__ __forceinline__ float2 lane_next(float2 v) {
-  return make_float2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
+  return make_float2(__int_as_float(dpp_next(__float_as_int(v.x))),
+                     __int_as_float(dpp_next(__float_as_int(v.y))));
 }
-__device__ __forceinline__ int2 lane_prev(int2 v) {
-  return make_int2(__shfl_up(v.x, 1, 64), __shfl_up(v.y, 1, 64));
-}
-__device__ __forceinline__ int2 lane_next(int2 v) {
-  return make_int2(__shfl_down(v.x, 1, 64), __shfl_down(v.y, 1, 64));
-}
+__device__ __forceinline__ int2 lane_prev(int2 v) { return make_int2(dpp_prev(v.x), dpp_prev(v.y)); }
+__device__ __forceinline__ int2 lane_next(int2 v) { return make_int2(dpp_next(v.x), dpp_next(v.y)); }
 
 __device__ __forceinline__ float2 fma2(float s, float2 a, float2 c) {
   return make_float2(fmaf(s, a.x, c.x), fmaf(s, a.y, c.y));

@@ -165,8 +165,8 @@ __global__ __launch_bounds__(256) void ref_tree_level(
 // o)` fetches pair kc (0 <= kc < np) of the level input; `store(k, c, d)`
 // receives the owned outputs.
 // ===========================================================================
-template <int F, int UNROLL, class Load, class Store>
-__device__ __forceinline__ void lift_level_range(int np, int k0, int k1, Load load, Store store) {
+template <int F, int UNROLL, bool WIDE, class Load, class Store>
+__device__ __forceinline__ void lift_windows(int np, int k0, int k1, Load load, Store store) {
   using L = YLift<F>;
   using V = typename L::V;
   constexpr int OWN = 64 - L::HL - L::HR;
@@ -179,9 +179,18 @@ __device__ __forceinline__ void lift_level_range(int np, int k0, int k1, Load lo
     int kk[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
-      int k = k0 + (w0 + u) * OWN - L::HL + lane;
+      const int k = k0 + (w0 + u) * OWN - L::HL + lane;
       kk[u] = k;
-      load(pos_mod(k, np), e[u], o[u]);
+      int kc;
+      if constexpr (WIDE) {
+        // np >= 64: every needed index is in [-HL, np + HR); the rest only
+        // has to stay in bounds
+        kc = k < 0 ? k + np : (k >= np ? k - np : k);
+        kc = kc < np ? kc : np - 1;
+      } else {
+        kc = pos_mod(k, np);
+      }
+      load(kc, e[u], o[u]);
     }
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) L::run(e[u], o[u]);
@@ -191,6 +200,16 @@ __device__ __forceinline__ void lift_level_range(int np, int k0, int k1, Load lo
       if (lane >= L::HL && lane < 64 - L::HR && k < k1 && (w0 + u) < nwin) store(k, e[u], o[u]);
     }
   }
+}
+
+template <int F, int UNROLL, class Load, class Store>
+__device__ __forceinline__ void lift_level_range(int np, int k0, int k1, Load load, Store store) {
+  // the wrap is chosen once per level so that the unrolled loads carry no
+  // per-load branch (and no integer division when the level is wide)
+  if (np >= 64)
+    lift_windows<F, UNROLL, true>(np, k0, k1, load, store);
+  else
+    lift_windows<F, UNROLL, false>(np, k0, k1, load, store);
 }
 
 template <int F, int UNROLL, class Load, class Store>
@@ -208,15 +227,15 @@ __device__ __forceinline__ void pair_at(const V *src, int kc, int np, V &e, V &o
 
 // Level-1 input from the caller's pulse: complex64, or int16 I/Q widened to
 // int32.  Samples at index >= n are the zero padding up to N.
+// Branch-free: the load reads a clamped in-bounds index and the zero is
+// selected afterwards, so unrolled loads are not split by branches.
 __device__ __forceinline__ float2 rx_sample(const float2 *rx, long long n, int i) {
-  return (i < n) ? rx[i] : make_float2(0.f, 0.f);
+  const float2 v = rx[i < n ? i : n - 1];
+  return (i < n) ? v : make_float2(0.f, 0.f);
 }
 __device__ __forceinline__ int2 rx_sample(const short2 *rx, long long n, int i) {
-  if (i < n) {
-    short2 s = rx[i];
-    return make_int2(s.x, s.y);
-  }
-  return make_int2(0, 0);
+  const short2 s = rx[i < n ? i : n - 1];
+  return (i < n) ? make_int2(s.x, s.y) : make_int2(0, 0);
 }
 
 template <int F> struct RxOf { using T = float2; using Out = float; };
@@ -730,12 +749,28 @@ __global__ void batch_reset(int *counter) {
 // ===========================================================================
 // Lifting only: pyramid d_1 | ... | d_J | c_J written to HBM.
 // LDS holds the current approximation (odd levels at [0, N/2), even levels
-// at [N/2, 3N/4)).
+// at [N/2, 3N/4)).  The pulse is read and the pyramid written once, with
+// streaming (non-temporal) stores.
 // ===========================================================================
+// Threads per workgroup (measured: 512 for the complex64 filters; 256 for
+// the shorter int16 pulses, where more pulses in flight pay more).
+template <int F> struct LiftCfg { static constexpr int kThreads = 512; };
+template <> struct LiftCfg<F_LEGALL53_INT> { static constexpr int kThreads = 256; };
+
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef int i32x2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void store_stream(float2 *p, float2 v) {
+  __builtin_nontemporal_store(f32x2_t{v.x, v.y}, reinterpret_cast<f32x2_t *>(p));
+}
+__device__ __forceinline__ void store_stream(int2 *p, int2 v) {
+  __builtin_nontemporal_store(i32x2_t{v.x, v.y}, reinterpret_cast<i32x2_t *>(p));
+}
+
 template <int F>
-__global__ __launch_bounds__(256) void lift_many(int J, int N, const void *__restrict__ rx_all,
-                                                 long long n, long long rx_stride,
-                                                 void *__restrict__ pyr_all) {
+__global__ __launch_bounds__(LiftCfg<F>::kThreads) void lift_many(
+    int J, int N, const void *__restrict__ rx_all, long long n, long long rx_stride,
+    void *__restrict__ pyr_all) {
   using V = typename ElemOf<F>::T;
   using RxT = typename RxOf<F>::T;
   constexpr bool OB = YLift<F>::kOddBefore;
@@ -747,26 +782,28 @@ __global__ __launch_bounds__(256) void lift_many(int J, int N, const void *__res
   for (int l = 1; l <= J; ++l) {
     const int np = N >> l;
     V *dg = pyr + (N - (N >> (l - 1)));               // d_l
-    V *cl = (l == J) ? pyr + (N - np) : sm + ((l & 1) ? 0 : (N >> 1));
+    const bool last = l == J;
+    V *cl = last ? pyr + (N - np) : sm + ((l & 1) ? 0 : (N >> 1));
+    auto store = [&](int k, V c, V d) {
+      if (last)
+        store_stream(cl + k, c);
+      else
+        cl[k] = c;
+      store_stream(dg + k, d);
+    };
     if (l == 1) {
+      // two 8-byte (or 4-byte) loads per lane measured faster here than one
+      // 16-byte load per pair
       lift_level<F, 4>(
           np,
           [&](int kc, V &e, V &o) {
             e = rx_sample(rx, n, 2 * kc);
             o = rx_sample(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
           },
-          [&](int k, V c, V d) {
-            cl[k] = c;
-            dg[k] = d;
-          });
+          store);
     } else {
       const V *cin = sm + (((l - 1) & 1) ? 0 : (N >> 1));
-      lift_level<F, 2>(
-          np, [&](int kc, V &e, V &o) { pair_at<OB>(cin, kc, np, e, o); },
-          [&](int k, V c, V d) {
-            cl[k] = c;
-            dg[k] = d;
-          });
+      lift_level<F, 2>(np, [&](int kc, V &e, V &o) { pair_at<OB>(cin, kc, np, e, o); }, store);
     }
     __syncthreads();
   }
@@ -845,7 +882,7 @@ hipError_t launch_fused(const PlanDesc &plan, const FusedLayout &lay, const void
 template <int F>
 static hipError_t launch_lift_t(int J, int N, const void *rx, long long n, long long count,
                                 long long rx_stride, void *pyr, hipStream_t st) {
-  size_t shm = (size_t)(N / 2 + N / 4 + 1) * 8;
+  const size_t shm = (size_t)(N / 2 + N / 4 + 1) * sizeof(typename ElemOf<F>::T);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)lift_many<F>,
@@ -853,8 +890,8 @@ static hipError_t launch_lift_t(int J, int N, const void *rx, long long n, long 
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(lift_many<F>, dim3((unsigned)count), dim3(256), shm, st, J, N, rx, n,
-                     rx_stride, pyr);
+  hipLaunchKernelGGL(lift_many<F>, dim3((unsigned)count), dim3(LiftCfg<F>::kThreads), shm, st, J,
+                     N, rx, n, rx_stride, pyr);
   return hipGetLastError();
 }
 

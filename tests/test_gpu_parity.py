@@ -166,6 +166,44 @@ def test_lift_many_integer(dev):
         assert np.array_equal(pyr[i], want)
 
 
+@pytest.mark.parametrize("filt,J,n,count", [("cdf97", 5, 8192, 2000), ("d4", 5, 8192, 1100),
+                                              ("cdf97", 4, 16384, 300),
+                                              ("legall53_int", 6, 4096, 4000)])
+def test_lift_many_more_pulses_than_workgroups(dev, filt, J, n, count):
+    """Each workgroup lifts several pulses in turn (with the next pulse's
+    level-1 input prefetched when it fits, directly otherwise); sampled
+    pulses, including the first and the last, against the oracle."""
+    torch, S = dev
+    rng = np.random.default_rng(count)
+    print(f"[case] lift {filt} J={J} n={n} count={count}", flush=True)
+    if filt == "legall53_int":
+        rx = rng.integers(-2048, 2048, size=(count, n, 2)).astype(np.int16)
+    else:
+        rx = (rng.standard_normal((count, n)) + 1j * rng.standard_normal((count, n))).astype(
+            np.complex64)
+    pyr = S.lift_many(filt, J, torch.from_numpy(rx).cuda())
+    torch.cuda.synchronize()
+    N = O.transform_length(n, J)
+    for i in sorted({0, 1, count // 3, count // 2, count - 2, count - 1}):
+        g = pyr[i].cpu().numpy()
+        parts = []
+        if filt == "legall53_int":
+            re, im = rx[i, :, 0].astype(np.int64), rx[i, :, 1].astype(np.int64)
+            for _ in range(J):
+                (re, dre), (im, dim) = O.i2i_lift_y(re), O.i2i_lift_y(im)
+                parts.append(np.stack([dre, dim], -1))
+            want = np.concatenate(parts + [np.stack([re, im], -1)])
+            assert np.array_equal(g.astype(np.int64), want), i
+        else:
+            _, _, ylo, yhi = O.TAPS[filt]
+            c = O.zero_pad(rx[i].astype(np.complex128), N)
+            for _ in range(J):
+                c, d = O.analyze(c, ylo), O.analyze(c, yhi)
+                parts.append(d)
+            want = np.concatenate(parts + [c])
+            assert rel_l2(g.astype(complex), want) < 1e-6, i
+
+
 # ---------------------------------------------------------------------------
 # Integer path: bit-exact
 # ---------------------------------------------------------------------------

@@ -140,6 +140,32 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+def lifting_roofline(S, filt, J, rx, kernel, reps=20):
+    """The lifting-only kernel over the same batch: HBM roofline from the bytes
+    it must move (pulses in, pyramid out), timed with HIP events on the launch
+    stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    pyr = S.lift_many(filt, J, rx)
+    for _ in range(3):
+        S.lift_many(filt, J, rx, pyr=pyr)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        S.lift_many(filt, J, rx, pyr=pyr)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = rx.numel() * rx.element_size() + pyr.numel() * pyr.element_size()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    del pyr
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / PEAK_HBM_GBS, "us_per_launch": ms * 1e3, "bytes": nbytes,
+            "kernel": kernel}
+
+
 def bench_batched_uniform(args):
     import numpy as np
     import torch
@@ -191,22 +217,8 @@ def bench_batched_uniform(args):
         f"{achieved_tflops:.1f} TFLOP/s (wall {wall:.2f} s)")
 
     # Lifting-only kernel (a1 + a2), HBM roofline: 8 B in + 8 B out per sample.
-    pyr = torch.empty((args.count, N), dtype=torch.complex64, device=dev)
-    for _ in range(3):
-        S.lift_many(b.filter, J, rx, pyr=pyr)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    lift_reps = 20
-    for _ in range(lift_reps):
-        S.lift_many(b.filter, J, rx, pyr=pyr)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    lift_ms = e0.elapsed_time(e1) / lift_reps
-    lift_bytes = args.count * (args.n * 8 + N * 8)
-    lift_gbs = lift_bytes / (lift_ms * 1e-3) / 1e9
-    log(f"lifting only: {lift_ms * 1e3:.1f} us, {lift_gbs:.0f} GB/s")
+    lift = lifting_roofline(S, b.filter, J, rx, "lift_many<CDF97>")
+    log(f"lifting only: {lift['us_per_launch']:.1f} us, {lift['achieved']:.0f} GB/s")
 
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
@@ -244,9 +256,7 @@ def bench_batched_uniform(args):
                      "frac": achieved_tflops / PEAK_FP32_MATRIX_TFLOPS,
                      "traffic": profiled_traffic() if (args.count, args.n) == (4096, 8192) else None,
                      "kernel": "fused_correlate<CDF97>"},
-        "lifting_roofline": {"bound": "hbm", "achieved": lift_gbs, "peak": PEAK_HBM_GBS,
-                             "unit": "GB/s", "frac": lift_gbs / PEAK_HBM_GBS,
-                             "us_per_launch": lift_ms * 1e3, "kernel": "lift_many<CDF97>"},
+        "lifting_roofline": lift,
         "cpu_baseline": cpu,
     }
     plan.free()
@@ -410,6 +420,8 @@ def bench_integer(args):
     value = count * n / (ms * 1e-3)
     tflops = flops / (ms * 1e-3) / 1e12
     log(f"integer: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s (FP64 MFMA)")
+    lift = lifting_roofline(S, "legall53_int", J, rx, "lift_many<LEGALL53_INT>")
+    log(f"lifting only: {lift['us_per_launch']:.1f} us, {lift['achieved']:.0f} GB/s")
     cpu = None
     if args.cpu:
         items = [("legall53_int", J, ib.ref_iq, ib.rx_iq[i]) for i in range(16)]
@@ -427,6 +439,7 @@ def bench_integer(args):
                                f"bit-exact int64 planes"},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 78.6, "unit": "TFLOP/s",
                      "frac": tflops / 78.6, "traffic": None, "kernel": "fused_correlate<INT53>"},
+        "lifting_roofline": lift,
         "cpu_baseline": cpu,
     }
 

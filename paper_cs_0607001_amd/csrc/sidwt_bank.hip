@@ -180,7 +180,6 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   const BankTile *tb = tl + t0;
   const int rloc = 64 * wr + (lane & 31);        // row of the first row tile
   const int g = lane >> 5;                        // K half: offsets 4g..4g+3 of a step
-  const int col = lane & 31;
   f32x16 acc[2][4];
 #pragma unroll
   for (int h = 0; h < 2; ++h)

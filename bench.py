@@ -140,6 +140,27 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
+def plain_per_pulse(S, plans, rx, out):
+    """The plain per-pulse GPU path: one sidwt_correlate call (one launch)
+    per pulse, issued back to back on the current stream.  Returns the ms of
+    one pass over all pulses (after one untimed pass)."""
+    import torch
+    stream = torch.cuda.current_stream()
+
+    def one_pass():
+        for p, x, o in zip(plans, rx, out):
+            S.correlate(p, x, out=o)
+    one_pass()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    one_pass()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
 def lifting_roofline(S, filt, J, rx, kernel, reps=20):
     """The lifting-only kernel over the same batch: HBM roofline from the bytes
     it must move (pulses in, pyramid out), timed with HIP events on the launch
@@ -216,6 +237,11 @@ def bench_batched_uniform(args):
     log(f"fused: {ms_step:.3f} ms/step, {value / 1e9:.2f} G samples/s, "
         f"{achieved_tflops:.1f} TFLOP/s (wall {wall:.2f} s)")
 
+    # The plain per-pulse path over the same batch (one launch per pulse).
+    pp_ms = plain_per_pulse(S, [plan] * args.count, list(rx), list(out))
+    log(f"plain per-pulse path: {pp_ms:.2f} ms per batch ({pp_ms / ms_step:.1f}x the fused "
+        f"batch's time)")
+
     # Lifting-only kernel (a1 + a2), HBM roofline: 8 B in + 8 B out per sample.
     lift = lifting_roofline(S, b.filter, J, rx, "lift_many<CDF97>")
     log(f"lifting only: {lift['us_per_launch']:.1f} us, {lift['achieved']:.0f} GB/s")
@@ -257,6 +283,9 @@ def bench_batched_uniform(args):
                      "traffic": profiled_traffic() if (args.count, args.n) == (4096, 8192) else None,
                      "kernel": "fused_correlate<CDF97>"},
         "lifting_roofline": lift,
+        "plain_per_pulse": {"ms_per_batch": pp_ms,
+                            "samples_per_s": args.count * args.n / (pp_ms * 1e-3),
+                            "batched_speedup": pp_ms / ms_step},
         "cpu_baseline": cpu,
     }
     plan.free()
@@ -372,6 +401,8 @@ def bench_uneven(args):
     value = total / (ms * 1e-3)
     tflops = flops / (ms * 1e-3) / 1e12
     log(f"uneven: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s")
+    pp_ms = plain_per_pulse(S, plans, rx, out)
+    log(f"plain per-pulse path: {pp_ms:.2f} ms per batch ({pp_ms / ms:.1f}x the batched time)")
     cpu = None
     if args.cpu:
         idx = np.argsort(ns)[np.linspace(0, count - 1, 32).astype(int)]
@@ -393,6 +424,8 @@ def bench_uneven(args):
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
                      "kernel": "batch_persistent"},
+        "plain_per_pulse": {"ms_per_batch": pp_ms, "samples_per_s": total / (pp_ms * 1e-3),
+                            "batched_speedup": pp_ms / ms},
         "cpu_baseline": cpu,
     }
 
@@ -658,9 +691,11 @@ def bench_serving(args):
     b32 = S.Batch(plans, [x.numel() for x in prx])
     b32.tune(prx, pouts)
     ms_fp32 = _time_steps(lambda: b32.run(prx, pouts), 3, 1, stream)
+    ms_pp = plain_per_pulse(S, plans, prx, pouts)
     sub_samples = sum(pulses[i][0] for i in sub)
-    log(f"bank FP16 hi+lo: {ms_bank:.2f} ms, FP32 plain path: {ms_fp32:.2f} ms "
-        f"for {len(sub)} requests ({len(plans)} reference correlations)")
+    log(f"bank FP16 hi+lo: {ms_bank:.2f} ms, FP32 uneven batch: {ms_fp32:.2f} ms, FP32 plain "
+        f"per-pulse path: {ms_pp:.2f} ms for {len(sub)} requests ({len(plans)} reference "
+        f"correlations)")
     # per-scale error of the bank (FP16 hi+lo) against the oracle, sampled lags
     outs = bank.correlate(rx, Js)
     torch.cuda.synchronize()
@@ -692,6 +727,7 @@ def bench_serving(args):
                    "saturation": sat, "sweep": sweep,
                    "bank_vs_fp32": {"requests": len(sub), "samples": sub_samples,
                                     "bank_ms": ms_bank, "fp32_ms": ms_fp32,
+                                    "fp32_per_pulse_ms": ms_pp,
                                     "bank_samples_per_s": sub_samples / (ms_bank * 1e-3),
                                     "fp32_samples_per_s": sub_samples / (ms_fp32 * 1e-3)},
                    "bank_rel_l2_per_scale_max": err},

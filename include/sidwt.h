@@ -112,7 +112,12 @@ int sidwt_set_stream(sidwt_plan *p, void *hip_stream);
 /* One pulse: rx (device, n samples) -> out (device, sidwt_out_len
  * elements).  Fused kernel: y-side lifting of all J levels in LDS, each
  * level correlated against the plan's phases as soon as it exists
- * (eq. (20)/(20a)). */
+ * (eq. (20)/(20a)).  A pulse too long for one workgroup's LDS goes through
+ * the tiled path instead (levels lifted into an HBM scratch pyramid, then
+ * lag tiles on every CU, as in the uneven batch); the plan keeps that
+ * path's device buffers for the last (n, count) it saw, so calls on one
+ * plan must not overlap.  SIDWT_E_UNSUPPORTED for an integer plan in that
+ * case. */
 int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out);
 
 /* A uniform batch in one launch: `count` pulses of n samples each, pulse i

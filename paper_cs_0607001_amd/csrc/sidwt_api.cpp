@@ -33,6 +33,10 @@ struct sidwt_plan {
   PlanDesc desc;
   void *coef;
   size_t coef_bytes;
+  // Pulses too long for the whole-pulse LDS layout go through the tiled
+  // batch path; its buffers are kept for the last (n, count) seen.
+  mutable sidwt_batch *tiled = nullptr;
+  mutable int64_t tiled_n = 0, tiled_count = 0;
 };
 
 namespace {
@@ -148,6 +152,7 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
 
 void sidwt_free(sidwt_plan *p) {
   if (!p) return;
+  sidwt_batch_free(p->tiled);
   if (p->coef) {
     (void)hipDeviceSynchronize();
     (void)hipFree(p->coef);
@@ -174,9 +179,29 @@ int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t
   if (rc) return rc;
   if (rx_stride < n || out_stride < (int64_t)p->J * N) return SIDWT_E_INVAL;
   FusedLayout lay;
-  if (make_layout(p->desc, N, &lay) != 0) return SIDWT_E_UNSUPPORTED;
-  return map_err(sidwt::launch_fused(p->desc, lay, rx, n, count, rx_stride, out, out_stride,
-                                     p->stream));
+  if (make_layout(p->desc, N, &lay) == 0)
+    return map_err(sidwt::launch_fused(p->desc, lay, rx, n, count, rx_stride, out, out_stride,
+                                       p->stream));
+  // Too long for one workgroup's LDS: levels lifted into an HBM scratch
+  // pyramid, then lag tiles (the uneven-batch machinery, one plan).
+  if (p->filter == SIDWT_LEGALL53_INT) return SIDWT_E_UNSUPPORTED;
+  if (!p->tiled || p->tiled_n != n || p->tiled_count != count) {
+    sidwt_batch_free(p->tiled);
+    p->tiled = nullptr;
+    std::vector<const sidwt_plan *> ps((size_t)count, p);
+    std::vector<int64_t> ns((size_t)count, n);
+    rc = sidwt_batch_create(ps.data(), ns.data(), (int)count, &p->tiled);
+    if (rc) return rc;
+    p->tiled_n = n;
+    p->tiled_count = count;
+  }
+  std::vector<const void *> rxp((size_t)count);
+  std::vector<void *> outp((size_t)count);
+  for (int64_t i = 0; i < count; ++i) {
+    rxp[i] = static_cast<const char *>(rx) + i * rx_stride * 8;
+    outp[i] = static_cast<char *>(out) + i * out_stride * 8;
+  }
+  return sidwt_batch_run(p->tiled, rxp.data(), outp.data(), p->stream);
 }
 
 int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out) {

@@ -134,3 +134,31 @@ def test_batch_rejects_integer_plans(dev):
         with pytest.raises(S.SidwtError) as e:
             S.Batch([p], [256])
         assert e.value.code == -5
+
+
+@pytest.mark.parametrize("n,J,count", [(65536, 12, 1), (40000, 11, 3)])
+def test_plain_path_handles_pulses_beyond_one_workgroup(dev, n, J, count):
+    """sidwt_correlate / sidwt_correlate_many on pulses too long for the
+    whole-pulse LDS layout (tiled path), against the oracle at sampled lags,
+    twice (the plan's cached tiled buffers are reused)."""
+    torch, S = dev
+    rng = np.random.default_rng(n + count)
+    ref = W.reference_set(61, count=1, m_lo=900, m_hi=1000)[0]
+    ys = [W.echoes(n, ref, rng) for _ in range(count)]
+    print(f"[case] plain tiled n={n} J={J} count={count}", flush=True)
+    with S.plan_create("cdf97", J, ref) as plan:
+        rx = torch.from_numpy(np.stack(ys).astype(np.complex64)).cuda()
+        for rep in range(2):
+            if count == 1:
+                out = S.correlate(plan, rx[0])[None]
+            else:
+                out = S.correlate_many(plan, rx)
+            torch.cuda.synchronize()
+            N = O.transform_length(n, J)
+            for i in range(count):
+                g = out[i].cpu().numpy()
+                for j in (0, J // 2, J - 1):
+                    lags = np.concatenate([[0, N - 1], rng.integers(0, N, 12)])
+                    want = O.correlate_at("cdf97", J, ref, ys[i], j, lags)
+                    e = np.linalg.norm(g[j, lags] - want) / np.linalg.norm(want)
+                    assert e <= 1e-5, (rep, i, j, e)

@@ -52,7 +52,13 @@ struct PlanDesc {
 // c[q mod L].  A band is two planes (re, im); a plane is T polyphase
 // sub-sequences (element q lives in sub-sequence q mod T at index q / T,
 // sub-sequences Ls words apart), so the rows of an MFMA tile, which step
-// through the lag axis T elements apart, read consecutive words.
+// through the lag axis T elements apart, read consecutive words.  For
+// complex64 bands with T >= 4 the sub-sequences are interleaved in groups of
+// four: sub-sequences
+// 4k..4k+3 share a 4*Ls-word block, index i of sub-sequence 4k + t at word
+// 4i + t, so the four consecutive lag offsets one lane needs per MFMA group
+// are one aligned 16-byte word quad (and the rows still read consecutive
+// quads).
 struct FusedLayout {
   int N;
   int J;
@@ -241,9 +247,12 @@ __host__ __device__ inline int pos_mod(int a, int b) {
   return r < 0 ? r + b : r;
 }
 
-// Word offset of element q inside one plane of a band (see FusedLayout).
-__device__ __forceinline__ int poly_off(int q, int logT, int Ls) {
-  return (q & ((1 << logT) - 1)) * Ls + (q >> logT);
+// Word offset of element q inside one plane of a band (see FusedLayout);
+// grouped: complex64 bands (quads of sub-sequences when T >= 4).
+__host__ __device__ inline int poly_off(int q, int logT, int Ls, bool grouped) {
+  const int t = q & ((1 << logT) - 1), i = q >> logT;
+  if (grouped && logT >= 2) return (t >> 2) * (4 * Ls) + 4 * i + (t & 3);
+  return t * Ls + i;
 }
 
 // MFMA operand/accumulator vector types.

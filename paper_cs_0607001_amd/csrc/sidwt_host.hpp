@@ -254,6 +254,8 @@ inline int tile_layout_violation(const PlanDesc &d, const FusedLayout &lay) {
   for (int l = 1; l <= lay.J; ++l) {
     const int L = N >> l, T = lay.T[l], P = 1 << l;
     if (T < 1 || (1 << lay.logT[l]) != T || L % T) return 21;
+    // grouped sub-sequences (T >= 4) are read as aligned word quads
+    if (T >= 4 && ((lay.region_off[l] | lay.band_size[l] | lay.plane_stride[l]) & 3)) return 29;
     const int rows = lay.rows[l];
     if (rows < 64 || (rows & 63)) return 30;
     for (int b = 0; b < 2; ++b) {
@@ -282,6 +284,9 @@ inline int layout_violation(const PlanDesc &d, const FusedLayout &lay) {
   for (int l = 1; l <= lay.J; ++l) {
     const int L = N >> l, T = lay.T[l], Ls = lay.Ls[l], P = 1 << l;
     if (T < 1 || (1 << lay.logT[l]) != T || L % T) return 1;
+    // grouped sub-sequences (T >= 4) are read as aligned word quads
+    if (!is_int && T >= 4 && ((lay.region_off[l] | lay.band_size[l] | lay.plane_stride[l]) & 3))
+      return 16;
     // element q < ext: plane offset (q%T)*Ls + q/T must stay below T*Ls
     if ((lay.ext[l] + T - 1) / T > Ls) return 2;
     if (T * Ls + 32 > lay.plane_stride[l]) return 3;

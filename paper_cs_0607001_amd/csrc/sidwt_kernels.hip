@@ -329,11 +329,15 @@ __device__ __forceinline__ int row_start(const LevelView &v, int p1, int b) {
 }
 
 // FP32 correlation of rows [row_begin, row_end) of one level (32x32x2
-// tiles, two row tiles per wave that share the weight operand).  outp is
-// the plane's output (complex64 as float pairs), indexed by global lag.
-__device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, float *smf,
-                                   float *__restrict__ outp) {
-  const int P = v.P, l = v.l, T = v.T, logT = v.logT, Ls = v.Ls;
+// tiles, two row tiles per wave that share the weight operand), for a
+// compile-time Toeplitz block TT.  outp is the plane's output (complex64 as
+// float pairs), indexed by global lag.
+template <int TT>
+__device__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, float *smf,
+                                     float *__restrict__ outp) {
+  constexpr int LT = TT == 1 ? 0 : TT == 2 ? 1 : TT == 4 ? 2 : 3;
+  static_assert(TT == 1 || TT == 2 || TT == 4 || TT == 8, "Toeplitz block");
+  const int P = v.P, l = v.l, Ls = v.Ls;
   const int nrows = v.row_end - v.row_begin;
   const int mtiles = (nrows + 31) >> 5;
   const int mpairs = (mtiles + 1) >> 1;
@@ -349,8 +353,8 @@ __device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, flo
     const int pcc = min(v.pc, P - r0);
     stage_weights(plan, v, r0, pcc, W);
     __syncthreads();
-    // P < 16: one column tile holds all (p0, r) pairs, p0 < T; otherwise
-    // T = 1 and each column tile holds 16 phases.
+    // P < 16: one column tile holds all (p0, r) pairs, p0 < TT; otherwise
+    // TT = 1 and each column tile holds 16 phases.
     const int ntn = (P < 16) ? 1 : (pcc >> 4);
     const int ntiles = mpairs * ntn;
     for (int tile = wave; tile < ntiles; tile += nw) {
@@ -361,7 +365,7 @@ __device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, flo
       if (P < 16) {
         r = cc & (P - 1);
         p0 = cc >> l;
-        colok = p0 < T;
+        colok = p0 < TT;
         if (!colok) p0 = 0;
       } else {
         r = ntile * 16 + cc;
@@ -380,42 +384,61 @@ __device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, flo
       for (int b = 0; b < 2; ++b) {
         const int G = v.U[b] >> 2;
         const float *pl = smf + v.base[b] + ci * v.plane_stride;
-        const float *pa = pl + row_start(v, p1a, b);
-        const float *pb = pl + row_start(v, p1b, b);
+        const int ia = row_start(v, p1a, b), ib = row_start(v, p1b, b);  // sub-sequence index
         const float *wp = reinterpret_cast<const float *>(W + (b ? pcc * V0 : 0) + r * (b ? V1 : V0)) +
-                          2 * (T - 1 - p0) + (ci ^ co);
-        float a0[4], a1[4], w[4];
+                          2 * (TT - 1 - p0) + (ci ^ co);
+        // The four data values of group g (lag offsets 4g..4g+3) of a row
+        // whose first element has sub-sequence index i.
+        auto data = [&](int i, int g, float(&A)[4]) {
+          if constexpr (TT >= 4) {
+            // one quad: block g mod (TT/4), index i + g / (TT/4)
+            constexpr int GB = TT / 4, LGB = LT - 2;
+            const f32x4 q4 = *reinterpret_cast<const f32x4 *>(
+                pl + (g & (GB - 1)) * (4 * Ls) + 4 * (i + (g >> LGB)));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int off = (q & (T - 1)) * Ls + (q >> logT);
-          a0[q] = pa[off];
-          a1[q] = pb[off];
-          w[q] = wp[2 * q];
-        }
-        for (int g = 0; g < G; ++g) {
-          float na0[4], na1[4], nw_[4];
-          const int un = (g + 1 < G) ? 4 * (g + 1) : 4 * g;
+            for (int q = 0; q < 4; ++q) A[q] = q4[q];
+          } else if constexpr (TT == 2) {
+            // offsets u = 4g + q: sub-sequence q & 1, index i + 2g + q / 2
+            const float *p = pl + i + 2 * g;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) A[q] = p[(q & 1) * Ls + (q >> 1)];
+          } else {
+            const float *p = pl + i + 4 * g;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) A[q] = p[q];
+          }
+        };
+        // Groups of 4 lag offsets in two register sets (x, y): the loads of
+        // a group are issued one whole group of MFMAs before its use, with
+        // no register moves in between (a move would make the wave wait
+        // for the loads it just issued).  Columns with colok == false are
+        // computed but never stored.
+        auto load = [&](int g, float(&A0)[4], float(&A1)[4], float(&Wt)[4]) {
+          data(ia, g, A0);
+          data(ib, g, A1);
+          const float *w = wp + 8 * g;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) Wt[q] = w[2 * q];
+        };
+        auto mma = [&](const float(&A0)[4], const float(&A1)[4], const float(&Wt)[4]) {
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
-            const int u = un + q;
-            const int off = (u & (T - 1)) * Ls + (u >> logT);
-            na0[q] = pa[off];
-            na1[q] = pb[off];
-            nw_[q] = wp[2 * u];
+            const float wq = neg ? -Wt[q] : Wt[q];
+            acc0 = mfma32(A0[q], wq, acc0);
+            acc1 = mfma32(A1[q], wq, acc1);
           }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float wq = neg ? -w[q] : w[q];
-            wq = colok ? wq : 0.f;
-            acc0 = mfma32(a0[q], wq, acc0);
-            acc1 = mfma32(a1[q], wq, acc1);
-          }
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            a0[q] = na0[q];
-            a1[q] = na1[q];
-            w[q] = nw_[q];
-          }
+        };
+        float xa0[4], xa1[4], xw[4], ya0[4], ya1[4], yw[4];
+        load(0, xa0, xa1, xw);
+        for (int g = 0; g < G; g += 2) {
+          load(min(g + 1, G - 1), ya0, ya1, yw);
+          __builtin_amdgcn_sched_barrier(0);
+          mma(xa0, xa1, xw);
+          __builtin_amdgcn_sched_barrier(0);
+          load(min(g + 2, G - 1), xa0, xa1, xw);
+          __builtin_amdgcn_sched_barrier(0);
+          if (g + 1 < G) mma(ya0, ya1, yw);
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
       if (colok) {
@@ -426,7 +449,7 @@ __device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, flo
           for (int i = 0; i < 16; ++i) {
             const int pp1 = v.row_begin + mp * 64 + h * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
             if (pp1 < v.row_end) {
-              const long long s = (long long)P * (pp1 * T + p0) + r0 + r;
+              const long long s = (long long)P * (pp1 * TT + p0) + r0 + r;
               __builtin_nontemporal_store(h ? acc1[i] : acc0[i], &outp[2 * s + co]);
             }
           }
@@ -434,6 +457,16 @@ __device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, flo
       }
     }
     __syncthreads();
+  }
+}
+
+__device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, float *smf,
+                                   float *__restrict__ outp) {
+  switch (v.T) {
+    case 8: correlate_rows_f32_t<8>(plan, v, smf, outp); break;
+    case 4: correlate_rows_f32_t<4>(plan, v, smf, outp); break;
+    case 2: correlate_rows_f32_t<2>(plan, v, smf, outp); break;
+    default: correlate_rows_f32_t<1>(plan, v, smf, outp); break;
   }
 }
 
@@ -490,8 +523,8 @@ __device__ void correlate_level_int(const PlanDesc &plan, const LevelView &v, in
                         2 * (du - p0 + T - 1) + (ci ^ co);
         for (int st = 0; st < steps; ++st) {
           const int u = 2 * st + du;
-          const int a0 = pl[poly_off(qa + u, logT, Ls)];
-          const int a1 = pl[poly_off(qb + u, logT, Ls)];
+          const int a0 = pl[poly_off(qa + u, logT, Ls, false)];
+          const int a1 = pl[poly_off(qb + u, logT, Ls, false)];
           int wv = wp[4 * st];
           wv = neg ? -wv : wv;
           wv = colok ? wv : 0;
@@ -527,8 +560,9 @@ __device__ __forceinline__ void store_pair(S *sm, const FusedLayout &lay, int l,
   S *b0 = sm + lay.region_off[l];
   S *b1 = b0 + lay.band_size[l];
   const int ps = lay.plane_stride[l];
+  constexpr bool grouped = std::is_same<V, float2>::value;
   for (int q = k; q < lay.ext[l]; q += L) {
-    const int o = poly_off(q, lay.logT[l], lay.Ls[l]);
+    const int o = poly_off(q, lay.logT[l], lay.Ls[l], grouped);
     b0[o] = c.x;
     b0[o + ps] = c.y;
     b1[o] = d.x;
@@ -539,7 +573,7 @@ __device__ __forceinline__ void store_pair(S *sm, const FusedLayout &lay, int l,
 template <class V, class S>
 __device__ __forceinline__ V load_elem(const S *sm, const FusedLayout &lay, int l, int q) {
   const S *b0 = sm + lay.region_off[l];
-  const int o = poly_off(q, lay.logT[l], lay.Ls[l]);
+  const int o = poly_off(q, lay.logT[l], lay.Ls[l], std::is_same<V, float2>::value);
   V v;
   v.x = b0[o];
   v.y = b0[o + lay.plane_stride[l]];
@@ -700,7 +734,7 @@ __device__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const Bat
     const int step = pos_mod((int)blockDim.x, v.L);
     for (int q = threadIdx.x; q < Wb; q += blockDim.x) {
       const float2 x = src[e];
-      const int o = poly_off(q, v.logT, v.Ls);
+      const int o = poly_off(q, v.logT, v.Ls, true);
       pl[o] = x.x;
       pl[o + v.plane_stride] = x.y;
       e += step;

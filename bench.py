@@ -120,6 +120,8 @@ def main():
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--cpu-baseline", dest="cpu", action="store_true", default=True)
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false")
+    ap.add_argument("--no-per-pulse", dest="per_pulse", action="store_false", default=True,
+                    help="skip the plain per-pulse comparison (keeps profiles to the batch)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run an elementwise kernel that reads and writes 256 MiB "
                          "(calibrates the HBM byte counters)")
@@ -238,9 +240,11 @@ def bench_batched_uniform(args):
         f"{achieved_tflops:.1f} TFLOP/s (wall {wall:.2f} s)")
 
     # The plain per-pulse path over the same batch (one launch per pulse).
-    pp_ms = plain_per_pulse(S, [plan] * args.count, list(rx), list(out))
-    log(f"plain per-pulse path: {pp_ms:.2f} ms per batch ({pp_ms / ms_step:.1f}x the fused "
-        f"batch's time)")
+    pp_ms = None
+    if args.per_pulse:
+        pp_ms = plain_per_pulse(S, [plan] * args.count, list(rx), list(out))
+        log(f"plain per-pulse path: {pp_ms:.2f} ms per batch ({pp_ms / ms_step:.1f}x the fused "
+            f"batch's time)")
 
     # Lifting-only kernel (a1 + a2), HBM roofline: 8 B in + 8 B out per sample.
     lift = lifting_roofline(S, b.filter, J, rx, "lift_many<CDF97>")
@@ -283,9 +287,9 @@ def bench_batched_uniform(args):
                      "traffic": profiled_traffic() if (args.count, args.n) == (4096, 8192) else None,
                      "kernel": "fused_correlate<CDF97>"},
         "lifting_roofline": lift,
-        "plain_per_pulse": {"ms_per_batch": pp_ms,
-                            "samples_per_s": args.count * args.n / (pp_ms * 1e-3),
-                            "batched_speedup": pp_ms / ms_step},
+        "plain_per_pulse": None if pp_ms is None else {
+            "ms_per_batch": pp_ms, "samples_per_s": args.count * args.n / (pp_ms * 1e-3),
+            "batched_speedup": pp_ms / ms_step},
         "cpu_baseline": cpu,
     }
     plan.free()
@@ -401,8 +405,9 @@ def bench_uneven(args):
     value = total / (ms * 1e-3)
     tflops = flops / (ms * 1e-3) / 1e12
     log(f"uneven: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s")
-    pp_ms = plain_per_pulse(S, plans, rx, out)
-    log(f"plain per-pulse path: {pp_ms:.2f} ms per batch ({pp_ms / ms:.1f}x the batched time)")
+    pp_ms = plain_per_pulse(S, plans, rx, out) if args.per_pulse else None
+    if pp_ms is not None:
+        log(f"plain per-pulse path: {pp_ms:.2f} ms per batch ({pp_ms / ms:.1f}x the batched time)")
     cpu = None
     if args.cpu:
         idx = np.argsort(ns)[np.linspace(0, count - 1, 32).astype(int)]
@@ -424,8 +429,9 @@ def bench_uneven(args):
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
                      "kernel": "batch_persistent"},
-        "plain_per_pulse": {"ms_per_batch": pp_ms, "samples_per_s": total / (pp_ms * 1e-3),
-                            "batched_speedup": pp_ms / ms},
+        "plain_per_pulse": None if pp_ms is None else {
+            "ms_per_batch": pp_ms, "samples_per_s": total / (pp_ms * 1e-3),
+            "batched_speedup": pp_ms / ms},
         "cpu_baseline": cpu,
     }
 

@@ -726,19 +726,34 @@ __device__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const Bat
   // rows never exceeds the layout's tile rows, a multiple of 64).
   const int rows64 = (it.rows + 63) & ~63;
   const float2 *src0 = scratch + p.scratch + scratch_level_off(p.N, l);
+  // Each thread fetches 8 elements before storing any, so 8 HBM reads are
+  // in flight instead of one: e is always a valid element index, so the
+  // loads need no condition; only the LDS stores check q < Wb.
+  constexpr int KB = 8;
+  const int nt = blockDim.x;
+  const int step = pos_mod(nt, v.L);
   for (int b = 0; b < 2; ++b) {
     const float2 *src = src0 + (b ? v.L : 0);
     const int Wb = rows64 * v.T + v.U[b];
     float *pl = smf + v.base[b];
     int e = pos_mod(it.row0 * v.T + v.lo[b] + (int)threadIdx.x, v.L);
-    const int step = pos_mod((int)blockDim.x, v.L);
-    for (int q = threadIdx.x; q < Wb; q += blockDim.x) {
-      const float2 x = src[e];
-      const int o = poly_off(q, v.logT, v.Ls, true);
-      pl[o] = x.x;
-      pl[o + v.plane_stride] = x.y;
-      e += step;
-      if (e >= v.L) e -= v.L;
+    for (int q0 = threadIdx.x; q0 < Wb; q0 += KB * nt) {
+      float2 x[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        x[k] = src[e];
+        e += step;
+        if (e >= v.L) e -= v.L;
+      }
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const int q = q0 + k * nt;
+        if (q < Wb) {
+          const int o = poly_off(q, v.logT, v.Ls, true);
+          pl[o] = x[k].x;
+          pl[o + v.plane_stride] = x[k].y;
+        }
+      }
     }
   }
   __syncthreads();

@@ -200,45 +200,60 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
       pw[t] = wts + (t < nt_w ? tb[t].off[b] : 0) + 4 * lane;
       S = max(S, steps[t]);
     }
-    V8 bh[4], bl[4];
+    // Two operand sets (x, y) alternate: the loads of a step are issued one
+    // whole step of MFMAs before its use and no register moves follow them
+    // (a move would make the wave wait for the loads it just issued).  Load
+    // indices are clamped to valid steps, so no load sits under a branch;
+    // only the MFMAs of a tile past its own K length are skipped.
+    int last[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (steps[t] > 0) {
-        bh[t] = gload8<V8>(pw[t]);
-        bl[t] = gload8<V8>(pw[t] + 256);
+    for (int t = 0; t < 4; ++t) last[t] = steps[t] > 0 ? steps[t] - 1 : 0;
+    auto loadB = [&](int st, V8(&BH)[4], V8(&BL)[4]) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const unsigned *pp = pw[t] + min(st, last[t]) * kBankStepWords;
+        BH[t] = gload8<V8>(pp);
+        BL[t] = gload8<V8>(pp + 256);
       }
-    for (int s = 0; s < S; ++s) {
-      V8 nh[4], nl[4];
+    };
+    auto loadA = [&](int st, V8(&AH)[2], V8(&AL)[2]) {
+      const int u0 = 8 * st + 4 * g;
+      AH[0] = load8<V8>(dhi + rloc + u0);
+      AL[0] = load8<V8>(dlo + rloc + u0);
+      AH[1] = load8<V8>(dhi + rloc + 32 + u0);
+      AL[1] = load8<V8>(dlo + rloc + 32 + u0);
+    };
+    auto mma = [&](int st, const V8(&AH)[2], const V8(&AL)[2], const V8(&BH)[4],
+                   const V8(&BL)[4]) {
 #pragma unroll
       for (int t = 0; t < 4; ++t)
-        if (s + 1 < steps[t]) {
-          nh[t] = gload8<V8>(pw[t] + (s + 1) * kBankStepWords);
-          nl[t] = gload8<V8>(pw[t] + (s + 1) * kBankStepWords + 256);
-        }
-      const int u0 = 8 * s + 4 * g;
-      V8 ahi[2], alo[2];
-      ahi[0] = load8<V8>(dhi + rloc + u0);
-      alo[0] = load8<V8>(dlo + rloc + u0);
-      ahi[1] = load8<V8>(dhi + rloc + 32 + u0);
-      alo[1] = load8<V8>(dlo + rloc + 32 + u0);
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (s < steps[t]) {
-          acc[0][t] = H::mma(ahi[0], bh[t], acc[0][t]);
-          acc[0][t] = H::mma(ahi[0], bl[t], acc[0][t]);
-          acc[0][t] = H::mma(alo[0], bh[t], acc[0][t]);
+        if (st < steps[t]) {
+          acc[0][t] = H::mma(AH[0], BH[t], acc[0][t]);
+          acc[0][t] = H::mma(AH[0], BL[t], acc[0][t]);
+          acc[0][t] = H::mma(AL[0], BH[t], acc[0][t]);
           if (two) {
-            acc[1][t] = H::mma(ahi[1], bh[t], acc[1][t]);
-            acc[1][t] = H::mma(ahi[1], bl[t], acc[1][t]);
-            acc[1][t] = H::mma(alo[1], bh[t], acc[1][t]);
+            acc[1][t] = H::mma(AH[1], BH[t], acc[1][t]);
+            acc[1][t] = H::mma(AH[1], BL[t], acc[1][t]);
+            acc[1][t] = H::mma(AL[1], BH[t], acc[1][t]);
           }
         }
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (s + 1 < steps[t]) {
-          bh[t] = nh[t];
-          bl[t] = nl[t];
-        }
+    };
+    if (S > 0) {
+      V8 xbh[4], xbl[4], ybh[4], ybl[4], xah[2], xal[2], yah[2], yal[2];
+      loadB(0, xbh, xbl);
+      loadA(0, xah, xal);
+      for (int st = 0; st < S; st += 2) {
+        loadB(min(st + 1, S - 1), ybh, ybl);
+        loadA(min(st + 1, S - 1), yah, yal);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(st, xah, xal, xbh, xbl);
+        __builtin_amdgcn_sched_barrier(0);
+        loadB(min(st + 2, S - 1), xbh, xbl);
+        loadA(min(st + 2, S - 1), xah, xal);
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < S) mma(st + 1, yah, yal, ybh, ybl);
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
 

@@ -30,11 +30,14 @@
 
 namespace sidwt {
 hipError_t batch_set_lds(size_t bytes);
-hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu);
-hipError_t launch_batch(const PlanDesc *plans, const FusedLayout *lays, const BatchPulse *pulses,
-                        const BatchItem *items, int nitems, int *counter, float2 *scratch,
-                        const LiftChunk *const *chunks, const int *nchunks, int Jmax, int grid,
-                        size_t lds_bytes, hipStream_t st);
+hipError_t batch_occupancy(bool tiles_only, size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
+                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
+                              float2 *scratch, hipStream_t st);
+hipError_t launch_batch_items(bool tiles_only, const PlanDesc *plans, const FusedLayout *lays,
+                              const BatchPulse *pulses, const BatchItem *items, int nitems,
+                              int *counter, float2 *scratch, int grid, size_t lds_bytes,
+                              hipStream_t st);
 }  // namespace sidwt
 
 // The plan object is defined in sidwt_api.cpp; the batch only needs its
@@ -96,6 +99,12 @@ struct sidwt_batch {
   int nchunks[kMaxLevels + 2] = {0};
   int Jmax = 0, n_fused = 0, n_tiles = 0, grid = 0;
   size_t lds_bytes = 0;
+  // Items run in up to three persistent launches, in this order: whole-pulse
+  // items (general kernel), tile items whose layout needs more LDS than two
+  // workgroups per CU allow, the remaining tile items (tile-only kernel, two
+  // or more workgroups per CU).  cls_n / cls_grid / cls_lds per class.
+  int cls_n[3] = {0, 0, 0}, cls_grid[3] = {0, 0, 0};
+  size_t cls_lds[3] = {0, 0, 0};
   long long scratch_elems = 0;
   // device
   PlanDesc *d_plans = nullptr;
@@ -150,6 +159,7 @@ int build(sidwt_batch *b) {
   b->Jmax = 0;
   b->n_fused = b->n_tiles = 0;
   std::vector<std::pair<double, BatchItem>> costed;
+  std::vector<char> costed_cls;
   for (int i = 0; i < b->count; ++i) {
     const int pi = b->pulse_plan[i];
     const PlanDesc &d = b->plans[pi];
@@ -180,6 +190,7 @@ int build(sidwt_batch *b) {
       it.kind = 0;
       it.pulse = i;
       costed.push_back({item_cost(d, it, (int)N, L), it});
+      costed_cls.push_back(0);
       ++b->n_fused;
     } else {
       p.scratch = scratch;
@@ -194,6 +205,7 @@ int build(sidwt_batch *b) {
           it.row0 = r0;
           it.rows = std::min(L.rows[l], rows_l - r0);
           costed.push_back({item_cost(d, it, (int)N, L), it});
+          costed_cls.push_back(L.total > kLdsWordsTwoPerCu ? 1 : 2);
           ++b->n_tiles;
         }
         const int np = (int)(N >> l);
@@ -202,11 +214,22 @@ int build(sidwt_batch *b) {
       }
     }
   }
-  std::stable_sort(costed.begin(), costed.end(),
-                   [](const std::pair<double, BatchItem> &x, const std::pair<double, BatchItem> &y) {
-                     return x.first > y.first;
-                   });
-  for (auto &c : costed) b->items.push_back(c.second);
+  // by class, each class longest first
+  std::vector<int> order(costed.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (costed_cls[x] != costed_cls[y]) return costed_cls[x] < costed_cls[y];
+    return costed[x].first > costed[y].first;
+  });
+  size_t cls_words[3] = {0, 0, 0};
+  for (int c = 0; c < 3; ++c) b->cls_n[c] = 0;
+  for (int k : order) {
+    const BatchItem &it = costed[k].second;
+    const int c = costed_cls[k];
+    ++b->cls_n[c];
+    cls_words[c] = std::max<size_t>(cls_words[c], b->lays[b->pulses[it.pulse].layout].total);
+    b->items.push_back(it);
+  }
   for (int l = 0; l <= kMaxLevels + 1; ++l) b->chunk_off[l] = b->nchunks[l] = 0;
   for (int l = 1; l <= kMaxLevels; ++l) {
     b->chunk_off[l] = (int)b->chunks.size();
@@ -232,23 +255,38 @@ int build(sidwt_batch *b) {
   }
   hipError_t e = batch_set_lds(b->lds_bytes);
   if (e != hipSuccess) return map_err(e, "hipFuncSetAttribute (LDS)");
-  int per_cu = 0, cus = 0, dev = 0;
-  e = batch_occupancy(b->lds_bytes, &per_cu);
-  if (e == hipSuccess) e = hipGetDevice(&dev);
+  int cus = 0, dev = 0;
+  e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return map_err(e, "occupancy query");
-  if (per_cu < 1) return SIDWT_E_UNSUPPORTED;
-  b->grid = std::max(1, std::min<int>(per_cu * cus, (int)b->items.size()));
+  if (e != hipSuccess) return map_err(e, "device query");
+  b->grid = 0;
+  for (int c = 0; c < 3; ++c) {
+    b->cls_lds[c] = std::max<size_t>(cls_words[c] * 4, 1024);
+    b->cls_grid[c] = 0;
+    if (b->cls_n[c] == 0) continue;
+    int per_cu = 0;
+    e = batch_occupancy(c > 0, b->cls_lds[c], &per_cu);
+    if (e != hipSuccess) return map_err(e, "occupancy query");
+    if (per_cu < 1) return SIDWT_E_UNSUPPORTED;
+    b->cls_grid[c] = std::max(1, std::min<int>(per_cu * cus, b->cls_n[c]));
+    b->grid = std::max(b->grid, b->cls_grid[c]);
+  }
   return SIDWT_OK;
 }
 
 int enqueue(sidwt_batch *b, hipStream_t st) {
   const LiftChunk *chunk_ptr[kMaxLevels + 2];
   for (int l = 0; l <= kMaxLevels + 1; ++l) chunk_ptr[l] = b->d_chunks + b->chunk_off[l];
-  return map_err(launch_batch(b->d_plans, b->d_lays, b->d_pulses, b->d_items, (int)b->items.size(),
-                              b->d_counter, b->d_scratch, chunk_ptr, b->nchunks, b->Jmax, b->grid,
-                              b->lds_bytes, st),
-                 "kernel launch");
+  hipError_t e = launch_lift_levels(b->d_plans, b->d_pulses, chunk_ptr, b->nchunks, b->Jmax,
+                                    b->d_scratch, st);
+  int first = 0;
+  for (int c = 0; c < 3 && e == hipSuccess; ++c) {
+    e = launch_batch_items(c > 0, b->d_plans, b->d_lays, b->d_pulses, b->d_items + first,
+                           b->cls_n[c], b->d_counter + c, b->d_scratch, b->cls_grid[c],
+                           b->cls_lds[c], st);
+    first += b->cls_n[c];
+  }
+  return map_err(e, "kernel launch");
 }
 
 int ensure_graph(sidwt_batch *b) {
@@ -337,7 +375,7 @@ int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int cou
     b->N.push_back(N);
     b->J.push_back(d->J);
   }
-  hipError_t e = hipMalloc(&b->d_counter, sizeof(int));
+  hipError_t e = hipMalloc(&b->d_counter, 3 * sizeof(int));
   int rc = map_err(e);
   if (!rc) rc = build(b);
   if (rc) {

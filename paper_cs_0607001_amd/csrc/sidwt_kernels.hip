@@ -760,6 +760,12 @@ __device__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const Bat
   correlate_rows_f32(plan, v, smf, reinterpret_cast<float *>(p.out) + 2LL * (l - 1) * p.N);
 }
 
+// Persistent kernel over work items taken from an atomic counter.  The
+// general instance runs whole-pulse and tile items; the TILES_ONLY instance
+// compiles only the tile path (83 instead of 243 VGPRs: the inlined
+// whole-pulse path of three filters sets the general one's register count),
+// so tile items can run at two workgroups per CU.
+template <bool TILES_ONLY>
 __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
     const PlanDesc *__restrict__ plans, const FusedLayout *__restrict__ lays,
     const BatchPulse *__restrict__ pulses, const BatchItem *__restrict__ items, int nitems,
@@ -769,25 +775,27 @@ __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     __syncthreads();
-    const int i = next;
+    const int i = __builtin_amdgcn_readfirstlane(next);
     __syncthreads();
     if (i >= nitems) break;  // the counter only grows: every workgroup exits
     const BatchItem it = items[i];
     const BatchPulse &p = pulses[it.pulse];
     const PlanDesc &plan = plans[p.plan];
     const FusedLayout &lay = lays[p.layout];
-    if (it.kind == 0) {
-      const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
-      float *out = reinterpret_cast<float *>(p.out);
-      switch (plan.filter) {
-        case F_LEGALL53: fused_pulse<F_LEGALL53>(plan, lay, rx, p.n, out, smem_batch); break;
-        case F_CDF97: fused_pulse<F_CDF97>(plan, lay, rx, p.n, out, smem_batch); break;
-        case F_D4: fused_pulse<F_D4>(plan, lay, rx, p.n, out, smem_batch); break;
-        default: break;
+    if constexpr (!TILES_ONLY) {
+      if (it.kind == 0) {
+        const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
+        float *out = reinterpret_cast<float *>(p.out);
+        switch (plan.filter) {
+          case F_LEGALL53: fused_pulse<F_LEGALL53>(plan, lay, rx, p.n, out, smem_batch); break;
+          case F_CDF97: fused_pulse<F_CDF97>(plan, lay, rx, p.n, out, smem_batch); break;
+          case F_D4: fused_pulse<F_D4>(plan, lay, rx, p.n, out, smem_batch); break;
+          default: break;
+        }
+        continue;
       }
-    } else {
-      tile_item(plan, lay, p, it, scratch, reinterpret_cast<float *>(smem_batch));
     }
+    if (it.kind == 1) tile_item(plan, lay, p, it, scratch, reinterpret_cast<float *>(smem_batch));
   }
 }
 
@@ -983,34 +991,43 @@ hipError_t launch_lift(int filter, int J, int N, const void *rx, long long n, lo
 }
 
 hipError_t batch_set_lds(size_t bytes) {
-  return hipFuncSetAttribute((const void *)batch_persistent,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  hipError_t e = hipFuncSetAttribute((const void *)batch_persistent<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)batch_persistent<true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  return e;
 }
 
-hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent,
+hipError_t batch_occupancy(bool tiles_only, size_t lds_bytes, int *blocks_per_cu) {
+  if (tiles_only)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent<true>,
+                                                        kFusedThreads, lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_persistent<false>,
                                                       kFusedThreads, lds_bytes);
 }
 
-hipError_t launch_batch(const PlanDesc *plans, const FusedLayout *lays, const BatchPulse *pulses,
-                        const BatchItem *items, int nitems, int *counter, float2 *scratch,
-                        const LiftChunk *const *chunks, const int *nchunks, int Jmax, int grid,
-                        size_t lds_bytes, hipStream_t st) {
+// Lifting of every tiled pulse into its scratch pyramid, level by level.
+hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
+                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
+                              float2 *scratch, hipStream_t st);
+
+// One persistent launch over items [0, nitems) with its own counter.
+hipError_t launch_batch_items(bool tiles_only, const PlanDesc *plans, const FusedLayout *lays,
+                              const BatchPulse *pulses, const BatchItem *items, int nitems,
+                              int *counter, float2 *scratch, int grid, size_t lds_bytes,
+                              hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, counter);
   hipError_t e = hipGetLastError();
-  for (int l = 1; l <= Jmax && e == hipSuccess; ++l) {
-    if (nchunks[l] == 0) continue;
-    hipLaunchKernelGGL(batch_lift, dim3(nchunks[l]), dim3(256), 0, st, plans, pulses, chunks[l], l,
-                       scratch);
-    e = hipGetLastError();
-  }
   if (e != hipSuccess) return e;
-  if (nitems > 0) {
-    hipLaunchKernelGGL(batch_persistent, dim3(grid), dim3(kFusedThreads), lds_bytes, st, plans,
-                       lays, pulses, items, nitems, counter, scratch);
-    e = hipGetLastError();
-  }
-  return e;
+  if (tiles_only)
+    hipLaunchKernelGGL(batch_persistent<true>, dim3(grid), dim3(kFusedThreads), lds_bytes, st,
+                       plans, lays, pulses, items, nitems, counter, scratch);
+  else
+    hipLaunchKernelGGL(batch_persistent<false>, dim3(grid), dim3(kFusedThreads), lds_bytes, st,
+                       plans, lays, pulses, items, nitems, counter, scratch);
+  return hipGetLastError();
 }
 
 hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,

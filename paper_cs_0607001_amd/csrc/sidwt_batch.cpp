@@ -134,6 +134,13 @@ void drop_graph(sidwt_batch *b) {
   b->graph = nullptr;
 }
 
+// LDS words a tile item of level l needs: the level's band windows and its
+// staged weights (the tile layout's total is the largest over its levels).
+int tile_level_words(const FusedLayout &L, int l) {
+  const int row = 2 * (L.V[l][0] + L.V[l][1]);
+  return std::max(2 * L.band_size[l], L.w_at[l] + std::min(L.pc[l], 1 << l) * row);
+}
+
 double item_cost(const PlanDesc &d, const BatchItem &it, int N, const FusedLayout &lay) {
   if (it.kind == 0) {
     double c = 0;
@@ -160,6 +167,7 @@ int build(sidwt_batch *b) {
   b->n_fused = b->n_tiles = 0;
   std::vector<std::pair<double, BatchItem>> costed;
   std::vector<char> costed_cls;
+  std::vector<int> costed_words;   // LDS words the item needs
   for (int i = 0; i < b->count; ++i) {
     const int pi = b->pulse_plan[i];
     const PlanDesc &d = b->plans[pi];
@@ -190,6 +198,7 @@ int build(sidwt_batch *b) {
       it.kind = 0;
       it.pulse = i;
       costed.push_back({item_cost(d, it, (int)N, L), it});
+      costed_words.push_back(L.total);
       costed_cls.push_back(0);
       ++b->n_fused;
     } else {
@@ -205,7 +214,8 @@ int build(sidwt_batch *b) {
           it.row0 = r0;
           it.rows = std::min(L.rows[l], rows_l - r0);
           costed.push_back({item_cost(d, it, (int)N, L), it});
-          costed_cls.push_back(L.total > kLdsWordsTwoPerCu ? 1 : 2);
+          costed_words.push_back(tile_level_words(L, l));
+          costed_cls.push_back(costed_words.back() > kLdsWordsTwoPerCu ? 1 : 2);
           ++b->n_tiles;
         }
         const int np = (int)(N >> l);
@@ -227,7 +237,7 @@ int build(sidwt_batch *b) {
     const BatchItem &it = costed[k].second;
     const int c = costed_cls[k];
     ++b->cls_n[c];
-    cls_words[c] = std::max<size_t>(cls_words[c], b->lays[b->pulses[it.pulse].layout].total);
+    cls_words[c] = std::max<size_t>(cls_words[c], costed_words[k]);
     b->items.push_back(it);
   }
   for (int l = 0; l <= kMaxLevels + 1; ++l) b->chunk_off[l] = b->nchunks[l] = 0;

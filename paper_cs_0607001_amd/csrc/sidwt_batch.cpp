@@ -247,7 +247,7 @@ int build(sidwt_batch *b) {
     b->chunks.insert(b->chunks.end(), per_level[l].begin(), per_level[l].end());
   }
   b->scratch_elems = scratch;
-  b->lds_bytes = std::max<size_t>(lds_words * 4, 1024);
+  b->lds_bytes = std::max<size_t>(lds_words * 4, b->n_tiles ? kBalMinLdsBytes : 1024);
   // device side
   int rc = upload(&b->d_plans, &b->c_plans, b->plans);
   if (!rc) rc = upload(&b->d_lays, &b->c_lays, b->lays);
@@ -271,7 +271,9 @@ int build(sidwt_batch *b) {
   if (e != hipSuccess) return map_err(e, "device query");
   b->grid = 0;
   for (int c = 0; c < 3; ++c) {
-    b->cls_lds[c] = std::max<size_t>(cls_words[c] * 4, 1024);
+    // tile classes: at least one partial-tile slot per wave (free below two
+    // workgroups per CU, which the tile kernel's registers allow at most)
+    b->cls_lds[c] = std::max<size_t>(cls_words[c] * 4, c > 0 ? kBalMinLdsBytes : 1024);
     b->cls_grid[c] = 0;
     if (b->cls_n[c] == 0) continue;
     int per_cu = 0;

@@ -23,6 +23,11 @@ constexpr int kMaxLevels = 16;
 // Threads per workgroup of the fused kernel (8 waves: two workgroups per CU
 // give four waves per SIMD to hide LDS latency behind the MFMA pipe).
 constexpr int kFusedThreads = 512;
+// Per-wave LDS slot (words) for a partial 64x32 FP32 tile handed between
+// waves, and the allocation the tile-only batch kernel needs for one slot
+// per wave.
+constexpr int kBalSlotWords = 2 * 16 * 64;
+constexpr int kBalMinLdsBytes = (kFusedThreads / 64) * kBalSlotWords * 4;
 
 // Per level l (1..J) and band b (0 = approximation a~, 1 = detail b~): the
 // stored linear support [lo, lo+len) of every phase, and the element offset

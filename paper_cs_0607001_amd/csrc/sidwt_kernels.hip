@@ -332,8 +332,17 @@ __device__ __forceinline__ int row_start(const LevelView &v, int p1, int b) {
 // tiles, two row tiles per wave that share the weight operand), for a
 // compile-time Toeplitz block TT.  outp is the plane's output (complex64 as
 // float pairs), indexed by global lag.
-template <int TT>
-__device__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, float *smf,
+//
+// A tile's work is its G0 + G1 groups of four lag offsets (band 0, then
+// band 1).  Tiles go to waves round-robin.  With BAL, on a level's last
+// column chunk, when the last round would leave more than half of the waves
+// idle, its rem tiles are each cut into NW / rem equal group ranges, one per
+// wave: the partial sums pass through LDS slots of kBalSlotWords per wave
+// (aliasing the band windows and weights, which are no longer read) and
+// are added in wave order, so the result does not depend on timing.  BAL
+// needs an LDS allocation of at least NW * kBalSlotWords words.
+template <int TT, bool BAL>
+__device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, float *smf,
                                      float *__restrict__ outp) {
   constexpr int LT = TT == 1 ? 0 : TT == 2 ? 1 : TT == 4 ? 2 : 3;
   static_assert(TT == 1 || TT == 2 || TT == 4 || TT == 8, "Toeplitz block");
@@ -341,9 +350,11 @@ __device__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, f
   const int nrows = v.row_end - v.row_begin;
   const int mtiles = (nrows + 31) >> 5;
   const int mpairs = (mtiles + 1) >> 1;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   float2 *W = reinterpret_cast<float2 *>(smf + v.w_at);
   const int V0 = v.V[0], V1 = v.V[1];
+  const int G0 = v.U[0] >> 2, GT = G0 + (v.U[1] >> 2);
   const int row = lane & 31;
   const int ci = lane >> 5;
   const int co = lane & 1;
@@ -357,32 +368,37 @@ __device__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, f
     // TT = 1 and each column tile holds 16 phases.
     const int ntn = (P < 16) ? 1 : (pcc >> 4);
     const int ntiles = mpairs * ntn;
-    for (int tile = wave; tile < ntiles; tile += nw) {
-      const int mp = tile % mpairs;
-      const int ntile = tile / mpairs;
-      int r, p0;
-      bool colok;
+    // Tile (mp, nt): row pair mp, column tile nt.  Column r / block offset
+    // p0 of this lane; false for the columns of a P < 16 tile beyond TT
+    // blocks (computed, never stored).
+    auto place = [&](int nt, int &r, int &p0) {
       if (P < 16) {
         r = cc & (P - 1);
         p0 = cc >> l;
-        colok = p0 < TT;
-        if (!colok) p0 = 0;
-      } else {
-        r = ntile * 16 + cc;
-        p0 = 0;
-        colok = true;
+        const bool ok = p0 < TT;
+        if (!ok) p0 = 0;
+        return ok;
       }
+      r = nt * 16 + cc;
+      p0 = 0;
+      return true;
+    };
+    // acc0/acc1 (row tiles 2*mp, 2*mp + 1) += groups [ga, gb) of tile (mp, nt).
+    auto accumulate = [&](int mp, int nt, int ga, int gb, f32x16 &acc0, f32x16 &acc1) {
+      int r, p0;
+      (void)place(nt, r, p0);
       const int p1a = v.row_begin + mp * 64 + row;
       const int p1b = p1a + 32;
-      f32x16 acc0, acc1;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        acc0[i] = 0.f;
-        acc1[i] = 0.f;
-      }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
         const int G = v.U[b] >> 2;
+        int glo = 0, ghi = G;
+        if constexpr (BAL) {
+          const int off = b ? G0 : 0;
+          glo = max(ga - off, 0);
+          ghi = min(gb - off, G);
+          if (glo >= ghi) continue;
+        }
         const float *pl = smf + v.base[b] + ci * v.plane_stride;
         const int ia = row_start(v, p1a, b), ib = row_start(v, p1b, b);  // sub-sequence index
         const float *wp = reinterpret_cast<const float *>(W + (b ? pcc * V0 : 0) + r * (b ? V1 : V0)) +
@@ -411,8 +427,7 @@ __device__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, f
         // Groups of 4 lag offsets in two register sets (x, y): the loads of
         // a group are issued one whole group of MFMAs before its use, with
         // no register moves in between (a move would make the wave wait
-        // for the loads it just issued).  Columns with colok == false are
-        // computed but never stored.
+        // for the loads it just issued).
         auto load = [&](int g, float(&A0)[4], float(&A1)[4], float(&Wt)[4]) {
           data(ia, g, A0);
           data(ib, g, A1);
@@ -429,44 +444,107 @@ __device__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, f
           }
         };
         float xa0[4], xa1[4], xw[4], ya0[4], ya1[4], yw[4];
-        load(0, xa0, xa1, xw);
-        for (int g = 0; g < G; g += 2) {
-          load(min(g + 1, G - 1), ya0, ya1, yw);
+        load(glo, xa0, xa1, xw);
+        for (int g = glo; g < ghi; g += 2) {
+          load(min(g + 1, ghi - 1), ya0, ya1, yw);
           __builtin_amdgcn_sched_barrier(0);
           mma(xa0, xa1, xw);
           __builtin_amdgcn_sched_barrier(0);
-          load(min(g + 2, G - 1), xa0, xa1, xw);
+          load(min(g + 2, ghi - 1), xa0, xa1, xw);
           __builtin_amdgcn_sched_barrier(0);
-          if (g + 1 < G) mma(ya0, ya1, yw);
+          if (g + 1 < ghi) mma(ya0, ya1, yw);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
-      if (colok) {
-        // register i of lane l: row 8*(i/4) + 4*(l/32) + i%4, column l%32
+    };
+    auto store = [&](int mp, int nt, const f32x16 &acc0, const f32x16 &acc1) {
+      int r, p0;
+      if (!place(nt, r, p0)) return;
+      // With BAL the lane index is made opaque here so that the compiler
+      // cannot precompute these addresses ahead of the MFMA loop (which would
+      // hold them in registers through it).
+      int ln = lane;
+      if constexpr (BAL) asm volatile("" : "+v"(ln));
+      // register i of lane l: row 8*(i/4) + 4*(l/32) + i%4, column l%32
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < 2; ++h) {
 #pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int pp1 = v.row_begin + mp * 64 + h * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-            if (pp1 < v.row_end) {
-              const long long s = (long long)P * (pp1 * TT + p0) + r0 + r;
-              __builtin_nontemporal_store(h ? acc1[i] : acc0[i], &outp[2 * s + co]);
+        for (int i = 0; i < 16; ++i) {
+          const int pp1 = v.row_begin + mp * 64 + h * 32 + 8 * (i >> 2) + 4 * (ln >> 5) + (i & 3);
+          if (pp1 < v.row_end) {
+            const long long s = (long long)P * (pp1 * TT + p0) + r0 + r;
+            __builtin_nontemporal_store(h ? acc1[i] : acc0[i], &outp[2 * s + co]);
+          }
+        }
+      }
+    };
+    auto zero = [](f32x16 &a) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) a[i] = 0.f;
+    };
+    // Whole tiles round-robin; with BAL, on a level's last chunk, the
+    // rem = ntiles mod NW tiles of an incomplete last round (rem <= NW / 2)
+    // are each cut into c = NW / rem group ranges, one per wave.
+    constexpr int NW = kFusedThreads / 64;  // both batch kernels run kFusedThreads
+    int rem = 0;
+    if constexpr (BAL) {
+      if (r0 + pcc == P && ntiles % NW <= NW / 2) rem = ntiles % NW;
+    }
+    for (int tile = wave; tile < ntiles - rem; tile += nw) {
+      const int mp = tile % mpairs, nt = tile / mpairs;
+      f32x16 acc0, acc1;
+      zero(acc0);
+      zero(acc1);
+      accumulate(mp, nt, 0, GT, acc0, acc1);
+      store(mp, nt, acc0, acc1);
+    }
+    if (rem > 0) {
+      const int c = NW / rem;
+      const int part = wave % c;
+      const int tile = ntiles - rem + wave / c;
+      const int mp = tile % mpairs, nt = tile / mpairs;
+      f32x16 acc0, acc1;
+      zero(acc0);
+      zero(acc1);
+      if (wave < rem * c) accumulate(mp, nt, part * GT / c, (part + 1) * GT / c, acc0, acc1);
+      __syncthreads();  // every wave is done with the windows and weights
+      if (wave < rem * c && part > 0) {
+        f32x4 *sl = reinterpret_cast<f32x4 *>(smf + wave * kBalSlotWords) + lane;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          sl[k * 64] = f32x4{acc0[4 * k], acc0[4 * k + 1], acc0[4 * k + 2], acc0[4 * k + 3]};
+          sl[(k + 4) * 64] = f32x4{acc1[4 * k], acc1[4 * k + 1], acc1[4 * k + 2], acc1[4 * k + 3]};
+        }
+      }
+      __syncthreads();
+      if (wave < rem * c && part == 0) {
+        for (int k2 = 1; k2 < c; ++k2) {  // in wave order: the sum does not depend on timing
+          const f32x4 *sl = reinterpret_cast<const f32x4 *>(smf + (wave + k2) * kBalSlotWords) + lane;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const f32x4 a = sl[k * 64], b = sl[(k + 4) * 64];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              acc0[4 * k + j] += a[j];
+              acc1[4 * k + j] += b[j];
             }
           }
         }
+        store(mp, nt, acc0, acc1);
       }
     }
     __syncthreads();
   }
 }
 
-__device__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, float *smf,
+template <bool BAL = false>
+__device__ __forceinline__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, float *smf,
                                    float *__restrict__ outp) {
   switch (v.T) {
-    case 8: correlate_rows_f32_t<8>(plan, v, smf, outp); break;
-    case 4: correlate_rows_f32_t<4>(plan, v, smf, outp); break;
-    case 2: correlate_rows_f32_t<2>(plan, v, smf, outp); break;
-    default: correlate_rows_f32_t<1>(plan, v, smf, outp); break;
+    case 8: correlate_rows_f32_t<8, BAL>(plan, v, smf, outp); break;
+    case 4: correlate_rows_f32_t<4, BAL>(plan, v, smf, outp); break;
+    case 2: correlate_rows_f32_t<2, BAL>(plan, v, smf, outp); break;
+    default: correlate_rows_f32_t<1, BAL>(plan, v, smf, outp); break;
   }
 }
 
@@ -698,7 +776,8 @@ __global__ __launch_bounds__(256) void batch_lift(const PlanDesc *__restrict__ p
 // Lag tile of a long pulse: level l, rows [row0, row0 + rows).  `tl` is the
 // pulse's tile layout (per level: T, windows, staging geometry; bands start
 // at word 0, band 1 at 2*plane_stride, weights at w_at).
-__device__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const BatchPulse &p,
+template <bool BAL>
+__device__ __forceinline__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const BatchPulse &p,
                           const BatchItem &it, const float2 *__restrict__ scratch, float *smf) {
   const int l = it.level;
   LevelView v;
@@ -757,14 +836,16 @@ __device__ void tile_item(const PlanDesc &plan, const FusedLayout &tl, const Bat
     }
   }
   __syncthreads();
-  correlate_rows_f32(plan, v, smf, reinterpret_cast<float *>(p.out) + 2LL * (l - 1) * p.N);
+  correlate_rows_f32<BAL>(plan, v, smf, reinterpret_cast<float *>(p.out) + 2LL * (l - 1) * p.N);
 }
 
 // Persistent kernel over work items taken from an atomic counter.  The
 // general instance runs whole-pulse and tile items; the TILES_ONLY instance
 // compiles only the tile path (83 instead of 243 VGPRs: the inlined
 // whole-pulse path of three filters sets the general one's register count),
-// so tile items can run at two workgroups per CU.
+// so tile items can run at two workgroups per CU; it also spreads each
+// tile item's work evenly over the waves (see correlate_rows_f32_t), which
+// needs an LDS allocation of at least kBalMinLdsBytes.
 template <bool TILES_ONLY>
 __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
     const PlanDesc *__restrict__ plans, const FusedLayout *__restrict__ lays,
@@ -795,7 +876,8 @@ __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
         continue;
       }
     }
-    if (it.kind == 1) tile_item(plan, lay, p, it, scratch, reinterpret_cast<float *>(smem_batch));
+    if (it.kind == 1)
+      tile_item<TILES_ONLY>(plan, lay, p, it, scratch, reinterpret_cast<float *>(smem_batch));
   }
 }
 
@@ -1018,6 +1100,7 @@ hipError_t launch_batch_items(bool tiles_only, const PlanDesc *plans, const Fuse
                               int *counter, float2 *scratch, int grid, size_t lds_bytes,
                               hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
+  if (tiles_only && lds_bytes < (size_t)kBalMinLdsBytes) return hipErrorInvalidValue;
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, counter);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

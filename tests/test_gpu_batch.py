@@ -79,6 +79,31 @@ def test_uneven_batch_matches_oracle(dev):
         p.free()
 
 
+@pytest.mark.parametrize("window", [1024, 4096])
+def test_all_tile_split_matches_oracle(dev, window):
+    """Every pulse as lag tiles: short pulses give levels of one to four
+    tiles, whose groups are cut over several waves and summed through LDS."""
+    torch, S = dev
+    plans, rx, meta, cache = make_batch(S, torch, seed=45)
+    ns = [x.numel() for x in rx]
+    print(f"[case] all tiles, tile_window={window}", flush=True)
+    with S.Batch(plans, ns) as b:
+        b.config(0, window)
+        info = b.info()
+        assert info["whole_pulse_items"] == 0 and info["tile_items"] > 0
+        out = S.batch_outputs(plans, ns, rx[0].device)
+        b.run(rx, out)
+        torch.cuda.synchronize()
+        check_against_oracle(out, meta)
+        first = [o.clone() for o in out]
+        b.run(rx, out)
+        torch.cuda.synchronize()
+        for o, r in zip(out, first):
+            assert torch.equal(o, r)
+    for p in cache.values():
+        p.free()
+
+
 def test_work_splits_agree_and_graph_replays(dev):
     torch, S = dev
     plans, rx, meta, cache = make_batch(S, torch, seed=43)

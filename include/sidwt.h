@@ -78,9 +78,10 @@ typedef enum {
 enum {
   SIDWT_OK = 0,
   SIDWT_E_INVAL = -1,   /* NULL pointer, n<1, m<1, J<1 or J>16, N/2^J<2,
-                           unknown filter, bad count                      */
+                           unknown filter, negative count                 */
   SIDWT_E_SIZE = -2,    /* m > N; integer plan support would wrap at this N;
-                           or a size beyond the library's limits          */
+                           integer plan whose sums could reach 2^53; or a
+                           size beyond the library's limits               */
   SIDWT_E_NOMEM = -3,   /* device allocation failed                       */
   SIDWT_E_DEVICE = -4,  /* a HIP runtime error (including earlier faults) */
   SIDWT_E_UNSUPPORTED = -5 /* valid request this build does not handle    */
@@ -93,7 +94,12 @@ enum {
  * of the reference, a~_l^{(r)} and b~_l^{(r)} for l = 1..J and
  * r = 0..2^l-1 (Sec. II "even and odd shifts"; Fig. 5), on their linear
  * support.  The plan owns its device memory until sidwt_free.  The call is
- * synchronous.  *out is set only on success. */
+ * synchronous.  *out is set only on success.
+ * Integer plans (int16 I/Q reference) are exact for every int16 pulse: the
+ * plan is refused with SIDWT_E_SIZE, before any device work, when a bound
+ * on the partial sums of some level (full-scale pulse, this reference's
+ * peak, growth 2 per level for details and 3/2 for approximations) reaches
+ * 2^53, the limit of exact integers in the FP64 accumulation. */
 int sidwt_plan_create(int filter, int J, const void *ref, int64_t m,
                       sidwt_plan **out);
 
@@ -123,7 +129,8 @@ int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out);
 /* A uniform batch in one launch: `count` pulses of n samples each, pulse i
  * at rx + i * rx_stride samples; its planes at out + i * out_stride
  * elements (elements are complex64 or int64 pairs).  rx_stride >= n and
- * out_stride >= sidwt_out_len(p, n). */
+ * out_stride >= sidwt_out_len(p, n).  count = 0 checks the sizes and
+ * launches nothing (rx and out may then be NULL). */
 int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n,
                          int64_t count, int64_t rx_stride, void *out,
                          int64_t out_stride);
@@ -134,7 +141,7 @@ int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n,
  * N elements at pyr + i*N in the order  d_1 | d_2 | ... | d_J | c_J
  * (lengths N/2, N/4, ..., N/2^J, N/2^J).  Element type = output element
  * type of the lifting (complex64 for float filters, int32 pairs for the
- * integer filter). */
+ * integer filter).  count = 0 checks the sizes and launches nothing. */
 int sidwt_lift_many(int filter, int J, const void *rx, int64_t n,
                     int64_t count, int64_t rx_stride, void *pyr,
                     void *hip_stream);
@@ -219,7 +226,8 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
  * out[i] (device, sidwt_bank_out_len(bank, n[i], J[i]) complex64, laid out
  * [e][j][k] for eligible reference e, scale j, lag k; 16-byte aligned, else
  * SIDWT_E_INVAL).  All requests go through one lifting pass and one GEMM
- * launch on `hip_stream`; returns once both are queued. */
+ * launch on `hip_stream`; returns once both are queued.  count = 0 is a
+ * no-op (nothing launched or timed). */
 int sidwt_bank_correlate(sidwt_bank *bank, const void *const *rx, const int64_t *n,
                          const int *J, void *const *out, int count, void *hip_stream);
 

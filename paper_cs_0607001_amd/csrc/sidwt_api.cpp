@@ -88,6 +88,19 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
   if (!out || !ref || !valid_filter(filter) || J < 1 || J > SIDWT_MAX_LEVELS || m < 1)
     return SIDWT_E_INVAL;
   if (m > kMaxRef) return SIDWT_E_SIZE;
+  if (filter == SIDWT_LEGALL53_INT) {
+    // Exactness of the FP64 accumulation, checked on the host before any
+    // device work (for a full-scale int16 pulse and this reference's peak).
+    PlanDesc probe;
+    std::memset(&probe, 0, sizeof(probe));
+    probe.J = J;
+    probe.m = (int)m;
+    plan_windows(filter, J, (int)m, &probe);
+    const int16_t *r16 = static_cast<const int16_t *>(ref);
+    int peak = 0;
+    for (int64_t i = 0; i < 2 * m; ++i) peak = std::max(peak, std::abs((int)r16[i]));
+    if (!int_sums_exact(probe, peak)) return SIDWT_E_SIZE;
+  }
   sidwt_plan *p = new (std::nothrow) sidwt_plan();
   if (!p) return SIDWT_E_NOMEM;
   p->filter = filter;
@@ -173,11 +186,13 @@ int sidwt_set_stream(sidwt_plan *p, void *hip_stream) {
 
 int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
                          int64_t rx_stride, void *out, int64_t out_stride) {
-  if (!p || !rx || !out || count < 1 || count > 0x7fffffff) return SIDWT_E_INVAL;
+  if (!p || count < 0 || count > 0x7fffffff) return SIDWT_E_INVAL;
   int64_t N = 0;
   int rc = check_pulse(p, n, &N);
   if (rc) return rc;
   if (rx_stride < n || out_stride < (int64_t)p->J * N) return SIDWT_E_INVAL;
+  if (count == 0) return SIDWT_OK;
+  if (!rx || !out) return SIDWT_E_INVAL;
   FusedLayout lay;
   if (make_layout(p->desc, N, &lay) == 0)
     return map_err(sidwt::launch_fused(p->desc, lay, rx, n, count, rx_stride, out, out_stride,
@@ -211,12 +226,14 @@ int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out) {
 
 int sidwt_lift_many(int filter, int J, const void *rx, int64_t n, int64_t count,
                     int64_t rx_stride, void *pyr, void *hip_stream) {
-  if (!rx || !pyr || !valid_filter(filter) || J < 1 || J > SIDWT_MAX_LEVELS || n < 1 ||
-      count < 1 || count > 0x7fffffff || rx_stride < n)
+  if (!valid_filter(filter) || J < 1 || J > SIDWT_MAX_LEVELS || n < 1 || count < 0 ||
+      count > 0x7fffffff || rx_stride < n)
     return SIDWT_E_INVAL;
   const int64_t N = transform_length(n, J);
   if ((N >> J) < 2) return SIDWT_E_INVAL;
   if (2 * (N / 2 + N / 4 + 1) > kLdsWords) return SIDWT_E_UNSUPPORTED;
+  if (count == 0) return SIDWT_OK;
+  if (!rx || !pyr) return SIDWT_E_INVAL;
   return map_err(sidwt::launch_lift(filter, J, (int)N, rx, n, count, rx_stride, pyr,
                                     static_cast<hipStream_t>(hip_stream)));
 }

@@ -397,7 +397,8 @@ int sidwt_bank_info(const sidwt_bank *bk, int64_t *v, int nv) {
 
 int sidwt_bank_correlate(sidwt_bank *bk, const void *const *rx, const int64_t *n, const int *J,
                          void *const *out, int count, void *hip_stream) {
-  if (!bk) return SIDWT_E_INVAL;
+  if (!bk || count < 0) return SIDWT_E_INVAL;
+  if (count == 0) return SIDWT_OK;
   if (!bk->ws) {
     int rc = sidwt_bank_ws_create(bk, &bk->ws);
     if (rc) return rc;
@@ -408,7 +409,9 @@ int sidwt_bank_correlate(sidwt_bank *bk, const void *const *rx, const int64_t *n
 int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const *rx,
                             const int64_t *n, const int *J, void *const *out, int count,
                             void *hip_stream) {
-  if (!bk || !ws || !rx || !n || !J || !out || count < 1) return SIDWT_E_INVAL;
+  if (!bk || !ws || count < 0) return SIDWT_E_INVAL;
+  if (count == 0) return SIDWT_OK;
+  if (!rx || !n || !J || !out) return SIDWT_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   std::vector<BatchPulse> pulses(count);
   std::vector<BankSeg> segs;

@@ -65,6 +65,27 @@ inline long long plan_windows(int filter, int J, int m, PlanDesc *d) {
   return off;
 }
 
+// Integer plans accumulate integer products in FP64, which is exact while
+// every partial sum stays below 2^53 in magnitude.  One level of the
+// reversible 5/3 lifting with inputs bounded by X gives |d| <= 2X + 1 (the
+// highpass has l1 norm 2) and |c| <= 1.5X + 2 (lowpass l1 norm 3/2, plus
+// the floors).  An output of level l sums, over both bands' taps, complex
+// products of two such bounded values (two real products per component),
+// so its partial sums are bounded by
+//   (2 Xp + 1)(2 Xr + 1) * 2 (len_0 + len_1),
+// Xp, Xr the bounds of level l - 1 for the pulse (any int16: 32768) and the
+// reference (its own peak component).
+inline bool int_sums_exact(const PlanDesc &d, int ref_peak) {
+  double xp = 32768.0, xr = ref_peak;
+  for (int l = 1; l <= d.J; ++l) {
+    const double terms = 2.0 * ((double)d.lv[l].len[0] + d.lv[l].len[1]);
+    if ((2 * xp + 1) * (2 * xr + 1) * terms >= 9007199254740992.0) return false;
+    xp = 1.5 * xp + 2;
+    xr = 1.5 * xr + 2;
+  }
+  return true;
+}
+
 // Integer plans hold linear-support phases; they equal the circular
 // integer lifting at length N only if no level's input support (plus the
 // one-sample delay and the +-2 reach of the 5/3 steps) wraps around.

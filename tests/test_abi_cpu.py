@@ -69,3 +69,33 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     assert L.sidwt_lift_many(7, 3, vp(16), 64, 1, 64, vp(16), None) == -1
     assert L.sidwt_lift_many(1, 3, vp(16), 8, 1, 8, vp(16), None) == -1
     assert L.sidwt_lift_many(1, 3, vp(16), 64, 1, 32, vp(16), None) == -1
+    assert L.sidwt_lift_many(1, 3, vp(16), 64, -1, 64, vp(16), None) == -1
+
+
+def test_zero_pulses_is_a_no_op(L):
+    # sizes are still checked; nothing is launched, so no device is needed
+    assert L.sidwt_lift_many(2, 3, None, 64, 0, 64, None, None) == 0
+    assert L.sidwt_lift_many(2, 3, None, 8, 0, 8, None, None) == -1   # N / 2^J < 2
+    assert L.sidwt_bank_correlate(None, None, None, None, None, 0, None) == -1
+
+
+def test_integer_plans_that_could_lose_exactness_are_refused(L):
+    """A full-scale int16 reference at J = 16: the level-16 bound on the
+    partial sums (growth 2 per level for details, 3/2 for approximations)
+    passes 2^53, so the plan is refused on the host; a small reference peak
+    keeps the same plan under it."""
+    vp = ctypes.c_void_p
+    m = 64
+    loud = (ctypes.c_int16 * (2 * m))(*([32767, -32768] * m))
+    quiet = (ctypes.c_int16 * (2 * m))(*([100, -100] * m))
+    h = vp()
+    assert L.sidwt_plan_create(4, 16, ctypes.cast(loud, vp), m, ctypes.byref(h)) == -2
+    assert h.value is None
+    rc = L.sidwt_plan_create(4, 16, ctypes.cast(quiet, vp), m, ctypes.byref(h))
+    assert rc != -2      # -4 without a device
+    if rc == 0:
+        L.sidwt_free(h)
+    rc = L.sidwt_plan_create(4, 8, ctypes.cast(loud, vp), m, ctypes.byref(h))
+    assert rc != -2
+    if rc == 0:
+        L.sidwt_free(h)

@@ -222,6 +222,20 @@ def test_integer_path_bit_exact(dev, J, m, n):
     assert np.array_equal(out.cpu().numpy(), want)
 
 
+def test_integer_full_scale_bit_exact(dev):
+    """Pulse and reference at the int16 extremes (random signs of 32767 and
+    -32768): the largest products the integer path can meet at J = 8."""
+    torch, S = dev
+    rng = np.random.default_rng(77)
+    ref = np.where(rng.random((200, 2)) < 0.5, 32767, -32768).astype(np.int16)
+    rx = np.where(rng.random((4096, 2)) < 0.5, 32767, -32768).astype(np.int16)
+    print("[case] int full scale J=8 m=200 n=4096", flush=True)
+    with S.plan_create("legall53_int", 8, ref) as plan:
+        out = S.correlate(plan, torch.from_numpy(rx).cuda())
+        torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), O.correlate_int(8, ref, rx))
+
+
 def test_integer_support_wrap_is_rejected(dev):
     torch, S = dev
     ref = np.ones((60, 2), np.int16)
@@ -262,3 +276,23 @@ def test_correlate_many_matches_oracle(dev):
         out = out.cpu().numpy()
     for i in range(5):
         assert_planes_close(out[i], O.correlate_direct(b.filter, b.J, b.ref, b.rx[i]))
+
+
+# ---------------------------------------------------------------------------
+# Empty batches: sizes are checked, nothing is launched
+# ---------------------------------------------------------------------------
+
+def test_empty_batches(dev):
+    torch, S = dev
+    rng = np.random.default_rng(12)
+    with S.plan_create("cdf97", 3, crandn(rng, 20)) as plan:
+        out = S.correlate_many(plan, torch.empty((0, 100), dtype=torch.complex64, device="cuda"))
+        assert tuple(out.shape) == (0, 3, 104)
+    pyr = S.lift_many("d4", 4, torch.empty((0, 64), dtype=torch.complex64, device="cuda"))
+    assert tuple(pyr.shape) == (0, 64)
+    with S.plan_create("legall53_int", 2, np.ones((8, 2), np.int16)) as plan:
+        out = S.correlate_many(plan, torch.empty((0, 64, 2), dtype=torch.int16, device="cuda"))
+        assert tuple(out.shape) == (0, 2, 64, 2)
+    with S.Bank("cdf97", 3, [crandn(rng, 16), crandn(rng, 32)]) as bank:
+        assert bank.correlate([], []) == []
+    torch.cuda.synchronize()

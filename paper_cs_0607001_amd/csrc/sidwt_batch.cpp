@@ -34,6 +34,7 @@ hipError_t batch_occupancy(bool tiles_only, size_t lds_bytes, int *blocks_per_cu
 hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
                               const LiftChunk *const *chunks, const int *nchunks, int Jmax,
                               float2 *scratch, hipStream_t st);
+hipError_t launch_batch_reset(int *counters, int n, hipStream_t st);
 hipError_t launch_batch_items(bool tiles_only, const PlanDesc *plans, const FusedLayout *lays,
                               const BatchPulse *pulses, const BatchItem *items, int nitems,
                               int *counter, float2 *scratch, int grid, size_t lds_bytes,
@@ -117,7 +118,13 @@ struct sidwt_batch {
   size_t c_items = 0;
   LiftChunk *d_chunks = nullptr;
   size_t c_chunks = 0;
-  int *d_counter = nullptr;
+  int *d_counter = nullptr;          // one work counter per item class
+  // Per-pulse device pointers: staged through pinned host memory (so the
+  // copy is asynchronous) and uploaded only when they change; up_done marks
+  // the end of the last copy out of h_pulses.
+  BatchPulse *h_pulses = nullptr;
+  hipEvent_t up_done = nullptr;
+  bool uploaded = false;
   float2 *d_scratch = nullptr;
   long long scratch_cap = 0;
   hipGraph_t graph = nullptr;
@@ -157,6 +164,7 @@ int build(sidwt_batch *b) {
   drop_graph(b);
   b->lays.clear();
   b->pulses.assign(b->count, BatchPulse{});
+  b->uploaded = false;
   b->items.clear();
   b->chunks.clear();
   std::vector<std::vector<LiftChunk>> per_level(kMaxLevels + 1);
@@ -289,8 +297,10 @@ int build(sidwt_batch *b) {
 int enqueue(sidwt_batch *b, hipStream_t st) {
   const LiftChunk *chunk_ptr[kMaxLevels + 2];
   for (int l = 0; l <= kMaxLevels + 1; ++l) chunk_ptr[l] = b->d_chunks + b->chunk_off[l];
-  hipError_t e = launch_lift_levels(b->d_plans, b->d_pulses, chunk_ptr, b->nchunks, b->Jmax,
-                                    b->d_scratch, st);
+  hipError_t e = launch_batch_reset(b->d_counter, 3, st);
+  if (e == hipSuccess)
+    e = launch_lift_levels(b->d_plans, b->d_pulses, chunk_ptr, b->nchunks, b->Jmax, b->d_scratch,
+                           st);
   int first = 0;
   for (int c = 0; c < 3 && e == hipSuccess; ++c) {
     e = launch_batch_items(c > 0, b->d_plans, b->d_lays, b->d_pulses, b->d_items + first,
@@ -327,15 +337,26 @@ int ensure_graph(sidwt_batch *b) {
 }
 
 int set_pointers(sidwt_batch *b, const void *const *rx, void *const *out, hipStream_t st) {
+  bool same = b->uploaded;
   for (int i = 0; i < b->count; ++i) {
     if (!rx[i] || !out[i]) return SIDWT_E_INVAL;
+    same = same && b->pulses[i].rx == rx[i] && b->pulses[i].out == out[i];
     b->pulses[i].rx = rx[i];
     b->pulses[i].out = out[i];
   }
-  // pageable source: the runtime stages it before returning
-  return map_err(hipMemcpyAsync(b->d_pulses, b->pulses.data(), b->pulses.size() * sizeof(BatchPulse),
-                                hipMemcpyHostToDevice, st),
-                 "hipMemcpyAsync (pointers)");
+  if (same) return SIDWT_OK;  // the device copy already holds these pointers
+  const size_t bytes = b->pulses.size() * sizeof(BatchPulse);
+  hipError_t e = hipSuccess;
+  if (!b->h_pulses) e = hipHostMalloc((void **)&b->h_pulses, bytes, hipHostMallocDefault);
+  if (e == hipSuccess && !b->up_done) e = hipEventCreateWithFlags(&b->up_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventSynchronize(b->up_done);  // h_pulses is free again
+  if (e != hipSuccess) return map_err(e, "pointer staging");
+  std::memcpy(b->h_pulses, b->pulses.data(), bytes);
+  e = hipMemcpyAsync(b->d_pulses, b->h_pulses, bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(b->up_done, st);
+  if (e != hipSuccess) return map_err(e, "hipMemcpyAsync (pointers)");
+  b->uploaded = true;
+  return SIDWT_OK;
 }
 
 int run(sidwt_batch *b, const void *const *rx, void *const *out, hipStream_t st, bool use_graph) {
@@ -410,6 +431,8 @@ void sidwt_batch_free(sidwt_batch *b) {
   (void)hipFree(b->d_chunks);
   (void)hipFree(b->d_counter);
   (void)hipFree(b->d_scratch);
+  if (b->h_pulses) (void)hipHostFree(b->h_pulses);
+  if (b->up_done) (void)hipEventDestroy(b->up_done);
   delete b;
 }
 

@@ -881,8 +881,10 @@ __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
   }
 }
 
-__global__ void batch_reset(int *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+// Work counters of a batch's persistent launches, cleared by a kernel (a
+// node that graph replays reproduce faithfully) rather than a memset.
+__global__ void batch_reset(int *counters, int n) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < n) counters[threadIdx.x] = 0;
 }
 
 // ===========================================================================
@@ -1094,22 +1096,29 @@ hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
                               const LiftChunk *const *chunks, const int *nchunks, int Jmax,
                               float2 *scratch, hipStream_t st);
 
-// One persistent launch over items [0, nitems) with its own counter.
+// Zero counters[0..n), n <= 64.
+hipError_t launch_batch_reset(int *counters, int n, hipStream_t st);
+
+// One persistent launch over items [0, nitems) with its own counter, which
+// must be zero (launch_batch_reset) when the launch starts.
 hipError_t launch_batch_items(bool tiles_only, const PlanDesc *plans, const FusedLayout *lays,
                               const BatchPulse *pulses, const BatchItem *items, int nitems,
                               int *counter, float2 *scratch, int grid, size_t lds_bytes,
                               hipStream_t st) {
   if (nitems <= 0) return hipSuccess;
   if (tiles_only && lds_bytes < (size_t)kBalMinLdsBytes) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, counter);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   if (tiles_only)
     hipLaunchKernelGGL(batch_persistent<true>, dim3(grid), dim3(kFusedThreads), lds_bytes, st,
                        plans, lays, pulses, items, nitems, counter, scratch);
   else
     hipLaunchKernelGGL(batch_persistent<false>, dim3(grid), dim3(kFusedThreads), lds_bytes, st,
                        plans, lays, pulses, items, nitems, counter, scratch);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(int *counters, int n, hipStream_t st) {
+  if (n < 1 || n > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, counters, n);
   return hipGetLastError();
 }
 

@@ -835,7 +835,8 @@ __device__ __forceinline__ void tile_item(const PlanDesc &plan, const FusedLayou
       }
     }
   }
-  __syncthreads();
+  // No barrier here: the correlation stages its weights first and its
+  // barrier after the staging also covers these window stores.
   correlate_rows_f32<BAL>(plan, v, smf, reinterpret_cast<float *>(p.out) + 2LL * (l - 1) * p.N);
 }
 
@@ -852,19 +853,26 @@ __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
     const BatchPulse *__restrict__ pulses, const BatchItem *__restrict__ items, int nitems,
     int *__restrict__ counter, const float2 *__restrict__ scratch) {
   extern __shared__ __align__(16) char smem_batch[];
-  __shared__ int next;
-  for (;;) {
-    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
-    __syncthreads();
-    const int i = __builtin_amdgcn_readfirstlane(next);
-    __syncthreads();
-    if (i >= nitems) break;  // the counter only grows: every workgroup exits
+  // Items are claimed one ahead: thread 0 holds the claim for the following
+  // item while the current one runs (hiding the atomic's latency), and the
+  // claimed index is published through alternating slots, so one barrier
+  // per item both publishes it and ends every wave's use of the item's LDS.
+  // The counter only grows, so every workgroup ends on a claim >= nitems.
+  __shared__ int slot[2];
+  if (threadIdx.x == 0) slot[0] = atomicAdd(counter, 1);
+  __syncthreads();
+  int i = __builtin_amdgcn_readfirstlane(slot[0]);
+  for (int k = 1; i < nitems; k ^= 1) {
+    int ahead = 0;
+    if (threadIdx.x == 0) ahead = atomicAdd(counter, 1);
     const BatchItem it = items[i];
     const BatchPulse &p = pulses[it.pulse];
     const PlanDesc &plan = plans[p.plan];
     const FusedLayout &lay = lays[p.layout];
+    bool whole = false;
     if constexpr (!TILES_ONLY) {
       if (it.kind == 0) {
+        whole = true;
         const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
         float *out = reinterpret_cast<float *>(p.out);
         switch (plan.filter) {
@@ -873,11 +881,13 @@ __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
           case F_D4: fused_pulse<F_D4>(plan, lay, rx, p.n, out, smem_batch); break;
           default: break;
         }
-        continue;
       }
     }
-    if (it.kind == 1)
+    if (!whole && it.kind == 1)
       tile_item<TILES_ONLY>(plan, lay, p, it, scratch, reinterpret_cast<float *>(smem_batch));
+    if (threadIdx.x == 0) slot[k] = ahead;
+    __syncthreads();
+    i = __builtin_amdgcn_readfirstlane(slot[k]);
   }
 }
 

@@ -665,7 +665,7 @@ __device__ __forceinline__ V load_elem(const S *sm, const FusedLayout &lay, int 
 // LDS regions so that c_l stays intact while level l+1 is written.
 // ===========================================================================
 template <int F>
-__device__ void fused_pulse(const PlanDesc &plan, const FusedLayout &lay,
+__device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLayout &lay,
                             const typename RxOf<F>::T *__restrict__ rx, long long n,
                             typename RxOf<F>::Out *__restrict__ out, char *smem) {
   constexpr bool INT = (F == F_LEGALL53_INT);
@@ -841,12 +841,11 @@ __device__ __forceinline__ void tile_item(const PlanDesc &plan, const FusedLayou
 }
 
 // Persistent kernel over work items taken from an atomic counter.  The
-// general instance runs whole-pulse and tile items; the TILES_ONLY instance
-// compiles only the tile path (83 instead of 243 VGPRs: the inlined
-// whole-pulse path of three filters sets the general one's register count),
-// so tile items can run at two workgroups per CU; it also spreads each
-// tile item's work evenly over the waves (see correlate_rows_f32_t), which
-// needs an LDS allocation of at least kBalMinLdsBytes.
+// general instance runs whole-pulse items (the fused path of three filters,
+// inlined) and tile items; the TILES_ONLY instance compiles only the tile
+// path and spreads each tile item's work evenly over the waves (see
+// correlate_rows_f32_t), which needs an LDS allocation of at least
+// kBalMinLdsBytes.
 template <bool TILES_ONLY>
 __global__ __launch_bounds__(kFusedThreads) void batch_persistent(
     const PlanDesc *__restrict__ plans, const FusedLayout *__restrict__ lays,

@@ -455,6 +455,9 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
       const int per_last = bank_tiles_per_item(last);
       sg.g_full = (sg.ntiles + 3) / 4;
       sg.g_last = (sg.ntiles + per_last - 1) / per_last;
+      // Level 1 has the longest panels: its full blocks take the wave shape
+      // with half the panel loads per MFMA.
+      sg.wide = l == 1;
       segs.push_back(sg);
       // cost of one item: rows x steps of its tiles (mean over the level's tiles)
       const long long *pre = bk->steps_pre.data() + bk->tile_base[l] + (l - 1);

@@ -86,6 +86,165 @@ __device__ __forceinline__ V8 gload8(const unsigned *p) {
 constexpr int kBankThreads = 256;  // 4 waves; a wave owns 64 rows x up to 4 column tiles
 constexpr int kStageLd = 36;       // staging row stride (floats): 32 columns + pad, 16-byte rows
 
+// The waves of one item.  Wave = (row group wr of 32 RT rows, tile group wt
+// of TW = 8 / RT column tiles): RT = 2 gives 64 rows x 4 tiles (any row
+// block); RT = 4 gives 128 rows x 2 tiles (full 256-row blocks), which
+// halves the panel loads per MFMA at the cost of twice the data-operand
+// reads (used where the windows are longest).
+template <bool BF16, int RT>
+__device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
+                                           const BankRefLevel *__restrict__ rl, int Jmax,
+                                           const unsigned *__restrict__ wts, const unsigned *dat,
+                                           float *stg, int Wmax, int rows, int row0, int tile0,
+                                           int ntiles, int wave, int lane, float inv_sd) {
+  using H = Half<BF16>;
+  using V8 = typename H::V8;
+  static_assert(RT == 2 || RT == 4, "row tiles per wave");
+  constexpr int TW = 8 / RT, RWS = 32 * RT;
+  const int l = q.level, P = 1 << l, N = q.N;
+  const int rw = RT == 4 ? 2 : rows > 128 ? 4 : rows > 64 ? 2 : 1;
+  const int wr = wave % rw, wt = wave / rw;
+  const int rows_w = rows - RWS * wr;
+  const int t0 = tile0 + TW * wt;
+  const int nt_w = min(TW, tile0 + ntiles - t0);
+  if (rows_w <= 0 || nt_w <= 0) return;          // no barrier follows
+  const int nh = min(RT, (rows_w + 31) >> 5);    // 32-row tiles in use
+  const BankTile *tb = tl + t0;
+  const int rloc = RWS * wr + (lane & 31);       // row of the first row tile
+  const int g = lane >> 5;                        // K half: offsets 4g..4g+3 of a step
+  f32x16 acc[RT][TW];
+#pragma unroll
+  for (int h = 0; h < RT; ++h)
+#pragma unroll
+    for (int t = 0; t < TW; ++t)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[h][t][i] = 0.f;
+
+  for (int b = 0; b < 2; ++b) {
+    const unsigned *dhi = dat + (2 * b) * Wmax;
+    const unsigned *dlo = dhi + Wmax;
+    int steps[TW];
+    const unsigned *pw[TW];
+    int S = 0;
+#pragma unroll
+    for (int t = 0; t < TW; ++t) {
+      steps[t] = t < nt_w ? tb[t].steps[b] : 0;
+      pw[t] = wts + (t < nt_w ? tb[t].off[b] : 0) + 4 * lane;
+      S = max(S, steps[t]);
+    }
+    // Two operand sets (x, y) alternate: the loads of a step are issued one
+    // whole step of MFMAs before its use and no register moves follow them
+    // (a move would make the wave wait for the loads it just issued).  Load
+    // indices are clamped to valid steps, so no load sits under a branch;
+    // only the MFMAs of a tile past its own K length are skipped.
+    int last[TW];
+#pragma unroll
+    for (int t = 0; t < TW; ++t) last[t] = steps[t] > 0 ? steps[t] - 1 : 0;
+    auto loadB = [&](int st, V8(&BH)[TW], V8(&BL)[TW]) {
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        const unsigned *pp = pw[t] + min(st, last[t]) * kBankStepWords;
+        BH[t] = gload8<V8>(pp);
+        BL[t] = gload8<V8>(pp + 256);
+      }
+    };
+    auto loadA = [&](int st, V8(&AH)[RT], V8(&AL)[RT]) {
+      const int u0 = 8 * st + 4 * g;
+#pragma unroll
+      for (int h = 0; h < RT; ++h) {
+        AH[h] = load8<V8>(dhi + rloc + 32 * h + u0);
+        AL[h] = load8<V8>(dlo + rloc + 32 * h + u0);
+      }
+    };
+    auto mma = [&](int st, const V8(&AH)[RT], const V8(&AL)[RT], const V8(&BH)[TW],
+                   const V8(&BL)[TW]) {
+#pragma unroll
+      for (int t = 0; t < TW; ++t)
+        if (st < steps[t]) {
+#pragma unroll
+          for (int h = 0; h < RT; ++h)
+            if (h == 0 || h < nh) {
+              acc[h][t] = H::mma(AH[h], BH[t], acc[h][t]);
+              acc[h][t] = H::mma(AH[h], BL[t], acc[h][t]);
+              acc[h][t] = H::mma(AL[h], BH[t], acc[h][t]);
+            }
+        }
+    };
+    if (S > 0) {
+      V8 xbh[TW], xbl[TW], ybh[TW], ybl[TW], xah[RT], xal[RT], yah[RT], yal[RT];
+      loadB(0, xbh, xbl);
+      loadA(0, xah, xal);
+      for (int st = 0; st < S; st += 2) {
+        loadB(min(st + 1, S - 1), ybh, ybl);
+        loadA(min(st + 1, S - 1), yah, yal);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(st, xah, xal, xbh, xbl);
+        __builtin_amdgcn_sched_barrier(0);
+        loadB(min(st + 2, S - 1), xbh, xbl);
+        loadA(min(st + 2, S - 1), xah, xal);
+        __builtin_amdgcn_sched_barrier(0);
+        if (st + 1 < S) mma(st + 1, yah, yal, ybh, ybl);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  }
+
+  // Output.  Accumulator register i of lane l holds row 8*(i/4) + 4*(l/32)
+  // + i%4, column l%32 (column 2 pp + v: pair pp of the tile, v = re/im).
+  // Each tile goes through the wave's staging area (64 rows at a time) and
+  // leaves as 16-byte runs (2 consecutive phases of one reference at one
+  // lag), ordered so a store instruction covers whole runs of
+  // out[e][l-1][P p + r]: per reference of the tile Q = min(P, 16) pairs,
+  // Q / 2 runs per lag.
+  // (an opaque copy of the lane index keeps this index math from being
+  // hoisted into the MFMA loop, where it would hold registers)
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
+  float *out = reinterpret_cast<float *>(q.out);
+  const int pairs = q.E * P;
+  const int lq = min(l, 4);                       // log2 Q
+  const int lcpr = lq - 1;                        // log2 runs per lag
+#pragma unroll
+  for (int t = 0; t < TW; ++t) {
+    if (t >= nt_w) break;
+    const int c = kBankTilePairs * (t0 + t) + ((ln & 31) >> 1);
+    const float scale =
+        c < pairs ? inv_sd * rl[(c >> l) * (Jmax + 1) + l].inv_scale : 0.f;
+#pragma unroll
+    for (int hh = 0; hh < RT / 2; ++hh) {
+      if (64 * hh >= rows_w) break;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          stg[(32 * h + 8 * (i >> 2) + 4 * (ln >> 5) + (i & 3)) * kStageLd + (ln & 31)] =
+              acc[2 * hh + h][t][i] * scale;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int kk = 64 * j + ln;
+        const int ch = kk & ((1 << lcpr) - 1);
+        const int rest = kk >> lcpr;
+        const int row = rest & 63;
+        const int pp = ((rest >> 6) << lq) + 2 * ch;
+        const int cc = kBankTilePairs * (t0 + t) + pp;
+        if (64 * hh + row < rows_w && cc < pairs) {
+          const f32x4 v = *reinterpret_cast<const f32x4 *>(stg + row * kStageLd + 2 * pp);
+          const int e = cc >> l, r = cc & (P - 1);
+          float *o = out + 2 * (((long long)e * q.J + (l - 1)) * N +
+                                (long long)P * (row0 + RWS * wr + 64 * hh + row) + r);
+          __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(o));
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+}
+
 // LDS: data windows [band][hi/lo][Wmax] words (W = 64 rw + umax of the
 // item), then one output staging tile [64 rows][kStageLd] floats per wave.
 // Weights are read from their panels straight into registers (no LDS, no
@@ -170,142 +329,12 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   }
   __syncthreads();
 
-  // Wave role: row group wr (64 rows), tile group wt (up to 4 tiles).
-  const int wr = wave % rw, wt = wave / rw;
-  const int rows_w = rows - 64 * wr;
-  const int t0 = tile0 + 4 * wt;
-  const int nt_w = min(4, tile0 + ntiles - t0);
-  if (rows_w <= 0 || nt_w <= 0) return;          // no barrier follows
-  const bool two = rows_w > 32;                  // second 32-row half in use
-  const BankTile *tb = tl + t0;
-  const int rloc = 64 * wr + (lane & 31);        // row of the first row tile
-  const int g = lane >> 5;                        // K half: offsets 4g..4g+3 of a step
-  f32x16 acc[2][4];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int i = 0; i < 16; ++i) acc[h][t][i] = 0.f;
-
-  for (int b = 0; b < 2; ++b) {
-    const unsigned *dhi = dat + (2 * b) * Wmax;
-    const unsigned *dlo = dhi + Wmax;
-    int steps[4];
-    const unsigned *pw[4];
-    int S = 0;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      steps[t] = t < nt_w ? tb[t].steps[b] : 0;
-      pw[t] = wts + (t < nt_w ? tb[t].off[b] : 0) + 4 * lane;
-      S = max(S, steps[t]);
-    }
-    // Two operand sets (x, y) alternate: the loads of a step are issued one
-    // whole step of MFMAs before its use and no register moves follow them
-    // (a move would make the wave wait for the loads it just issued).  Load
-    // indices are clamped to valid steps, so no load sits under a branch;
-    // only the MFMAs of a tile past its own K length are skipped.
-    int last[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) last[t] = steps[t] > 0 ? steps[t] - 1 : 0;
-    auto loadB = [&](int st, V8(&BH)[4], V8(&BL)[4]) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const unsigned *pp = pw[t] + min(st, last[t]) * kBankStepWords;
-        BH[t] = gload8<V8>(pp);
-        BL[t] = gload8<V8>(pp + 256);
-      }
-    };
-    auto loadA = [&](int st, V8(&AH)[2], V8(&AL)[2]) {
-      const int u0 = 8 * st + 4 * g;
-      AH[0] = load8<V8>(dhi + rloc + u0);
-      AL[0] = load8<V8>(dlo + rloc + u0);
-      AH[1] = load8<V8>(dhi + rloc + 32 + u0);
-      AL[1] = load8<V8>(dlo + rloc + 32 + u0);
-    };
-    auto mma = [&](int st, const V8(&AH)[2], const V8(&AL)[2], const V8(&BH)[4],
-                   const V8(&BL)[4]) {
-#pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (st < steps[t]) {
-          acc[0][t] = H::mma(AH[0], BH[t], acc[0][t]);
-          acc[0][t] = H::mma(AH[0], BL[t], acc[0][t]);
-          acc[0][t] = H::mma(AL[0], BH[t], acc[0][t]);
-          if (two) {
-            acc[1][t] = H::mma(AH[1], BH[t], acc[1][t]);
-            acc[1][t] = H::mma(AH[1], BL[t], acc[1][t]);
-            acc[1][t] = H::mma(AL[1], BH[t], acc[1][t]);
-          }
-        }
-    };
-    if (S > 0) {
-      V8 xbh[4], xbl[4], ybh[4], ybl[4], xah[2], xal[2], yah[2], yal[2];
-      loadB(0, xbh, xbl);
-      loadA(0, xah, xal);
-      for (int st = 0; st < S; st += 2) {
-        loadB(min(st + 1, S - 1), ybh, ybl);
-        loadA(min(st + 1, S - 1), yah, yal);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(st, xah, xal, xbh, xbl);
-        __builtin_amdgcn_sched_barrier(0);
-        loadB(min(st + 2, S - 1), xbh, xbl);
-        loadA(min(st + 2, S - 1), xah, xal);
-        __builtin_amdgcn_sched_barrier(0);
-        if (st + 1 < S) mma(st + 1, yah, yal, ybh, ybl);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-  }
-
-  // Output.  Accumulator register i of lane l holds row 8*(i/4) + 4*(l/32)
-  // + i%4, column l%32 (column 2 pp + v: pair pp of the tile, v = re/im).
-  // Each tile goes through the wave's staging area and leaves as 16-byte
-  // runs (2 consecutive phases of one reference at one lag), ordered so a
-  // store instruction covers whole runs of out[e][l-1][P p + r]: per
-  // reference of the tile Q = min(P, 16) pairs, Q / 2 runs per lag.
-  // (an opaque copy of the lane index keeps this index math from being
-  // hoisted into the MFMA loop, where it would hold registers)
-  int ln = lane;
-  asm volatile("" : "+v"(ln));
-  float *out = reinterpret_cast<float *>(q.out);
-  const int pairs = q.E * P;
-  const int lq = min(l, 4);                       // log2 Q
-  const int lcpr = lq - 1;                        // log2 runs per lag
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t >= nt_w) break;
-    const int c = kBankTilePairs * (t0 + t) + ((ln & 31) >> 1);
-    const float scale =
-        c < pairs ? inv_sd * rl[(c >> l) * (Jmax + 1) + l].inv_scale : 0.f;
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int i = 0; i < 16; ++i)
-        stg[(32 * h + 8 * (i >> 2) + 4 * (ln >> 5) + (i & 3)) * kStageLd + (ln & 31)] =
-            acc[h][t][i] * scale;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int kk = 64 * j + ln;
-      const int ch = kk & ((1 << lcpr) - 1);
-      const int rest = kk >> lcpr;
-      const int row = rest & 63;
-      const int pp = ((rest >> 6) << lq) + 2 * ch;
-      const int cc = kBankTilePairs * (t0 + t) + pp;
-      if (row < rows_w && cc < pairs) {
-        const f32x4 v = *reinterpret_cast<const f32x4 *>(stg + row * kStageLd + 2 * pp);
-        const int e = cc >> l, r = cc & (P - 1);
-        float *o = out + 2 * (((long long)e * q.J + (l - 1)) * N +
-                              (long long)P * (row0 + 64 * wr + row) + r);
-        __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(o));
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
+  if (sg.wide && rows == 256)
+    bank_waves<BF16, 4>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0, ntiles, wave,
+                        lane, inv_sd);
+  else
+    bank_waves<BF16, 2>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0, ntiles, wave,
+                        lane, inv_sd);
 }
 
 size_t bank_lds_bytes(int Wmax) {

@@ -36,7 +36,8 @@ struct BankSeg {
   int L, ntiles;
   int nblocks;          // row blocks, the last holding L - 256 (nblocks - 1) lags
   int g_full, g_last;   // tile groups per full block / in the last block
-  int pad_[3];
+  int wide;             // full blocks run 128 rows x 2 tiles per wave (else 64 x 4)
+  int pad_[2];
 };
 
 // Per (reference e, level l): 1 / weight scale.

@@ -925,9 +925,6 @@ __device__ __forceinline__ void rx_pair(const short2 *rx, int i, int2 &e, int2 &
   e = make_int2(v[0], v[1]);
   o = make_int2(v[2], v[3]);
 }
-// The complex64 form (one 16-byte load) measured no faster than two 8-byte
-// loads per lane and is not used.
-__device__ __forceinline__ void rx_pair(const float2 *, int, float2 &, float2 &) {}
 
 template <int F>
 __global__ __launch_bounds__(LiftCfg<F>::kThreads) void lift_many(
@@ -962,9 +959,15 @@ __global__ __launch_bounds__(LiftCfg<F>::kThreads) void lift_many(
       store_stream(dg + k, d);
     };
     auto level = [&](auto store) {
-      if (l == 1 && pair_loads) {
-        lift_level<F, 4>(np, [&](int kc, V &e, V &o) { rx_pair(rx, 2 * kc, e, o); }, store);
-      } else if (l == 1) {
+      // (complex64 pulses keep two 8-byte loads per lane: one 16-byte load
+      // per pair measured no faster)
+      if constexpr (F == F_LEGALL53_INT) {
+        if (l == 1 && pair_loads) {
+          lift_level<F, 4>(np, [&](int kc, V &e, V &o) { rx_pair(rx, 2 * kc, e, o); }, store);
+          return;
+        }
+      }
+      if (l == 1) {
         lift_level<F, 4>(
             np,
             [&](int kc, V &e, V &o) {

@@ -43,6 +43,10 @@ using namespace sidwt::host;
 namespace {
 
 constexpr int kChunk = 4096;
+// Panel steps (both bands, summed over an item's tiles) an item should run
+// per data window, and the most tile groups one item may take.
+constexpr double kBankItemSteps = 256.0;
+constexpr int kBankMaxGroups = 16;
 
 int map_err(hipError_t e, const char *what = nullptr) {
   if (e == hipSuccess) return SIDWT_OK;
@@ -453,15 +457,22 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
       sg.nblocks = (L + 255) / 256;
       const int last = L - 256 * (sg.nblocks - 1);
       const int per_last = bank_tiles_per_item(last);
-      sg.g_full = (sg.ntiles + 3) / 4;
-      sg.g_last = (sg.ntiles + per_last - 1) / per_last;
       // Level 1 has the longest panels: its full blocks take the wave shape
       // with half the panel loads per MFMA.
       sg.wide = l == 1;
+      // Short panels (high levels): several tile groups per item, so that
+      // an item runs about kBankItemSteps panel steps per tile column over
+      // one data window (its load, max reduction and hi/lo split).
+      const long long *pre = bk->steps_pre.data() + bk->tile_base[l] + (l - 1);
+      const long long st = pre[sg.ntiles];   // steps (both bands) of the segment's tiles
+      const double per_tile = (double)st / std::max(1, sg.ntiles);
+      int gm = 1;
+      while (gm < kBankMaxGroups && 4.0 * gm * per_tile < kBankItemSteps) gm *= 2;
+      sg.gmul = gm;
+      sg.g_full = ((sg.ntiles + 3) / 4 + gm - 1) / gm;
+      sg.g_last = ((sg.ntiles + per_last - 1) / per_last + gm - 1) / gm;
       segs.push_back(sg);
       // cost of one item: rows x steps of its tiles (mean over the level's tiles)
-      const long long *pre = bk->steps_pre.data() + bk->tile_base[l] + (l - 1);
-      const long long st = pre[sg.ntiles];
       cost.push_back(std::min(L, 256) * st / std::max(1, sg.nblocks > 1 ? sg.g_full : sg.g_last) +
                      std::min(L, 256) * 8);
     }

@@ -280,8 +280,8 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   const int rows = min(256, L - row0);
   const int rw = rows > 128 ? 4 : rows > 64 ? 2 : 1;
   const int per = bank_tiles_per_item(rows);
-  const int tile0 = grp * per;
-  const int ntiles = min(per, sg.ntiles - tile0);
+  const int tile0 = grp * per * sg.gmul;
+  const int ntiles = min(per * sg.gmul, sg.ntiles - tile0);
   const BankTile *tl = tiles + tile_base[l];
   int umax = 0;
   for (int t = tile0; t < tile0 + ntiles; ++t)
@@ -329,12 +329,17 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   }
   __syncthreads();
 
-  if (sg.wide && rows == 256)
-    bank_waves<BF16, 4>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0, ntiles, wave,
-                        lane, inv_sd);
-  else
-    bank_waves<BF16, 2>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0, ntiles, wave,
-                        lane, inv_sd);
+  // The item's tile groups, one after another over the same data window
+  // (each wave only touches its own staging area: no barrier in between).
+  for (int g0 = 0; g0 < ntiles; g0 += per) {
+    const int ng = min(per, ntiles - g0);
+    if (sg.wide && rows == 256)
+      bank_waves<BF16, 4>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0 + g0, ng,
+                          wave, lane, inv_sd);
+    else
+      bank_waves<BF16, 2>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0 + g0, ng,
+                          wave, lane, inv_sd);
+  }
 }
 
 size_t bank_lds_bytes(int Wmax) {

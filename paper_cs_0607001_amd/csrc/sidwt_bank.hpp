@@ -22,8 +22,9 @@ struct BankTile {
 
 // Work of one request and level: its lags are cut into blocks of 256 (the
 // last may be shorter) and its tiles [0, ntiles) into groups of
-// bank_tiles_per_item(rows) tiles; one work item per (block, group),
-// numbered block-major from item0.
+// bank_tiles_per_item(rows) tiles; one work item per (block, gmul
+// consecutive groups), numbered block-major from item0.  An item loads its
+// data window once and runs its groups one after another.
 __host__ __device__ inline int bank_tiles_per_item(int rows) {
   return rows > 128 ? 4 : rows > 64 ? 8 : 16;
 }
@@ -35,9 +36,10 @@ struct BankSeg {
   int N, J, E, level;   // E: eligible references (the first E of the bank)
   int L, ntiles;
   int nblocks;          // row blocks, the last holding L - 256 (nblocks - 1) lags
-  int g_full, g_last;   // tile groups per full block / in the last block
+  int g_full, g_last;   // items per full block / in the last block
   int wide;             // full blocks run 128 rows x 2 tiles per wave (else 64 x 4)
-  int pad_[2];
+  int gmul;             // tile groups per item
+  int pad_;
 };
 
 // Per (reference e, level l): 1 / weight scale.

@@ -113,6 +113,12 @@ struct sidwt_bank_ws {
   bool timing = false;
   bool timed = false;                // the last call recorded its events
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  // Pinned host staging of a call's four descriptor arrays (so their
+  // uploads are asynchronous); up_done follows the last upload, and the next
+  // call waits for it before rewriting the staging buffer.
+  char *h_stage = nullptr;
+  size_t c_stage = 0;
+  hipEvent_t up_done = nullptr;
 };
 
 struct sidwt_bank {
@@ -336,6 +342,8 @@ int sidwt_bank_ws_create(const sidwt_bank *bk, sidwt_bank_ws **out) {
 void sidwt_bank_ws_free(sidwt_bank_ws *w) {
   if (!w) return;
   (void)hipDeviceSynchronize();
+  if (w->h_stage) (void)hipHostFree(w->h_stage);
+  if (w->up_done) (void)hipEventDestroy(w->up_done);
   (void)hipFree(w->d_segs);
   (void)hipFree(w->d_item_seg);
   (void)hipFree(w->d_pulses);
@@ -509,20 +517,29 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   if (!rc) rc = grow(&ws->d_chunks, &ws->c_chunks, chunks.size());
   if (!rc) rc = grow(&ws->d_scratch, &ws->c_scratch, (size_t)scratch);
   if (rc) return rc;
-  // pageable sources: the runtime stages them before returning
+  // Descriptor uploads through the workspace's pinned staging buffer.
+  const size_t nb[4] = {sorted.size() * sizeof(BankSeg), item_seg.size() * sizeof(int),
+                        pulses.size() * sizeof(BatchPulse), chunks.size() * sizeof(LiftChunk)};
+  const void *src[4] = {sorted.data(), item_seg.data(), pulses.data(), chunks.data()};
+  void *dst[4] = {ws->d_segs, ws->d_item_seg, ws->d_pulses, ws->d_chunks};
+  size_t at[5] = {0};
+  for (int k = 0; k < 4; ++k) at[k + 1] = at[k] + ((nb[k] + 255) & ~size_t(255));
   hipError_t e = hipSuccess;
-  if (!sorted.empty())
-    e = hipMemcpyAsync(ws->d_segs, sorted.data(), sorted.size() * sizeof(BankSeg),
-                       hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !item_seg.empty())
-    e = hipMemcpyAsync(ws->d_item_seg, item_seg.data(), item_seg.size() * sizeof(int),
-                       hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(ws->d_pulses, pulses.data(), pulses.size() * sizeof(BatchPulse),
-                       hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !chunks.empty())
-    e = hipMemcpyAsync(ws->d_chunks, chunks.data(), chunks.size() * sizeof(LiftChunk),
-                       hipMemcpyHostToDevice, st);
+  if (!ws->up_done) e = hipEventCreateWithFlags(&ws->up_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventSynchronize(ws->up_done);  // staging free again
+  if (e == hipSuccess && ws->c_stage < at[4]) {
+    if (ws->h_stage) (void)hipHostFree(ws->h_stage);
+    ws->h_stage = nullptr;
+    ws->c_stage = 0;
+    e = hipHostMalloc((void **)&ws->h_stage, at[4], hipHostMallocDefault);
+    if (e == hipSuccess) ws->c_stage = at[4];
+  }
+  for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+    if (!nb[k]) continue;
+    std::memcpy(ws->h_stage + at[k], src[k], nb[k]);
+    e = hipMemcpyAsync(dst[k], ws->h_stage + at[k], nb[k], hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess) e = hipEventRecord(ws->up_done, st);
   if (e != hipSuccess) return map_err(e, "descriptor upload");
   const LiftChunk *cp[kMaxLevels + 2];
   for (int l = 0; l <= kMaxLevels + 1; ++l) cp[l] = ws->d_chunks + off[l];

@@ -465,9 +465,9 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
       sg.nblocks = (L + 255) / 256;
       const int last = L - 256 * (sg.nblocks - 1);
       const int per_last = bank_tiles_per_item(last);
-      // Level 1 has the longest panels: its full blocks take the wave shape
-      // with half the panel loads per MFMA.
-      sg.wide = l == 1;
+      // Levels 1 and 2 have the longest panels: their full blocks take the
+      // wave shape with half the panel loads per MFMA.
+      sg.wide = l <= 2;
       // Short panels (high levels): several tile groups per item, so that
       // an item runs about kBankItemSteps panel steps per tile column over
       // one data window (its load, max reduction and hi/lo split).

@@ -93,8 +93,10 @@ enum {
  * builds on the current device the even/odd shift-circulant phase pyramid
  * of the reference, a~_l^{(r)} and b~_l^{(r)} for l = 1..J and
  * r = 0..2^l-1 (Sec. II "even and odd shifts"; Fig. 5), on their linear
- * support.  The plan owns its device memory until sidwt_free.  The call is
- * synchronous.  *out is set only on success.
+ * support.  The plan owns its device memory until sidwt_free; it belongs to
+ * the device current at creation, and correlation calls made with another
+ * device current return SIDWT_E_INVAL.  The call is synchronous.  *out is
+ * set only on success.
  * Integer plans (int16 I/Q reference) are exact for every int16 pulse: the
  * plan is refused with SIDWT_E_SIZE, before any device work, when a bound
  * on the partial sums of some level (full-scale pulse, this reference's

@@ -53,6 +53,9 @@ int map_err(hipError_t e) {
 
 int check_pulse(const sidwt_plan *p, int64_t n, int64_t *N_out) {
   if (n < 1) return SIDWT_E_INVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SIDWT_E_DEVICE;
+  if (dev != p->device) return SIDWT_E_INVAL;  // the plan's memory lives on its own device
   const int64_t N = transform_length(n, p->J);
   if (N > kMaxN) return SIDWT_E_SIZE;
   if ((N >> p->J) < 2) return SIDWT_E_INVAL;

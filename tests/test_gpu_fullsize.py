@@ -70,3 +70,82 @@ def test_integer_full_size_sampled(dev):
             for j in range(J):
                 want = O.correlate_int_at(J, ib.ref_iq, ib.rx_iq[i], j, lags)
                 assert np.array_equal(got[j], want), (i, j)
+
+
+def _sampled_lags(rng, N, k=8):
+    return np.unique(np.concatenate([[0, 1, N - 1], rng.integers(0, N, k)]))
+
+
+def test_uneven_full_size_sampled(dev):
+    """10^4 pulses of log-uniform length in [512, 65536], 16 references, D4
+    and 9/7, autotuned split and one graph-replayed run, as in the uneven
+    benchmark; sampled pulses (first, last, middle, longest, shortest)."""
+    torch, S = dev
+    refs, reqs = W.uneven_batch(seed=4, count=10000)
+    print("[case] uneven 10000 pulses, autotuned", flush=True)
+    plans, cache = [], {}
+    for r in reqs:
+        key = (r.ref_index, r.filter, r.J)
+        if key not in cache:
+            cache[key] = S.plan_create(r.filter, r.J, refs[r.ref_index])
+        plans.append(cache[key])
+    ns = [r.n for r in reqs]
+    rx = [torch.from_numpy(r.rx.astype(np.complex64)).cuda() for r in reqs]
+    out = S.batch_outputs(plans, ns, rx[0].device)
+    with S.Batch(plans, ns) as b:
+        info = b.tune(rx, out)
+        print(f"[case] tuned {info}", flush=True)
+        b.run(rx, out)
+        torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    picks = {0, len(reqs) // 2, len(reqs) - 1, int(np.argmax(ns)), int(np.argmin(ns))}
+    for i in sorted(picks):
+        r = reqs[i]
+        N = O.transform_length(r.n, r.J)
+        lags = _sampled_lags(rng, N)
+        got = out[i][:, lags].cpu().numpy().astype(np.complex128)
+        for j in range(r.J):
+            want = O.correlate_at(r.filter, r.J, refs[r.ref_index],
+                                  r.rx.astype(np.complex128), j, lags)
+            e = np.linalg.norm(got[j] - want) / np.linalg.norm(want)
+            assert e <= 1e-5, (i, r.n, j, e)
+    del out, rx
+    for p in cache.values():
+        p.free()
+    torch.cuda.empty_cache()
+
+
+def test_bank_full_size_sampled(dev):
+    """256 requests of the serving mix against the 64-reference 9/7 bank
+    (FP16 hi+lo), one call as in the bank benchmark; sampled requests and
+    references (first, middle and last eligible)."""
+    torch, S = dev
+    refs = W.reference_set(5, count=64)
+    rng = np.random.default_rng([5, 1])     # the benchmark's request stream
+    reqs = []
+    for _ in range(256):
+        n = W.uneven_length(rng)
+        elig = [k for k, r in enumerate(refs) if len(r) <= n // 2] or [0]
+        k = elig[int(rng.integers(0, len(elig)))]
+        reqs.append((n, W.levels_for(n), W.echoes(n, refs[k], rng).astype(np.complex64)))
+    print("[case] bank 256 requests x 64 references", flush=True)
+    with S.Bank("cdf97", 12, refs, "fp16") as bank:
+        rx = [torch.from_numpy(y).cuda() for _, _, y in reqs]
+        outs = bank.correlate(rx, [J for _, J, _ in reqs])
+        torch.cuda.synchronize()
+        srng = np.random.default_rng(12)
+        ns = [n for n, _, _ in reqs]
+        picks = {0, 255, 128, int(np.argmax(ns))}
+        for i in sorted(picks):
+            n, J, y = reqs[i]
+            E = bank.eligible(n)
+            N = O.transform_length(n, J)
+            lags = _sampled_lags(srng, N, k=6)
+            for e in sorted({0, E // 2, E - 1}):
+                got = outs[i][e][:, lags].cpu().numpy().astype(np.complex128)
+                for j in range(J):
+                    want = O.correlate_at("cdf97", J, refs[e], y.astype(np.complex128), j, lags)
+                    err = np.linalg.norm(got[j] - want) / np.linalg.norm(want)
+                    assert err <= 1e-5, (i, n, e, j, err)
+        del outs, rx
+    torch.cuda.empty_cache()

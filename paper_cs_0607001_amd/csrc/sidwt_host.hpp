@@ -341,5 +341,23 @@ inline int layout_violation(const PlanDesc &d, const FusedLayout &lay) {
   return 0;
 }
 
+// Whether some level of a whole-pulse layout ends with a round of MFMA
+// tiles that leaves more than half of a workgroup's waves idle (1 .. NW/2
+// tiles for NW waves): the case the balanced correlation cuts over the
+// waves.  Mirrors the tile count of correlate_rows_f32_t.
+inline bool fused_wants_bal(const FusedLayout &lay) {
+  constexpr int NW = kFusedThreads / 64;
+  for (int l = 1; l <= lay.J; ++l) {
+    const int P = 1 << l;
+    const int rows = (lay.N >> l) >> lay.logT[l];
+    const int mpairs = (((rows + 31) >> 5) + 1) >> 1;
+    const int pc = lay.pc[l] > 0 ? lay.pc[l] : P;
+    const int last = P - ((P - 1) / pc) * pc;   // phases of the last column chunk
+    const int rem = (mpairs * (P < 16 ? 1 : last >> 4)) % NW;
+    if (rem >= 1 && rem <= NW / 2) return true;
+  }
+  return false;
+}
+
 }  // namespace host
 }  // namespace sidwt

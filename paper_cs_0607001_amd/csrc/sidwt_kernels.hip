@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "sidwt_device.hpp"
+#include "sidwt_host.hpp"
 
 namespace sidwt {
 
@@ -339,11 +340,14 @@ __device__ __forceinline__ int row_start(const LevelView &v, int p1, int b) {
 // idle, its rem tiles are each cut into NW / rem equal group ranges, one per
 // wave: the partial sums pass through LDS slots of kBalSlotWords per wave
 // (aliasing the band windows and weights, which are no longer read) and
-// are added in wave order, so the result does not depend on timing.  BAL
-// needs an LDS allocation of at least NW * kBalSlotWords words.
+// are added in wave order, so the result does not depend on timing.  The
+// slots start at word slot_at of smf: 0 for a tile item (they alias its
+// windows and weights, no longer read), the end of the layout for a whole
+// pulse (whose bands stay live); the allocation must hold NW * kBalSlotWords
+// words from there.
 template <int TT, bool BAL>
 __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const LevelView &v, float *smf,
-                                     float *__restrict__ outp) {
+                                     float *__restrict__ outp, int slot_at) {
   constexpr int LT = TT == 1 ? 0 : TT == 2 ? 1 : TT == 4 ? 2 : 3;
   static_assert(TT == 1 || TT == 2 || TT == 4 || TT == 8, "Toeplitz block");
   const int P = v.P, l = v.l, Ls = v.Ls;
@@ -509,7 +513,7 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
       if (wave < rem * c) accumulate(mp, nt, part * GT / c, (part + 1) * GT / c, acc0, acc1);
       __syncthreads();  // every wave is done with the windows and weights
       if (wave < rem * c && part > 0) {
-        f32x4 *sl = reinterpret_cast<f32x4 *>(smf + wave * kBalSlotWords) + lane;
+        f32x4 *sl = reinterpret_cast<f32x4 *>(smf + slot_at + wave * kBalSlotWords) + lane;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           sl[k * 64] = f32x4{acc0[4 * k], acc0[4 * k + 1], acc0[4 * k + 2], acc0[4 * k + 3]};
@@ -519,7 +523,8 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
       __syncthreads();
       if (wave < rem * c && part == 0) {
         for (int k2 = 1; k2 < c; ++k2) {  // in wave order: the sum does not depend on timing
-          const f32x4 *sl = reinterpret_cast<const f32x4 *>(smf + (wave + k2) * kBalSlotWords) + lane;
+          const f32x4 *sl =
+              reinterpret_cast<const f32x4 *>(smf + slot_at + (wave + k2) * kBalSlotWords) + lane;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const f32x4 a = sl[k * 64], b = sl[(k + 4) * 64];
@@ -539,12 +544,12 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
 
 template <bool BAL = false>
 __device__ __forceinline__ void correlate_rows_f32(const PlanDesc &plan, const LevelView &v, float *smf,
-                                   float *__restrict__ outp) {
+                                   float *__restrict__ outp, int slot_at = 0) {
   switch (v.T) {
-    case 8: correlate_rows_f32_t<8, BAL>(plan, v, smf, outp); break;
-    case 4: correlate_rows_f32_t<4, BAL>(plan, v, smf, outp); break;
-    case 2: correlate_rows_f32_t<2, BAL>(plan, v, smf, outp); break;
-    default: correlate_rows_f32_t<1, BAL>(plan, v, smf, outp); break;
+    case 8: correlate_rows_f32_t<8, BAL>(plan, v, smf, outp, slot_at); break;
+    case 4: correlate_rows_f32_t<4, BAL>(plan, v, smf, outp, slot_at); break;
+    case 2: correlate_rows_f32_t<2, BAL>(plan, v, smf, outp, slot_at); break;
+    default: correlate_rows_f32_t<1, BAL>(plan, v, smf, outp, slot_at); break;
   }
 }
 
@@ -662,9 +667,12 @@ __device__ __forceinline__ V load_elem(const S *sm, const FusedLayout &lay, int 
 // Fused kernel: one workgroup per pulse.  Level 1 is lifted straight from
 // HBM; every level's bands are correlated as soon as they exist, then the
 // next level is lifted from c_l.  Odd and even levels live in alternating
-// LDS regions so that c_l stays intact while level l+1 is written.
+// LDS regions so that c_l stays intact while level l+1 is written.  With
+// BAL (float filters), levels whose last round of tiles would leave most
+// waves idle cut those tiles over the waves (see correlate_rows_f32_t),
+// with partial-sum slots from word lay.total of smem.
 // ===========================================================================
-template <int F>
+template <int F, bool BAL = false>
 __device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLayout &lay,
                             const typename RxOf<F>::T *__restrict__ rx, long long n,
                             typename RxOf<F>::Out *__restrict__ out, char *smem) {
@@ -689,7 +697,7 @@ __device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLay
     if constexpr (INT) {
       correlate_level_int(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N);
     } else {
-      correlate_rows_f32(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N);
+      correlate_rows_f32<BAL>(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N, lay.total);
     }
     if (l < lay.J) {
       const int np = N >> (l + 1);
@@ -706,7 +714,7 @@ __device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLay
   }
 }
 
-template <int F>
+template <int F, bool BAL>
 __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, FusedLayout lay,
                                                                 const void *__restrict__ rx_all,
                                                                 long long n, long long rx_stride,
@@ -716,8 +724,8 @@ __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, 
   using OutT = typename RxOf<F>::Out;
   extern __shared__ __align__(16) char smem_fused[];
   const long long pulse = blockIdx.x;
-  fused_pulse<F>(plan, lay, reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride, n,
-                 reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2, smem_fused);
+  fused_pulse<F, BAL>(plan, lay, reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride, n,
+                      reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2, smem_fused);
 }
 
 // ===========================================================================
@@ -1032,16 +1040,31 @@ template <int F>
 static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, const void *rx,
                                  long long n, long long count, long long rx_stride, void *out,
                                  long long out_stride, hipStream_t st) {
-  size_t shm = (size_t)lay.total * 4;
+  // The balanced instance needs partial-sum slots after the layout: taken
+  // when they fit and cost no occupancy (two workgroups per CU still fit,
+  // or there are no more pulses than CUs).
+  constexpr size_t kSlots = (size_t)(kFusedThreads / 64) * kBalSlotWords;
+  const size_t bal_words = (size_t)lay.total + kSlots;
+  const bool bal = F != F_LEGALL53_INT && host::fused_wants_bal(lay) &&
+                   (bal_words <= (size_t)host::kLdsWordsTwoPerCu ||
+                    (count <= 256 && bal_words <= (size_t)host::kLdsWords));
+  const size_t shm = (bal ? bal_words : (size_t)lay.total) * 4;
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)fused_correlate<F>,
+    hipError_t e = hipFuncSetAttribute((const void *)fused_correlate<F, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)fused_correlate<F, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(fused_correlate<F>, dim3((unsigned)count), dim3(kFusedThreads), shm, st, plan, lay, rx,
-                     n, rx_stride, out, out_stride);
+  if (bal)
+    hipLaunchKernelGGL((fused_correlate<F, true>), dim3((unsigned)count), dim3(kFusedThreads), shm,
+                       st, plan, lay, rx, n, rx_stride, out, out_stride);
+  else
+    hipLaunchKernelGGL((fused_correlate<F, false>), dim3((unsigned)count), dim3(kFusedThreads),
+                       shm, st, plan, lay, rx, n, rx_stride, out, out_stride);
   return hipGetLastError();
 }
 

@@ -341,12 +341,15 @@ inline int layout_violation(const PlanDesc &d, const FusedLayout &lay) {
   return 0;
 }
 
-// Whether some level of a whole-pulse layout ends with a round of MFMA
-// tiles that leaves more than half of a workgroup's waves idle (1 .. NW/2
-// tiles for NW waves): the case the balanced correlation cuts over the
-// waves.  Mirrors the tile count of correlate_rows_f32_t.
-inline bool fused_wants_bal(const FusedLayout &lay) {
+// Partial-sum slots (kBalSlotWords each) the balanced correlation needs for
+// a whole-pulse layout: a level whose last round of MFMA tiles leaves more
+// than half of a workgroup's NW waves idle (rem = 1 .. NW/2 tiles) cuts each
+// of those tiles over NW / rem waves, whose rem * (NW / rem - 1) helpers
+// hand over partial sums; 0 if no level does.  Mirrors the tile count of
+// correlate_rows_f32_t.
+inline int fused_bal_slots(const FusedLayout &lay) {
   constexpr int NW = kFusedThreads / 64;
+  int slots = 0;
   for (int l = 1; l <= lay.J; ++l) {
     const int P = 1 << l;
     const int rows = (lay.N >> l) >> lay.logT[l];
@@ -354,9 +357,9 @@ inline bool fused_wants_bal(const FusedLayout &lay) {
     const int pc = lay.pc[l] > 0 ? lay.pc[l] : P;
     const int last = P - ((P - 1) / pc) * pc;   // phases of the last column chunk
     const int rem = (mpairs * (P < 16 ? 1 : last >> 4)) % NW;
-    if (rem >= 1 && rem <= NW / 2) return true;
+    if (rem >= 1 && rem <= NW / 2) slots = std::max(slots, rem * (NW / rem - 1));
   }
-  return false;
+  return slots;
 }
 
 }  // namespace host

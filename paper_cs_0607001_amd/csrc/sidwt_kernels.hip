@@ -341,7 +341,7 @@ __device__ __forceinline__ int row_start(const LevelView &v, int p1, int b) {
 // wave: the partial sums pass through LDS slots of kBalSlotWords per wave
 // (aliasing the band windows and weights, which are no longer read) and
 // are added in wave order, so the result does not depend on timing.  The
-// slots start at word slot_at of smf: 0 for a tile item (they alias its
+// rem * (NW / rem - 1) slots (at most NW - 1) start at word slot_at of smf: 0 for a tile item (they alias its
 // windows and weights, no longer read), the end of the layout for a whole
 // pulse (whose bands stay live); the allocation must hold NW * kBalSlotWords
 // words from there.
@@ -513,7 +513,10 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
       if (wave < rem * c) accumulate(mp, nt, part * GT / c, (part + 1) * GT / c, acc0, acc1);
       __syncthreads();  // every wave is done with the windows and weights
       if (wave < rem * c && part > 0) {
-        f32x4 *sl = reinterpret_cast<f32x4 *>(smf + slot_at + wave * kBalSlotWords) + lane;
+        // compact slots: the c - 1 helpers of each cut tile, in wave order
+        f32x4 *sl = reinterpret_cast<f32x4 *>(
+                        smf + slot_at + ((wave / c) * (c - 1) + part - 1) * kBalSlotWords) +
+                    lane;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           sl[k * 64] = f32x4{acc0[4 * k], acc0[4 * k + 1], acc0[4 * k + 2], acc0[4 * k + 3]};
@@ -523,8 +526,9 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
       __syncthreads();
       if (wave < rem * c && part == 0) {
         for (int k2 = 1; k2 < c; ++k2) {  // in wave order: the sum does not depend on timing
-          const f32x4 *sl =
-              reinterpret_cast<const f32x4 *>(smf + slot_at + (wave + k2) * kBalSlotWords) + lane;
+          const f32x4 *sl = reinterpret_cast<const f32x4 *>(
+                                smf + slot_at + ((wave / c) * (c - 1) + k2 - 1) * kBalSlotWords) +
+                            lane;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
             const f32x4 a = sl[k * 64], b = sl[(k + 4) * 64];
@@ -1043,9 +1047,9 @@ static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, c
   // The balanced instance needs partial-sum slots after the layout: taken
   // when they fit and cost no occupancy (two workgroups per CU still fit,
   // or there are no more pulses than CUs).
-  constexpr size_t kSlots = (size_t)(kFusedThreads / 64) * kBalSlotWords;
-  const size_t bal_words = (size_t)lay.total + kSlots;
-  const bool bal = F != F_LEGALL53_INT && host::fused_wants_bal(lay) &&
+  const int slots = host::fused_bal_slots(lay);
+  const size_t bal_words = (size_t)lay.total + (size_t)slots * kBalSlotWords;
+  const bool bal = F != F_LEGALL53_INT && slots > 0 &&
                    (bal_words <= (size_t)host::kLdsWordsTwoPerCu ||
                     (count <= 256 && bal_words <= (size_t)host::kLdsWords));
   const size_t shm = (bal ? bal_words : (size_t)lay.total) * 4;

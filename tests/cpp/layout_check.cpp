@@ -43,9 +43,37 @@ static int check(int filter, int J, int m, long long n, bool verbose, long long 
     return 1;
   }
   ++*n_ok;
+  // Balanced correlation (float filters): the helpers of every cut tile get
+  // distinct partial-sum slots below fused_bal_slots(lay).  The tile count
+  // is formed here as the correlation loop forms it (column chunks of pc).
+  const int slots = fused_bal_slots(lay);
+  if (filter != F_LEGALL53_INT) {
+    for (int l = 1; l <= J; ++l) {
+      const int P = 1 << l, L = (int)(N >> l);
+      const int mtiles = (L / lay.T[l] + 31) / 32, mpairs = (mtiles + 1) / 2;
+      int pcc = P;
+      for (int r0 = 0; r0 < P; r0 += lay.pc[l]) pcc = std::min(lay.pc[l], P - r0);
+      const int ntiles = mpairs * (P < 16 ? 1 : pcc / 16);
+      const int NW = kFusedThreads / 64, rem = ntiles % NW;
+      if (rem < 1 || rem > NW / 2) continue;
+      const int c = NW / rem;
+      bool seen[64] = {};
+      for (int w = 0; w < rem * c; ++w) {
+        if (w % c == 0) continue;  // the tile's owner keeps its sum in registers
+        const int idx = (w / c) * (c - 1) + w % c - 1;
+        if (idx < 0 || idx >= slots || seen[idx]) {
+          std::printf("SLOT VIOLATION: filter=%d J=%d m=%d n=%lld level %d wave %d\n", filter, J,
+                      m, n, l, w);
+          return 1;
+        }
+        seen[idx] = true;
+      }
+    }
+  }
   if (verbose)
-    std::printf("filter=%d J=%d m=%d n=%lld N=%lld: LDS %d bytes (%s per CU)\n", filter, J, m, n,
-                N, lay.total * 4, lay.total <= kLdsWordsTwoPerCu ? "2" : "1");
+    std::printf("filter=%d J=%d m=%d n=%lld N=%lld: LDS %d bytes (%s per CU), balanced +%d slots\n",
+                filter, J, m, n, N, lay.total * 4, lay.total <= kLdsWordsTwoPerCu ? "2" : "1",
+                slots);
   return bad;
 }
 
@@ -58,6 +86,8 @@ int main() {
   bad += check(F_LEGALL53_INT, 6, 512, 4096, true, &ok);
   bad += check(F_D4, 9, 2048, 8192, true, &ok);
   bad += check(F_CDF97, 10, 2048, 16384, true, &ok);
+  bad += check(F_CDF97, 5, 512, 4096, true, &ok);
+  bad += check(F_CDF97, 5, 512, 2048, true, &ok);
   // sweep
   const int filters[] = {F_LEGALL53, F_CDF97, F_D4, F_LEGALL53_INT};
   const int ms[] = {1, 2, 5, 16, 37, 64, 100, 255, 512, 1000, 2048, 4096};

@@ -296,3 +296,25 @@ def test_empty_batches(dev):
     with S.Bank("cdf97", 3, [crandn(rng, 16), crandn(rng, 32)]) as bank:
         assert bank.correlate([], []) == []
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_uniform_batch_of_short_pulses(dev, n):
+    """More pulses than CUs of a length whose levels leave most waves idle:
+    the balanced whole-pulse instance with its partial-sum slots after the
+    layout (two workgroups per CU)."""
+    torch, S = dev
+    count, J = 300, 5
+    b = W.batched_uniform(seed=31, count=count, n=n, m=256, J=J)
+    print(f"[case] uniform {count} x {n}, 9/7 J=5", flush=True)
+    with S.plan_create(b.filter, J, b.ref) as plan:
+        out = S.correlate_many(plan, torch.from_numpy(b.rx).cuda())
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(2)
+        for i in (0, 151, count - 1):
+            lags = np.unique(np.concatenate([[0, 1, n - 1], rng.integers(0, n, 40)]))
+            got = out[i][:, lags].cpu().numpy().astype(np.complex128)
+            for j in range(J):
+                want = O.correlate_at(b.filter, J, b.ref, b.rx[i].astype(np.complex128), j, lags)
+                e = np.linalg.norm(got[j] - want) / np.linalg.norm(want)
+                assert e <= 1e-5, (n, i, j, e)

@@ -215,10 +215,15 @@ int sidwt_correlate_batch(const sidwt_plan *const *plans,
  * scratch: issue them on one stream (or synchronise in between). */
 typedef struct sidwt_bank sidwt_bank;
 
-enum { SIDWT_BANK_FP16 = 1, SIDWT_BANK_BF16 = 2 };
+enum { SIDWT_BANK_FP32 = 0, SIDWT_BANK_FP16 = 1, SIDWT_BANK_BF16 = 2 };
 
 /* refs[e]: host complex64 arrays of m[e] samples (ascending m).  Builds one
- * plan per reference and the split weights; synchronous.
+ * plan per reference and, for FP16/BF16, the split weights; synchronous.
+ * SIDWT_BANK_FP32 keeps the FP32 path instead: a call runs every (request,
+ * eligible reference) pair as one pulse of a one-shot uneven batch (the
+ * kernels of sidwt_correlate_batch, FP32 MFMA, same output layout and
+ * tolerance as sidwt_correlate); such calls synchronise `hip_stream` before
+ * returning, record no workspace timing, and use no workspace scratch.
  * SIDWT_E_UNSUPPORTED for the integer filter; SIDWT_E_INVAL if m is not
  * ascending. */
 int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64_t *m,
@@ -227,7 +232,7 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
 /* `count` requests: rx[i] (device, n[i] complex64), J[i] <= Jmax scales,
  * out[i] (device, sidwt_bank_out_len(bank, n[i], J[i]) complex64, laid out
  * [e][j][k] for eligible reference e, scale j, lag k; 16-byte aligned, else
- * SIDWT_E_INVAL).  All requests go through one lifting pass and one GEMM
+ * SIDWT_E_INVAL; NULL allowed for a request with no eligible reference).  All requests go through one lifting pass and one GEMM
  * launch on `hip_stream`; returns once both are queued.  count = 0 is a
  * no-op (nothing launched or timed). */
 int sidwt_bank_correlate(sidwt_bank *bank, const void *const *rx, const int64_t *n,
@@ -255,7 +260,8 @@ int sidwt_bank_ws_timing(sidwt_bank_ws *ws, int on);
 int sidwt_bank_ws_times(sidwt_bank_ws *ws, float *lift_ms, float *gemm_ms);
 
 /* Device scratch one request needs inside a workspace (bytes; -1 on bad
- * arguments). */
+ * arguments); for SIDWT_BANK_FP32, the most its one-shot batch may hold
+ * (one pyramid per eligible reference). */
 int64_t sidwt_bank_scratch_bytes(const sidwt_bank *bank, int64_t n, int J);
 
 /* Eligible references for a pulse of n samples (-1 on bad arguments). */

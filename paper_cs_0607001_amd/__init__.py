@@ -303,7 +303,7 @@ def correlate_batch(plans, rx, out=None, stream=None):
 # Reference banks (16-bit MFMA, hi+lo correction)
 # ---------------------------------------------------------------------------
 
-BANK_PRECISION = {"fp16": 1, "bf16": 2}
+BANK_PRECISION = {"fp32": 0, "fp16": 1, "bf16": 2}
 BANK_INFO_KEYS = ("references", "Jmax", "precision", "weight_bytes", "max_window")
 
 

@@ -18,6 +18,7 @@
 #include <cstdlib>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -36,6 +37,10 @@ hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
 }  // namespace sidwt
 
 extern "C++" const sidwt::PlanDesc *sidwt_plan_desc(const sidwt_plan *p);
+// One-shot uneven batch over plan descriptors (sidwt_batch.cpp).
+extern "C++" int sidwt_batch_oneshot(const sidwt::PlanDesc *const *descs, const int64_t *n,
+                                     const void *const *rx, void *const *out, int count,
+                                     hipStream_t st);
 
 using namespace sidwt;
 using namespace sidwt::host;
@@ -143,12 +148,55 @@ struct sidwt_bank {
   sidwt_bank_ws *ws = nullptr;      // default workspace
 };
 
+namespace {
+
+// FP32 bank: every (request, eligible reference) pair as one pulse of a
+// one-shot uneven batch, with the reference's plan descriptor cut to the
+// request's J (its phases of levels 1..J are the same for any J <= Jmax).
+int correlate_fp32(sidwt_bank *bk, const void *const *rx, const int64_t *n, const int *J,
+                   void *const *out, int count, hipStream_t st) {
+  std::map<std::pair<int, int>, int> at;   // (reference, J) -> descs index
+  std::vector<std::pair<int, int>> key;    // per pulse
+  std::vector<int64_t> ns;
+  std::vector<const void *> rxs;
+  std::vector<void *> outs;
+  for (int i = 0; i < count; ++i) {
+    if (!rx[i] || n[i] < 1 || J[i] < 1 || J[i] > bk->Jmax) return SIDWT_E_INVAL;
+    const int64_t N = transform_length(n[i], J[i]);
+    if ((N >> J[i]) < 2) return SIDWT_E_INVAL;
+    const int E = (int)sidwt_bank_eligible(bk, n[i]);
+    // (no eligible reference: an empty output, whose pointer may be NULL)
+    if (E > 0 && (!out[i] || reinterpret_cast<uintptr_t>(out[i]) % 16)) return SIDWT_E_INVAL;
+    for (int e = 0; e < E; ++e) {
+      const std::pair<int, int> k(e, J[i]);
+      if (!at.count(k)) at.emplace(k, (int)at.size());
+      key.push_back(k);
+      ns.push_back(n[i]);
+      rxs.push_back(rx[i]);
+      outs.push_back(static_cast<char *>(out[i]) + (size_t)e * J[i] * N * 8);
+    }
+  }
+  if (key.empty()) return SIDWT_OK;
+  if (key.size() > 0x7fffffff) return SIDWT_E_SIZE;
+  std::vector<PlanDesc> descs(at.size());
+  for (const auto &kv : at) {
+    descs[kv.second] = *sidwt_plan_desc(bk->plans[kv.first.first]);
+    descs[kv.second].J = kv.first.second;
+  }
+  std::vector<const PlanDesc *> dp(key.size());
+  for (size_t q = 0; q < key.size(); ++q) dp[q] = &descs[at[key[q]]];
+  return sidwt_batch_oneshot(dp.data(), ns.data(), rxs.data(), outs.data(), (int)key.size(), st);
+}
+
+}  // namespace
+
 extern "C" {
 
 int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64_t *m, int count,
                       int precision, sidwt_bank **out) {
   if (!refs || !m || !out || count < 1 || Jmax < 1 || Jmax > SIDWT_MAX_LEVELS ||
-      (precision != SIDWT_BANK_FP16 && precision != SIDWT_BANK_BF16))
+      (precision != SIDWT_BANK_FP32 && precision != SIDWT_BANK_FP16 &&
+       precision != SIDWT_BANK_BF16))
     return SIDWT_E_INVAL;
   if (filter != SIDWT_LEGALL53 && filter != SIDWT_CDF97 && filter != SIDWT_D4_CAUSAL)
     return filter == SIDWT_LEGALL53_INT ? SIDWT_E_UNSUPPORTED : SIDWT_E_INVAL;
@@ -163,6 +211,7 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
   bk->E = count;
   bk->precision = precision;
   const bool bf16 = precision == SIDWT_BANK_BF16;
+  const bool fp32 = precision == SIDWT_BANK_FP32;  // plans only: no split weights
   int rc = SIDWT_OK;
   // split[e][l][b]: 4 arrays (hi re-out, hi im-out, lo re-out, lo im-out) of
   // len words for every phase r, as [r][a][u]
@@ -176,6 +225,7 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
     bk->m.push_back(m[e]);
     const PlanDesc &d = *sidwt_plan_desc(p);
     if (e == 0) bk->desc0 = d;
+    if (fp32) continue;
     long long total = 0;
     for (int l = 1; l <= Jmax; ++l) total += ((long long)d.lv[l].len[0] + d.lv[l].len[1]) << l;
     std::vector<float> coef(2 * (size_t)total);
@@ -225,7 +275,7 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
   }
   // Panels: per level, per tile of 16 pairs c = e * 2^l + r, per band.
   std::vector<unsigned> words;
-  if (!rc) {
+  if (!rc && !fp32) {
     bk->tile_base.assign(Jmax + 1, 0);
     for (int l = 1; l <= Jmax; ++l) {
       bk->tile_base[l] = (int)bk->tiles.size();
@@ -267,7 +317,7 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
       }
     }
   }
-  if (!rc) {
+  if (!rc && !fp32) {
     // per level: steps_pre[tile_base[l] + l - 1 + T] = steps of tiles [0, T)
     bk->steps_pre.clear();
     for (int l = 1; l <= Jmax; ++l) {
@@ -280,7 +330,7 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
       }
     }
   }
-  if (!rc) {
+  if (!rc && !fp32) {
     bk->lo_lb.assign(2 * (Jmax + 1), 0);
     for (int l = 1; l <= Jmax; ++l)
       for (int b = 0; b < 2; ++b) bk->lo_lb[2 * l + b] = bk->desc0.lv[l].lo[b];
@@ -381,7 +431,9 @@ int sidwt_bank_ws_times(sidwt_bank_ws *ws, float *lift_ms, float *gemm_ms) {
 
 int64_t sidwt_bank_scratch_bytes(const sidwt_bank *bk, int64_t n, int J) {
   if (!bk || n < 1 || J < 1 || J > bk->Jmax) return -1;
-  return 2 * transform_length(n, J) * (int64_t)sizeof(float2);
+  const int64_t pyramid = 2 * transform_length(n, J) * (int64_t)sizeof(float2);
+  // FP32: the one-shot batch may hold one pyramid per eligible reference
+  return bk->precision == SIDWT_BANK_FP32 ? sidwt_bank_eligible(bk, n) * pyramid : pyramid;
 }
 
 int64_t sidwt_bank_eligible(const sidwt_bank *bk, int64_t n) {
@@ -424,6 +476,8 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   if (!bk || !ws || count < 0) return SIDWT_E_INVAL;
   if (count == 0) return SIDWT_OK;
   if (!rx || !n || !J || !out) return SIDWT_E_INVAL;
+  if (bk->precision == SIDWT_BANK_FP32)
+    return correlate_fp32(bk, rx, n, J, out, count, static_cast<hipStream_t>(hip_stream));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   std::vector<BatchPulse> pulses(count);
   std::vector<BankSeg> segs;
@@ -432,12 +486,13 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   long long scratch = 0;
   int Jmax = 0;
   for (int i = 0; i < count; ++i) {
-    if (!rx[i] || !out[i] || n[i] < 1 || J[i] < 1 || J[i] > bk->Jmax) return SIDWT_E_INVAL;
-    if (reinterpret_cast<uintptr_t>(out[i]) & 15) return SIDWT_E_INVAL;
+    if (!rx[i] || n[i] < 1 || J[i] < 1 || J[i] > bk->Jmax) return SIDWT_E_INVAL;
     const int64_t N = transform_length(n[i], J[i]);
     if ((N >> J[i]) < 2) return SIDWT_E_INVAL;
     if (N > (int64_t(1) << 26)) return SIDWT_E_SIZE;
     const int E = (int)sidwt_bank_eligible(bk, n[i]);
+    // (no eligible reference: an empty output, whose pointer may be NULL)
+    if (E > 0 && (!out[i] || (reinterpret_cast<uintptr_t>(out[i]) & 15))) return SIDWT_E_INVAL;
     BatchPulse &p = pulses[i];
     p = BatchPulse{};
     p.rx = rx[i];

@@ -368,19 +368,16 @@ int run(sidwt_batch *b, const void *const *rx, void *const *out, hipStream_t st,
   return map_err(hipGraphLaunch(b->exec, st), "hipGraphLaunch");
 }
 
-}  // namespace
-
-extern "C" {
-
-int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int count,
-                       sidwt_batch **out) {
-  if (!plans || !n || !out || count < 1) return SIDWT_E_INVAL;
+// A batch over plan descriptors (equal pointers share one plan entry).
+int create_from_descs(const PlanDesc *const *descs, const int64_t *n, int count,
+                      sidwt_batch **out) {
+  if (!descs || !n || !out || count < 1) return SIDWT_E_INVAL;
   sidwt_batch *b = new (std::nothrow) sidwt_batch();
   if (!b) return SIDWT_E_NOMEM;
   b->count = count;
-  std::map<const sidwt_plan *, int> idx;
+  std::map<const PlanDesc *, int> idx;
   for (int i = 0; i < count; ++i) {
-    const PlanDesc *d = plans[i] ? sidwt_plan_desc(plans[i]) : nullptr;
+    const PlanDesc *d = descs[i];
     if (!d || n[i] < 1) {
       delete b;
       return SIDWT_E_INVAL;
@@ -398,9 +395,9 @@ int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int cou
       delete b;
       return SIDWT_E_SIZE;
     }
-    auto it = idx.find(plans[i]);
+    auto it = idx.find(d);
     if (it == idx.end()) {
-      it = idx.emplace(plans[i], (int)b->plans.size()).first;
+      it = idx.emplace(d, (int)b->plans.size()).first;
       b->plans.push_back(*d);
     }
     b->pulse_plan.push_back(it->second);
@@ -417,6 +414,36 @@ int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int cou
   }
   *out = b;
   return SIDWT_OK;
+}
+
+}  // namespace
+
+// One-shot batch over plan descriptors (C++ linkage, for the FP32 bank path
+// of the same library): runs without graph capture on `st`, synchronises it
+// and frees the batch.
+int sidwt_batch_oneshot(const sidwt::PlanDesc *const *descs, const int64_t *n,
+                        const void *const *rx, void *const *out, int count, hipStream_t st) {
+  if (!rx || !out) return SIDWT_E_INVAL;
+  sidwt_batch *b = nullptr;
+  int rc = create_from_descs(descs, n, count, &b);
+  if (rc) return rc;
+  rc = run(b, rx, out, st, false);
+  if (!rc) rc = map_err(hipStreamSynchronize(st));
+  sidwt_batch_free(b);
+  return rc;
+}
+
+extern "C" {
+
+int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int count,
+                       sidwt_batch **out) {
+  if (!plans || !n || !out || count < 1) return SIDWT_E_INVAL;
+  std::vector<const PlanDesc *> descs((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    descs[i] = plans[i] ? sidwt_plan_desc(plans[i]) : nullptr;
+    if (!descs[i]) return SIDWT_E_INVAL;
+  }
+  return create_from_descs(descs.data(), n, count, out);
 }
 
 void sidwt_batch_free(sidwt_batch *b) {

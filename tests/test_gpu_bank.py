@@ -9,7 +9,7 @@ import workloads as W
 pytestmark = pytest.mark.gpu
 
 # relative L2 error per plane against the FP64 oracle
-TOL = {"fp16": 1e-5, "bf16": 1e-4}
+TOL = {"fp32": 1e-5, "fp16": 1e-5, "bf16": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +26,7 @@ def bank_refs(seed=7, count=6):
     return W.reference_set(seed, count=count, m_lo=24, m_hi=400)
 
 
-@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
 @pytest.mark.parametrize("filt", ["cdf97", "d4"])
 def test_bank_matches_oracle(dev, filt, precision):
     torch, S = dev
@@ -119,3 +119,31 @@ def test_workspace_kernel_timing(dev):
         torch.cuda.synchronize()
         assert torch.equal(a, b)                 # timing changes nothing in the results
         ws.free()
+
+
+def test_fp32_bank_equals_split_bank(dev):
+    """The FP32 bank (one-shot batch of every request-reference pair) and the
+    FP16 hi+lo bank agree within the FP16 split's tolerance on one request
+    mix, including a request with no eligible reference."""
+    torch, S = dev
+    refs = bank_refs(seed=10, count=5)
+    rng = np.random.default_rng(8)
+    ns = [20, 900, 5000]          # 20 < every reference: no eligible one
+    Js = [1, W.levels_for(900), W.levels_for(5000)]
+    ys = [W.echoes(n, refs[0], rng) if n >= len(refs[0]) else rng.standard_normal(n) + 0j
+          for n in ns]
+    rx = [torch.from_numpy(y.astype(np.complex64)).cuda() for y in ys]
+    with S.Bank("cdf97", 10, refs, "fp32") as b32, S.Bank("cdf97", 10, refs, "fp16") as b16:
+        o32 = b32.correlate(rx, Js)
+        o16 = b16.correlate(rx, Js)
+        torch.cuda.synchronize()
+        assert o32[0].shape[0] == 0 and o16[0].shape[0] == 0
+        for n, a, c in zip(ns, o32, o16):
+            assert a.shape == c.shape
+            if a.numel() == 0:
+                continue
+            for e in range(a.shape[0]):
+                for j in range(a.shape[1]):
+                    x, y = a[e, j].cpu().numpy(), c[e, j].cpu().numpy()
+                    err = np.linalg.norm(x - y) / np.linalg.norm(x)
+                    assert err <= 1e-5, (n, e, j, err)

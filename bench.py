@@ -288,6 +288,7 @@ def bench_batched_uniform(args):
                      "traffic": profiled_traffic() if (args.count, args.n) == (4096, 8192) else None,
                      "kernel": "fused_correlate<CDF97>"},
         "lifting_roofline": lift,
+        "planes_out": {"bytes": out.numel() * 8, "gb_per_s": out.numel() * 8 / (ms_step * 1e-3) / 1e9},
         "plain_per_pulse": None if pp_ms is None else {
             "ms_per_batch": pp_ms, "samples_per_s": args.count * args.n / (pp_ms * 1e-3),
             "batched_speedup": pp_ms / ms_step},
@@ -430,6 +431,8 @@ def bench_uneven(args):
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
                      "kernel": "batch_persistent"},
+        "planes_out": {"bytes": out_all.numel() * 8,
+                       "gb_per_s": out_all.numel() * 8 / (ms * 1e-3) / 1e9},
         "plain_per_pulse": None if pp_ms is None else {
             "ms_per_batch": pp_ms, "samples_per_s": total / (pp_ms * 1e-3),
             "batched_speedup": pp_ms / ms},

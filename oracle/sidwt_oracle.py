@@ -329,6 +329,45 @@ def unlift_x(filt: str, A: np.ndarray, B: np.ndarray) -> np.ndarray:
     return u
 
 
+def unlift_y(filt: str, C: np.ndarray, D: np.ndarray) -> np.ndarray:
+    """Inverse of lift_y (synthesis of one finer approximation from the
+    y-side approximation and detail, the coarse-to-fine step of eq. (21)):
+    the y-side steps undone in reverse order."""
+    if filt == "legall53":
+        e, o = C * 1.0, 0.5 * D
+        o = o + 0.25 * (e + _adv(e))
+        e = e - 0.5 * (o + _dly(o))
+    elif filt == "cdf97":
+        c = CDF97_TABLE_I
+        e, o = C * c["x"], D / c["x"]
+        o = o + c["d"] * (e + _adv(e))
+        e = e + c["g"] * (o + _dly(o))
+        o = o + c["b"] * (e + _adv(e))
+        e = e + c["a"] * (o + _dly(o))
+    elif filt == "d4":
+        return unlift_x("d4", C, D)     # one matrix serves both sides (Sec. III-B)
+    else:
+        raise ValueError(filt)
+    u = np.zeros(C.shape[:-1] + (2 * C.shape[-1],), dtype=np.result_type(e, o))
+    u[..., 0::2] = e
+    u[..., 1::2] = o
+    return u
+
+
+def synthesize_y(filt: str, details, cJ, to: int):
+    """Coarse-to-fine formation (eq. (21) applied level by level): from the
+    coarsest approximation c_J and the details d_J, ..., d_{to+1} (details[l-1]
+    = d_l), the approximation c_to of the received pulse (c_0 = the zero
+    padded pulse).  Integer filter: the reversible steps."""
+    c = cJ
+    for l in range(len(details), to, -1):
+        if filt == "legall53_int":
+            c = i2i_unlift_y(c, details[l - 1])
+        else:
+            c = unlift_y(filt, c, details[l - 1])
+    return c
+
+
 # ---------------------------------------------------------------------------
 # DWT-domain (two-band, level j+1) form of eq. (15), float filters
 # ---------------------------------------------------------------------------

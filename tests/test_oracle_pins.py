@@ -212,6 +212,37 @@ def test_integer_lifting_is_reversible():
     assert np.array_equal(O.i2i_unlift_y(C, D), u)
 
 
+@pytest.mark.parametrize("filt", ["legall53", "cdf97", "d4"])
+def test_y_side_synthesis_inverts_y_side_analysis(filt):
+    """The coarse-to-fine step (eq. (21)): the y-side steps undone in reverse
+    order return the finer approximation, one level and across J levels
+    (synthesize_y from c_J and the details gives back c_to, c_0 = the pulse)."""
+    rng = np.random.default_rng(15)
+    u = crandn(rng, 64)
+    C, D = O.lift_y(filt, u)
+    assert np.abs(O.unlift_y(filt, C, D) - u).max() < 1e-13
+    J, c, details, approx = 4, u, [], [u]
+    for _ in range(J):
+        c, d = O.lift_y(filt, c)
+        details.append(d)
+        approx.append(c)
+    for to in range(J):
+        got = O.synthesize_y(filt, details, approx[J], to)
+        assert np.abs(got - approx[to]).max() < 1e-12 * np.abs(approx[to]).max()
+
+
+def test_integer_synthesis_is_exact():
+    rng = np.random.default_rng(16)
+    u = rng.integers(-2048, 2048, size=(3, 64))
+    J, c, details, approx = 5, u, [], [u]
+    for _ in range(J):
+        c, d = O.i2i_lift_y(c)
+        details.append(d)
+        approx.append(c)
+    for to in range(J):
+        assert np.array_equal(O.synthesize_y("legall53_int", details, approx[J], to), approx[to])
+
+
 def test_53_synthesis_matrix_inverts_analysis():
     # Sec. III-C Case I: P~(z^-1) P(z) = I/2, so the synthesis P(z) as printed
     # (scaled by 2) applied to (A, B) returns 2x... the oracle's unlift uses

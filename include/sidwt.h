@@ -148,6 +148,18 @@ int sidwt_lift_many(int filter, int J, const void *rx, int64_t n,
                     int64_t count, int64_t rx_stride, void *pyr,
                     void *hip_stream);
 
+/* Coarse-to-fine formation (eq. (21), Sec. V): the inverse of the y-side
+ * lifting, level by level, from a critical pyramid laid out as
+ * sidwt_lift_many writes it (pyr + i*N: d_1 | ... | d_J | c_J, N elements
+ * of the lifting's element type) to the approximation c_to of each pulse
+ * (out + i*(N >> to), N >> to elements; to = 0 gives the zero-padded pulse
+ * back, to < J).  N is a transform length (a multiple of 2^J with
+ * N/2^J >= 2); one workgroup per pulse holds 3 (N >> (to+1)) elements in
+ * LDS, so SIDWT_E_UNSUPPORTED beyond 160 KB.  Float filters reconstruct to
+ * FP32 rounding; the integer filter exactly.  count = 0 launches nothing. */
+int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N,
+                     int64_t count, void *out, void *hip_stream);
+
 /* ---- Uneven batches (one persistent launch) ------------------------------
  * A batch fixes `count` pulses, each with its own plan (float filters; the
  * filter and J may differ per pulse) and length n[i].  Short pulses are

@@ -177,6 +177,23 @@ def lift_many(filt: str, J: int, rx, pyr=None, stream=None):
     return pyr
 
 
+def synth_many(filt: str, J: int, pyr, to: int = 0, out=None, stream=None):
+    """Coarse-to-fine formation: from pyramids as lift_many returns them
+    ((count, N) complex64, or (count, N, 2) int32 for the integer filter),
+    the approximations c_to, (count, N >> to) (c_0 = the zero-padded pulses)."""
+    torch = _torch()
+    if not pyr.is_cuda or not pyr.is_contiguous():
+        raise ValueError("pyr must be a contiguous device tensor")
+    count, N = pyr.shape[0], pyr.shape[1]
+    if out is None:
+        shape = (count, N >> to, 2) if filt == "legall53_int" else (count, N >> to)
+        out = torch.empty(shape, dtype=pyr.dtype, device=pyr.device)
+    check(lib().sidwt_synth_many(FILTERS[filt], J, to, ctypes.c_void_p(pyr.data_ptr()), N, count,
+                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+          "sidwt_synth_many")
+    return out
+
+
 def plan_phase(plan: Plan, level: int, band: int, r: int):
     """(lo, coefficients) of a stored phase (test introspection)."""
     lo = ctypes.c_int32()

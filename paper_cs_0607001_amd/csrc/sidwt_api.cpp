@@ -19,6 +19,9 @@ hipError_t launch_fused(const PlanDesc &plan, const FusedLayout &lay, const void
                         hipStream_t st);
 hipError_t launch_lift(int filter, int J, int N, const void *rx, long long n, long long count,
                        long long rx_stride, void *pyr, hipStream_t st);
+hipError_t launch_synth(int filter, int J, int to, int N, const void *pyr, long long count,
+                        void *out, hipStream_t st);
+size_t synth_lds_bytes(int N, int to);
 }  // namespace sidwt
 
 using sidwt::FusedLayout;
@@ -239,6 +242,19 @@ int sidwt_lift_many(int filter, int J, const void *rx, int64_t n, int64_t count,
   if (!rx || !pyr) return SIDWT_E_INVAL;
   return map_err(sidwt::launch_lift(filter, J, (int)N, rx, n, count, rx_stride, pyr,
                                     static_cast<hipStream_t>(hip_stream)));
+}
+
+int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N, int64_t count,
+                     void *out, void *hip_stream) {
+  if (!valid_filter(filter) || J < 1 || J > SIDWT_MAX_LEVELS || to < 0 || to >= J || N < 2 ||
+      N > kMaxN || (N & ((int64_t(1) << J) - 1)) || (N >> J) < 2 || count < 0 ||
+      count > 0x7fffffff)
+    return SIDWT_E_INVAL;
+  if (sidwt::synth_lds_bytes((int)N, to) > (size_t)kLdsWords * 4) return SIDWT_E_UNSUPPORTED;
+  if (count == 0) return SIDWT_OK;
+  if (!pyr || !out) return SIDWT_E_INVAL;
+  return map_err(sidwt::launch_synth(filter, J, to, (int)N, pyr, count, out,
+                                     static_cast<hipStream_t>(hip_stream)));
 }
 
 int sidwt_plan_phase(const sidwt_plan *p, int level, int band, int r, int32_t *lo, int32_t *len,

@@ -99,3 +99,13 @@ def test_integer_plans_that_could_lose_exactness_are_refused(L):
     assert rc != -2
     if rc == 0:
         L.sidwt_free(h)
+
+
+def test_synthesis_arguments_are_checked_on_the_host(L):
+    vp = ctypes.c_void_p
+    assert L.sidwt_synth_many(2, 3, 3, vp(16), 64, 1, vp(16), None) == -1    # to >= J
+    assert L.sidwt_synth_many(2, 3, -1, vp(16), 64, 1, vp(16), None) == -1   # to < 0
+    assert L.sidwt_synth_many(2, 3, 0, vp(16), 60, 1, vp(16), None) == -1    # N % 2^J
+    assert L.sidwt_synth_many(9, 3, 0, vp(16), 64, 1, vp(16), None) == -1    # filter
+    assert L.sidwt_synth_many(2, 3, 0, None, 64, 0, None, None) == 0         # nothing to do
+    assert L.sidwt_synth_many(2, 3, 0, vp(16), 1 << 20, 1, vp(16), None) == -5  # LDS

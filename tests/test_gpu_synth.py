@@ -1,0 +1,94 @@
+"""Coarse-to-fine formation (the inverse y-side lifting of eq. (21)) on the
+GPU against the oracle: from an oracle-computed pyramid to every finer
+approximation, and end to end (lift_many, then synth_many back to the
+zero-padded pulse)."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+FLOAT = ["legall53", "cdf97", "d4"]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_cs_0607001_amd as S
+    S._lib.lib()
+    return torch, S
+
+
+def rel_l2(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def oracle_pyramid(filt, J, u):
+    """(details, approximations) of the y-side lifting of each row of u."""
+    c, details, approx = u, [], [u]
+    for _ in range(J):
+        c, d = O.i2i_lift_y(c) if filt == "legall53_int" else O.lift_y(filt, c)
+        details.append(d)
+        approx.append(c)
+    return details, approx
+
+
+@pytest.mark.parametrize("filt,J,N", [("legall53", 3, 1024), ("cdf97", 5, 4096),
+                                      ("d4", 4, 8192), ("cdf97", 6, 640)])
+def test_synthesis_from_oracle_pyramid(dev, filt, J, N):
+    torch, S = dev
+    rng = np.random.default_rng(J * 100 + N % 97)
+    u = rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))
+    details, approx = oracle_pyramid(filt, J, u)
+    pyr = np.concatenate(details + [approx[J]], axis=-1).astype(np.complex64)
+    print(f"[case] synth {filt} J={J} N={N}", flush=True)
+    for to in sorted({0, 1, J - 1}):
+        got = S.synth_many(filt, J, torch.from_numpy(pyr).cuda(), to=to)
+        torch.cuda.synchronize()
+        want = O.synthesize_y(filt, details, approx[J], to)
+        for i in range(3):
+            assert rel_l2(got[i].cpu().numpy().astype(np.complex128), want[i]) <= 1e-5, (to, i)
+
+
+def test_integer_synthesis_is_bit_exact(dev):
+    torch, S = dev
+    rng = np.random.default_rng(4)
+    J, N = 6, 4096
+    re = rng.integers(-2048, 2048, (5, N))
+    im = rng.integers(-2048, 2048, (5, N))
+    dre, are = oracle_pyramid("legall53_int", J, re)
+    dim, aim = oracle_pyramid("legall53_int", J, im)
+    pyr = np.stack([np.concatenate(dre + [are[J]], -1), np.concatenate(dim + [aim[J]], -1)],
+                   -1).astype(np.int32)
+    print("[case] synth integer 5/3 J=6 N=4096", flush=True)
+    for to in (0, 2, J - 1):
+        got = S.synth_many("legall53_int", J, torch.from_numpy(pyr).cuda(), to=to)
+        torch.cuda.synchronize()
+        g = got.cpu().numpy()
+        assert np.array_equal(g[..., 0], are[to]) and np.array_equal(g[..., 1], aim[to]), to
+
+
+@pytest.mark.parametrize("filt", FLOAT + ["legall53_int"])
+def test_lift_then_synthesize_returns_the_pulse(dev, filt):
+    torch, S = dev
+    rng = np.random.default_rng(7)
+    J, n = 5, 3000                        # N = 3008: the padding comes back as zeros
+    N = O.transform_length(n, J)
+    print(f"[case] round trip {filt} n={n}", flush=True)
+    if filt == "legall53_int":
+        rx = rng.integers(-2048, 2048, (4, n, 2)).astype(np.int16)
+        pyr = S.lift_many(filt, J, torch.from_numpy(rx).cuda())
+        back = S.synth_many(filt, J, pyr, to=0).cpu().numpy()
+        want = np.zeros((4, N, 2), np.int64)
+        want[:, :n] = rx
+        assert np.array_equal(back, want)
+    else:
+        rx = (rng.standard_normal((4, n)) + 1j * rng.standard_normal((4, n))).astype(np.complex64)
+        pyr = S.lift_many(filt, J, torch.from_numpy(rx).cuda())
+        back = S.synth_many(filt, J, pyr, to=0).cpu().numpy().astype(np.complex128)
+        for i in range(4):
+            want = O.zero_pad(rx[i].astype(np.complex128), N)
+            assert rel_l2(back[i], want) <= 1e-5, i

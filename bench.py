@@ -189,6 +189,33 @@ def lifting_roofline(S, filt, J, rx, kernel, reps=20):
             "kernel": kernel}
 
 
+def synthesis_roofline(S, filt, J, rx, kernel, reps=20):
+    """Coarse-to-fine formation over the same batch: from its pyramid back to
+    the zero-padded pulses (c_0), HBM roofline from the bytes it must move
+    (pyramid in, pulses out), timed with HIP events on the launch stream."""
+    import torch
+    stream = torch.cuda.current_stream()
+    pyr = S.lift_many(filt, J, rx)
+    out = S.synth_many(filt, J, pyr, to=0)
+    for _ in range(3):
+        S.synth_many(filt, J, pyr, to=0, out=out)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        S.synth_many(filt, J, pyr, to=0, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = pyr.numel() * pyr.element_size() + out.numel() * out.element_size()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    del pyr, out
+    return {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": gbs / PEAK_HBM_GBS, "us_per_launch": ms * 1e3, "bytes": nbytes,
+            "kernel": kernel}
+
+
 def bench_batched_uniform(args):
     import numpy as np
     import torch
@@ -250,6 +277,8 @@ def bench_batched_uniform(args):
     # Lifting-only kernel (a1 + a2), HBM roofline: 8 B in + 8 B out per sample.
     lift = lifting_roofline(S, b.filter, J, rx, "lift_many<CDF97>")
     log(f"lifting only: {lift['us_per_launch']:.1f} us, {lift['achieved']:.0f} GB/s")
+    synth = synthesis_roofline(S, b.filter, J, rx, "synth_many<CDF97>")
+    log(f"coarse-to-fine synthesis: {synth['us_per_launch']:.1f} us, {synth['achieved']:.0f} GB/s")
 
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
@@ -288,6 +317,7 @@ def bench_batched_uniform(args):
                      "traffic": profiled_traffic() if (args.count, args.n) == (4096, 8192) else None,
                      "kernel": "fused_correlate<CDF97>"},
         "lifting_roofline": lift,
+        "synthesis_roofline": synth,
         "planes_out": {"bytes": out.numel() * 8, "gb_per_s": out.numel() * 8 / (ms_step * 1e-3) / 1e9},
         "plain_per_pulse": None if pp_ms is None else {
             "ms_per_batch": pp_ms, "samples_per_s": args.count * args.n / (pp_ms * 1e-3),
@@ -465,6 +495,8 @@ def bench_integer(args):
     log(f"integer: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s (FP64 MFMA)")
     lift = lifting_roofline(S, "legall53_int", J, rx, "lift_many<LEGALL53_INT>")
     log(f"lifting only: {lift['us_per_launch']:.1f} us, {lift['achieved']:.0f} GB/s")
+    synth = synthesis_roofline(S, "legall53_int", J, rx, "synth_many<LEGALL53_INT>")
+    log(f"coarse-to-fine synthesis: {synth['us_per_launch']:.1f} us, {synth['achieved']:.0f} GB/s")
     cpu = None
     if args.cpu:
         items = [("legall53_int", J, ib.ref_iq, ib.rx_iq[i]) for i in range(16)]
@@ -483,6 +515,7 @@ def bench_integer(args):
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 78.6, "unit": "TFLOP/s",
                      "frac": tflops / 78.6, "traffic": None, "kernel": "fused_correlate<INT53>"},
         "lifting_roofline": lift,
+        "synthesis_roofline": synth,
         "cpu_baseline": cpu,
     }
 

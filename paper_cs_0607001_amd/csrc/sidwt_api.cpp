@@ -21,7 +21,7 @@ hipError_t launch_lift(int filter, int J, int N, const void *rx, long long n, lo
                        long long rx_stride, void *pyr, hipStream_t st);
 hipError_t launch_synth(int filter, int J, int to, int N, const void *pyr, long long count,
                         void *out, hipStream_t st);
-size_t synth_lds_bytes(int N, int to);
+size_t synth_lds_bytes(int filter, int N, int to);
 }  // namespace sidwt
 
 using sidwt::FusedLayout;
@@ -250,7 +250,7 @@ int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N, int6
       N > kMaxN || (N & ((int64_t(1) << J) - 1)) || (N >> J) < 2 || count < 0 ||
       count > 0x7fffffff)
     return SIDWT_E_INVAL;
-  if (sidwt::synth_lds_bytes((int)N, to) > (size_t)kLdsWords * 4) return SIDWT_E_UNSUPPORTED;
+  if (sidwt::synth_lds_bytes(filter, (int)N, to) > (size_t)kLdsWords * 4) return SIDWT_E_UNSUPPORTED;
   if (count == 0) return SIDWT_OK;
   if (!pyr || !out) return SIDWT_E_INVAL;
   return map_err(sidwt::launch_synth(filter, J, to, (int)N, pyr, count, out,

@@ -280,6 +280,19 @@ def bench_batched_uniform(args):
     synth = synthesis_roofline(S, b.filter, J, rx, "synth_many<CDF97>")
     log(f"coarse-to-fine synthesis: {synth['us_per_launch']:.1f} us, {synth['achieved']:.0f} GB/s")
 
+    # Scale mask: the two coarsest planes only (every level still lifted).
+    coarse = [J - 2, J - 1]
+    for _ in range(3):
+        S.correlate_many(plan, rx, out=out, planes=coarse)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        S.correlate_many(plan, rx, out=out, planes=coarse)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    coarse_ms = ev0.elapsed_time(ev1) / args.steps
+    log(f"coarse planes {coarse} only: {coarse_ms:.3f} ms/step ({ms_step / coarse_ms:.1f}x faster "
+        f"than all {J})")
+
     if args.copy_probe:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
@@ -318,6 +331,8 @@ def bench_batched_uniform(args):
                      "kernel": "fused_correlate<CDF97>"},
         "lifting_roofline": lift,
         "synthesis_roofline": synth,
+        "coarse_planes_only": {"planes": coarse, "ms_per_step": coarse_ms,
+                               "samples_per_s": samples / (coarse_ms * 1e-3)},
         "planes_out": {"bytes": out.numel() * 8, "gb_per_s": out.numel() * 8 / (ms_step * 1e-3) / 1e9},
         "plain_per_pulse": None if pp_ms is None else {
             "ms_per_batch": pp_ms, "samples_per_s": args.count * args.n / (pp_ms * 1e-3),

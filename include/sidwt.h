@@ -137,6 +137,16 @@ int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n,
                          int64_t count, int64_t rx_stride, void *out,
                          int64_t out_stride);
 
+/* Scale mask (Sec. V: the coarse scales can be correlated on their own):
+ * as sidwt_correlate_many, but only the planes j with bit j of plane_mask
+ * set are computed (every level is still lifted); the other planes of out
+ * are left untouched.  Bits at or above J are ignored; no plane left ->
+ * SIDWT_E_INVAL.  Pulses that need the tiled path (longer than one
+ * workgroup's LDS) take only the full mask (else SIDWT_E_UNSUPPORTED). */
+int sidwt_correlate_planes(const sidwt_plan *p, const void *rx, int64_t n,
+                           int64_t count, int64_t rx_stride, void *out,
+                           int64_t out_stride, unsigned plane_mask);
+
 /* Lifting only (a1 + a2 of the path, for bandwidth measurement and for
  * callers that correlate elsewhere): `count` pulses of n samples, pulse i
  * at rx + i*rx_stride; writes the critical y-side pyramid of each pulse,

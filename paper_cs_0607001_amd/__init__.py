@@ -145,18 +145,30 @@ def correlate(plan: Plan, rx, out=None, stream=None):
     return out
 
 
-def correlate_many(plan: Plan, rx, out=None, stream=None):
+def correlate_many(plan: Plan, rx, out=None, stream=None, planes=None):
     """Uniform batch in one launch.  rx: complex64 (count, n) or int16
-    (count, n, 2); returns (count, J, N) or (count, J, N, 2)."""
+    (count, n, 2); returns (count, J, N) or (count, J, N, 2).  planes: an
+    iterable of plane indices to compute (the others of out are left as they
+    are); None computes all."""
     _check_rx(plan, rx)
     count, n = rx.shape[0], rx.shape[1]
     N = transform_length(n, plan.J)
     if out is None:
         out = _out_like(plan, (count,), N, rx.device)
     check(lib().sidwt_set_stream(plan.handle, _stream_ptr(stream)), "sidwt_set_stream")
-    check(lib().sidwt_correlate_many(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count, n,
-                                     ctypes.c_void_p(out.data_ptr()), plan.J * N),
-          "sidwt_correlate_many")
+    if planes is None:
+        check(lib().sidwt_correlate_many(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count, n,
+                                         ctypes.c_void_p(out.data_ptr()), plan.J * N),
+              "sidwt_correlate_many")
+    else:
+        mask = 0
+        for j in planes:
+            if not 0 <= int(j) < plan.J:
+                raise ValueError(f"plane {j} outside 0..{plan.J - 1}")
+            mask |= 1 << int(j)
+        check(lib().sidwt_correlate_planes(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count,
+                                           n, ctypes.c_void_p(out.data_ptr()), plan.J * N, mask),
+              "sidwt_correlate_planes")
     return out
 
 

@@ -48,6 +48,8 @@ def _declare(L):
     L.sidwt_correlate_many.restype = i32
     L.sidwt_lift_many.argtypes = [i32, i32, vp, i64, i64, i64, vp, vp]
     L.sidwt_lift_many.restype = i32
+    L.sidwt_correlate_planes.argtypes = [vp, vp, i64, i64, i64, vp, i64, c.c_uint]
+    L.sidwt_correlate_planes.restype = i32
     L.sidwt_synth_many.argtypes = [i32, i32, i32, vp, i64, i64, vp, vp]
     L.sidwt_synth_many.restype = i32
     L.sidwt_correlate_batch.argtypes = [c.POINTER(vp), c.POINTER(vp), c.POINTER(i64),

@@ -16,7 +16,7 @@ hipError_t launch_tree(int filter, const void *in, int in_lo, int in_len, int le
                        hipStream_t st);
 hipError_t launch_fused(const PlanDesc &plan, const FusedLayout &lay, const void *rx, long long n,
                         long long count, long long rx_stride, void *out, long long out_stride,
-                        hipStream_t st);
+                        unsigned planes, hipStream_t st);
 hipError_t launch_lift(int filter, int J, int N, const void *rx, long long n, long long count,
                        long long rx_stride, void *pyr, hipStream_t st);
 hipError_t launch_synth(int filter, int J, int to, int N, const void *pyr, long long count,
@@ -190,9 +190,14 @@ int sidwt_set_stream(sidwt_plan *p, void *hip_stream) {
   return SIDWT_OK;
 }
 
-int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
-                         int64_t rx_stride, void *out, int64_t out_stride) {
+// Uniform batch, the planes of `planes` (bit j: plane j) only.
+static int correlate_many_planes(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                                 int64_t rx_stride, void *out, int64_t out_stride,
+                                 unsigned planes) {
   if (!p || count < 0 || count > 0x7fffffff) return SIDWT_E_INVAL;
+  const unsigned all = (1u << p->J) - 1u;
+  planes &= all;
+  if (!planes) return SIDWT_E_INVAL;
   int64_t N = 0;
   int rc = check_pulse(p, n, &N);
   if (rc) return rc;
@@ -202,10 +207,10 @@ int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t
   FusedLayout lay;
   if (make_layout(p->desc, N, &lay) == 0)
     return map_err(sidwt::launch_fused(p->desc, lay, rx, n, count, rx_stride, out, out_stride,
-                                       p->stream));
+                                       planes, p->stream));
   // Too long for one workgroup's LDS: levels lifted into an HBM scratch
   // pyramid, then lag tiles (the uneven-batch machinery, one plan).
-  if (p->filter == SIDWT_LEGALL53_INT) return SIDWT_E_UNSUPPORTED;
+  if (p->filter == SIDWT_LEGALL53_INT || planes != all) return SIDWT_E_UNSUPPORTED;
   if (!p->tiled || p->tiled_n != n || p->tiled_count != count) {
     sidwt_batch_free(p->tiled);
     p->tiled = nullptr;
@@ -223,6 +228,17 @@ int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t
     outp[i] = static_cast<char *>(out) + i * out_stride * 8;
   }
   return sidwt_batch_run(p->tiled, rxp.data(), outp.data(), p->stream);
+}
+
+int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                         int64_t rx_stride, void *out, int64_t out_stride) {
+  return correlate_many_planes(p, rx, n, count, rx_stride, out, out_stride, ~0u);
+}
+
+int sidwt_correlate_planes(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                           int64_t rx_stride, void *out, int64_t out_stride,
+                           unsigned plane_mask) {
+  return correlate_many_planes(p, rx, n, count, rx_stride, out, out_stride, plane_mask);
 }
 
 int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out) {

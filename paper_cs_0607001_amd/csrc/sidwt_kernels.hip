@@ -679,7 +679,8 @@ __device__ __forceinline__ V load_elem(const S *sm, const FusedLayout &lay, int 
 template <int F, bool BAL = false>
 __device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLayout &lay,
                             const typename RxOf<F>::T *__restrict__ rx, long long n,
-                            typename RxOf<F>::Out *__restrict__ out, char *smem) {
+                            typename RxOf<F>::Out *__restrict__ out, char *smem,
+                            unsigned planes = ~0u) {
   constexpr bool INT = (F == F_LEGALL53_INT);
   using V = typename ElemOf<F>::T;
   using S = typename std::conditional<INT, int, float>::type;
@@ -698,10 +699,14 @@ __device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLay
   __syncthreads();
 
   for (int l = 1; l <= lay.J; ++l) {
-    if constexpr (INT) {
-      correlate_level_int(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N);
-    } else {
-      correlate_rows_f32<BAL>(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N, lay.total);
+    // plane l-1 only if requested (a coarse-scale subset costs only its own
+    // correlation; every level is still lifted)
+    if ((planes >> (l - 1)) & 1u) {
+      if constexpr (INT) {
+        correlate_level_int(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N);
+      } else {
+        correlate_rows_f32<BAL>(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N, lay.total);
+      }
     }
     if (l < lay.J) {
       const int np = N >> (l + 1);
@@ -723,13 +728,15 @@ __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, 
                                                                 const void *__restrict__ rx_all,
                                                                 long long n, long long rx_stride,
                                                                 void *__restrict__ out_all,
-                                                                long long out_stride) {
+                                                                long long out_stride,
+                                                                unsigned planes) {
   using RxT = typename RxOf<F>::T;
   using OutT = typename RxOf<F>::Out;
   extern __shared__ __align__(16) char smem_fused[];
   const long long pulse = blockIdx.x;
   fused_pulse<F, BAL>(plan, lay, reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride, n,
-                      reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2, smem_fused);
+                      reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2, smem_fused,
+                      planes);
 }
 
 // ===========================================================================
@@ -1043,7 +1050,7 @@ hipError_t launch_tree(int filter, const void *in, int in_lo, int in_len, int le
 template <int F>
 static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, const void *rx,
                                  long long n, long long count, long long rx_stride, void *out,
-                                 long long out_stride, hipStream_t st) {
+                                 long long out_stride, unsigned planes, hipStream_t st) {
   // The balanced instance needs partial-sum slots after the layout: taken
   // when they fit and cost no occupancy (two workgroups per CU still fit,
   // or there are no more pulses than CUs).
@@ -1065,20 +1072,20 @@ static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, c
   }
   if (bal)
     hipLaunchKernelGGL((fused_correlate<F, true>), dim3((unsigned)count), dim3(kFusedThreads), shm,
-                       st, plan, lay, rx, n, rx_stride, out, out_stride);
+                       st, plan, lay, rx, n, rx_stride, out, out_stride, planes);
   else
     hipLaunchKernelGGL((fused_correlate<F, false>), dim3((unsigned)count), dim3(kFusedThreads),
-                       shm, st, plan, lay, rx, n, rx_stride, out, out_stride);
+                       shm, st, plan, lay, rx, n, rx_stride, out, out_stride, planes);
   return hipGetLastError();
 }
 
 hipError_t launch_fused(const PlanDesc &plan, const FusedLayout &lay, const void *rx, long long n,
                         long long count, long long rx_stride, void *out, long long out_stride,
-                        hipStream_t st) {
+                        unsigned planes, hipStream_t st) {
   switch (plan.filter) {
 #define X(F) \
   case F:    \
-    return launch_fused_t<F>(plan, lay, rx, n, count, rx_stride, out, out_stride, st);
+    return launch_fused_t<F>(plan, lay, rx, n, count, rx_stride, out, out_stride, planes, st);
     SIDWT_FOR_FILTERS(X)
 #undef X
   }

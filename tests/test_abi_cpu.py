@@ -109,3 +109,8 @@ def test_synthesis_arguments_are_checked_on_the_host(L):
     assert L.sidwt_synth_many(9, 3, 0, vp(16), 64, 1, vp(16), None) == -1    # filter
     assert L.sidwt_synth_many(2, 3, 0, None, 64, 0, None, None) == 0         # nothing to do
     assert L.sidwt_synth_many(2, 3, 0, vp(16), 1 << 20, 1, vp(16), None) == -5  # LDS
+
+
+def test_plane_mask_entry_rejects_a_null_plan(L):
+    vp = ctypes.c_void_p
+    assert L.sidwt_correlate_planes(None, vp(16), 64, 1, 64, vp(16), 3 * 64, 1) == -1

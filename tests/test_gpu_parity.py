@@ -318,3 +318,33 @@ def test_uniform_batch_of_short_pulses(dev, n):
                 want = O.correlate_at(b.filter, J, b.ref, b.rx[i].astype(np.complex128), j, lags)
                 e = np.linalg.norm(got[j] - want) / np.linalg.norm(want)
                 assert e <= 1e-5, (n, i, j, e)
+
+
+@pytest.mark.parametrize("filt,planes", [("cdf97", [4]), ("cdf97", [3, 4]), ("d4", [0, 2]),
+                                         ("legall53_int", [5])])
+def test_plane_mask_computes_only_the_chosen_planes(dev, filt, planes):
+    """Scale mask (coarse scales on their own): the chosen planes equal the
+    full correlation's, the others keep what out held."""
+    torch, S = dev
+    rng = np.random.default_rng(len(planes) * 7 + len(filt))
+    count = 3
+    print(f"[case] plane mask {filt} {planes}", flush=True)
+    if filt == "legall53_int":
+        J, n, m = 6, 1024, 40
+        ref = rng.integers(-2047, 2048, size=(m, 2)).astype(np.int16)
+        rx = torch.from_numpy(rng.integers(-2048, 2048, size=(count, n, 2)).astype(np.int16))
+    else:
+        J, n, m = 5, 1000, 60
+        ref = crandn(rng, m)
+        rx = torch.from_numpy(np.stack([crandn(rng, n) for _ in range(count)]).astype(np.complex64))
+    with S.plan_create(filt, J, ref) as plan:
+        rx = rx.cuda()
+        full = S.correlate_many(plan, rx)
+        part = torch.full_like(full, 7)
+        S.correlate_many(plan, rx, out=part, planes=planes)
+        torch.cuda.synchronize()
+        for j in range(J):
+            if j in planes:
+                assert torch.equal(part[:, j], full[:, j]), j
+            else:
+                assert bool((part[:, j] == 7).all()), j

@@ -164,8 +164,8 @@ int sidwt_lift_many(int filter, int J, const void *rx, int64_t n,
  * of the lifting's element type) to the approximation c_to of each pulse
  * (out + i*(N >> to), N >> to elements; to = 0 gives the zero-padded pulse
  * back, to < J).  N is a transform length (a multiple of 2^J with
- * N/2^J >= 2); one workgroup per pulse holds 2 (N >> (to+1)) elements in
- * LDS (3 for D4), so SIDWT_E_UNSUPPORTED beyond 160 KB.  Float filters reconstruct to
+ * N/2^J >= 2); one workgroup per pulse holds 1.5 (N >> (to+1)) elements
+ * in LDS, so SIDWT_E_UNSUPPORTED beyond 160 KB.  Float filters reconstruct to
  * FP32 rounding; the integer filter exactly.  count = 0 launches nothing. */
 int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N,
                      int64_t count, void *out, void *hip_stream);

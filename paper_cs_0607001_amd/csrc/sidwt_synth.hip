@@ -13,178 +13,193 @@
 
 namespace sidwt {
 
-constexpr int kSynthThreads = 512;
+// Workgroup size: 8 waves for the float filters, 4 for the integer filter
+// (its pulses are shorter and its levels more numerous per byte; measured
+// faster with more, smaller workgroups).
+template <int F> struct SynthCfg { static constexpr int kThreads = 512; };
+template <> struct SynthCfg<F_LEGALL53_INT> { static constexpr int kThreads = 256; };
 
-// One level, in place: E holds c_l, O holds d_l (L pairs each), both already
-// multiplied by kE / kO (the inverse of the final diagonal scaling); on
-// return E holds the even and O the odd samples of c_{l-1} (for D4: O[k] is
-// sample 2k - 1, the pairing of the forward steps).  A pass that reads only
-// the array it does not write works in place; D4 needs one scratch array T
-// (kBuffers = 3).
-template <int F> struct YSynth;
+// One level of the inverse, in registers: lane k of a 64-lane window holds
+// the pair (c_l[k] * kE, d_l[k] * kO) (kE, kO undo the final diagonal
+// scaling) and leaves with (c_{l-1}[2k], c_{l-1}[2k+1]).  Neighbour taps come
+// from the adjacent lanes; the HL leftmost and HR rightmost lanes of a window
+// only feed their neighbours.
+template <int F> struct YUnlift;
 
-template <> struct YSynth<F_LEGALL53> {
+template <> struct YUnlift<F_LEGALL53> {
   // undo diag(1, 2), then [1 0; -(1+z)/4 1], then [1 (1+z^-1)/2; 0 1]
+  static constexpr int HL = 1, HR = 1;
   static constexpr float kE = 1.0f, kO = 0.5f;
-  static constexpr int kBuffers = 2;
-  __device__ static void run(float2 *E, float2 *O, float2 *, int L, int tid, int nt) {
-    for (int k = tid; k < L; k += nt) {
-      const int k1 = k + 1 == L ? 0 : k + 1;
-      O[k] = fma2(0.25f, add2(E[k], E[k1]), O[k]);
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += nt) {
-      const int km = k == 0 ? L - 1 : k - 1;
-      E[k] = fma2(-0.5f, add2(O[km], O[k]), E[k]);
-    }
-    __syncthreads();
+  __device__ __forceinline__ static void run(float2 &e, float2 &o) {
+    o = fma2(0.25f, add2(e, lane_next(e)), o);
+    e = fma2(-0.5f, add2(lane_prev(o), o), e);
   }
 };
 
-template <> struct YSynth<F_CDF97> {
+template <> struct YUnlift<F_CDF97> {
   // undo diag(1/x, x), then the four steps d, g, b, a in reverse order
+  static constexpr int HL = 2, HR = 2;
   static constexpr float kE = C97::xi, kO = C97::inv_xi;
-  static constexpr int kBuffers = 2;
-  __device__ static void run(float2 *E, float2 *O, float2 *, int L, int tid, int nt) {
-    for (int k = tid; k < L; k += nt) {
-      const int k1 = k + 1 == L ? 0 : k + 1;
-      O[k] = fma2(C97::d, add2(E[k], E[k1]), O[k]);
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += nt) {
-      const int km = k == 0 ? L - 1 : k - 1;
-      E[k] = fma2(C97::g, add2(O[km], O[k]), E[k]);
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += nt) {
-      const int k1 = k + 1 == L ? 0 : k + 1;
-      O[k] = fma2(C97::b, add2(E[k], E[k1]), O[k]);
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += nt) {
-      const int km = k == 0 ? L - 1 : k - 1;
-      E[k] = fma2(C97::a, add2(O[km], O[k]), E[k]);
-    }
-    __syncthreads();
+  __device__ __forceinline__ static void run(float2 &e, float2 &o) {
+    o = fma2(C97::d, add2(e, lane_next(e)), o);
+    e = fma2(C97::g, add2(lane_prev(o), o), e);
+    o = fma2(C97::b, add2(e, lane_next(e)), o);
+    e = fma2(C97::a, add2(lane_prev(o), o), e);
   }
 };
 
-template <> struct YSynth<F_D4> {
-  // undo eq. (17): e1 = c / ka, o2 = d / kb (the load scalings);
-  // o1[k] = o2[k+1] - e1[k+1] (undoes [1 0; 1 z^-1]), into the scratch T;
-  // e = e1 - u0 o1[k] - u1 o1[k-1]; o = o1 + sqrt3 e
+template <> struct YUnlift<F_D4> {
+  // undo eq. (17) on pairs (u[2k], u[2k-1]): after the load scalings
+  // e1 = c / ka and o2 = d / kb, o1[k] = o2[k+1] - e1[k+1] (undoes
+  // [1 0; 1 z^-1]); e = e1 - u0 o1[k] - u1 o1[k-1]; u[2k-1] = o1 + sqrt3 e.
+  // The odd output is then taken from the next lane (u[2k+1]).
+  static constexpr int HL = 1, HR = 2;
   static constexpr float kE = 1.0f / CD4::ka, kO = 1.0f / CD4::kb;
-  static constexpr int kBuffers = 3;
-  __device__ static void run(float2 *E, float2 *O, float2 *T, int L, int tid, int nt) {
-    for (int k = tid; k < L; k += nt) {
-      const int k1 = k + 1 == L ? 0 : k + 1;
-      T[k] = add2(O[k1], scale2(-1.0f, E[k1]));
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += nt) {
-      const int km = k == 0 ? L - 1 : k - 1;
-      const float2 e = fma2(-CD4::u1, T[km], fma2(-CD4::u0, T[k], E[k]));
-      E[k] = e;
-      O[k] = fma2(CD4::s3, e, T[k]);
-    }
-    __syncthreads();
+  __device__ __forceinline__ static void run(float2 &e, float2 &o) {
+    const float2 t = lane_next(add2(o, scale2(-1.0f, e)));
+    e = fma2(-CD4::u1, lane_prev(t), fma2(-CD4::u0, t, e));
+    o = lane_next(fma2(CD4::s3, e, t));
   }
 };
 
-template <> struct YSynth<F_LEGALL53_INT> {
+template <> struct YUnlift<F_LEGALL53_INT> {
   // exact inverse of the reversible steps: o += (e[k] + e[k+1] + 2) >> 2,
   // then e -= (o[k-1] + o[k] + 1) >> 1
+  static constexpr int HL = 1, HR = 1;
   static constexpr float kE = 1.0f, kO = 1.0f;  // unused (no scaling)
-  static constexpr int kBuffers = 2;
-  __device__ static void run(int2 *E, int2 *O, int2 *, int L, int tid, int nt) {
-    for (int k = tid; k < L; k += nt) {
-      const int k1 = k + 1 == L ? 0 : k + 1;
-      O[k].x += (E[k].x + E[k1].x + 2) >> 2;
-      O[k].y += (E[k].y + E[k1].y + 2) >> 2;
-    }
-    __syncthreads();
-    for (int k = tid; k < L; k += nt) {
-      const int km = k == 0 ? L - 1 : k - 1;
-      E[k].x -= (O[km].x + O[k].x + 1) >> 1;
-      E[k].y -= (O[km].y + O[k].y + 1) >> 1;
-    }
-    __syncthreads();
+  __device__ __forceinline__ static void run(int2 &e, int2 &o) {
+    const int2 en = lane_next(e);
+    o.x += (e.x + en.x + 2) >> 2;
+    o.y += (e.y + en.y + 2) >> 2;
+    const int2 op = lane_prev(o);
+    e.x -= (op.x + o.x + 1) >> 1;
+    e.y -= (op.y + o.y + 1) >> 1;
   }
 };
 
 template <class V> __device__ __forceinline__ V scaled(float s, V v) { return scale2(s, v); }
 template <> __device__ __forceinline__ int2 scaled<int2>(float, int2 v) { return v; }
 
-// One workgroup per pulse.  LDS: X and Y (and T for D4) of Lmax = N >> (to
-// + 1) elements.  Level l: X = c_l (scaled by kE), Y = d_l (scaled by kO);
-// after the steps c_{l-1} goes to HBM at the last level, else it is
-// interleaved into X, already scaled for the next level: top-down chunks of
-// one pair per thread, each read before a barrier and written after it (a
-// chunk from pair c0 on writes X[2 c0 ...], which no lower chunk reads).
+// Two consecutive elements in one 16-byte store: to LDS, or streamed to HBM
+// (written once, never read back by this kernel).
+__device__ __forceinline__ void store_pair(float2 *dst, float2 a, float2 b) {
+  *reinterpret_cast<float4 *>(dst) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void store_pair(int2 *dst, int2 a, int2 b) {
+  *reinterpret_cast<int4 *>(dst) = make_int4(a.x, a.y, b.x, b.y);
+}
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void stream_pair(float2 *dst, float2 a, float2 b) {
+  __builtin_nontemporal_store(f32x4_t{a.x, a.y, b.x, b.y}, reinterpret_cast<f32x4_t *>(dst));
+}
+__device__ __forceinline__ void stream_pair(int2 *dst, int2 a, int2 b) {
+  __builtin_nontemporal_store(i32x4_t{a.x, a.y, b.x, b.y}, reinterpret_cast<i32x4_t *>(dst));
+}
+
+// One level over the workgroup: each wave takes UNROLL windows of 64 lanes
+// at a time (64 - HL - HR owned pairs each, circular indices).
+// `load(kc, e, o)` fetches pair kc in [0, L); `store(k, e, o)` receives the
+// owned outputs c_{l-1}[2k], c_{l-1}[2k+1].
+template <int F, int UNROLL, class Load, class Store>
+__device__ __forceinline__ void unlift_level(int L, Load load, Store store) {
+  using U = YUnlift<F>;
+  using V = typename ElemOf<F>::T;
+  constexpr int OWN = 64 - U::HL - U::HR;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int nwin = (L + OWN - 1) / OWN;
+  const bool wide = L >= 64;
+  for (int w0 = wave * UNROLL; w0 < nwin; w0 += nw * UNROLL) {
+    V e[UNROLL], o[UNROLL];
+    int kk[UNROLL];
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int k = (w0 + u) * OWN - U::HL + lane;
+      kk[u] = k;
+      int kc;
+      if (wide) {
+        // every index a stored output needs lies in [-HL, L + HR); the
+        // rest (windows past the end) only has to stay in bounds
+        kc = k < 0 ? k + L : (k >= L ? k - L : k);
+        kc = kc < L ? kc : L - 1;
+      } else {
+        kc = pos_mod(k, L);
+      }
+      load(kc, e[u], o[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) U::run(e[u], o[u]);
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const int k = kk[u];
+      if (lane >= U::HL && lane < 64 - U::HR && k < L && (w0 + u) < nwin) store(k, e[u], o[u]);
+    }
+  }
+}
+
+// One workgroup per pulse.  c_J and every d_l are read from the pyramid in
+// HBM; the intermediate approximations c_{J-1} ... c_{to+1} alternate
+// between two LDS buffers (P: N >> (to+1) elements, holding c_{to+1},
+// c_{to+3}, ...; Q: half that, holding c_{to+2}, c_{to+4}, ...), one barrier
+// per level; c_to goes straight to HBM.  Separate load / store lambdas per
+// source and destination keep every pointer's address space known to the
+// compiler (LDS and global instructions, no flat ones).
 template <int F>
-__global__ __launch_bounds__(kSynthThreads) void synth_many(
+__global__ __launch_bounds__(SynthCfg<F>::kThreads) void synth_many(
     int J, int to, int N, const typename ElemOf<F>::T *__restrict__ pyr_all,
     typename ElemOf<F>::T *__restrict__ out_all) {
   using V = typename ElemOf<F>::T;
-  using Y = YSynth<F>;
-  constexpr bool OB = YLift<F>::kOddBefore;
+  using U = YUnlift<F>;
+  constexpr int UNROLL = 2;
   extern __shared__ __align__(16) char smem_synth[];
   const int Lmax = N >> (to + 1);
-  V *X = reinterpret_cast<V *>(smem_synth);
-  V *Yb = X + Lmax;
-  V *T = Yb + Lmax;   // allocated for D4 only
+  V *const P = reinterpret_cast<V *>(smem_synth);
+  V *const Q = P + Lmax;
   const V *pyr = pyr_all + (long long)blockIdx.x * N;
   V *out = out_all + (long long)blockIdx.x * (N >> to);
-  const int tid = threadIdx.x, nt = blockDim.x;
-  {
-    const int L = N >> J;
-    const V *c = pyr + (N - (N >> J));
-    for (int k = tid; k < L; k += nt) X[k] = scaled(Y::kE, c[k]);
-  }
+  const V *cJ = pyr + (N - (N >> J));
   for (int l = J; l > to; --l) {
     const int L = N >> l;
     const V *d = pyr + (N - (N >> (l - 1)));
-    for (int k = tid; k < L; k += nt) Yb[k] = scaled(Y::kO, d[k]);
-    __syncthreads();
-    Y::run(X, Yb, T, L, tid, nt);
-    if (l - 1 == to) {
-      for (int k = tid; k < L; k += nt) {
-        out[2 * k] = X[k];
-        out[2 * k + 1] = Yb[OB ? (k + 1 == L ? 0 : k + 1) : k];   // OB: Yb[k] is sample 2k - 1
-      }
-    } else {
-      for (int c0 = ((L - 1) / nt) * nt; c0 >= 0; c0 -= nt) {
-        const int k = c0 + tid;
-        V ev{}, ov{};
-        if (k < L) {
-          ev = X[k];
-          ov = Yb[OB ? (k + 1 == L ? 0 : k + 1) : k];
-        }
-        __syncthreads();
-        if (k < L) {
-          X[2 * k] = scaled(Y::kE, ev);
-          X[2 * k + 1] = scaled(Y::kE, ov);
-        }
-        __syncthreads();
-      }
-    }
+    const V *c = ((l - to - 1) & 1) ? Q : P;         // c_l (l < J)
+    V *cn = ((l - to - 2) & 1) ? Q : P;              // c_{l-1} (l - 1 > to)
+    auto load_hbm = [&](int kc, V &e, V &o) {
+      e = scaled(U::kE, cJ[kc]);
+      o = scaled(U::kO, d[kc]);
+    };
+    auto load_lds = [&](int kc, V &e, V &o) {
+      e = scaled(U::kE, c[kc]);
+      o = scaled(U::kO, d[kc]);
+    };
+    auto store_lds = [&](int k, V e, V o) { store_pair(cn + 2 * k, e, o); };
+    auto store_hbm = [&](int k, V e, V o) { stream_pair(out + 2 * k, e, o); };
+    auto level = [&](auto load) {
+      if (l - 1 == to)
+        unlift_level<F, UNROLL>(L, load, store_hbm);
+      else
+        unlift_level<F, UNROLL>(L, load, store_lds);
+    };
+    if (l == J)
+      level(load_hbm);
+    else
+      level(load_lds);
     __syncthreads();
   }
 }
 
 // LDS of one pulse.
-template <int F> size_t synth_lds_bytes_t(int N, int to) {
-  return (size_t)YSynth<F>::kBuffers * (N >> (to + 1)) * 8;
-}
-size_t synth_lds_bytes(int filter, int N, int to) {
-  return filter == F_D4 ? synth_lds_bytes_t<F_D4>(N, to) : synth_lds_bytes_t<F_CDF97>(N, to);
+size_t synth_lds_bytes(int, int N, int to) {
+  const size_t Lmax = (size_t)(N >> (to + 1));
+  return (Lmax + Lmax / 2) * 8;
 }
 
 template <int F>
 static hipError_t launch_synth_t(int J, int to, int N, const void *pyr, long long count, void *out,
                                  hipStream_t st) {
   using V = typename ElemOf<F>::T;
-  const size_t shm = synth_lds_bytes_t<F>(N, to);
+  const size_t shm = synth_lds_bytes(F, N, to);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)synth_many<F>,
@@ -192,7 +207,7 @@ static hipError_t launch_synth_t(int J, int to, int N, const void *pyr, long lon
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(synth_many<F>, dim3((unsigned)count), dim3(kSynthThreads), shm, st, J, to,
+  hipLaunchKernelGGL(synth_many<F>, dim3((unsigned)count), dim3(SynthCfg<F>::kThreads), shm, st, J, to,
                      N, static_cast<const V *>(pyr), static_cast<V *>(out));
   return hipGetLastError();
 }

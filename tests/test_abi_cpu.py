@@ -109,6 +109,10 @@ def test_synthesis_arguments_are_checked_on_the_host(L):
     assert L.sidwt_synth_many(9, 3, 0, vp(16), 64, 1, vp(16), None) == -1    # filter
     assert L.sidwt_synth_many(2, 3, 0, None, 64, 0, None, None) == 0         # nothing to do
     assert L.sidwt_synth_many(2, 3, 0, vp(16), 1 << 20, 1, vp(16), None) == -5  # LDS
+    # 1.5 (N >> (to+1)) complex elements in LDS: 26624 fits in 160 KB, 27648 does not
+    assert L.sidwt_synth_many(2, 5, 0, None, 26624, 0, None, None) == 0
+    assert L.sidwt_synth_many(2, 5, 0, None, 27648, 0, None, None) == -5
+    assert L.sidwt_synth_many(2, 5, 1, None, 27648, 0, None, None) == 0
 
 
 def test_plane_mask_entry_rejects_a_null_plan(L):

@@ -37,7 +37,9 @@ def oracle_pyramid(filt, J, u):
 
 
 @pytest.mark.parametrize("filt,J,N", [("legall53", 3, 1024), ("cdf97", 5, 4096),
-                                      ("d4", 4, 8192), ("cdf97", 6, 640)])
+                                      ("d4", 4, 8192), ("cdf97", 6, 640), ("d4", 5, 192),
+                                      ("d4", 3, 16), ("legall53", 4, 32), ("cdf97", 2, 8),
+                                      ("cdf97", 5, 26624)])   # the largest c_0 in LDS
 def test_synthesis_from_oracle_pyramid(dev, filt, J, N):
     torch, S = dev
     rng = np.random.default_rng(J * 100 + N % 97)

@@ -396,6 +396,36 @@ def correlate_dwt(filt: str, J: int, ref, rx, chunk: int = 256) -> np.ndarray:
     return out
 
 
+def correlate_swapped(filt: str, J: int, ref, rx, chunk: int = 256) -> np.ndarray:
+    """Roles exchanged (Sec. I: the redundant transform may sit on either
+    signal; eq. (20a) approximation form): the received signal gets the
+    all-shift (redundant) y-side analysis and the reference only its critical
+    x-side one.  Plane j, lag s: inner product (conjugate on the reference)
+    of the level-j approximation of the reference with the level-j
+    approximation of the received signal advanced by s, i.e. of
+    roll(y, -s).  Plane 0 is the circular cross-correlation, as for
+    correlate_direct; a shift of rx by t shifts every plane by exactly t;
+    at lags that are multiples of 2^j plane j equals correlate_direct's.
+    Returns complex128 [J, N]."""
+    _check_float(filt)
+    ref = np.asarray(ref, dtype=np.complex128)
+    rx = np.asarray(rx, dtype=np.complex128)
+    N = transform_length(len(rx), J)
+    if len(ref) > N:
+        raise ValueError("reference longer than the transform length")
+    x = zero_pad(ref, N)
+    y = zero_pad(rx, N)
+    xlo, _, ylo, _ = TAPS[filt]
+    out = np.zeros((J, N), dtype=np.complex128)
+    for j in range(J):
+        a = approximation(x, xlo, j)
+        for s0 in range(0, N, chunk):
+            lags = np.arange(s0, min(N, s0 + chunk))
+            Y = np.stack([np.roll(y, -int(s)) for s in lags])
+            out[j, lags] = approximation(Y, ylo, j) @ np.conj(a)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Integer-to-integer 5/3 (reversible lifting with floor shifts).
 # The paper cites reversible integer lifting but prints no rounding rule;

@@ -475,3 +475,87 @@ def test_correlate_at_matches_full_planes():
     lags = [0, 5, 47, 95]
     for j in range(3):
         assert np.abs(O.correlate_at("cdf97", 3, x, y, j, lags) - R[j, lags]).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# P13: roles exchanged (redundant analysis on the received signal, critical
+# on the reference): plane 0 is the FFT cross-correlation, a shift of the
+# received signal shifts every plane by exactly that many lags, plane j
+# agrees with the direct form at lags that are multiples of 2^j (where both
+# sides see the same phase), for the orthogonal D4 bank the exchange is the
+# conjugate of the direct form with the signals' roles swapped, and scalar
+# brute force on a tiny input.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("filt", FLOATS)
+def test_swapped_plane0_is_fft_cross_correlation(filt):
+    rng = np.random.default_rng(31)
+    x, y = crandn(rng, 29), crandn(rng, 90)     # N = 96
+    r = O.correlate_swapped(filt, 3, x, y)
+    X = np.zeros(96, complex)
+    X[:29] = x
+    Y = np.zeros(96, complex)
+    Y[:90] = y
+    want = np.fft.ifft(np.conj(np.fft.fft(X)) * np.fft.fft(Y))
+    assert np.abs(r[0] - want).max() < 1e-12 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("filt", FLOATS)
+def test_swapped_is_exactly_covariant_in_the_received_shift(filt):
+    rng = np.random.default_rng(32)
+    J, N = 4, 128
+    x, y = crandn(rng, 19), crandn(rng, N)
+    r = O.correlate_swapped(filt, J, x, y)
+    for t in (1, 3, 8):
+        rt = O.correlate_swapped(filt, J, x, np.roll(y, t))
+        assert np.abs(rt - np.roll(r, t, axis=1)).max() < 1e-12 * np.abs(r).max()
+    # the direct form is not (its redundant analysis sits on the reference)
+    d = O.correlate_direct(filt, J, x, y)
+    d1 = O.correlate_direct(filt, J, x, np.roll(y, 1))
+    assert np.abs(d1[1:] - np.roll(d[1:], 1, axis=1)).max() > 1e-3 * np.abs(d).max()
+
+
+@pytest.mark.parametrize("filt", FLOATS)
+def test_swapped_equals_direct_on_the_common_phase(filt):
+    rng = np.random.default_rng(33)
+    J, N = 4, 96
+    x, y = crandn(rng, 23), crandn(rng, N)
+    r = O.correlate_swapped(filt, J, x, y)
+    d = O.correlate_direct(filt, J, x, y)
+    for j in range(J):
+        s = np.arange(0, N, 1 << j)
+        assert np.abs(r[j, s] - d[j, s]).max() < 1e-12 * np.abs(d).max()
+        if j:   # other lags: a different polyphase component, not equal
+            o = np.arange(1, N, 1 << j)
+            assert np.abs(r[j, o] - d[j, o]).max() > 1e-3 * np.abs(d).max()
+
+
+def test_swapped_d4_is_the_conjugate_of_the_direct_form_with_roles_swapped():
+    rng = np.random.default_rng(34)
+    J, N = 3, 64
+    x, y = crandn(rng, N), crandn(rng, N)
+    r = O.correlate_swapped("d4", J, x, y)
+    d = O.correlate_direct("d4", J, y, x)
+    neg = (-np.arange(N)) % N
+    assert np.abs(r - np.conj(d[:, neg])).max() < 1e-12 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("filt", FLOATS)
+def test_swapped_brute_force_tiny(filt):
+    rng = np.random.default_rng(35)
+    J, n, m = 3, 24, 6
+    x, y = crandn(rng, m), crandn(rng, n)
+    R = O.correlate_swapped(filt, J, x, y)
+    xlo, _, ylo, _ = O.TAPS[filt]
+    N = 24
+    xs = list(x) + [0] * (N - m)
+    for j in range(J):
+        a = list(xs)
+        for _ in range(j):
+            a = _scalar_analyze(a, xlo)
+        for s in range(N):
+            c = [y[(t + s) % N] for t in range(N)]
+            for _ in range(j):
+                c = _scalar_analyze(c, ylo)
+            want = sum(complex(ai).conjugate() * ci for ai, ci in zip(a, c))
+            assert abs(R[j, s] - want) < 1e-12

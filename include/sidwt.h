@@ -170,6 +170,30 @@ int sidwt_lift_many(int filter, int J, const void *rx, int64_t n,
 int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N,
                      int64_t count, void *out, void *hip_stream);
 
+/* Roles exchanged (Sec. I: the redundant, all-shift analysis may sit on
+ * either signal; eq. (20a)'s approximation form at every scale): each
+ * received pulse gets the redundant y-side tree and the plan's reference
+ * only its critical x-side approximations.  Plane j, lag s (0 <= j < J,
+ * 0 <= s < N): sum_k conj(a_j[k]) * Y_{j,p}[k + s / 2^j] with p = s mod 2^j,
+ * a_j the level-j x-side approximation of the reference (a_0 = the
+ * reference) and Y_{j,p} the level-j y-side approximation of the pulse
+ * advanced by p samples.  A shift of the pulse shifts every plane by
+ * exactly as many lags; at lags that are multiples of 2^j plane j equals
+ * sidwt_correlate_many's.  Layout and strides as sidwt_correlate_many
+ * (complex64 in and out).  `workspace` (device, caller-owned, at least
+ * sidwt_swap_workspace_bytes(p, n, count) bytes; may be NULL when J = 1)
+ * holds levels 1 .. J-1 of the pulses' trees; the plan's stream orders the
+ * launches, and calls that share a workspace must not overlap.  One
+ * workgroup per (pulse, plane) holds that plane's phases in LDS (about
+ * N + 2^j (len_j + 31) complex elements): SIDWT_E_UNSUPPORTED beyond
+ * 160 KB and for the integer filter; SIDWT_E_INVAL for a short workspace.
+ * count = 0 checks the sizes and launches nothing. */
+int64_t sidwt_swap_workspace_bytes(const sidwt_plan *p, int64_t n, int64_t count);
+int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n,
+                            int64_t count, int64_t rx_stride, void *out,
+                            int64_t out_stride, void *workspace,
+                            int64_t workspace_bytes);
+
 /* ---- Uneven batches (one persistent launch) ------------------------------
  * A batch fixes `count` pulses, each with its own plan (float filters; the
  * filter and J may differ per pulse) and length n[i].  Short pulses are

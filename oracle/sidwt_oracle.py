@@ -426,6 +426,23 @@ def correlate_swapped(filt: str, J: int, ref, rx, chunk: int = 256) -> np.ndarra
     return out
 
 
+def correlate_swapped_at(filt: str, J: int, ref, rx, plane: int, lags) -> np.ndarray:
+    """correlate_swapped's plane `plane` at the listed lags only (for
+    sampled checks at sizes where every lag would be too slow)."""
+    _check_float(filt)
+    ref = np.asarray(ref, dtype=np.complex128)
+    rx = np.asarray(rx, dtype=np.complex128)
+    N = transform_length(len(rx), J)
+    x = zero_pad(ref, N)
+    y = zero_pad(rx, N)
+    xlo, _, ylo, _ = TAPS[filt]
+    a = approximation(x, xlo, plane)
+    lags = np.asarray(lags, dtype=np.int64)
+    Y = np.stack([np.roll(y, -int(s)) for s in lags]) if len(lags) else \
+        np.zeros((0, N), np.complex128)
+    return approximation(Y, ylo, plane) @ np.conj(a)
+
+
 # ---------------------------------------------------------------------------
 # Integer-to-integer 5/3 (reversible lifting with floor shifts).
 # The paper cites reversible integer lifting but prints no rounding rule;

@@ -20,7 +20,8 @@ import numpy as np
 
 from ._lib import FILTERS, SidwtError, check, lib  # noqa: F401
 
-__all__ = ["Plan", "plan_create", "correlate", "correlate_many", "lift_many", "out_len",
+__all__ = ["Plan", "plan_create", "correlate", "correlate_many", "correlate_swapped", "lift_many",
+           "synth_many", "out_len",
            "transform_length", "plan_phase", "Batch", "correlate_batch", "Bank",
            "SidwtError", "FILTERS", "version"]
 
@@ -169,6 +170,32 @@ def correlate_many(plan: Plan, rx, out=None, stream=None, planes=None):
         check(lib().sidwt_correlate_planes(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count,
                                            n, ctypes.c_void_p(out.data_ptr()), plan.J * N, mask),
               "sidwt_correlate_planes")
+    return out
+
+
+def correlate_swapped(plan: Plan, rx, out=None, workspace=None, stream=None):
+    """Roles exchanged: redundant y-side analysis on each received pulse,
+    critical x-side on the plan's reference (plane j, lag s pairs the
+    reference's level-j approximation with that of the pulse advanced by s).
+    rx: complex64 (count, n); returns (count, J, N).  workspace: a device
+    buffer of at least sidwt_swap_workspace_bytes (allocated if None)."""
+    _check_rx(plan, rx)
+    torch = _torch()
+    count, n = rx.shape[0], rx.shape[1]
+    N = transform_length(n, plan.J)
+    if out is None:
+        out = _out_like(plan, (count,), N, rx.device)
+    need = lib().sidwt_swap_workspace_bytes(plan.handle, n, count)
+    if need < 0:
+        raise SidwtError(-1, "sidwt_swap_workspace_bytes")
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=rx.device)
+    check(lib().sidwt_set_stream(plan.handle, _stream_ptr(stream)), "sidwt_set_stream")
+    check(lib().sidwt_correlate_swapped(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count, n,
+                                        ctypes.c_void_p(out.data_ptr()), plan.J * N,
+                                        ctypes.c_void_p(workspace.data_ptr()),
+                                        workspace.numel() * workspace.element_size()),
+          "sidwt_correlate_swapped")
     return out
 
 

@@ -52,6 +52,10 @@ def _declare(L):
     L.sidwt_correlate_planes.restype = i32
     L.sidwt_synth_many.argtypes = [i32, i32, i32, vp, i64, i64, vp, vp]
     L.sidwt_synth_many.restype = i32
+    L.sidwt_swap_workspace_bytes.argtypes = [vp, i64, i64]
+    L.sidwt_swap_workspace_bytes.restype = i64
+    L.sidwt_correlate_swapped.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp, i64]
+    L.sidwt_correlate_swapped.restype = i32
     L.sidwt_correlate_batch.argtypes = [c.POINTER(vp), c.POINTER(vp), c.POINTER(i64),
                                         c.POINTER(vp), i32, vp]
     L.sidwt_correlate_batch.restype = i32

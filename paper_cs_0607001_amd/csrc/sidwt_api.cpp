@@ -9,6 +9,7 @@
 
 #include "../../include/sidwt.h"
 #include "sidwt_host.hpp"
+#include "sidwt_swap.hpp"
 
 namespace sidwt {
 hipError_t launch_tree(int filter, const void *in, int in_lo, int in_len, int level, int k0,
@@ -36,6 +37,9 @@ struct sidwt_plan {
   PlanDesc desc;
   void *coef;
   size_t coef_bytes;
+  // The reference as complex64 (float filters): plane 0's weights of the
+  // roles-exchanged correlation.
+  void *ref_dev = nullptr;
   // Pulses too long for the whole-pulse LDS layout go through the tiled
   // batch path; its buffers are kept for the last (n, count) seen.
   mutable sidwt_batch *tiled = nullptr;
@@ -159,12 +163,16 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
     in_len = lv.len[0];
   }
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-  if (ref_dev) (void)hipFree(ref_dev);
+  if (e != hipSuccess || filter == SIDWT_LEGALL53_INT) {
+    if (ref_dev) (void)hipFree(ref_dev);
+    ref_dev = nullptr;
+  }
   if (e != hipSuccess) {
     (void)hipFree(p->coef);
     delete p;
     return map_err(e);
   }
+  p->ref_dev = ref_dev;
   *out = p;
   return SIDWT_OK;
 }
@@ -172,10 +180,9 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
 void sidwt_free(sidwt_plan *p) {
   if (!p) return;
   sidwt_batch_free(p->tiled);
-  if (p->coef) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(p->coef);
-  }
+  if (p->coef || p->ref_dev) (void)hipDeviceSynchronize();
+  if (p->coef) (void)hipFree(p->coef);
+  if (p->ref_dev) (void)hipFree(p->ref_dev);
   delete p;
 }
 
@@ -244,6 +251,47 @@ int sidwt_correlate_planes(const sidwt_plan *p, const void *rx, int64_t n, int64
 int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out) {
   if (!p) return SIDWT_E_INVAL;
   return sidwt_correlate_many(p, rx, n, 1, n, out, sidwt_out_len(p, n));
+}
+
+namespace {
+
+// Workspace of the roles-exchanged correlation: levels 1 .. J-1 of the
+// redundant tree, N complex64 elements per level and pulse.
+int64_t swap_ws_bytes(int J, int64_t N, int64_t count) { return (int64_t)(J - 1) * N * count * 8; }
+
+}  // namespace
+
+int64_t sidwt_swap_workspace_bytes(const sidwt_plan *p, int64_t n, int64_t count) {
+  if (!p || n < 1 || count < 0) return -1;
+  return swap_ws_bytes(p->J, transform_length(n, p->J), count);
+}
+
+int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                            int64_t rx_stride, void *out, int64_t out_stride, void *workspace,
+                            int64_t workspace_bytes) {
+  if (!p || count < 0 || (int64_t)count * p->J > 0x7fffffff) return SIDWT_E_INVAL;
+  if (p->filter == SIDWT_LEGALL53_INT || !p->ref_dev) return SIDWT_E_UNSUPPORTED;
+  int64_t N = 0;
+  int rc = check_pulse(p, n, &N);
+  if (rc) return rc;
+  if (rx_stride < n || out_stride < (int64_t)p->J * N) return SIDWT_E_INVAL;
+  sidwt::SwapDesc wd;
+  std::memset(&wd, 0, sizeof(wd));
+  size_t lds = 0;
+  for (int j = 0; j < p->J; ++j) {
+    const int K = j == 0 ? (int)p->m : p->desc.lv[j].len[0];
+    lds = std::max(lds, sidwt::swap_lds_bytes((int)N, j, K));
+    wd.a[j] = j == 0 ? static_cast<const float2 *>(p->ref_dev)
+                     : static_cast<const float2 *>(p->coef) + p->desc.lv[j].off[0];
+    wd.lo[j] = j == 0 ? 0 : p->desc.lv[j].lo[0];
+    wd.len[j] = K;
+  }
+  if (lds > (size_t)kLdsWords * 4) return SIDWT_E_UNSUPPORTED;
+  if (count == 0) return SIDWT_OK;
+  if (!rx || !out || (p->J > 1 && !workspace)) return SIDWT_E_INVAL;
+  if (workspace_bytes < swap_ws_bytes(p->J, N, count)) return SIDWT_E_INVAL;
+  return map_err(sidwt::launch_swap(p->filter, p->J, (int)N, rx, n, count, rx_stride, workspace,
+                                    wd, lds, out, out_stride, p->stream));
 }
 
 int sidwt_lift_many(int filter, int J, const void *rx, int64_t n, int64_t count,

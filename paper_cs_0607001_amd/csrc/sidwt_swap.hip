@@ -1,0 +1,254 @@
+// Roles-exchanged correlation for gfx950: the received pulse gets the
+// redundant (all-shift) y-side analysis and the reference only its critical
+// x-side one (Sec. I: the redundant transform may sit on either signal; the
+// approximation form of eq. (20a) at every scale).  Plane j, lag s:
+//
+//   R'_j[s] = sum_k conj(a_j[k]) * Y_{j,s mod 2^j}[k + s / 2^j]
+//
+// where a_j is the level-j x-side approximation of the reference (phase 0 of
+// the plan's tree; a_0 is the reference itself) and Y_{j,p} is the level-j
+// y-side approximation of the received pulse advanced by p samples
+// (0 <= p < 2^j; Y_{0,0} is the pulse).  A shift of the pulse shifts every
+// plane by exactly as many lags.
+//
+// Two kernels:
+//  * swap_tree_level: level j of the redundant tree (approximations only),
+//    phase-major (phase p of level j at p * (N >> j) of the level's block),
+//    from level j - 1: child p = p' + 2^(j-1) b is the lifting of parent
+//    phase p' advanced by b samples.  Register windows with lane-shift taps.
+//  * swap_correlate: one workgroup per (pulse, plane); the plane's phases go
+//    to LDS (extended by the weight span so no window wraps, in 16-way
+//    polyphase order) and every phase is a Toeplitz-blocked real GEMM on
+//    v_mfma_f32_32x32x2_f32: row i of a tile holds lags 16 i .. 16 i + 15,
+//    the K axis runs over (offset v, re/im) and the 32 columns over
+//    (lag t within the block, re/im) with B[v][t] = conj(a)[v - t].
+#include "sidwt_swap.hpp"
+
+namespace sidwt {
+
+constexpr int kSwapTreeThreads = 256;
+constexpr int kSwapThreads = 256;
+constexpr int kSwapRT = 4;  // row tiles per wave sharing one weight fragment
+
+__device__ __forceinline__ f32x16 swap_mfma(float a, float b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Redundant tree, one level.  Block (pulse, child phase p): L = N >> j pairs.
+// Level 1 reads the pulse (n valid samples, zero beyond); deeper levels read
+// level j - 1 of the workspace (N elements per pulse and level).
+// ---------------------------------------------------------------------------
+template <int F>
+__global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
+    int j, int N, const float2 *__restrict__ parent_all, long long parent_stride, int n_valid,
+    float2 *__restrict__ child_all, long long child_stride) {
+  using Lf = YLift<F>;
+  constexpr bool OB = Lf::kOddBefore;
+  constexpr int OWN = 64 - Lf::HL - Lf::HR;
+  const int P = 1 << j;
+  const int p = blockIdx.x & (P - 1);
+  const long long pulse = blockIdx.x >> j;
+  const int pp = p & ((P >> 1) - 1);  // parent phase (0 at level 1)
+  const int b = p >> (j - 1);         // advance of the parent, in its samples
+  const int Lp = N >> (j - 1), L = N >> j;
+  const float2 *par = parent_all + pulse * parent_stride + (long long)pp * Lp;
+  float2 *child = child_all + pulse * child_stride + (long long)p * L;
+  auto sample = [&](int i) -> float2 {
+    return i < n_valid ? par[i] : make_float2(0.f, 0.f);
+  };
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int nwin = (L + OWN - 1) / OWN;
+  constexpr int U = 2;
+  for (int w0 = wave * U; w0 < nwin; w0 += nw * U) {
+    float2 e[U], o[U];
+    int kk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = (w0 + u) * OWN - Lf::HL + lane;
+      kk[u] = k;
+      const int kc = pos_mod(k, L);
+      const int ie = 2 * kc + b;  // < Lp
+      const int io = OB ? (ie == 0 ? Lp - 1 : ie - 1) : (ie + 1 == Lp ? 0 : ie + 1);
+      e[u] = sample(ie);
+      o[u] = sample(io);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) Lf::run(e[u], o[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = kk[u];
+      if (lane >= Lf::HL && lane < 64 - Lf::HR && k < L && (w0 + u) < nwin) child[k] = e[u];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Correlation of one plane of one pulse.
+// ---------------------------------------------------------------------------
+
+// LDS geometry of plane j (host and device): rows of 16 lags per phase R,
+// padded to whole 32-row tiles (RP), extended phase length E = 16 RP + K + 15
+// rounded up to a multiple of 16, sub-sequence length S = E / 16.
+struct SwapGeom {
+  int L, R, RP, S, tiles_per_phase, K;
+  __host__ __device__ SwapGeom(int N, int j, int K_) : K(K_) {
+    L = N >> j;
+    R = (L + 15) / 16;
+    tiles_per_phase = (R + 31) / 32;
+    RP = tiles_per_phase * 32;
+    S = (16 * RP + K + 15 + 15) / 16;
+  }
+  __host__ __device__ int phase_words() const { return 16 * S * 2; }  // floats per phase
+};
+
+__host__ __device__ inline size_t swap_lds_bytes_geom(int N, int j, int K) {
+  const SwapGeom g(N, j, K);
+  return ((size_t)(1 << j) * g.phase_words() + 2 * (size_t)(K + 32)) * 4;
+}
+
+__global__ __launch_bounds__(kSwapThreads) void swap_correlate(
+    int J, int N, int count, const float2 *__restrict__ rx_all, long long rx_stride, int n,
+    const float2 *__restrict__ tree_all, long long tree_stride, SwapDesc wd,
+    float2 *__restrict__ out_all, long long out_stride) {
+  extern __shared__ __align__(16) float smem_swap[];
+  // heaviest planes (j = 0) first in launch order
+  const int j = blockIdx.x / count;
+  const long long pulse = blockIdx.x - (long long)j * count;
+  const int K = wd.len[j], lo = wd.lo[j];
+  const SwapGeom g(N, j, K);
+  const int P = 1 << j;
+  const int L = g.L, S = g.S;
+  float *ys = smem_swap;                               // P phases x 16 S complex
+  float2 *wp = reinterpret_cast<float2 *>(ys + P * g.phase_words());  // K + 32
+  const int tid = threadIdx.x, nt = blockDim.x;
+
+  // weights: wp[u + 16] = conj(a[lo + u]) for 0 <= u < K, zero around
+  for (int u = tid; u < K + 32; u += nt) {
+    const int k = u - 16;
+    float2 w = make_float2(0.f, 0.f);
+    if (k >= 0 && k < K) {
+      const float2 a = wd.a[j][k];
+      w = make_float2(a.x, -a.y);
+    }
+    wp[u] = w;
+  }
+  // phases, extended: element e of phase p is Y_p[(e + lo) mod L], stored
+  // as complex64 at sub-sequence e mod 16, index e / 16 (element
+  // (e mod 16) * S + e / 16 of the phase), so the 32 rows of a tile, 16
+  // elements apart, read consecutive elements
+  const float2 *src0 = j == 0 ? rx_all + pulse * rx_stride
+                              : tree_all + pulse * tree_stride + (long long)(j - 1) * N;
+  const int E = 16 * S;
+  for (int p = 0; p < P; ++p) {
+    const float2 *src = src0 + (long long)p * L;
+    float2 *dst = reinterpret_cast<float2 *>(ys + p * g.phase_words());
+    for (int e = tid; e < E; e += nt) {
+      const int i = pos_mod(e + lo, L);
+      float2 v;
+      if (j == 0)
+        v = i < n ? src[i] : make_float2(0.f, 0.f);
+      else
+        v = src[i];
+      dst[(e & 15) * S + (e >> 4)] = v;
+    }
+  }
+  __syncthreads();
+
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  const int row = lane & 31, kc = lane >> 5;      // A fragment: row, re/im
+  const int col = lane & 31;                      // B fragment column
+  const int bt = col >> 1, bc = col & 1;          // lag within the block, re/im
+  const int ntiles = P * g.tiles_per_phase;
+  const int Kp = K + 15;                          // offsets v in [0, K + 15)
+  float *outp = reinterpret_cast<float *>(out_all + pulse * out_stride + (long long)j * N);
+  for (int t0 = wave * kSwapRT; t0 < ntiles; t0 += nw * kSwapRT) {
+    // tile t: phase t / tiles_per_phase, rows 32 * (t % tiles_per_phase) ..
+    int abase[kSwapRT];
+#pragma unroll
+    for (int r = 0; r < kSwapRT; ++r) {
+      const int t = min(t0 + r, ntiles - 1);
+      const int p = t / g.tiles_per_phase, rt = t - p * g.tiles_per_phase;
+      abase[r] = p * g.phase_words() + 2 * (rt * 32 + row) + kc;
+    }
+    f32x16 acc[kSwapRT];
+#pragma unroll
+    for (int r = 0; r < kSwapRT; ++r)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[r][i] = 0.f;
+    for (int v = 0; v < Kp; ++v) {
+      const float2 w = wp[v - bt + 16];
+      // K index 0 multiplies Re(y), 1 multiplies Im(y):
+      // Re(out) = Re y Re w - Im y Im w ; Im(out) = Re y Im w + Im y Re w
+      const float bv = kc == 0 ? (bc == 0 ? w.x : w.y) : (bc == 0 ? -w.y : w.x);
+      const int off = 2 * ((v & 15) * S + (v >> 4));
+#pragma unroll
+      for (int r = 0; r < kSwapRT; ++r) acc[r] = swap_mfma(ys[abase[r] + off], bv, acc[r]);
+    }
+    // register i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32
+#pragma unroll
+    for (int r = 0; r < kSwapRT; ++r) {
+      const int t = t0 + r;
+      if (t >= ntiles) break;
+      const int p = t / g.tiles_per_phase, rt = t - p * g.tiles_per_phase;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int rr = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const int q = 16 * rr + bt;
+        if (q < L) outp[2 * ((long long)q * P + p) + bc] = acc[r][i];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers (C++ linkage, used by sidwt_api.cpp).
+// ---------------------------------------------------------------------------
+size_t swap_lds_bytes(int N, int j, int K) { return swap_lds_bytes_geom(N, j, K); }
+
+
+template <int F>
+static hipError_t launch_swap_tree_t(int J, int N, const void *rx, long long n, long long count,
+                                     long long rx_stride, void *tree, hipStream_t st) {
+  float2 *t = static_cast<float2 *>(tree);
+  const long long ts = (long long)(J - 1) * N;
+  for (int j = 1; j < J; ++j) {
+    const float2 *par = j == 1 ? static_cast<const float2 *>(rx) : t + (long long)(j - 2) * N;
+    const long long ps = j == 1 ? rx_stride : ts;
+    const int nv = j == 1 ? (int)n : (N >> (j - 1));
+    hipLaunchKernelGGL(swap_tree_level<F>, dim3((unsigned)(count << j)), dim3(kSwapTreeThreads),
+                       0, st, j, N, par, ps, nv, t + (long long)(j - 1) * N, ts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_swap(int filter, int J, int N, const void *rx, long long n, long long count,
+                       long long rx_stride, void *tree, const SwapDesc &wd, size_t lds_bytes,
+                       void *out, long long out_stride, hipStream_t st) {
+  hipError_t e;
+  switch (filter) {
+    case F_LEGALL53: e = launch_swap_tree_t<F_LEGALL53>(J, N, rx, n, count, rx_stride, tree, st); break;
+    case F_CDF97: e = launch_swap_tree_t<F_CDF97>(J, N, rx, n, count, rx_stride, tree, st); break;
+    case F_D4: e = launch_swap_tree_t<F_D4>(J, N, rx, n, count, rx_stride, tree, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  static bool attr_set = false;
+  if (!attr_set) {
+    e = hipFuncSetAttribute((const void *)swap_correlate, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(swap_correlate, dim3((unsigned)(count * J)), dim3(kSwapThreads), lds_bytes, st,
+                     J, N, (int)count, static_cast<const float2 *>(rx), rx_stride, (int)n,
+                     static_cast<const float2 *>(tree), (long long)(J - 1) * N, wd,
+                     static_cast<float2 *>(out), out_stride);
+  return hipGetLastError();
+}
+
+}  // namespace sidwt

@@ -118,3 +118,9 @@ def test_synthesis_arguments_are_checked_on_the_host(L):
 def test_plane_mask_entry_rejects_a_null_plan(L):
     vp = ctypes.c_void_p
     assert L.sidwt_correlate_planes(None, vp(16), 64, 1, 64, vp(16), 3 * 64, 1) == -1
+
+
+def test_swapped_entry_points_reject_a_null_plan(L):
+    vp = ctypes.c_void_p
+    assert L.sidwt_swap_workspace_bytes(None, 64, 1) == -1
+    assert L.sidwt_correlate_swapped(None, vp(16), 64, 1, 64, vp(16), 192, vp(16), 1 << 20) == -1

@@ -559,3 +559,12 @@ def test_swapped_brute_force_tiny(filt):
                 c = _scalar_analyze(c, ylo)
             want = sum(complex(ai).conjugate() * ci for ai, ci in zip(a, c))
             assert abs(R[j, s] - want) < 1e-12
+
+
+def test_swapped_sampled_lags_equal_the_full_planes():
+    rng = np.random.default_rng(36)
+    x, y = crandn(rng, 17), crandn(rng, 80)
+    r = O.correlate_swapped("cdf97", 4, x, y)
+    lags = [0, 3, 17, 79]
+    for j in range(4):
+        assert np.abs(O.correlate_swapped_at("cdf97", 4, x, y, j, lags) - r[j, lags]).max() < 1e-13

@@ -126,7 +126,8 @@ def main():
                     help="also run an elementwise kernel that reads and writes 256 MiB "
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="batched_uniform",
-                    choices=["batched_uniform", "uneven", "integer", "single", "serving", "bank"])
+                    choices=["batched_uniform", "uneven", "integer", "single", "serving", "bank",
+                             "swapped"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path in this library "
@@ -137,7 +138,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     fn = {"batched_uniform": bench_batched_uniform, "uneven": bench_uneven,
           "integer": bench_integer, "single": bench_single,
-          "serving": bench_serving, "bank": bench_bank}[args.workload]
+          "serving": bench_serving, "bank": bench_bank,
+          "swapped": bench_swapped}[args.workload]
     rec = fn(args)
     print(json.dumps(rec), flush=True)
 
@@ -532,6 +534,64 @@ def bench_integer(args):
         "lifting_roofline": lift,
         "synthesis_roofline": synth,
         "cpu_baseline": cpu,
+    }
+
+
+def bench_swapped(args):
+    """Roles exchanged on the uniform batch (4096 x 8192 complex64, 512-sample
+    chirp echoes, CDF 9/7, J = 5): redundant y-side tree of every received
+    pulse (J - 1 tree launches into a workspace), then one correlation launch
+    over (pulse, plane).  The forward path on the same batch is timed beside
+    it."""
+    import ctypes
+
+    import torch
+
+    import paper_cs_0607001_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    J, m = 5, 512
+    log(f"generating {args.count} x {args.n} pulses")
+    b = W.batched_uniform(seed=2, count=args.count, n=args.n, m=m, J=J)
+    N = S.transform_length(args.n, J)
+    rx = torch.from_numpy(b.rx).to(dev)
+    plan = S.plan_create(b.filter, J, b.ref)
+    out = torch.empty((args.count, J, N), dtype=torch.complex64, device=dev)
+    ws = torch.empty(S._lib.lib().sidwt_swap_workspace_bytes(plan.handle, args.n, args.count),
+                     dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ms = _time_steps(lambda: S.correlate_swapped(plan, rx, out=out, workspace=ws), args.steps,
+                     args.warmup, stream)
+    # 8 real flops per complex MAC: every lag of plane j takes the support of
+    # the reference's level-j approximation (plane 0: the reference itself)
+    flops = 8 * N * m
+    for j in range(1, J):
+        lo, ln = ctypes.c_int32(), ctypes.c_int32()
+        S._lib.check(S._lib.lib().sidwt_plan_phase(plan.handle, j, 0, 0, ctypes.byref(lo),
+                                                   ctypes.byref(ln), None))
+        flops += 8 * N * ln.value
+    flops *= args.count
+    value = args.count * args.n / (ms * 1e-3)
+    tflops = flops / (ms * 1e-3) / 1e12
+    log(f"swapped: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s "
+        f"(tree + correlation)")
+    fwd = _time_steps(lambda: S.correlate_many(plan, rx, out=out), args.steps, args.warmup, stream)
+    log(f"forward path on the same batch: {fwd:.3f} ms/step")
+    plan.free()
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT correlate",
+        "value": value, "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"roles exchanged: {args.count} pulses x {args.n} complex64, "
+                               f"{m}-sample LFM chirp echoes, CDF 9/7, J={J}; redundant tree on "
+                               f"each pulse, critical reference"},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
+                     "kernel": "swap_tree_level + swap_correlate (whole call)"},
+        "forward_ms_per_step": fwd,
+        "cpu_baseline": None,
     }
 
 

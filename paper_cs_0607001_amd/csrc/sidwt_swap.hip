@@ -27,8 +27,8 @@
 namespace sidwt {
 
 constexpr int kSwapTreeThreads = 256;
-constexpr int kSwapThreads = 256;
-constexpr int kSwapRT = 4;  // row tiles per wave sharing one weight fragment
+constexpr int kSwapThreads = 512;
+constexpr int kSwapRT = 2;  // row tiles per wave sharing one weight fragment
 
 __device__ __forceinline__ f32x16 swap_mfma(float a, float b, f32x16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);

@@ -443,6 +443,34 @@ def correlate_swapped_at(filt: str, J: int, ref, rx, plane: int, lags) -> np.nda
     return approximation(Y, ylo, plane) @ np.conj(a)
 
 
+def detect_peaks(planes, rel: float, max_peaks: int):
+    """Target declaration on the correlation magnitude (Sec. V-A, Fig. 6:
+    |R| in dB at each scale, targets read off as peaks above a level): on
+    each plane (last axis, circular lags) a lag s is a peak when its power
+    p[s] = Re^2 + Im^2 exceeds p[s-1], is not below p[s+1] (the first
+    sample of a flat top) and is not below rel * max(p).  The decisions use
+    single precision with one rounding per operation (each square, the sum,
+    rel times the maximum), the precision the planes are delivered in.
+    Returns, per plane, (lags in increasing order, all of them; dB of each
+    relative to the plane's maximum, float64)."""
+    planes = np.asarray(planes)
+    assert planes.dtype == np.complex64
+    re = planes.real.astype(np.float32)
+    im = planes.imag.astype(np.float32)
+    p = re * re + im * im
+    p2 = p.reshape(-1, p.shape[-1])
+    out = []
+    for row in p2:
+        M = row.max()
+        thr = np.float32(rel) * M
+        peak = (row > np.roll(row, 1)) & (row >= np.roll(row, -1)) & (row >= thr)
+        lags = np.nonzero(peak)[0]
+        db = 10.0 * np.log10(row[lags].astype(np.float64) / np.float64(M)) if len(lags) else \
+            np.zeros(0)
+        out.append((lags, db))
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Integer-to-integer 5/3 (reversible lifting with floor shifts).
 # The paper cites reversible integer lifting but prints no rounding rule;

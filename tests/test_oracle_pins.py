@@ -568,3 +568,54 @@ def test_swapped_sampled_lags_equal_the_full_planes():
     lags = [0, 3, 17, 79]
     for j in range(4):
         assert np.abs(O.correlate_swapped_at("cdf97", 4, x, y, j, lags) - r[j, lags]).max() < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# P14: target declaration (local power maxima above a level relative to the
+# plane's peak): closed-form cases and scalar brute force.
+# ---------------------------------------------------------------------------
+
+def _plane(N, pts):
+    z = np.zeros(N, np.complex64)
+    for i, v in pts.items():
+        z[i] = v
+    return z
+
+
+def test_detect_closed_forms():
+    rel = np.float32(0.1)
+    (l, d), = O.detect_peaks(_plane(64, {7: 3 - 4j}), rel, 8)
+    assert list(l) == [7] and abs(d[0]) < 1e-12                       # a delta
+    bumps = _plane(64, {9: 0.5, 10: 1.0, 11: 0.5, 39: 0.3j, 40: np.sqrt(0.5) * 1j, 41: 0.3j})
+    (l, d), = O.detect_peaks(bumps, rel, 8)
+    assert list(l) == [10, 40] and abs(d[1] - 10 * np.log10(0.5)) < 1e-6
+    (l, _), = O.detect_peaks(bumps, np.float32(0.6), 8)               # level above the second
+    assert list(l) == [10]
+    (l, _), = O.detect_peaks(_plane(32, {20: 1.0, 21: 1.0}), rel, 8)  # flat top: first sample
+    assert list(l) == [20]
+    (l, _), = O.detect_peaks(_plane(32, {0: 1.0, 31: 0.5, 1: 0.5}), rel, 8)   # circular
+    assert list(l) == [0]
+    (l, _), = O.detect_peaks(_plane(32, {31: 1.0, 30: 0.5, 0: 0.5}), rel, 8)
+    assert list(l) == [31]
+    (l, _), = O.detect_peaks(np.zeros(16, np.complex64), rel, 8)      # nothing there
+    assert len(l) == 0
+    (l, _), = O.detect_peaks(np.full(16, 1 + 1j, np.complex64), rel, 8)  # constant: no rise
+    assert len(l) == 0
+
+
+def test_detect_brute_force_tiny():
+    rng = np.random.default_rng(37)
+    f32 = np.float32
+    for trial in range(20):
+        N = int(rng.integers(3, 40))
+        z = (rng.standard_normal(N) + 1j * rng.standard_normal(N)).astype(np.complex64)
+        if trial % 3 == 0:   # some exact ties
+            z[int(rng.integers(0, N))] = z[0]
+        rel = f32(rng.choice([0.0, 0.05, 0.3, 0.9]))
+        (l, _), = O.detect_peaks(z, rel, 64)
+        p = [f32(f32(f32(c.real) * f32(c.real)) + f32(f32(c.imag) * f32(c.imag))) for c in z]
+        M = max(p)
+        thr = f32(rel * M)
+        want = [s for s in range(N)
+                if p[s] > p[(s - 1) % N] and p[s] >= p[(s + 1) % N] and p[s] >= thr]
+        assert list(l) == want, trial

@@ -126,6 +126,51 @@ def batched_uniform(seed: int = 2, count: int = 4096, n: int = 8192, m: int = 51
 
 
 # ---------------------------------------------------------------------------
+# Multi-target scene (Sec. V-A, Fig. 6 analogue): P point targets, CDF 9/7
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Scene:
+    filter: str
+    J: int
+    ref: np.ndarray
+    rx: np.ndarray      # [count, n]
+    delays: np.ndarray  # [count, P]
+    refl: np.ndarray    # [count, P] complex reflectivities
+
+
+def multi_target(seed: int = 5, count: int = 1, n: int = 1024, m: int = 160, P: int = 5,
+                 J: int = 3, snr_db: float = 20.0, dtype=np.complex64) -> Scene:
+    """Backscatter of P point targets: y[n] = sum_k s_k x[n - d_k] plus noise,
+    x a chirp of time-bandwidth product 160 sampled at its bandwidth (m =
+    160 samples).  Four targets sit close together (gaps of 3..12 samples)
+    and one about 60..100 samples earlier, as in the paper's scene; |s_k| ~
+    U[0.5, 1], arg s_k ~ U[0, 2 pi); SNR per sample relative to a unit
+    echo."""
+    ref = lfm_chirp(m, float(m))
+    rx = np.empty((count, n), dtype)
+    delays = np.empty((count, P), np.int64)
+    refl = np.empty((count, P), np.complex128)
+    for i in range(count):
+        rng = _rng(seed, i)
+        base = int(rng.integers(n // 4, n - m - 60))
+        d = [base]
+        for _ in range(P - 2):
+            d.append(d[-1] + int(rng.integers(3, 13)))
+        d.insert(0, base - int(rng.integers(60, 101)))
+        y = np.zeros(n, np.complex128)
+        s = rng.uniform(0.5, 1.0, P) * np.exp(2j * math.pi * rng.random(P))
+        for dk, sk in zip(d, s):
+            seg = min(m, n - dk)
+            y[dk:dk + seg] += sk * ref[:seg]
+        y += noise(n, 10.0 ** (-snr_db / 10.0), rng)
+        rx[i] = y
+        delays[i] = d
+        refl[i] = s
+    return Scene("cdf97", J, ref, rx, delays, refl)
+
+
+# ---------------------------------------------------------------------------
 # Workload 3: integer path, int16 I/Q, reversible 5/3, J = 6
 # ---------------------------------------------------------------------------
 

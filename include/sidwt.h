@@ -194,6 +194,24 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n,
                             int64_t out_stride, void *workspace,
                             int64_t workspace_bytes);
 
+/* Target declaration (Sec. V-A, Fig. 6: targets read off |R| in dB at each
+ * scale as peaks above a level).  planes: device complex64, pulse i's plane
+ * j at planes + i*pulse_stride + j*N elements (the layout of
+ * sidwt_correlate_many).  Lag s of a plane is a peak when its power
+ * p[s] = Re^2 + Im^2 exceeds p[s-1], is not below p[s+1] (circular lags;
+ * the first sample of a flat top) and is not below rel_power * max(p)
+ * (rel_power = 10^(level_dB / 10), e.g. 0.1 for -10 dB); single precision,
+ * one rounding per operation.  For item k = i*J + j: found[k] = number of
+ * peaks; the first min(found[k], max_peaks) in increasing lag order go to
+ * lags[k*max_peaks ...] (int32) with db[...] = 10 log10(p / max p) (float).
+ * All arrays are device memory; lags and db may be NULL when max_peaks = 0.
+ * SIDWT_E_INVAL for a negative or NaN rel_power or inconsistent sizes;
+ * count = 0 launches nothing. */
+int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N,
+                       int64_t pulse_stride, float rel_power, int max_peaks,
+                       int32_t *lags, float *db, int32_t *found,
+                       void *hip_stream);
+
 /* ---- Uneven batches (one persistent launch) ------------------------------
  * A batch fixes `count` pulses, each with its own plan (float filters; the
  * filter and J may differ per pulse) and length n[i].  Short pulses are

@@ -21,7 +21,7 @@ import numpy as np
 from ._lib import FILTERS, SidwtError, check, lib  # noqa: F401
 
 __all__ = ["Plan", "plan_create", "correlate", "correlate_many", "correlate_swapped", "lift_many",
-           "synth_many", "out_len",
+           "synth_many", "detect_peaks", "out_len",
            "transform_length", "plan_phase", "Batch", "correlate_batch", "Bank",
            "SidwtError", "FILTERS", "version"]
 
@@ -197,6 +197,29 @@ def correlate_swapped(plan: Plan, rx, out=None, workspace=None, stream=None):
                                         workspace.numel() * workspace.element_size()),
           "sidwt_correlate_swapped")
     return out
+
+
+def detect_peaks(planes, level_db: float = -10.0, max_peaks: int = 64, stream=None):
+    """Target declaration on correlation planes (count, J, N) complex64 (as
+    correlate_many returns them): per plane, the lags whose power is a local
+    maximum at least level_db relative to the plane's peak.  Returns (lags
+    int32 (count, J, max_peaks), db float32 (count, J, max_peaks), found
+    int32 (count, J)); entries past found are unspecified."""
+    torch = _torch()
+    count, J, N = planes.shape
+    if planes.dtype != torch.complex64 or not planes.is_contiguous():
+        raise ValueError("planes must be contiguous complex64 (count, J, N)")
+    import numpy as np
+    rel = float(np.float32(10.0 ** (level_db / 10.0)))
+    lags = torch.empty((count, J, max_peaks), dtype=torch.int32, device=planes.device)
+    db = torch.empty((count, J, max_peaks), dtype=torch.float32, device=planes.device)
+    found = torch.empty((count, J), dtype=torch.int32, device=planes.device)
+    check(lib().sidwt_detect_peaks(ctypes.c_void_p(planes.data_ptr()), count, J, N, J * N, rel,
+                                   max_peaks, ctypes.c_void_p(lags.data_ptr()),
+                                   ctypes.c_void_p(db.data_ptr()),
+                                   ctypes.c_void_p(found.data_ptr()), _stream_ptr(stream)),
+          "sidwt_detect_peaks")
+    return lags, db, found
 
 
 def lift_many(filt: str, J: int, rx, pyr=None, stream=None):

@@ -56,6 +56,8 @@ def _declare(L):
     L.sidwt_swap_workspace_bytes.restype = i64
     L.sidwt_correlate_swapped.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp, i64]
     L.sidwt_correlate_swapped.restype = i32
+    L.sidwt_detect_peaks.argtypes = [vp, i64, i32, i64, i64, c.c_float, i32, vp, vp, vp, vp]
+    L.sidwt_detect_peaks.restype = i32
     L.sidwt_correlate_batch.argtypes = [c.POINTER(vp), c.POINTER(vp), c.POINTER(i64),
                                         c.POINTER(vp), i32, vp]
     L.sidwt_correlate_batch.restype = i32

@@ -12,6 +12,12 @@
 #include "sidwt_swap.hpp"
 
 namespace sidwt {
+hipError_t launch_detect(const void *planes, long long pulse_stride, int J, int N, long long count,
+                         float rel, int max_peaks, int *lags, float *db, int *found,
+                         hipStream_t st);
+}
+
+namespace sidwt {
 hipError_t launch_tree(int filter, const void *in, int in_lo, int in_len, int level, int k0,
                        int np, void *outA, int loA, int lenA, void *outB, int loB, int lenB,
                        hipStream_t st);
@@ -292,6 +298,20 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int6
   if (workspace_bytes < swap_ws_bytes(p->J, N, count)) return SIDWT_E_INVAL;
   return map_err(sidwt::launch_swap(p->filter, p->J, (int)N, rx, n, count, rx_stride, workspace,
                                     wd, lds, out, out_stride, p->stream));
+}
+
+int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N, int64_t pulse_stride,
+                       float rel_power, int max_peaks, int32_t *lags, float *db, int32_t *found,
+                       void *hip_stream) {
+  if (count < 0 || J < 1 || J > SIDWT_MAX_LEVELS || N < 1 || N > 0x7fffffff ||
+      pulse_stride < (int64_t)J * N || count * J > 0x7fffffff || max_peaks < 0 ||
+      !(rel_power >= 0.f) || rel_power > 3.0e38f)
+    return SIDWT_E_INVAL;
+  if (count == 0) return SIDWT_OK;
+  if (!planes || !found || (max_peaks > 0 && (!lags || !db))) return SIDWT_E_INVAL;
+  return map_err(sidwt::launch_detect(planes, pulse_stride, J, (int)N, count, rel_power,
+                                      max_peaks, lags, db, found,
+                                      static_cast<hipStream_t>(hip_stream)));
 }
 
 int sidwt_lift_many(int filter, int J, const void *rx, int64_t n, int64_t count,

@@ -1,0 +1,95 @@
+// Target declaration on the correlation planes for gfx950 (Sec. V-A,
+// Fig. 6: targets are read off the magnitude of each scale's correlation
+// as peaks above a level).  A lag s of a plane is a peak when its power
+// p[s] = Re^2 + Im^2 exceeds p[s-1], is not below p[s+1] (the first sample
+// of a flat top; lags are circular) and is not below rel * max(p).  Every
+// decision uses single precision with one rounding per operation (no fused
+// multiply-add), so it is reproducible off the GPU.
+//
+// One workgroup per (pulse, plane): a block maximum, then the lags in
+// chunks of one per thread; each chunk's peaks are compacted in lag order by
+// a wave ballot and a scan over the waves, so the output order is
+// deterministic and no atomics are used.
+#include <hip/hip_runtime.h>
+
+namespace sidwt {
+
+constexpr int kDetectThreads = 256;
+
+// Each square and the sum rounded separately: contraction into a fused
+// multiply-add is switched off here (the compiler would otherwise form one).
+__device__ __forceinline__ float plane_power(float2 z) {
+#pragma clang fp contract(off)
+  const float a = z.x * z.x;
+  const float b = z.y * z.y;
+  return a + b;
+}
+
+__global__ __launch_bounds__(kDetectThreads) void detect_peaks(
+    const float2 *__restrict__ planes, long long pulse_stride, int J, int N, float rel,
+    int max_peaks, int *__restrict__ lags, float *__restrict__ db, int *__restrict__ found) {
+  constexpr int NW = kDetectThreads / 64;
+  __shared__ float wmax[NW];
+  __shared__ int wcount[NW];
+  const long long item = blockIdx.x;  // pulse * J + plane
+  const long long pulse = item / J;
+  const int j = (int)(item - pulse * J);
+  const float2 *R = planes + pulse * pulse_stride + (long long)j * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+  float m = 0.f;
+  for (int s = tid; s < N; s += kDetectThreads) m = fmaxf(m, plane_power(R[s]));
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (lane == 0) wmax[wave] = m;
+  __syncthreads();
+  float M = wmax[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) M = fmaxf(M, wmax[w]);
+  const float thr = rel * M;
+
+  int *ol = lags + item * max_peaks;
+  float *od = db + item * max_peaks;
+  int base = 0;
+  for (int c0 = 0; c0 < N; c0 += kDetectThreads) {
+    const int s = c0 + tid;
+    bool pk = false;
+    float ps = 0.f;
+    if (s < N) {
+      ps = plane_power(R[s]);
+      const float pl = plane_power(R[s == 0 ? N - 1 : s - 1]);
+      const float pr = plane_power(R[s + 1 == N ? 0 : s + 1]);
+      pk = ps > pl && ps >= pr && ps >= thr;
+    }
+    const unsigned long long bal = __ballot(pk);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    __syncthreads();  // every wave has read the previous chunk's counts
+    if (lane == 0) wcount[wave] = __popcll(bal);
+    __syncthreads();
+    int off = base, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      off += w < wave ? wcount[w] : 0;
+      tot += wcount[w];
+    }
+    if (pk) {
+      const int k = off + before;
+      if (k < max_peaks) {
+        ol[k] = s;
+        od[k] = 10.f * log10f(ps / M);
+      }
+    }
+    base += tot;
+  }
+  if (tid == 0) found[item] = base;
+}
+
+hipError_t launch_detect(const void *planes, long long pulse_stride, int J, int N, long long count,
+                         float rel, int max_peaks, int *lags, float *db, int *found,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(detect_peaks, dim3((unsigned)(count * J)), dim3(kDetectThreads), 0, st,
+                     static_cast<const float2 *>(planes), pulse_stride, J, N, rel, max_peaks, lags,
+                     db, found);
+  return hipGetLastError();
+}
+
+}  // namespace sidwt

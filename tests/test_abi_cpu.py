@@ -124,3 +124,14 @@ def test_swapped_entry_points_reject_a_null_plan(L):
     vp = ctypes.c_void_p
     assert L.sidwt_swap_workspace_bytes(None, 64, 1) == -1
     assert L.sidwt_correlate_swapped(None, vp(16), 64, 1, 64, vp(16), 192, vp(16), 1 << 20) == -1
+
+
+def test_detect_arguments_are_checked_on_the_host(L):
+    vp = ctypes.c_void_p
+    nan = float("nan")
+    assert L.sidwt_detect_peaks(None, 0, 3, 64, 192, 0.1, 8, None, None, None, None) == 0
+    assert L.sidwt_detect_peaks(vp(16), 1, 3, 64, 191, 0.1, 8, vp(16), vp(16), vp(16), None) == -1
+    assert L.sidwt_detect_peaks(vp(16), 1, 3, 64, 192, nan, 8, vp(16), vp(16), vp(16), None) == -1
+    assert L.sidwt_detect_peaks(vp(16), 1, 3, 64, 192, -1.0, 8, vp(16), vp(16), vp(16), None) == -1
+    assert L.sidwt_detect_peaks(vp(16), 1, 3, 64, 192, 0.1, -1, vp(16), vp(16), vp(16), None) == -1
+    assert L.sidwt_detect_peaks(vp(16), 1, 3, 64, 192, 0.1, 8, None, vp(16), vp(16), None) == -1

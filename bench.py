@@ -127,7 +127,7 @@ def main():
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="batched_uniform",
                     choices=["batched_uniform", "uneven", "integer", "single", "serving", "bank",
-                             "swapped"])
+                             "swapped", "detect"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path in this library "
@@ -139,7 +139,7 @@ def main():
     fn = {"batched_uniform": bench_batched_uniform, "uneven": bench_uneven,
           "integer": bench_integer, "single": bench_single,
           "serving": bench_serving, "bank": bench_bank,
-          "swapped": bench_swapped}[args.workload]
+          "swapped": bench_swapped, "detect": bench_detect}[args.workload]
     rec = fn(args)
     print(json.dumps(rec), flush=True)
 
@@ -591,6 +591,59 @@ def bench_swapped(args):
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
                      "kernel": "swap_tree_level + swap_correlate (whole call)"},
         "forward_ms_per_step": fwd,
+        "cpu_baseline": None,
+    }
+
+
+def bench_detect(args):
+    """Target declaration after the correlation: the uniform batch's planes
+    (4096 x 5 x 8192 complex64) scanned for peaks at -10 dB, timed alone (HBM
+    roofline: the planes are read once) and as correlation + declaration; the
+    five-target scene (CDF 9/7, J = 3) reports its peaks per plane."""
+    import numpy as np
+    import torch
+
+    import paper_cs_0607001_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    J, m = 5, 512
+    log(f"generating {args.count} x {args.n} pulses")
+    b = W.batched_uniform(seed=2, count=args.count, n=args.n, m=m, J=J)
+    N = S.transform_length(args.n, J)
+    rx = torch.from_numpy(b.rx).to(dev)
+    plan = S.plan_create(b.filter, J, b.ref)
+    planes = S.correlate_many(plan, rx)
+    stream = torch.cuda.current_stream()
+    ms_det = _time_steps(lambda: S.detect_peaks(planes, -10.0, 64), args.steps, args.warmup,
+                         stream)
+    ms_all = _time_steps(lambda: (S.correlate_many(plan, rx, out=planes),
+                                  S.detect_peaks(planes, -10.0, 64)), args.steps, args.warmup,
+                         stream)
+    nbytes = planes.numel() * planes.element_size()
+    gbs = nbytes / (ms_det * 1e-3) / 1e9
+    value = args.count * args.n / (ms_all * 1e-3)
+    _, _, found = S.detect_peaks(planes, -10.0, 64)
+    mean_found = found.float().mean(dim=0).cpu().numpy()
+    log(f"declaration: {ms_det * 1e3:.1f} us ({gbs:.0f} GB/s of planes); correlation + "
+        f"declaration {ms_all:.3f} ms/step; mean peaks per plane {np.round(mean_found, 2)}")
+    plan.free()
+    sc = W.multi_target(seed=5, count=8)
+    with S.plan_create(sc.filter, sc.J, sc.ref) as sp:
+        sl, sd, sf = S.detect_peaks(S.correlate_many(sp, torch.from_numpy(sc.rx).to(dev)), -10.0, 32)
+    sf = sf.cpu().numpy()
+    log(f"five-target scene, peaks at -10 dB per plane (8 pulses): {sf.tolist()}")
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT correlate",
+        "value": value, "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_all, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"correlation + target declaration at -10 dB: {args.count} pulses "
+                               f"x {args.n} complex64, {m}-sample chirp echoes, CDF 9/7, J={J}"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "detect_peaks",
+                     "us_per_launch": ms_det * 1e3, "bytes": nbytes},
+        "scene_peaks_per_plane": sf.tolist(),
         "cpu_baseline": None,
     }
 

@@ -6,10 +6,10 @@
 // decision uses single precision with one rounding per operation (no fused
 // multiply-add), so it is reproducible off the GPU.
 //
-// One workgroup per (pulse, plane): a block maximum, then the lags in
-// chunks of one per thread; each chunk's peaks are compacted in lag order by
-// a wave ballot and a scan over the waves, so the output order is
-// deterministic and no atomics are used.
+// One workgroup per (pulse, plane): a block maximum (the powers kept in LDS
+// when the plane fits), then the lags in chunks of one per thread; each
+// chunk's peaks are compacted in lag order by a wave ballot and a scan over
+// the waves, so the output order is deterministic and no atomics are used.
 #include <hip/hip_runtime.h>
 
 namespace sidwt {
@@ -25,12 +25,17 @@ __device__ __forceinline__ float plane_power(float2 z) {
   return a + b;
 }
 
+// LDS: the plane's powers (N floats) when they fit, so the plane is read
+// from HBM once; otherwise the neighbours are re-read from global memory.
+template <bool LDS>
 __global__ __launch_bounds__(kDetectThreads) void detect_peaks(
     const float2 *__restrict__ planes, long long pulse_stride, int J, int N, float rel,
     int max_peaks, int *__restrict__ lags, float *__restrict__ db, int *__restrict__ found) {
   constexpr int NW = kDetectThreads / 64;
+  constexpr int U = 4;  // independent loads in flight per thread
   __shared__ float wmax[NW];
   __shared__ int wcount[NW];
+  extern __shared__ float sp[];
   const long long item = blockIdx.x;  // pulse * J + plane
   const long long pulse = item / J;
   const int j = (int)(item - pulse * J);
@@ -38,7 +43,21 @@ __global__ __launch_bounds__(kDetectThreads) void detect_peaks(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
   float m = 0.f;
-  for (int s = tid; s < N; s += kDetectThreads) m = fmaxf(m, plane_power(R[s]));
+  for (int s0 = tid; s0 < N; s0 += U * kDetectThreads) {
+    float2 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = s0 + u * kDetectThreads;
+      v[u] = s < N ? R[s] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = s0 + u * kDetectThreads;
+      const float p = plane_power(v[u]);
+      if (LDS && s < N) sp[s] = p;
+      m = fmaxf(m, p);
+    }
+  }
   for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
   if (lane == 0) wmax[wave] = m;
   __syncthreads();
@@ -46,6 +65,7 @@ __global__ __launch_bounds__(kDetectThreads) void detect_peaks(
 #pragma unroll
   for (int w = 1; w < NW; ++w) M = fmaxf(M, wmax[w]);
   const float thr = rel * M;
+  auto power_at = [&](int s) { return LDS ? sp[s] : plane_power(R[s]); };
 
   int *ol = lags + item * max_peaks;
   float *od = db + item * max_peaks;
@@ -55,9 +75,9 @@ __global__ __launch_bounds__(kDetectThreads) void detect_peaks(
     bool pk = false;
     float ps = 0.f;
     if (s < N) {
-      ps = plane_power(R[s]);
-      const float pl = plane_power(R[s == 0 ? N - 1 : s - 1]);
-      const float pr = plane_power(R[s + 1 == N ? 0 : s + 1]);
+      ps = power_at(s);
+      const float pl = power_at(s == 0 ? N - 1 : s - 1);
+      const float pr = power_at(s + 1 == N ? 0 : s + 1);
       pk = ps > pl && ps >= pr && ps >= thr;
     }
     const unsigned long long bal = __ballot(pk);
@@ -83,12 +103,29 @@ __global__ __launch_bounds__(kDetectThreads) void detect_peaks(
   if (tid == 0) found[item] = base;
 }
 
+constexpr int kDetectLdsBytes = 160 * 1024 - 64;  // beside the static arrays
+
 hipError_t launch_detect(const void *planes, long long pulse_stride, int J, int N, long long count,
                          float rel, int max_peaks, int *lags, float *db, int *found,
                          hipStream_t st) {
-  hipLaunchKernelGGL(detect_peaks, dim3((unsigned)(count * J)), dim3(kDetectThreads), 0, st,
-                     static_cast<const float2 *>(planes), pulse_stride, J, N, rel, max_peaks, lags,
-                     db, found);
+  const size_t lds = (size_t)N * 4;
+  if (lds <= (size_t)kDetectLdsBytes) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      hipError_t e = hipFuncSetAttribute((const void *)detect_peaks<true>,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         kDetectLdsBytes);
+      if (e != hipSuccess) return e;
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(detect_peaks<true>, dim3((unsigned)(count * J)), dim3(kDetectThreads), lds,
+                       st, static_cast<const float2 *>(planes), pulse_stride, J, N, rel,
+                       max_peaks, lags, db, found);
+  } else {
+    hipLaunchKernelGGL(detect_peaks<false>, dim3((unsigned)(count * J)), dim3(kDetectThreads), 0,
+                       st, static_cast<const float2 *>(planes), pulse_stride, J, N, rel,
+                       max_peaks, lags, db, found);
+  }
   return hipGetLastError();
 }
 

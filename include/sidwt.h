@@ -58,6 +58,7 @@ extern "C" {
 #endif
 
 typedef struct sidwt_plan sidwt_plan;
+typedef struct sidwt_lifting sidwt_lifting;
 
 /* Lifting factorisations (Sec. III).
  * SIDWT_LEGALL53:     5/3 in dual analysis bases, Sec. III-C Case I.
@@ -210,6 +211,39 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n,
 int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N,
                        int64_t pulse_stride, float rel_power, int max_peaks,
                        int32_t *lags, float *db, int32_t *found,
+                       void *hip_stream);
+
+/* Lifting factorization (Sec. III-A, eq. (16): Euclid on the polyphase
+ * components of the lowpass, one last step for the highpass) of any
+ * perfect-reconstruction analysis pair given by taps (host doubles):
+ * lowpass out[k] = sum_t lo[t] u[2k + lo_first + t], highpass likewise.
+ * With e[k] = u[2k], o[k] = u[2k+1] the result is a list of steps applied
+ * in order, step s: kind 0 (predict) o[k] += sum_t coef[t] e[k + first + t],
+ * kind 1 (update) e[k] += sum_t coef[t] o[k + first + t]; then
+ * c[k] = ke e[k + se], d[k] = ko o[k + so].  Each division is balanced
+ * (the quotient cancels as many low as high terms), so symmetric pairs give
+ * symmetric steps.  SIDWT_E_INVAL when the polyphase determinant is not a
+ * monomial (no perfect reconstruction) or an argument is out of range (at
+ * most 64 taps, first in [-64, 64]); SIDWT_E_UNSUPPORTED beyond 16 steps or
+ * 8 taps per step.  Host only; the object is freed with
+ * sidwt_lifting_free. */
+int sidwt_lifting_factorize(const double *lo, int lo_first, int lo_len,
+                            const double *hi, int hi_first, int hi_len,
+                            sidwt_lifting **out);
+int sidwt_lifting_count(const sidwt_lifting *f);
+int sidwt_lifting_step(const sidwt_lifting *f, int i, int *kind, int *first,
+                       int *len, double *coef);
+int sidwt_lifting_scaling(const sidwt_lifting *f, double *ke, int *se,
+                          double *ko, int *so);
+void sidwt_lifting_free(sidwt_lifting *f);
+
+/* Critical lifting of a batch with a factorized pair (its steps taken at
+ * run time, in single precision): as sidwt_lift_many (same pyramid layout
+ * d_1 | ... | d_J | c_J, complex64 in and out, I and Q alike), for pairs the
+ * compiled filters do not cover.  SIDWT_E_UNSUPPORTED when the steps' reach
+ * exceeds 48 lanes per 64-lane window or the pulse exceeds the LDS. */
+int sidwt_lift_generic(const sidwt_lifting *f, int J, const void *rx, int64_t n,
+                       int64_t count, int64_t rx_stride, void *pyr,
                        void *hip_stream);
 
 /* ---- Uneven batches (one persistent launch) ------------------------------

@@ -21,7 +21,7 @@ import numpy as np
 from ._lib import FILTERS, SidwtError, check, lib  # noqa: F401
 
 __all__ = ["Plan", "plan_create", "correlate", "correlate_many", "correlate_swapped", "lift_many",
-           "synth_many", "detect_peaks", "out_len",
+           "synth_many", "detect_peaks", "Lifting", "lift_generic", "out_len",
            "transform_length", "plan_phase", "Batch", "correlate_batch", "Bank",
            "SidwtError", "FILTERS", "version"]
 
@@ -220,6 +220,76 @@ def detect_peaks(planes, level_db: float = -10.0, max_peaks: int = 64, stream=No
                                    ctypes.c_void_p(found.data_ptr()), _stream_ptr(stream)),
           "sidwt_detect_peaks")
     return lags, db, found
+
+
+class Lifting:
+    """Lifting factorization (eq. (16)) of an analysis pair given as tap
+    dicts {offset i: c_i} (out[k] = sum_i c_i u[2k + i]), computed by the
+    library on the host.  steps: [(kind, first, coefs)] with kind 0 =
+    predict (o += q e), 1 = update (e += q o); scaling: (ke, se, ko, so)."""
+
+    def __init__(self, lo: dict, hi: dict):
+        def arr(t):
+            first = min(t)
+            vals = [float(t.get(i, 0.0)) for i in range(first, max(t) + 1)]
+            return first, (ctypes.c_double * len(vals))(*vals), len(vals)
+        lf, la, ln = arr(lo)
+        hf, ha, hn = arr(hi)
+        h = ctypes.c_void_p()
+        check(lib().sidwt_lifting_factorize(la, lf, ln, ha, hf, hn, ctypes.byref(h)),
+              "sidwt_lifting_factorize")
+        self.handle = h
+
+    @property
+    def steps(self):
+        out = []
+        for i in range(lib().sidwt_lifting_count(self.handle)):
+            kind, first, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            coef = (ctypes.c_double * 8)()
+            check(lib().sidwt_lifting_step(self.handle, i, ctypes.byref(kind), ctypes.byref(first),
+                                           ctypes.byref(n), coef), "sidwt_lifting_step")
+            out.append((kind.value, first.value, list(coef[:n.value])))
+        return out
+
+    @property
+    def scaling(self):
+        ke, ko = ctypes.c_double(), ctypes.c_double()
+        se, so = ctypes.c_int32(), ctypes.c_int32()
+        check(lib().sidwt_lifting_scaling(self.handle, ctypes.byref(ke), ctypes.byref(se),
+                                          ctypes.byref(ko), ctypes.byref(so)),
+              "sidwt_lifting_scaling")
+        return ke.value, se.value, ko.value, so.value
+
+    def free(self):
+        if self.handle:
+            lib().sidwt_lifting_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.free()
+
+
+def lift_generic(lifting: Lifting, J: int, rx, pyr=None, stream=None):
+    """Critical lifting of complex64 pulses (count, n) with a factorized pair;
+    returns (count, N): d_1 | ... | d_J | c_J, as lift_many."""
+    torch = _torch()
+    count, n = rx.shape[0], rx.shape[1]
+    N = transform_length(n, J)
+    if pyr is None:
+        pyr = torch.empty((count, N), dtype=torch.complex64, device=rx.device)
+    check(lib().sidwt_lift_generic(lifting.handle, J, ctypes.c_void_p(rx.data_ptr()), n, count, n,
+                                   ctypes.c_void_p(pyr.data_ptr()), _stream_ptr(stream)),
+          "sidwt_lift_generic")
+    return pyr
 
 
 def lift_many(filt: str, J: int, rx, pyr=None, stream=None):

@@ -58,6 +58,20 @@ def _declare(L):
     L.sidwt_correlate_swapped.restype = i32
     L.sidwt_detect_peaks.argtypes = [vp, i64, i32, i64, i64, c.c_float, i32, vp, vp, vp, vp]
     L.sidwt_detect_peaks.restype = i32
+    dp = c.POINTER(c.c_double)
+    ip = c.POINTER(i32)
+    L.sidwt_lifting_factorize.argtypes = [dp, i32, i32, dp, i32, i32, c.POINTER(vp)]
+    L.sidwt_lifting_factorize.restype = i32
+    L.sidwt_lifting_count.argtypes = [vp]
+    L.sidwt_lifting_count.restype = i32
+    L.sidwt_lifting_step.argtypes = [vp, i32, ip, ip, ip, dp]
+    L.sidwt_lifting_step.restype = i32
+    L.sidwt_lifting_scaling.argtypes = [vp, dp, ip, dp, ip]
+    L.sidwt_lifting_scaling.restype = i32
+    L.sidwt_lifting_free.argtypes = [vp]
+    L.sidwt_lifting_free.restype = None
+    L.sidwt_lift_generic.argtypes = [vp, i32, vp, i64, i64, i64, vp, vp]
+    L.sidwt_lift_generic.restype = i32
     L.sidwt_correlate_batch.argtypes = [c.POINTER(vp), c.POINTER(vp), c.POINTER(i64),
                                         c.POINTER(vp), i32, vp]
     L.sidwt_correlate_batch.restype = i32

@@ -10,8 +10,12 @@
 #include "../../include/sidwt.h"
 #include "sidwt_host.hpp"
 #include "sidwt_swap.hpp"
+#include "sidwt_factor.hpp"
 
 namespace sidwt {
+bool generic_steps_fit(const LiftingDesc &d);
+hipError_t launch_generic(const LiftingDesc &d, int J, int N, const void *rx, long long n,
+                          long long count, long long rx_stride, void *pyr, hipStream_t st);
 hipError_t launch_detect(const void *planes, long long pulse_stride, int J, int N, long long count,
                          float rel, int max_peaks, int *lags, float *db, int *found,
                          hipStream_t st);
@@ -312,6 +316,22 @@ int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N, int6
   return map_err(sidwt::launch_detect(planes, pulse_stride, J, (int)N, count, rel_power,
                                       max_peaks, lags, db, found,
                                       static_cast<hipStream_t>(hip_stream)));
+}
+
+int sidwt_lift_generic(const sidwt_lifting *f, int J, const void *rx, int64_t n, int64_t count,
+                       int64_t rx_stride, void *pyr, void *hip_stream) {
+  const sidwt::LiftingDesc *d = sidwt::lifting_desc(f);
+  if (!d || J < 1 || J > SIDWT_MAX_LEVELS || n < 1 || count < 0 || count > 0x7fffffff ||
+      rx_stride < n)
+    return SIDWT_E_INVAL;
+  const int64_t N = transform_length(n, J);
+  if ((N >> J) < 2) return SIDWT_E_INVAL;
+  if (2 * (N / 2 + N / 4 + 1) > kLdsWords || !sidwt::generic_steps_fit(*d))
+    return SIDWT_E_UNSUPPORTED;
+  if (count == 0) return SIDWT_OK;
+  if (!rx || !pyr) return SIDWT_E_INVAL;
+  return map_err(sidwt::launch_generic(*d, J, (int)N, rx, n, count, rx_stride, pyr,
+                                       static_cast<hipStream_t>(hip_stream)));
 }
 
 int sidwt_lift_many(int filter, int J, const void *rx, int64_t n, int64_t count,

@@ -1,0 +1,141 @@
+// Critical lifting of a batch with any factorized filter pair (eq. (16)):
+// the steps come at run time from the host factorizer (sidwt_factor.cpp)
+// instead of being compiled in, for filter pairs the specialised kernels do
+// not carry.  Same output as sidwt_lift_many: per pulse d_1 | ... | d_J | c_J
+// (complex64, N elements), I and Q lifted alike (Sec. IV).
+//
+// One workgroup per pulse; c_l (l < J) in LDS at alternating offsets 0 and
+// N/2; each level in 64-lane register windows where a step's taps at offset
+// v come from lane + v (ds_bpermute shuffles), so the HL leftmost and HR
+// rightmost lanes of a window only feed their neighbours.
+#include <hip/hip_runtime.h>
+
+#include "sidwt_device.hpp"
+#include "sidwt_factor.hpp"
+
+namespace sidwt {
+
+constexpr int kGenericThreads = 512;
+
+// Single-precision copy of a factorization, with the window halos.
+struct GenericSteps {
+  int n;
+  int kind[kMaxLiftSteps];
+  int lo[kMaxLiftSteps];
+  int len[kMaxLiftSteps];
+  float c[kMaxLiftSteps][kMaxLiftTaps];
+  float ke, ko;
+  int se, so;
+  int HL, HR;
+};
+
+__device__ __forceinline__ float2 lane_at(float2 v, int src) {
+  return make_float2(__shfl(v.x, src), __shfl(v.y, src));
+}
+
+__global__ __launch_bounds__(kGenericThreads) void lift_generic(
+    GenericSteps st, int J, int N, const float2 *__restrict__ rx_all, long long n,
+    long long rx_stride, float2 *__restrict__ pyr_all) {
+  extern __shared__ __align__(16) float2 smem_gen[];
+  const long long pulse = blockIdx.x;
+  const float2 *rx = rx_all + pulse * rx_stride;
+  float2 *pyr = pyr_all + pulse * (long long)N;
+  const int ni = (int)n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int OWN = 64 - st.HL - st.HR;
+  for (int l = 1; l <= J; ++l) {
+    const int np = N >> l;
+    const float2 *cin = smem_gen + (((l - 1) & 1) ? 0 : (N >> 1));  // c_{l-1} (l >= 2)
+    float2 *cs = smem_gen + ((l & 1) ? 0 : (N >> 1));              // c_l (l < J)
+    float2 *dg = pyr + (N - (N >> (l - 1)));
+    float2 *cg = pyr + (N - np);
+    const int nwin = (np + OWN - 1) / OWN;
+    for (int w = wave; w < nwin; w += nw) {
+      const int k = w * OWN - st.HL + lane;
+      const int kc = pos_mod(k, np);
+      float2 e, o;
+      if (l == 1) {
+        e = 2 * kc < ni ? rx[2 * kc] : make_float2(0.f, 0.f);
+        o = 2 * kc + 1 < ni ? rx[2 * kc + 1] : make_float2(0.f, 0.f);
+      } else {
+        e = cin[2 * kc];
+        o = cin[2 * kc + 1];
+      }
+      for (int s = 0; s < st.n; ++s) {
+        const float2 src = st.kind[s] == kPredict ? e : o;
+        float2 acc = make_float2(0.f, 0.f);
+        for (int t = 0; t < st.len[s]; ++t) {
+          const float2 v = lane_at(src, lane + st.lo[s] + t);
+          acc.x = fmaf(st.c[s][t], v.x, acc.x);
+          acc.y = fmaf(st.c[s][t], v.y, acc.y);
+        }
+        if (st.kind[s] == kPredict)
+          o = add2(o, acc);
+        else
+          e = add2(e, acc);
+      }
+      const float2 c = scale2(st.ke, lane_at(e, lane + st.se));
+      const float2 d = scale2(st.ko, lane_at(o, lane + st.so));
+      if (lane >= st.HL && lane < 64 - st.HR && k < np) {
+        dg[k] = d;
+        if (l == J)
+          cg[k] = c;
+        else
+          cs[k] = c;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Halos: a step reading lanes lane + lo .. lane + lo + len - 1 widens the
+// invalid edge regions by max(0, -lo) on the left and max(0, lo + len - 1)
+// on the right; so do the final shifts.
+bool generic_steps(const LiftingDesc &d, GenericSteps *g) {
+  g->n = d.n;
+  int HL = 0, HR = 0;
+  for (int s = 0; s < d.n; ++s) {
+    g->kind[s] = d.kind[s];
+    g->lo[s] = d.lo[s];
+    g->len[s] = d.len[s];
+    for (int t = 0; t < kMaxLiftTaps; ++t) g->c[s][t] = t < d.len[s] ? (float)d.c[s][t] : 0.f;
+    HL += d.lo[s] < 0 ? -d.lo[s] : 0;
+    HR += d.lo[s] + d.len[s] - 1 > 0 ? d.lo[s] + d.len[s] - 1 : 0;
+  }
+  g->ke = (float)d.ke;
+  g->ko = (float)d.ko;
+  g->se = d.se;
+  g->so = d.so;
+  const int smin = d.se < d.so ? d.se : d.so, smax = d.se > d.so ? d.se : d.so;
+  HL += smin < 0 ? -smin : 0;
+  HR += smax > 0 ? smax : 0;
+  g->HL = HL;
+  g->HR = HR;
+  return HL + HR <= 48;
+}
+
+bool generic_steps_fit(const LiftingDesc &d) {
+  GenericSteps g;
+  return generic_steps(d, &g);
+}
+
+size_t generic_lds_bytes(int N) { return (size_t)(N / 2 + N / 4 + 1) * 8; }
+
+hipError_t launch_generic(const LiftingDesc &d, int J, int N, const void *rx, long long n,
+                          long long count, long long rx_stride, void *pyr, hipStream_t st) {
+  GenericSteps g;
+  if (!generic_steps(d, &g)) return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void *)lift_generic,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(lift_generic, dim3((unsigned)count), dim3(kGenericThreads),
+                     generic_lds_bytes(N), st, g, J, N, static_cast<const float2 *>(rx), n,
+                     rx_stride, static_cast<float2 *>(pyr));
+  return hipGetLastError();
+}
+
+}  // namespace sidwt

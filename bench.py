@@ -127,7 +127,7 @@ def main():
                          "(calibrates the HBM byte counters)")
     ap.add_argument("--workload", default="batched_uniform",
                     choices=["batched_uniform", "uneven", "integer", "single", "serving", "bank",
-                             "swapped", "detect"])
+                             "swapped", "detect", "generic"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path in this library "
@@ -139,7 +139,8 @@ def main():
     fn = {"batched_uniform": bench_batched_uniform, "uneven": bench_uneven,
           "integer": bench_integer, "single": bench_single,
           "serving": bench_serving, "bank": bench_bank,
-          "swapped": bench_swapped, "detect": bench_detect}[args.workload]
+          "swapped": bench_swapped, "detect": bench_detect,
+          "generic": bench_generic}[args.workload]
     rec = fn(args)
     print(json.dumps(rec), flush=True)
 
@@ -644,6 +645,84 @@ def bench_detect(args):
                      "frac": gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "detect_peaks",
                      "us_per_launch": ms_det * 1e3, "bytes": nbytes},
         "scene_peaks_per_plane": sf.tolist(),
+        "cpu_baseline": None,
+    }
+
+
+def _impulse_taps(lift):
+    """Lowpass and highpass tap dicts of a one-level lifting, from its
+    impulse responses (out[k] = sum_i c_i u[2k + i])."""
+    import numpy as np
+    lo, hi = {}, {}
+    for i in range(-12, 13):
+        u = np.zeros(64)
+        u[i % 64] = 1.0
+        A, B = lift(u)
+        if abs(A[0]) > 1e-15:
+            lo[i] = float(A[0])
+        if abs(B[0]) > 1e-15:
+            hi[i] = float(B[0])
+    return lo, hi
+
+
+def _cdf97_x_lift(t):
+    """x-side 9/7 lifting of the Case II family at parameter t (Sec. III-C),
+    written out here so that the benchmark needs no test code."""
+    import numpy as np
+    a = (-2 * t + 1) / (4 * (t - 1))
+    b = -(t - 1) ** 2
+    g = 1 / (4 * t * (t - 1))
+    d = t ** 3 - 7 / 4 * t ** 2 + t
+    x = np.sqrt(2) / t
+
+    def lift(u):
+        e, o = u[0::2].copy(), u[1::2].copy()
+        o = o + a * (e + np.roll(e, -1))
+        e = e + b * (o + np.roll(o, 1))
+        o = o + g * (e + np.roll(e, -1))
+        e = e + d * (o + np.roll(o, 1))
+        return x * e, o / x
+    return lift
+
+
+def bench_generic(args):
+    """Generic lifting (steps from the host factorizer at run time) with the
+    irrational CDF 9/7 (t = 1.2301741...) on the uniform batch (4096 x 8192
+    complex64, J = 5), against the compiled Table I lifting kernel."""
+    import torch
+
+    import paper_cs_0607001_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    J = 5
+    log(f"generating {args.count} x {args.n} pulses")
+    b = W.batched_uniform(seed=2, count=args.count, n=args.n, m=512, J=J)
+    rx = torch.from_numpy(b.rx).to(dev)
+    lo, hi = _impulse_taps(_cdf97_x_lift(1.230174104914001))
+    f = S.Lifting(lo, hi)
+    pyr = S.lift_generic(f, J, rx)
+    stream = torch.cuda.current_stream()
+    ms = _time_steps(lambda: S.lift_generic(f, J, rx, pyr=pyr), args.steps, args.warmup, stream)
+    nbytes = rx.numel() * rx.element_size() + pyr.numel() * pyr.element_size()
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    ms_c = _time_steps(lambda: S.lift_many("cdf97", J, rx, pyr=pyr), args.steps, args.warmup,
+                       stream)
+    log(f"generic lifting (irrational 9/7, {len(f.steps)} steps): {ms * 1e3:.1f} us, {gbs:.0f} GB/s; "
+        f"compiled Table I lifting {ms_c * 1e3:.1f} us")
+    f.free()
+    value = args.count * args.n / (ms * 1e-3)
+    return {
+        "metric": "complex samples/sec through J-scale SIDWT lifting",
+        "value": value, "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"generic lifting: {args.count} x {args.n} complex64, irrational "
+                               f"CDF 9/7 factorized on the host, J={J}"},
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs / PEAK_HBM_GBS, "traffic": None, "kernel": "lift_generic",
+                     "us_per_launch": ms * 1e3, "bytes": nbytes},
+        "compiled_lift_many_us": ms_c * 1e3,
         "cpu_baseline": None,
     }
 

@@ -33,9 +33,50 @@ __device__ __forceinline__ float2 lane_at(float2 v, int src) {
   return make_float2(__shfl(v.x, src), __shfl(v.y, src));
 }
 
+__device__ __forceinline__ void stream_store(float2 *p, float2 v) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(f2{v.x, v.y}, reinterpret_cast<f2 *>(p));
+}
+
+// Steps of one window, in place on the lane's pair.  SMALL: at most
+// kSmallSteps steps of at most kSmallTaps taps, loops unrolled with
+// predication so every coefficient sits at a fixed kernel-argument offset
+// (loaded once, ahead of the arithmetic); otherwise plain loops.
+constexpr int kSmallSteps = 8;
+constexpr int kSmallTaps = 4;
+
+template <bool SMALL>
+__device__ __forceinline__ void run_steps(const GenericSteps &st, int lane, float2 &e, float2 &o) {
+  constexpr int MS = SMALL ? kSmallSteps : kMaxLiftSteps;
+  constexpr int MT = SMALL ? kSmallTaps : kMaxLiftTaps;
+#pragma unroll
+  for (int s = 0; s < MS; ++s) {
+    if (s >= st.n) break;
+    const bool pred = st.kind[s] == kPredict;
+    const float2 src = pred ? e : o;
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      if (t >= st.len[s]) break;
+      const float2 v = lane_at(src, lane + st.lo[s] + t);
+      acc.x = fmaf(st.c[s][t], v.x, acc.x);
+      acc.y = fmaf(st.c[s][t], v.y, acc.y);
+    }
+    if (pred)
+      o = add2(o, acc);
+    else
+      e = add2(e, acc);
+  }
+  const float2 ce = lane_at(e, lane + st.se), co = lane_at(o, lane + st.so);
+  e = scale2(st.ke, ce);
+  o = scale2(st.ko, co);
+}
+
+template <bool SMALL>
 __global__ __launch_bounds__(kGenericThreads) void lift_generic(
     GenericSteps st, int J, int N, const float2 *__restrict__ rx_all, long long n,
     long long rx_stride, float2 *__restrict__ pyr_all) {
+  constexpr int U = 2;  // windows in flight per wave
   extern __shared__ __align__(16) float2 smem_gen[];
   const long long pulse = blockIdx.x;
   const float2 *rx = rx_all + pulse * rx_stride;
@@ -50,38 +91,41 @@ __global__ __launch_bounds__(kGenericThreads) void lift_generic(
     float2 *dg = pyr + (N - (N >> (l - 1)));
     float2 *cg = pyr + (N - np);
     const int nwin = (np + OWN - 1) / OWN;
-    for (int w = wave; w < nwin; w += nw) {
-      const int k = w * OWN - st.HL + lane;
-      const int kc = pos_mod(k, np);
-      float2 e, o;
-      if (l == 1) {
-        e = 2 * kc < ni ? rx[2 * kc] : make_float2(0.f, 0.f);
-        o = 2 * kc + 1 < ni ? rx[2 * kc + 1] : make_float2(0.f, 0.f);
-      } else {
-        e = cin[2 * kc];
-        o = cin[2 * kc + 1];
-      }
-      for (int s = 0; s < st.n; ++s) {
-        const float2 src = st.kind[s] == kPredict ? e : o;
-        float2 acc = make_float2(0.f, 0.f);
-        for (int t = 0; t < st.len[s]; ++t) {
-          const float2 v = lane_at(src, lane + st.lo[s] + t);
-          acc.x = fmaf(st.c[s][t], v.x, acc.x);
-          acc.y = fmaf(st.c[s][t], v.y, acc.y);
+    const bool wide = np >= 64;  // every needed index lies in [-HL, np + HR)
+    for (int w0 = wave * U; w0 < nwin; w0 += nw * U) {
+      float2 e[U], o[U];
+      int kk[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = (w0 + u) * OWN - st.HL + lane;
+        kk[u] = k;
+        int kc;
+        if (wide) {
+          kc = k < 0 ? k + np : (k >= np ? k - np : k);
+          kc = kc < np ? kc : np - 1;  // windows past the end only stay in bounds
+        } else {
+          kc = pos_mod(k, np);
         }
-        if (st.kind[s] == kPredict)
-          o = add2(o, acc);
-        else
-          e = add2(e, acc);
+        if (l == 1) {
+          e[u] = 2 * kc < ni ? rx[2 * kc] : make_float2(0.f, 0.f);
+          o[u] = 2 * kc + 1 < ni ? rx[2 * kc + 1] : make_float2(0.f, 0.f);
+        } else {
+          e[u] = cin[2 * kc];
+          o[u] = cin[2 * kc + 1];
+        }
       }
-      const float2 c = scale2(st.ke, lane_at(e, lane + st.se));
-      const float2 d = scale2(st.ko, lane_at(o, lane + st.so));
-      if (lane >= st.HL && lane < 64 - st.HR && k < np) {
-        dg[k] = d;
-        if (l == J)
-          cg[k] = c;
-        else
-          cs[k] = c;
+#pragma unroll
+      for (int u = 0; u < U; ++u) run_steps<SMALL>(st, lane, e[u], o[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int k = kk[u];
+        if (lane >= st.HL && lane < 64 - st.HR && k < np && w0 + u < nwin) {
+          stream_store(dg + k, o[u]);
+          if (l == J)
+            stream_store(cg + k, e[u]);
+          else
+            cs[k] = e[u];
+        }
       }
     }
     __syncthreads();
@@ -121,21 +165,31 @@ bool generic_steps_fit(const LiftingDesc &d) {
 
 size_t generic_lds_bytes(int N) { return (size_t)(N / 2 + N / 4 + 1) * 8; }
 
-hipError_t launch_generic(const LiftingDesc &d, int J, int N, const void *rx, long long n,
-                          long long count, long long rx_stride, void *pyr, hipStream_t st) {
-  GenericSteps g;
-  if (!generic_steps(d, &g)) return hipErrorInvalidValue;
+template <bool SMALL>
+static hipError_t launch_generic_t(const GenericSteps &g, int J, int N, const void *rx,
+                                   long long n, long long count, long long rx_stride, void *pyr,
+                                   hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)lift_generic,
+    hipError_t e = hipFuncSetAttribute((const void *)lift_generic<SMALL>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(lift_generic, dim3((unsigned)count), dim3(kGenericThreads),
+  hipLaunchKernelGGL(lift_generic<SMALL>, dim3((unsigned)count), dim3(kGenericThreads),
                      generic_lds_bytes(N), st, g, J, N, static_cast<const float2 *>(rx), n,
                      rx_stride, static_cast<float2 *>(pyr));
   return hipGetLastError();
+}
+
+hipError_t launch_generic(const LiftingDesc &d, int J, int N, const void *rx, long long n,
+                          long long count, long long rx_stride, void *pyr, hipStream_t st) {
+  GenericSteps g;
+  if (!generic_steps(d, &g)) return hipErrorInvalidValue;
+  bool small = d.n <= kSmallSteps;
+  for (int s = 0; s < d.n; ++s) small = small && d.len[s] <= kSmallTaps;
+  return small ? launch_generic_t<true>(g, J, N, rx, n, count, rx_stride, pyr, st)
+               : launch_generic_t<false>(g, J, N, rx, n, count, rx_stride, pyr, st);
 }
 
 }  // namespace sidwt

@@ -47,6 +47,11 @@ def pairs():
     out["cdf97_irrational"] = taps_of(lambda u, c: O.lift_x("cdf97", u, c),
                                       O.cdf97_constants_from_t(1.230174104914001))
     out["haar"] = ({0: s, 1: s}, {0: -s, 1: s})
+    # a six-tap predictor on the lazy split (one step longer than four taps:
+    # the kernel's general, non-unrolled instance)
+    p = [0.6, -0.25, 0.1, -0.05, 0.02, 0.01]
+    out["wide_predict"] = ({0: 1.0}, {1: 1.0, 0: -p[0], 2: -p[1], -2: -p[2], 4: -p[3], -4: -p[4],
+                                      6: -p[5]})
     return out
 
 

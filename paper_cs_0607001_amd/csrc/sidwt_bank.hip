@@ -257,15 +257,13 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
     const BankRefLevel *__restrict__ rl, int Jmax, const int *__restrict__ lo_lb,
     const unsigned *__restrict__ wts,
     const float2 *__restrict__ scratch, int Wmax) {
-  using H = Half<BF16>;
-  using V8 = typename H::V8;
   extern __shared__ __align__(16) unsigned sm_bank[];
   __shared__ float s_max;
 
   // Item: segment, row block and tile group (uniform across the block).
   const BankSeg sg = segs[item_seg[blockIdx.x]];
   const BankSeg &q = sg;                         // the request's fields
-  const int l = sg.level, P = 1 << l, L = sg.L, N = q.N;
+  const int l = sg.level, L = sg.L, N = q.N;
   int k = (int)(blockIdx.x - sg.item0);
   const int kfull = (sg.nblocks - 1) * sg.g_full;
   int rb, grp;

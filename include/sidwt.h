@@ -186,8 +186,11 @@ int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N,
  * holds levels 1 .. J-1 of the pulses' trees; the plan's stream orders the
  * launches, and calls that share a workspace must not overlap.  One
  * workgroup per (pulse, plane) holds that plane's phases in LDS (about
- * N + 2^j (len_j + 31) complex elements): SIDWT_E_UNSUPPORTED beyond
- * 160 KB and for the integer filter; SIDWT_E_INVAL for a short workspace.
+ * N + 2^j (len_j + 31) complex elements); when that exceeds 160 KB for some
+ * plane, every plane goes in chunks (one workgroup per pulse, plane, phase
+ * and group of up to 8192 lags: about 8192 + 2 len_j + 63 elements).
+ * SIDWT_E_UNSUPPORTED when even a chunk exceeds 160 KB and for the integer
+ * filter; SIDWT_E_INVAL for a short workspace.
  * count = 0 checks the sizes and launches nothing. */
 int64_t sidwt_swap_workspace_bytes(const sidwt_plan *p, int64_t n, int64_t count);
 int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n,

@@ -287,21 +287,25 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int6
   if (rx_stride < n || out_stride < (int64_t)p->J * N) return SIDWT_E_INVAL;
   sidwt::SwapDesc wd;
   std::memset(&wd, 0, sizeof(wd));
-  size_t lds = 0;
+  size_t lds = 0, lds_chunk = 0;
   for (int j = 0; j < p->J; ++j) {
     const int K = j == 0 ? (int)p->m : p->desc.lv[j].len[0];
-    lds = std::max(lds, sidwt::swap_lds_bytes((int)N, j, K));
+    lds = std::max(lds, sidwt::swap_lds_bytes((int)N, j, K, 0));
+    lds_chunk = std::max(lds_chunk, sidwt::swap_lds_bytes((int)N, j, K, 1));
     wd.a[j] = j == 0 ? static_cast<const float2 *>(p->ref_dev)
                      : static_cast<const float2 *>(p->coef) + p->desc.lv[j].off[0];
     wd.lo[j] = j == 0 ? 0 : p->desc.lv[j].lo[0];
     wd.len[j] = K;
   }
+  // whole planes per workgroup when they fit, else chunks of one phase
+  const int chunked = lds > (size_t)kLdsWords * 4;
+  if (chunked) lds = lds_chunk;
   if (lds > (size_t)kLdsWords * 4) return SIDWT_E_UNSUPPORTED;
   if (count == 0) return SIDWT_OK;
   if (!rx || !out || (p->J > 1 && !workspace)) return SIDWT_E_INVAL;
   if (workspace_bytes < swap_ws_bytes(p->J, N, count)) return SIDWT_E_INVAL;
   return map_err(sidwt::launch_swap(p->filter, p->J, (int)N, rx, n, count, rx_stride, workspace,
-                                    wd, lds, out, out_stride, p->stream));
+                                    wd, lds, chunked, out, out_stride, p->stream));
 }
 
 int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N, int64_t pulse_stride,

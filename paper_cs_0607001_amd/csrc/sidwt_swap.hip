@@ -16,8 +16,9 @@
 //    phase-major (phase p of level j at p * (N >> j) of the level's block),
 //    from level j - 1: child p = p' + 2^(j-1) b is the lifting of parent
 //    phase p' advanced by b samples.  Register windows with lane-shift taps.
-//  * swap_correlate: one workgroup per (pulse, plane); the plane's phases go
-//    to LDS (extended by the weight span so no window wraps, in 16-way
+//  * swap_correlate: one workgroup per (pulse, plane) (pulses too long for
+//    that: swap_correlate_chunks, one per (pulse, plane, phase, group of
+//    tiles)); the phases go to LDS (extended by the weight span so no window wraps, in 16-way
 //    polyphase order) and every phase is a Toeplitz-blocked real GEMM on
 //    v_mfma_f32_32x32x2_f32: row i of a tile holds lags 16 i .. 16 i + 15,
 //    the K axis runs over (offset v, re/im) and the 32 columns over
@@ -89,40 +90,42 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
 // Correlation of one plane of one pulse.
 // ---------------------------------------------------------------------------
 
-// LDS geometry of plane j (host and device): rows of 16 lags per phase R,
-// padded to whole 32-row tiles (RP), extended phase length E = 16 RP + K + 15
-// rounded up to a multiple of 16, sub-sequence length S = E / 16.
+// LDS geometry of one work item of plane j: ntp tiles of 32 rows (16 lags
+// per row) per phase; extended phase window E = 16 (32 ntp) + K + 15
+// elements rounded up to a multiple of 16, sub-sequence length S = E / 16.
+// A whole-plane item takes every tile of every phase; a chunk item (long
+// pulses) at most kSwapChunkTiles tiles of one phase.
+constexpr int kSwapChunkTiles = 16;
+
 struct SwapGeom {
-  int L, R, RP, S, tiles_per_phase, K;
-  __host__ __device__ SwapGeom(int N, int j, int K_) : K(K_) {
+  int L, tiles_per_phase, ntp, S, K;
+  __host__ __device__ SwapGeom(int N, int j, int K_, int chunk) : K(K_) {
     L = N >> j;
-    R = (L + 15) / 16;
+    const int R = (L + 15) / 16;
     tiles_per_phase = (R + 31) / 32;
-    RP = tiles_per_phase * 32;
-    S = (16 * RP + K + 15 + 15) / 16;
+    ntp = chunk ? (tiles_per_phase < kSwapChunkTiles ? tiles_per_phase : kSwapChunkTiles)
+                : tiles_per_phase;
+    S = (16 * 32 * ntp + K + 15 + 15) / 16;
   }
   __host__ __device__ int phase_words() const { return 16 * S * 2; }  // floats per phase
+  __host__ __device__ int chunks() const { return (tiles_per_phase + ntp - 1) / ntp; }
 };
 
-__host__ __device__ inline size_t swap_lds_bytes_geom(int N, int j, int K) {
-  const SwapGeom g(N, j, K);
-  return ((size_t)(1 << j) * g.phase_words() + 2 * (size_t)(K + 32)) * 4;
+__host__ __device__ inline size_t swap_lds_bytes_geom(int N, int j, int K, int chunk) {
+  const SwapGeom g(N, j, K, chunk);
+  return ((size_t)(chunk ? 1 : (1 << j)) * g.phase_words() + 2 * (size_t)(K + 32)) * 4;
 }
 
-__global__ __launch_bounds__(kSwapThreads) void swap_correlate(
-    int J, int N, int count, const float2 *__restrict__ rx_all, long long rx_stride, int n,
-    const float2 *__restrict__ tree_all, long long tree_stride, SwapDesc wd,
-    float2 *__restrict__ out_all, long long out_stride) {
-  extern __shared__ __align__(16) float smem_swap[];
-  // heaviest planes (j = 0) first in launch order
-  const int j = blockIdx.x / count;
-  const long long pulse = blockIdx.x - (long long)j * count;
-  const int K = wd.len[j], lo = wd.lo[j];
-  const SwapGeom g(N, j, K);
+// One item: phases p_begin .. p_begin + np_ - 1 of plane j, tiles rt0 ..
+// rt0 + ntp - 1 of each (rows 32 rt0 ..), for one pulse.
+__device__ __forceinline__ void swap_item(int j, int N, const SwapGeom &g, int p_begin, int np_,
+                                          int rt0, int ntp, const float2 *src0, int n,
+                                          const SwapDesc &wd, float *outp, float *smem) {
+  const int K = g.K, lo = wd.lo[j];
   const int P = 1 << j;
   const int L = g.L, S = g.S;
-  float *ys = smem_swap;                               // P phases x 16 S complex
-  float2 *wp = reinterpret_cast<float2 *>(ys + P * g.phase_words());  // K + 32
+  float *ys = smem;                                               // np_ phases x 16 S complex
+  float2 *wp = reinterpret_cast<float2 *>(ys + np_ * g.phase_words());  // K + 32
   const int tid = threadIdx.x, nt = blockDim.x;
 
   // weights: wp[u + 16] = conj(a[lo + u]) for 0 <= u < K, zero around
@@ -135,18 +138,16 @@ __global__ __launch_bounds__(kSwapThreads) void swap_correlate(
     }
     wp[u] = w;
   }
-  // phases, extended: element e of phase p is Y_p[(e + lo) mod L], stored
-  // as complex64 at sub-sequence e mod 16, index e / 16 (element
-  // (e mod 16) * S + e / 16 of the phase), so the 32 rows of a tile, 16
-  // elements apart, read consecutive elements
-  const float2 *src0 = j == 0 ? rx_all + pulse * rx_stride
-                              : tree_all + pulse * tree_stride + (long long)(j - 1) * N;
-  const int E = 16 * S;
-  for (int p = 0; p < P; ++p) {
-    const float2 *src = src0 + (long long)p * L;
-    float2 *dst = reinterpret_cast<float2 *>(ys + p * g.phase_words());
+  // phases, extended: element e of phase slot q is Y_p[(512 rt0 + e + lo)
+  // mod L], stored as complex64 at sub-sequence e mod 16, index e / 16
+  // (element (e mod 16) * S + e / 16 of the slot), so the 32 rows of a
+  // tile, 16 elements apart, read consecutive elements
+  const int E = 16 * S, base = 512 * rt0 + lo;
+  for (int q = 0; q < np_; ++q) {
+    const float2 *src = src0 + (long long)(p_begin + q) * L;
+    float2 *dst = reinterpret_cast<float2 *>(ys + q * g.phase_words());
     for (int e = tid; e < E; e += nt) {
-      const int i = pos_mod(e + lo, L);
+      const int i = pos_mod(base + e, L);
       float2 v;
       if (j == 0)
         v = i < n ? src[i] : make_float2(0.f, 0.f);
@@ -161,17 +162,16 @@ __global__ __launch_bounds__(kSwapThreads) void swap_correlate(
   const int row = lane & 31, kc = lane >> 5;      // A fragment: row, re/im
   const int col = lane & 31;                      // B fragment column
   const int bt = col >> 1, bc = col & 1;          // lag within the block, re/im
-  const int ntiles = P * g.tiles_per_phase;
+  const int ntiles = np_ * ntp;
   const int Kp = K + 15;                          // offsets v in [0, K + 15)
-  float *outp = reinterpret_cast<float *>(out_all + pulse * out_stride + (long long)j * N);
   for (int t0 = wave * kSwapRT; t0 < ntiles; t0 += nw * kSwapRT) {
-    // tile t: phase t / tiles_per_phase, rows 32 * (t % tiles_per_phase) ..
+    // tile t: phase slot t / ntp, local rows 32 * (t % ntp) ..
     int abase[kSwapRT];
 #pragma unroll
     for (int r = 0; r < kSwapRT; ++r) {
       const int t = min(t0 + r, ntiles - 1);
-      const int p = t / g.tiles_per_phase, rt = t - p * g.tiles_per_phase;
-      abase[r] = p * g.phase_words() + 2 * (rt * 32 + row) + kc;
+      const int q = t / ntp, rt = t - q * ntp;
+      abase[r] = q * g.phase_words() + 2 * (rt * 32 + row) + kc;
     }
     f32x16 acc[kSwapRT];
 #pragma unroll
@@ -192,21 +192,65 @@ __global__ __launch_bounds__(kSwapThreads) void swap_correlate(
     for (int r = 0; r < kSwapRT; ++r) {
       const int t = t0 + r;
       if (t >= ntiles) break;
-      const int p = t / g.tiles_per_phase, rt = t - p * g.tiles_per_phase;
+      const int q = t / ntp, rt = t - q * ntp;
+      const int p = p_begin + q;
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int rr = rt * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const int q = 16 * rr + bt;
-        if (q < L) outp[2 * ((long long)q * P + p) + bc] = acc[r][i];
+        const int rr = (rt0 + rt) * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+        const int lag = 16 * rr + bt;
+        if (lag < L) outp[2 * ((long long)lag * P + p) + bc] = acc[r][i];
       }
     }
   }
 }
 
+// Whole planes: one workgroup per (pulse, plane), heaviest planes (j = 0)
+// first in launch order.
+__global__ __launch_bounds__(kSwapThreads) void swap_correlate(
+    int J, int N, int count, const float2 *__restrict__ rx_all, long long rx_stride, int n,
+    const float2 *__restrict__ tree_all, long long tree_stride, SwapDesc wd,
+    float2 *__restrict__ out_all, long long out_stride) {
+  extern __shared__ __align__(16) float smem_swap[];
+  const int j = blockIdx.x / count;
+  const long long pulse = blockIdx.x - (long long)j * count;
+  const SwapGeom g(N, j, wd.len[j], 0);
+  const float2 *src0 = j == 0 ? rx_all + pulse * rx_stride
+                              : tree_all + pulse * tree_stride + (long long)(j - 1) * N;
+  float *outp = reinterpret_cast<float *>(out_all + pulse * out_stride + (long long)j * N);
+  swap_item(j, N, g, 0, 1 << j, 0, g.tiles_per_phase, src0, n, wd, outp, smem_swap);
+}
+
+// Long pulses: one workgroup per (plane, pulse, phase, chunk of at most
+// kSwapChunkTiles tiles); item0[j] = first item of plane j.
+struct SwapChunks {
+  int item0[kMaxLevels + 2];
+};
+
+__global__ __launch_bounds__(kSwapThreads) void swap_correlate_chunks(
+    int J, int N, int count, const float2 *__restrict__ rx_all, long long rx_stride, int n,
+    const float2 *__restrict__ tree_all, long long tree_stride, SwapDesc wd, SwapChunks ck,
+    float2 *__restrict__ out_all, long long out_stride) {
+  extern __shared__ __align__(16) float smem_swap[];
+  int j = 0;
+  while (j + 1 < J && (long long)blockIdx.x >= ck.item0[j + 1]) ++j;
+  const SwapGeom g(N, j, wd.len[j], 1);
+  const int per_pulse = (1 << j) * g.chunks();
+  const long long local = blockIdx.x - (long long)ck.item0[j];
+  const long long pulse = local / per_pulse;
+  const int rem = (int)(local - pulse * per_pulse);
+  const int p = rem / g.chunks(), c = rem - p * g.chunks();
+  const int rt0 = c * g.ntp;
+  const int ntp = min(g.ntp, g.tiles_per_phase - rt0);
+  const float2 *src0 = j == 0 ? rx_all + pulse * rx_stride
+                              : tree_all + pulse * tree_stride + (long long)(j - 1) * N;
+  float *outp = reinterpret_cast<float *>(out_all + pulse * out_stride + (long long)j * N);
+  swap_item(j, N, g, p, 1, rt0, ntp, src0, n, wd, outp, smem_swap);
+}
+
 // ---------------------------------------------------------------------------
 // Launch helpers (C++ linkage, used by sidwt_api.cpp).
 // ---------------------------------------------------------------------------
-size_t swap_lds_bytes(int N, int j, int K) { return swap_lds_bytes_geom(N, j, K); }
+size_t swap_lds_bytes(int N, int j, int K, int chunk) { return swap_lds_bytes_geom(N, j, K, chunk); }
 
 
 template <int F>
@@ -228,7 +272,7 @@ static hipError_t launch_swap_tree_t(int J, int N, const void *rx, long long n, 
 
 hipError_t launch_swap(int filter, int J, int N, const void *rx, long long n, long long count,
                        long long rx_stride, void *tree, const SwapDesc &wd, size_t lds_bytes,
-                       void *out, long long out_stride, hipStream_t st) {
+                       int chunked, void *out, long long out_stride, hipStream_t st) {
   hipError_t e;
   switch (filter) {
     case F_LEGALL53: e = launch_swap_tree_t<F_LEGALL53>(J, N, rx, n, count, rx_stride, tree, st); break;
@@ -241,12 +285,31 @@ hipError_t launch_swap(int filter, int J, int N, const void *rx, long long n, lo
   if (!attr_set) {
     e = hipFuncSetAttribute((const void *)swap_correlate, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void *)swap_correlate_chunks,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(swap_correlate, dim3((unsigned)(count * J)), dim3(kSwapThreads), lds_bytes, st,
-                     J, N, (int)count, static_cast<const float2 *>(rx), rx_stride, (int)n,
-                     static_cast<const float2 *>(tree), (long long)(J - 1) * N, wd,
+  if (!chunked) {
+    hipLaunchKernelGGL(swap_correlate, dim3((unsigned)(count * J)), dim3(kSwapThreads), lds_bytes,
+                       st, J, N, (int)count, static_cast<const float2 *>(rx), rx_stride, (int)n,
+                       static_cast<const float2 *>(tree), (long long)(J - 1) * N, wd,
+                       static_cast<float2 *>(out), out_stride);
+    return hipGetLastError();
+  }
+  SwapChunks ck;
+  long long items = 0;
+  for (int j = 0; j < J; ++j) {
+    ck.item0[j] = (int)items;
+    const SwapGeom g(N, j, wd.len[j], 1);
+    items += count * (long long)(1 << j) * g.chunks();
+  }
+  ck.item0[J] = (int)items;
+  if (items > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(swap_correlate_chunks, dim3((unsigned)items), dim3(kSwapThreads), lds_bytes,
+                     st, J, N, (int)count, static_cast<const float2 *>(rx), rx_stride, (int)n,
+                     static_cast<const float2 *>(tree), (long long)(J - 1) * N, wd, ck,
                      static_cast<float2 *>(out), out_stride);
   return hipGetLastError();
 }

@@ -19,9 +19,11 @@ struct SwapDesc {
   int len[kMaxLevels + 1];
 };
 
-size_t swap_lds_bytes(int N, int j, int K);
+// LDS of plane j's work item: whole plane (chunk = 0) or one chunk of one
+// phase (chunk = 1, long pulses).
+size_t swap_lds_bytes(int N, int j, int K, int chunk);
 hipError_t launch_swap(int filter, int J, int N, const void *rx, long long n, long long count,
                        long long rx_stride, void *tree, const SwapDesc &wd, size_t lds_bytes,
-                       void *out, long long out_stride, hipStream_t st);
+                       int chunked, void *out, long long out_stride, hipStream_t st);
 
 }  // namespace sidwt

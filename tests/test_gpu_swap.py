@@ -55,6 +55,31 @@ def test_swapped_matches_oracle(dev, filt, J, n, m, count):
             assert rel_l2(got[i, j], want[j]) <= 1e-5, (i, j)
 
 
+@pytest.mark.parametrize("filt,J,n,m,count", [
+    ("cdf97", 3, 24576, 100, 2),    # planes too long for one workgroup: chunks of one phase
+    ("cdf97", 5, 32768, 512, 1),
+    ("d4", 6, 65536, 2048, 1),
+    ("legall53", 4, 40000, 300, 1),
+])
+def test_swapped_long_pulses_sampled(dev, filt, J, n, m, count):
+    torch, S = dev
+    rng = np.random.default_rng(n + J)
+    ref, rx = crand(rng, m), crand(rng, count, n)
+    N = O.transform_length(n, J)
+    print(f"[case] swapped long {filt} J={J} n={n} m={m}", flush=True)
+    with S.plan_create(filt, J, ref) as plan:
+        out = S.correlate_swapped(plan, torch.from_numpy(rx).cuda())
+        torch.cuda.synchronize()
+        got_all = out.cpu().numpy().astype(np.complex128)
+    lags = np.concatenate([[0, 1, 15, 16, 511, 512, N - 1], rng.integers(0, N, 25)])
+    for i in range(count):
+        for j in range(J):
+            want = O.correlate_swapped_at(filt, J, ref.astype(np.complex128),
+                                          rx[i].astype(np.complex128), j, lags)
+            assert rel_l2(got_all[i, j, lags], want) <= 1e-5, (i, j)
+    assert np.isfinite(got_all).all()
+
+
 def test_swapped_is_covariant_in_the_received_shift_on_the_gpu(dev):
     torch, S = dev
     rng = np.random.default_rng(41)
@@ -113,7 +138,8 @@ def test_swapped_refuses_what_it_cannot_do(dev):
         small = torch.empty(16, dtype=torch.uint8, device="cuda")
         with pytest.raises(S.SidwtError):
             S.correlate_swapped(plan, rx, workspace=small)
-        # the largest plane-0 layout is about N complex elements: 40000 does not fit
+    # a reference whose weights and window exceed the LDS even in chunks
+    with S.plan_create("cdf97", 3, crand(rng, 8192)) as plan:
         big = torch.zeros((1, 40000), dtype=torch.complex64, device="cuda")
         with pytest.raises(S.SidwtError):
             S.correlate_swapped(plan, big)

@@ -111,3 +111,31 @@ def test_detect_full_size_property(dev):
                 want = np.nonzero(pk[j])[0]
                 assert f[i, j] == len(want)
                 assert np.array_equal(L[j, :min(64, len(want))], want[:64])
+
+
+def test_detect_through_the_c_abi_with_a_padded_pulse_stride(dev):
+    import ctypes
+    torch, S = dev
+    rng = np.random.default_rng(45)
+    count, J, N = 3, 2, 300
+    planes = (rng.standard_normal((count, J, N)) + 1j * rng.standard_normal((count, J, N))).astype(
+        np.complex64)
+    pitch = J * N + 50
+    padded = np.full((count, pitch), 100 + 0j, np.complex64)    # a tall peak in the padding
+    padded[:, :J * N] = planes.reshape(count, J * N)
+    pt = torch.from_numpy(padded).cuda()
+    lags = torch.empty((count * J * 16,), dtype=torch.int32, device="cuda")
+    db = torch.empty((count * J * 16,), dtype=torch.float32, device="cuda")
+    found = torch.empty((count * J,), dtype=torch.int32, device="cuda")
+    rel = np.float32(10.0 ** (-6.0 / 10.0))
+    rc = S._lib.lib().sidwt_detect_peaks(ctypes.c_void_p(pt.data_ptr()), count, J, N, pitch,
+                                         float(rel), 16, ctypes.c_void_p(lags.data_ptr()),
+                                         ctypes.c_void_p(db.data_ptr()),
+                                         ctypes.c_void_p(found.data_ptr()), None)
+    assert rc == 0
+    lags, found = lags.cpu().numpy().reshape(count, J, 16), found.cpu().numpy().reshape(count, J)
+    want = O.detect_peaks(planes, rel, 16)
+    for k, (wl, _) in enumerate(want):
+        i, j = divmod(k, J)
+        assert found[i, j] == len(wl)
+        assert np.array_equal(lags[i, j, :min(16, len(wl))], wl[:16])

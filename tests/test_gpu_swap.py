@@ -148,3 +148,36 @@ def test_swapped_refuses_what_it_cannot_do(dev):
         import ctypes
         rc = S._lib.lib().sidwt_correlate_swapped(plan.handle, None, 64, 0, 64, None, 128, None, 0)
         assert rc == -5
+
+
+def test_swapped_through_the_c_abi_with_padded_strides(dev):
+    """rx_stride > n and out_stride > J N: rows of a padded batch, output
+    planes at a padded pitch (the padding left untouched)."""
+    import ctypes
+    torch, S = dev
+    rng = np.random.default_rng(44)
+    J, n, m, count = 3, 1000, 60, 3
+    N = O.transform_length(n, J)
+    ref = crand(rng, m)
+    rx = crand(rng, count, n)
+    rxp = np.zeros((count, n + 37), np.complex64)
+    rxp[:, :n] = rx
+    rxp[:, n:] = 7 + 7j                      # must not be read
+    ostride = J * N + 100
+    out = torch.full((count, ostride), 3 + 3j, dtype=torch.complex64, device="cuda")
+    rx_t = torch.from_numpy(rxp).cuda()
+    with S.plan_create("cdf97", J, ref) as plan:
+        L = S._lib.lib()
+        ws = torch.empty(L.sidwt_swap_workspace_bytes(plan.handle, n, count), dtype=torch.uint8,
+                         device="cuda")
+        rc = L.sidwt_correlate_swapped(plan.handle, ctypes.c_void_p(rx_t.data_ptr()), n, count,
+                                       n + 37, ctypes.c_void_p(out.data_ptr()), ostride,
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel())
+        assert rc == 0
+        torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.all(got[:, J * N:] == np.complex64(3 + 3j))
+    for i in range(count):
+        want = O.correlate_swapped("cdf97", J, ref.astype(np.complex128), rx[i].astype(np.complex128))
+        for j in range(J):
+            assert rel_l2(got[i, j * N:(j + 1) * N].astype(np.complex128), want[j]) <= 1e-5

@@ -38,12 +38,32 @@ __device__ __forceinline__ void stream_store(float2 *p, float2 v) {
   __builtin_nontemporal_store(f2{v.x, v.y}, reinterpret_cast<f2 *>(p));
 }
 
-// Steps of one window, in place on the lane's pair.  SMALL: at most
-// kSmallSteps steps of at most kSmallTaps taps, loops unrolled with
-// predication so every coefficient sits at a fixed kernel-argument offset
-// (loaded once, ahead of the arithmetic); otherwise plain loops.
+// Steps of one window, in place on the lane's pair.  TWO_TAP: the shape of
+// the paper's factorizations (every predict step reads e[k], e[k+1], every
+// update step o[k-1], o[k], no shifts, at most kSmallSteps steps): one DPP
+// neighbour per step.  SMALL: at most kSmallSteps steps of at most
+// kSmallTaps taps, loops unrolled with predication so every coefficient sits
+// at a fixed kernel-argument offset (loaded once, ahead of the arithmetic);
+// otherwise plain loops.
 constexpr int kSmallSteps = 8;
 constexpr int kSmallTaps = 4;
+
+__device__ __forceinline__ void run_two_tap(const GenericSteps &st, float2 &e, float2 &o) {
+#pragma unroll
+  for (int s = 0; s < kSmallSteps; ++s) {
+    if (s >= st.n) break;
+    const float c0 = st.c[s][0], c1 = st.c[s][1];
+    if (st.kind[s] == kPredict) {
+      const float2 en = lane_next(e);
+      o = fma2(c1, en, fma2(c0, e, o));
+    } else {
+      const float2 op = lane_prev(o);
+      e = fma2(c1, o, fma2(c0, op, e));
+    }
+  }
+  e = scale2(st.ke, e);
+  o = scale2(st.ko, o);
+}
 
 template <bool SMALL>
 __device__ __forceinline__ void run_steps(const GenericSteps &st, int lane, float2 &e, float2 &o) {
@@ -72,7 +92,7 @@ __device__ __forceinline__ void run_steps(const GenericSteps &st, int lane, floa
   o = scale2(st.ko, co);
 }
 
-template <bool SMALL>
+template <int MODE>  // 0: loops, 1: unrolled shuffles, 2: two-tap DPP
 __global__ __launch_bounds__(kGenericThreads) void lift_generic(
     GenericSteps st, int J, int N, const float2 *__restrict__ rx_all, long long n,
     long long rx_stride, float2 *__restrict__ pyr_all) {
@@ -115,7 +135,12 @@ __global__ __launch_bounds__(kGenericThreads) void lift_generic(
         }
       }
 #pragma unroll
-      for (int u = 0; u < U; ++u) run_steps<SMALL>(st, lane, e[u], o[u]);
+      for (int u = 0; u < U; ++u) {
+        if constexpr (MODE == 2)
+          run_two_tap(st, e[u], o[u]);
+        else
+          run_steps<MODE == 1>(st, lane, e[u], o[u]);
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int k = kk[u];
@@ -165,18 +190,18 @@ bool generic_steps_fit(const LiftingDesc &d) {
 
 size_t generic_lds_bytes(int N) { return (size_t)(N / 2 + N / 4 + 1) * 8; }
 
-template <bool SMALL>
+template <int MODE>
 static hipError_t launch_generic_t(const GenericSteps &g, int J, int N, const void *rx,
                                    long long n, long long count, long long rx_stride, void *pyr,
                                    hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void *)lift_generic<SMALL>,
+    hipError_t e = hipFuncSetAttribute((const void *)lift_generic<MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  hipLaunchKernelGGL(lift_generic<SMALL>, dim3((unsigned)count), dim3(kGenericThreads),
+  hipLaunchKernelGGL(lift_generic<MODE>, dim3((unsigned)count), dim3(kGenericThreads),
                      generic_lds_bytes(N), st, g, J, N, static_cast<const float2 *>(rx), n,
                      rx_stride, static_cast<float2 *>(pyr));
   return hipGetLastError();
@@ -187,9 +212,14 @@ hipError_t launch_generic(const LiftingDesc &d, int J, int N, const void *rx, lo
   GenericSteps g;
   if (!generic_steps(d, &g)) return hipErrorInvalidValue;
   bool small = d.n <= kSmallSteps;
-  for (int s = 0; s < d.n; ++s) small = small && d.len[s] <= kSmallTaps;
-  return small ? launch_generic_t<true>(g, J, N, rx, n, count, rx_stride, pyr, st)
-               : launch_generic_t<false>(g, J, N, rx, n, count, rx_stride, pyr, st);
+  bool two = small && d.se == 0 && d.so == 0;
+  for (int s = 0; s < d.n; ++s) {
+    small = small && d.len[s] <= kSmallTaps;
+    two = two && d.len[s] == 2 && d.lo[s] == (d.kind[s] == kPredict ? 0 : -1);
+  }
+  if (two) return launch_generic_t<2>(g, J, N, rx, n, count, rx_stride, pyr, st);
+  if (small) return launch_generic_t<1>(g, J, N, rx, n, count, rx_stride, pyr, st);
+  return launch_generic_t<0>(g, J, N, rx, n, count, rx_stride, pyr, st);
 }
 
 }  // namespace sidwt

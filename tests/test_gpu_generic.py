@@ -2,7 +2,7 @@
 the GPU against the oracle's convolve-and-downsample analysis with the same
 taps, for the paper's pairs on both sides, the irrational CDF 9/7 member of
 the Case II family, D4 (a factorization with shifts), Haar, and predictors
-of four taps and of six taps (the latter past the unrolled instance);
+of four taps and of six taps (every one of the kernel's instances runs);
 ragged and tiny lengths; the benchmark size on sampled pulses."""
 import math
 

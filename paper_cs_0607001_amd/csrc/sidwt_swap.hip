@@ -62,6 +62,7 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
   const int wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
   const int nwin = (L + OWN - 1) / OWN;
+  const bool wide = L >= 64;  // every index a stored output needs lies in [-HL, L + HR)
   constexpr int U = 2;
   for (int w0 = wave * U; w0 < nwin; w0 += nw * U) {
     float2 e[U], o[U];
@@ -70,7 +71,13 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
     for (int u = 0; u < U; ++u) {
       const int k = (w0 + u) * OWN - Lf::HL + lane;
       kk[u] = k;
-      const int kc = pos_mod(k, L);
+      int kc;
+      if (wide) {
+        kc = k < 0 ? k + L : (k >= L ? k - L : k);
+        kc = kc < L ? kc : L - 1;  // windows past the end only stay in bounds
+      } else {
+        kc = pos_mod(k, L);
+      }
       const int ie = 2 * kc + b;  // < Lp
       const int io = OB ? (ie == 0 ? Lp - 1 : ie - 1) : (ie + 1 == Lp ? 0 : ie + 1);
       e[u] = sample(ie);
@@ -81,7 +88,10 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = kk[u];
-      if (lane >= Lf::HL && lane < 64 - Lf::HR && k < L && (w0 + u) < nwin) child[k] = e[u];
+      if (lane >= Lf::HL && lane < 64 - Lf::HR && k < L && (w0 + u) < nwin) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(f2{e[u].x, e[u].y}, reinterpret_cast<f2 *>(child + k));
+      }
     }
   }
 }

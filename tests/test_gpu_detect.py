@@ -48,7 +48,7 @@ def test_detect_on_oracle_planes_of_the_scene(dev):
         compare(S, torch, planes, level)
 
 
-@pytest.mark.parametrize("N", [3, 17, 64, 255, 256, 257, 1000, 4096, 40944, 40945, 50000])
+@pytest.mark.parametrize("N", [3, 17, 64, 255, 256, 257, 1000, 2047, 2048, 2049, 4096, 40896, 40897, 50000])
 def test_detect_random_planes_with_ties(dev, N):
     torch, S = dev
     rng = np.random.default_rng(N)

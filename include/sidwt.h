@@ -190,7 +190,9 @@ int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N,
  * plane, every plane goes in chunks (one workgroup per pulse, plane, phase
  * and group of up to 8192 lags: about 8192 + 2 len_j + 63 elements).
  * SIDWT_E_UNSUPPORTED when even a chunk exceeds 160 KB and for the integer
- * filter; SIDWT_E_INVAL for a short workspace.
+ * filter; SIDWT_E_INVAL for a short workspace; SIDWT_E_SIZE when the
+ * launch grid (count 2^(J-1) tree workgroups, or the chunks) exceeds 2^31
+ * or the workspace 2^63 bytes (sidwt_swap_workspace_bytes then returns -1).
  * count = 0 checks the sizes and launches nothing. */
 int64_t sidwt_swap_workspace_bytes(const sidwt_plan *p, int64_t n, int64_t count);
 int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -266,8 +267,13 @@ int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out) {
 namespace {
 
 // Workspace of the roles-exchanged correlation: levels 1 .. J-1 of the
-// redundant tree, N complex64 elements per level and pulse.
-int64_t swap_ws_bytes(int J, int64_t N, int64_t count) { return (int64_t)(J - 1) * N * count * 8; }
+// redundant tree, N complex64 elements per level and pulse; -1 when that
+// does not fit in 63 bits.
+int64_t swap_ws_bytes(int J, int64_t N, int64_t count) {
+  const int64_t per_pulse = (int64_t)(J - 1) * N * 8;  // < 2^48 (N <= 2^30)
+  if (per_pulse > 0 && count > INT64_MAX / per_pulse) return -1;
+  return per_pulse * count;
+}
 
 }  // namespace
 
@@ -281,9 +287,12 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int6
                             int64_t workspace_bytes) {
   if (!p || count < 0 || (int64_t)count * p->J > 0x7fffffff) return SIDWT_E_INVAL;
   if (p->filter == SIDWT_LEGALL53_INT || !p->ref_dev) return SIDWT_E_UNSUPPORTED;
+  // the deepest tree level launches one workgroup per (pulse, phase)
+  if ((count << (p->J - 1)) > 0x7fffffff) return SIDWT_E_SIZE;
   int64_t N = 0;
   int rc = check_pulse(p, n, &N);
   if (rc) return rc;
+  if (swap_ws_bytes(p->J, N, count) < 0) return SIDWT_E_SIZE;
   if (rx_stride < n || out_stride < (int64_t)p->J * N) return SIDWT_E_INVAL;
   sidwt::SwapDesc wd;
   std::memset(&wd, 0, sizeof(wd));
@@ -301,6 +310,11 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int6
   const int chunked = lds > (size_t)kLdsWords * 4;
   if (chunked) lds = lds_chunk;
   if (lds > (size_t)kLdsWords * 4) return SIDWT_E_UNSUPPORTED;
+  if (chunked) {  // one workgroup per (pulse, plane, phase, chunk of 8192 lags)
+    int64_t items = 0;
+    for (int j = 0; j < p->J; ++j) items += count * ((((N >> j) + 8191) / 8192) << j);
+    if (items > 0x7fffffff) return SIDWT_E_SIZE;
+  }
   if (count == 0) return SIDWT_OK;
   if (!rx || !out || (p->J > 1 && !workspace)) return SIDWT_E_INVAL;
   if (workspace_bytes < swap_ws_bytes(p->J, N, count)) return SIDWT_E_INVAL;

@@ -181,3 +181,16 @@ def test_swapped_through_the_c_abi_with_padded_strides(dev):
         want = O.correlate_swapped("cdf97", J, ref.astype(np.complex128), rx[i].astype(np.complex128))
         for j in range(J):
             assert rel_l2(got[i, j * N:(j + 1) * N].astype(np.complex128), want[j]) <= 1e-5
+
+
+def test_swapped_size_guards(dev):
+    """Grids and workspaces beyond what one launch or one int64 can address
+    are refused on the host (count = 0 is not needed for the check)."""
+    torch, S = dev
+    rng = np.random.default_rng(46)
+    L = S._lib.lib()
+    with S.plan_create("cdf97", 12, crand(rng, 64)) as plan:
+        # count * 2^(J-1) tree workgroups above 2^31
+        assert L.sidwt_correlate_swapped(plan.handle, None, 1 << 14, 1 << 20, 1 << 14, None,
+                                         12 << 14, None, 0) == -2
+        assert L.sidwt_swap_workspace_bytes(plan.handle, 1 << 30, (1 << 31) - 1) == -1

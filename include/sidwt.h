@@ -235,12 +235,16 @@ int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N,
 int sidwt_lifting_factorize(const double *lo, int lo_first, int lo_len,
                             const double *hi, int hi_first, int hi_len,
                             sidwt_lifting **out);
+/* Number of steps (SIDWT_E_INVAL for NULL). */
 int sidwt_lifting_count(const sidwt_lifting *f);
+/* Step i (0 <= i < count): kind, first offset, number of taps; coef (may be
+ * NULL) receives the len coefficients (at most 8). */
 int sidwt_lifting_step(const sidwt_lifting *f, int i, int *kind, int *first,
                        int *len, double *coef);
+/* Final scaling and shifts: c[k] = ke e[k + se], d[k] = ko o[k + so]. */
 int sidwt_lifting_scaling(const sidwt_lifting *f, double *ke, int *se,
                           double *ko, int *so);
-void sidwt_lifting_free(sidwt_lifting *f);
+void sidwt_lifting_free(sidwt_lifting *f);   /* NULL is a no-op */
 
 /* Critical lifting of a batch with a factorized pair (its steps taken at
  * run time, in single precision): as sidwt_lift_many (same pyramid layout

@@ -65,6 +65,26 @@ __device__ __forceinline__ void run_two_tap(const GenericSteps &st, float2 &e, f
   o = scale2(st.ko, o);
 }
 
+// The two-tap shape with NS alternating steps known at compile time (the
+// first a predict step when PRED_FIRST): only the coefficients are read at
+// run time.
+template <int NS, bool PRED_FIRST>
+__device__ __forceinline__ void run_alternating(const GenericSteps &st, float2 &e, float2 &o) {
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const float c0 = st.c[s][0], c1 = st.c[s][1];
+    if (((s & 1) == 0) == PRED_FIRST) {
+      const float2 en = lane_next(e);
+      o = fma2(c1, en, fma2(c0, e, o));
+    } else {
+      const float2 op = lane_prev(o);
+      e = fma2(c1, o, fma2(c0, op, e));
+    }
+  }
+  e = scale2(st.ke, e);
+  o = scale2(st.ko, o);
+}
+
 template <bool SMALL>
 __device__ __forceinline__ void run_steps(const GenericSteps &st, int lane, float2 &e, float2 &o) {
   constexpr int MS = SMALL ? kSmallSteps : kMaxLiftSteps;
@@ -92,7 +112,10 @@ __device__ __forceinline__ void run_steps(const GenericSteps &st, int lane, floa
   o = scale2(st.ko, co);
 }
 
-template <int MODE>  // 0: loops, 1: unrolled shuffles, 2: two-tap DPP
+// 0: loops, 1: unrolled shuffles, 2: two-tap DPP, 3 / 4: two / four
+// alternating two-tap steps starting with a predict step, 5 / 6: the same
+// starting with an update step
+template <int MODE>
 __global__ __launch_bounds__(kGenericThreads) void lift_generic(
     GenericSteps st, int J, int N, const float2 *__restrict__ rx_all, long long n,
     long long rx_stride, float2 *__restrict__ pyr_all) {
@@ -138,6 +161,14 @@ __global__ __launch_bounds__(kGenericThreads) void lift_generic(
       for (int u = 0; u < U; ++u) {
         if constexpr (MODE == 2)
           run_two_tap(st, e[u], o[u]);
+        else if constexpr (MODE == 3)
+          run_alternating<2, true>(st, e[u], o[u]);
+        else if constexpr (MODE == 4)
+          run_alternating<4, true>(st, e[u], o[u]);
+        else if constexpr (MODE == 5)
+          run_alternating<2, false>(st, e[u], o[u]);
+        else if constexpr (MODE == 6)
+          run_alternating<4, false>(st, e[u], o[u]);
         else
           run_steps<MODE == 1>(st, lane, e[u], o[u]);
       }
@@ -216,6 +247,18 @@ hipError_t launch_generic(const LiftingDesc &d, int J, int N, const void *rx, lo
   for (int s = 0; s < d.n; ++s) {
     small = small && d.len[s] <= kSmallTaps;
     two = two && d.len[s] == 2 && d.lo[s] == (d.kind[s] == kPredict ? 0 : -1);
+  }
+  if (two && (d.n == 2 || d.n == 4)) {
+    bool alt = true;
+    for (int s = 1; s < d.n; ++s) alt = alt && d.kind[s] != d.kind[s - 1];
+    if (alt) {
+      const bool pf = d.kind[0] == kPredict;
+      if (d.n == 2)
+        return pf ? launch_generic_t<3>(g, J, N, rx, n, count, rx_stride, pyr, st)
+                  : launch_generic_t<5>(g, J, N, rx, n, count, rx_stride, pyr, st);
+      return pf ? launch_generic_t<4>(g, J, N, rx, n, count, rx_stride, pyr, st)
+                : launch_generic_t<6>(g, J, N, rx, n, count, rx_stride, pyr, st);
+    }
   }
   if (two) return launch_generic_t<2>(g, J, N, rx, n, count, rx_stride, pyr, st);
   if (small) return launch_generic_t<1>(g, J, N, rx, n, count, rx_stride, pyr, st);

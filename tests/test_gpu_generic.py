@@ -1,8 +1,9 @@
 """Generic lifting (steps from the host factorizer, taken at run time) on
 the GPU against the oracle's convolve-and-downsample analysis with the same
 taps, for the paper's pairs on both sides, the irrational CDF 9/7 member of
-the Case II family, D4 (a factorization with shifts), Haar, and predictors
-of four taps and of six taps (every one of the kernel's instances runs);
+the Case II family, D4 (a factorization with shifts), Haar, a three-step
+pair, and predictors of four taps and of six taps (every one of the
+kernel's instances runs);
 ragged and tiny lengths; the benchmark size on sampled pulses."""
 import math
 
@@ -53,6 +54,14 @@ def pairs():
     p = [0.6, -0.25, 0.1, -0.05, 0.02, 0.01]
     out["wide_predict"] = ({0: 1.0}, {1: 1.0, 0: -p[0], 2: -p[1], -2: -p[2], 4: -p[3], -4: -p[4],
                                       6: -p[5]})
+    # three alternating two-tap steps (predict, update, predict) and a scaling
+    def three_steps(u, _):
+        e, o = u[0::2].copy(), u[1::2].copy()
+        o = o - 0.7 * (e + np.roll(e, -1))
+        e = e + 0.3 * (o + np.roll(o, 1))
+        o = o - 0.2 * (e + np.roll(e, -1))
+        return 1.3 * e, o / 1.3
+    out["three_steps"] = taps_of(three_steps, None)
     # a four-tap predictor reaching two lanes
     q = [0.55, -0.12, 0.07, -0.03]
     out["four_tap_predict"] = ({0: 1.0}, {1: 1.0, 0: -q[0], 2: -q[1], -2: -q[2], 4: -q[3]})

@@ -106,6 +106,10 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
 // A whole-plane item takes every tile of every phase; a chunk item (long
 // pulses) at most kSwapChunkTiles tiles of one phase.
 constexpr int kSwapChunkTiles = 16;
+// Zero-padded weights: 16 entries before, K + kSwapWPad - 16 after the
+// start (the offsets run in groups of four up to K + 17, a column t >= 0
+// reads entry v - t + 16 <= K + 33).
+constexpr int kSwapWPad = 36;
 
 struct SwapGeom {
   int L, tiles_per_phase, ntp, S, K;
@@ -123,7 +127,7 @@ struct SwapGeom {
 
 __host__ __device__ inline size_t swap_lds_bytes_geom(int N, int j, int K, int chunk) {
   const SwapGeom g(N, j, K, chunk);
-  return ((size_t)(chunk ? 1 : (1 << j)) * g.phase_words() + 2 * (size_t)(K + 32)) * 4;
+  return ((size_t)(chunk ? 1 : (1 << j)) * g.phase_words() + 2 * (size_t)(K + kSwapWPad)) * 4;
 }
 
 // One item: phases p_begin .. p_begin + np_ - 1 of plane j, tiles rt0 ..
@@ -135,11 +139,11 @@ __device__ __forceinline__ void swap_item(int j, int N, const SwapGeom &g, int p
   const int P = 1 << j;
   const int L = g.L, S = g.S;
   float *ys = smem;                                               // np_ phases x 16 S complex
-  float2 *wp = reinterpret_cast<float2 *>(ys + np_ * g.phase_words());  // K + 32
+  float2 *wp = reinterpret_cast<float2 *>(ys + np_ * g.phase_words());  // K + kSwapWPad
   const int tid = threadIdx.x, nt = blockDim.x;
 
   // weights: wp[u + 16] = conj(a[lo + u]) for 0 <= u < K, zero around
-  for (int u = tid; u < K + 32; u += nt) {
+  for (int u = tid; u < K + kSwapWPad; u += nt) {
     const int k = u - 16;
     float2 w = make_float2(0.f, 0.f);
     if (k >= 0 && k < K) {
@@ -149,13 +153,15 @@ __device__ __forceinline__ void swap_item(int j, int N, const SwapGeom &g, int p
     wp[u] = w;
   }
   // phases, extended: element e of phase slot q is Y_p[(512 rt0 + e + lo)
-  // mod L], stored as complex64 at sub-sequence e mod 16, index e / 16
-  // (element (e mod 16) * S + e / 16 of the slot), so the 32 rows of a
-  // tile, 16 elements apart, read consecutive elements
+  // mod L]; its re and im go to two planes of 16 S words, each in four
+  // groups of four sub-sequences: e = 16 i + 4 k + t lands at word
+  // 4 S k + 4 i + t, so the four consecutive offsets one row needs are one
+  // aligned 16-byte quad and the 32 rows of a tile read consecutive quads
   const int E = 16 * S, base = 512 * rt0 + lo;
   for (int q = 0; q < np_; ++q) {
     const float2 *src = src0 + (long long)(p_begin + q) * L;
-    float2 *dst = reinterpret_cast<float2 *>(ys + q * g.phase_words());
+    float *dre = ys + q * g.phase_words();
+    float *dim = dre + E;
     for (int e = tid; e < E; e += nt) {
       const int i = pos_mod(base + e, L);
       float2 v;
@@ -163,7 +169,9 @@ __device__ __forceinline__ void swap_item(int j, int N, const SwapGeom &g, int p
         v = i < n ? src[i] : make_float2(0.f, 0.f);
       else
         v = src[i];
-      dst[(e & 15) * S + (e >> 4)] = v;
+      const int w = 4 * S * ((e & 15) >> 2) + 4 * (e >> 4) + (e & 3);
+      dre[w] = v.x;
+      dim[w] = v.y;
     }
   }
   __syncthreads();
@@ -181,21 +189,33 @@ __device__ __forceinline__ void swap_item(int j, int N, const SwapGeom &g, int p
     for (int r = 0; r < kSwapRT; ++r) {
       const int t = min(t0 + r, ntiles - 1);
       const int q = t / ntp, rt = t - q * ntp;
-      abase[r] = q * g.phase_words() + 2 * (rt * 32 + row) + kc;
+      abase[r] = q * g.phase_words() + kc * E + 4 * (rt * 32 + row);
     }
     f32x16 acc[kSwapRT];
 #pragma unroll
     for (int r = 0; r < kSwapRT; ++r)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[r][i] = 0.f;
-    for (int v = 0; v < Kp; ++v) {
-      const float2 w = wp[v - bt + 16];
-      // K index 0 multiplies Re(y), 1 multiplies Im(y):
-      // Re(out) = Re y Re w - Im y Im w ; Im(out) = Re y Im w + Im y Re w
-      const float bv = kc == 0 ? (bc == 0 ? w.x : w.y) : (bc == 0 ? -w.y : w.x);
-      const int off = 2 * ((v & 15) * S + (v >> 4));
+    // offsets in groups of four: one 16-byte A read per tile, four MFMAs;
+    // offsets past K + 14 meet zero weights (wp is zero beyond K)
+    for (int v0 = 0; v0 < Kp; v0 += 4) {
+      const int off = 4 * S * ((v0 & 15) >> 2) + 4 * (v0 >> 4);
+      float4 a[kSwapRT];
 #pragma unroll
-      for (int r = 0; r < kSwapRT; ++r) acc[r] = swap_mfma(ys[abase[r] + off], bv, acc[r]);
+      for (int r = 0; r < kSwapRT; ++r)
+        a[r] = *reinterpret_cast<const float4 *>(ys + abase[r] + off);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float2 w = wp[v0 + t - bt + 16];
+        // K index 0 multiplies Re(y), 1 multiplies Im(y):
+        // Re(out) = Re y Re w - Im y Im w ; Im(out) = Re y Im w + Im y Re w
+        const float bv = kc == 0 ? (bc == 0 ? w.x : w.y) : (bc == 0 ? -w.y : w.x);
+#pragma unroll
+        for (int r = 0; r < kSwapRT; ++r) {
+          const float av = t == 0 ? a[r].x : t == 1 ? a[r].y : t == 2 ? a[r].z : a[r].w;
+          acc[r] = swap_mfma(av, bv, acc[r]);
+        }
+      }
     }
     // register i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32
 #pragma unroll

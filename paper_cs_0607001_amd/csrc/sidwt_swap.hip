@@ -18,11 +18,13 @@
 //    phase p' advanced by b samples.  Register windows with lane-shift taps.
 //  * swap_correlate: one workgroup per (pulse, plane) (pulses too long for
 //    that: swap_correlate_chunks, one per (pulse, plane, phase, group of
-//    tiles)); the phases go to LDS (extended by the weight span so no window wraps, in 16-way
-//    polyphase order) and every phase is a Toeplitz-blocked real GEMM on
-//    v_mfma_f32_32x32x2_f32: row i of a tile holds lags 16 i .. 16 i + 15,
-//    the K axis runs over (offset v, re/im) and the 32 columns over
-//    (lag t within the block, re/im) with B[v][t] = conj(a)[v - t].
+//    tiles)); the phases go to LDS, extended by the weight span so no window
+//    wraps, in 16-way polyphase order as re and im planes grouped in quads
+//    (one 16-byte read gives a row four consecutive offsets), and every
+//    phase is a Toeplitz-blocked real GEMM on v_mfma_f32_32x32x2_f32: row i
+//    of a tile holds lags 16 i .. 16 i + 15, the K axis runs over (offset v,
+//    re/im) and the 32 columns over (lag t within the block, re/im) with
+//    B[v][t] = conj(a)[v - t].
 #include "sidwt_swap.hpp"
 
 namespace sidwt {
@@ -121,7 +123,7 @@ struct SwapGeom {
                 : tiles_per_phase;
     S = (16 * 32 * ntp + K + 15 + 15) / 16;
   }
-  __host__ __device__ int phase_words() const { return 16 * S * 2; }  // floats per phase
+  __host__ __device__ int phase_words() const { return 16 * S * 2; }  // re + im planes
   __host__ __device__ int chunks() const { return (tiles_per_phase + ntp - 1) / ntp; }
 };
 

@@ -94,3 +94,27 @@ def test_lift_then_synthesize_returns_the_pulse(dev, filt):
         for i in range(4):
             want = O.zero_pad(rx[i].astype(np.complex128), N)
             assert rel_l2(back[i], want) <= 1e-5, i
+
+
+def test_synthesis_full_size_round_trips(dev):
+    """At the benchmark sizes and launch configuration: lift_many then
+    synth_many over the whole batch gives every sampled pulse back (FP32
+    within 1e-5; the reversible integer filter bit for bit)."""
+    torch, S = dev
+    import workloads as W
+    print("[case] synthesis round trip 4096 x 8192 cdf97 J=5", flush=True)
+    b = W.batched_uniform(seed=2, count=4096, n=8192, m=512, J=5)
+    rx = torch.from_numpy(b.rx).cuda()
+    back = S.synth_many("cdf97", 5, S.lift_many("cdf97", 5, rx), to=0)
+    torch.cuda.synchronize()
+    for i in (0, 1, 2047, 4095):
+        got = back[i].cpu().numpy().astype(np.complex128)
+        assert rel_l2(got, b.rx[i].astype(np.complex128)) <= 1e-5, i
+    del rx, back
+    print("[case] synthesis round trip 16384 x 4096 integer 5/3 J=6", flush=True)
+    ib = W.integer_batch(seed=3, count=16384, n=4096, m=512, J=6)
+    rxi = torch.from_numpy(ib.rx_iq).cuda()
+    backi = S.synth_many("legall53_int", 6, S.lift_many("legall53_int", 6, rxi), to=0)
+    torch.cuda.synchronize()
+    for i in (0, 8191, 16383):
+        assert np.array_equal(backi[i].cpu().numpy(), ib.rx_iq[i].astype(np.int64)), i

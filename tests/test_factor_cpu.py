@@ -127,3 +127,20 @@ def test_haar_and_refusals(S):
         S.Lifting({0: 1.0, 1: 1.0}, {0: 1.0, 1: 1.0})
     with pytest.raises(S.SidwtError):
         S.Lifting({0: 1.0, 1: 2.0, 2: 1.0}, {0: 1.0, 2: 1.0})
+
+
+def test_lift_generic_arguments_are_checked_on_the_host(S):
+    import ctypes
+    L = S._lib.lib()
+    vp = ctypes.c_void_p
+    with S.Lifting(*O.TAPS["cdf97"][:2]) as f:
+        h = f.handle
+        assert L.sidwt_lift_generic(h, 3, None, 64, 0, 64, None, None) == 0      # nothing to do
+        assert L.sidwt_lift_generic(h, 0, vp(16), 64, 1, 64, vp(16), None) == -1  # J
+        assert L.sidwt_lift_generic(h, 3, vp(16), 64, 1, 63, vp(16), None) == -1  # stride < n
+        assert L.sidwt_lift_generic(h, 6, vp(16), 64, 1, 64, vp(16), None) == -1  # N / 2^J < 2
+        assert L.sidwt_lift_generic(h, 3, None, 64, 1, 64, vp(16), None) == -1    # no input
+        assert L.sidwt_lift_generic(h, 3, vp(16), 1 << 20, 1, 1 << 20, vp(16), None) == -5  # LDS
+    assert L.sidwt_lift_generic(None, 3, vp(16), 64, 1, 64, vp(16), None) == -1
+    assert L.sidwt_lifting_count(None) == -1
+    assert L.sidwt_lifting_step(None, 0, None, None, None, None) == -1

@@ -234,6 +234,15 @@ __device__ __forceinline__ float2 rx_sample(const float2 *rx, int n, int i) {
   const float2 v = rx[i < n ? i : n - 1];
   return (i < n) ? v : make_float2(0.f, 0.f);
 }
+// A pulse reached through a batch descriptor: the compiler cannot tell its
+// address space and would issue flat loads; these read it as global memory.
+typedef float f32x2_global __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 rx_sample_global(const float2 *rx, int n, int i) {
+  const __attribute__((address_space(1))) f32x2_global *g =
+      (const __attribute__((address_space(1))) f32x2_global *)rx;
+  const f32x2_global v = g[i < n ? i : n - 1];
+  return (i < n) ? make_float2(v.x, v.y) : make_float2(0.f, 0.f);
+}
 __device__ __forceinline__ int2 rx_sample(const short2 *rx, int n, int i) {
   const short2 s = rx[i < n ? i : n - 1];
   return (i < n) ? make_int2(s.x, s.y) : make_int2(0, 0);
@@ -760,8 +769,8 @@ __device__ void lift_chunk(const BatchPulse &p, float2 *scratch, int l, int k0, 
     lift_level_range<F, 2>(
         np, k0, k1,
         [&](int kc, float2 &e, float2 &o) {
-          e = rx_sample(rx, n, 2 * kc);
-          o = rx_sample(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
+          e = rx_sample_global(rx, n, 2 * kc);
+          o = rx_sample_global(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
         },
         [&](int k, float2 cv, float2 dv) {
           c[k] = cv;

@@ -85,7 +85,7 @@ enum {
                            size beyond the library's limits               */
   SIDWT_E_NOMEM = -3,   /* device allocation failed                       */
   SIDWT_E_DEVICE = -4,  /* a HIP runtime error (including earlier faults) */
-  SIDWT_E_UNSUPPORTED = -5 /* valid request this build does not handle    */
+  SIDWT_E_UNSUPPORTED = -5 /* valid request the library does not handle  */
 };
 
 #define SIDWT_MAX_LEVELS 16

@@ -98,7 +98,7 @@ const char *sidwt_strerror(int code) {
     case SIDWT_E_SIZE: return "size out of range for this plan";
     case SIDWT_E_NOMEM: return "device allocation failed";
     case SIDWT_E_DEVICE: return "HIP runtime error";
-    case SIDWT_E_UNSUPPORTED: return "request not supported by this build";
+    case SIDWT_E_UNSUPPORTED: return "request not supported by the library";
     default: return "unknown error";
   }
 }

@@ -100,9 +100,12 @@ enum {
  * set only on success.
  * Integer plans (int16 I/Q reference) are exact for every int16 pulse: the
  * plan is refused with SIDWT_E_SIZE, before any device work, when a bound
- * on the partial sums of some level (full-scale pulse, this reference's
- * peak, growth 2 per level for details and 3/2 for approximations) reaches
- * 2^53, the limit of exact integers in the FP64 accumulation. */
+ * on the partial sums of some level reaches 2^53, the limit of exact
+ * integers in the FP64 accumulation.  The bound takes a full-scale pulse,
+ * whose approximation bound doubles per level (the y-side lowpass
+ * (1/2, 1, 1/2) has l1 norm 2), and this reference's peak, whose
+ * approximation bound grows by 3/2 per level (x-side lowpass l1 norm 3/2);
+ * details stay within 2X + 1 of their level's input bound X. */
 int sidwt_plan_create(int filter, int J, const void *ref, int64_t m,
                       sidwt_plan **out);
 

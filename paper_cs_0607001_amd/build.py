@@ -32,17 +32,27 @@ def flags():
     ]
 
 
-def build(verbose: bool = False) -> str:
-    objs = []
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     os.makedirs(os.path.join(PKG, "_build"), exist_ok=True)
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(PKG, "_build", src + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [hipcc()] + flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([hipcc()] + flags() + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    jobs = jobs or max(1, min(len(cmds), len(os.sched_getaffinity(0)), 8))
+    with ThreadPoolExecutor(jobs) as pool:
+        for r in pool.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds):
+            err = "\n".join(l for l in r.stderr.splitlines()
+                            if "packed-fp32-ops" not in l)
+            if err.strip():
+                print(err, file=sys.stderr, flush=True)
+            if r.returncode != 0:
+                raise subprocess.CalledProcessError(r.returncode, r.args)
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:

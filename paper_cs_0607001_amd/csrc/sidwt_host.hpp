@@ -66,23 +66,44 @@ inline long long plan_windows(int filter, int J, int m, PlanDesc *d) {
 }
 
 // Integer plans accumulate integer products in FP64, which is exact while
-// every partial sum stays below 2^53 in magnitude.  One level of the
-// reversible 5/3 lifting with inputs bounded by X gives |d| <= 2X + 1 (the
-// highpass has l1 norm 2) and |c| <= 1.5X + 2 (lowpass l1 norm 3/2, plus
-// the floors).  An output of level l sums, over both bands' taps, complex
-// products of two such bounded values (two real products per component),
-// so its partial sums are bounded by
+// every partial sum stays below 2^53 in magnitude.  Per level, with the
+// level l-1 approximations bounded by X:
+//   pulse (y-side, update first): c = e + ((o[k-1] + o[k] + 1) >> 1) is the
+//     lowpass (1/2, 1, 1/2) of l1 norm 2, so |c| <= 2X (the floor keeps the
+//     rounded half-sum within X); d = o - ((c[k] + c[k+1] + 2) >> 2) gives
+//     |d| <= X + X = 2X.  Both bands stay within 2X + 1, and the pulse
+//     bound doubles every level (a full-scale DC pulse reaches it).
+//   reference (x-side, predict first): d = o - ((e[k] + e[k+1]) >> 1),
+//     highpass (-1/2, 1, -1/2) of l1 norm 2, |d| <= 2X + 1;
+//     c = e + ((d[k-1] + d[k] + 2) >> 2) is the lowpass
+//     (-1/8, 1/4, 3/4, 1/4, -1/8) of l1 norm 3/2 plus at most one unit of
+//     rounding, |c| <= 1.5X + 2.
+// An output of level l sums, over both bands' stored supports, complex
+// products of such values (two real products per component), so each
+// partial sum is bounded by
 //   (2 Xp + 1)(2 Xr + 1) * 2 (len_0 + len_1),
-// Xp, Xr the bounds of level l - 1 for the pulse (any int16: 32768) and the
-// reference (its own peak component).
-inline bool int_sums_exact(const PlanDesc &d, int ref_peak) {
-  double xp = 32768.0, xr = ref_peak;
+// Xp, Xr the level l-1 approximation bounds of the pulse (any int16: 32768
+// at level 0) and of the reference (its own peak component).
+// int_level_bounds writes Xp, Xr of levels 0..J (arrays of J + 1).
+inline void int_level_bounds(const PlanDesc &d, int ref_peak, double *xp, double *xr) {
+  xp[0] = 32768.0;
+  xr[0] = ref_peak;
   for (int l = 1; l <= d.J; ++l) {
-    const double terms = 2.0 * ((double)d.lv[l].len[0] + d.lv[l].len[1]);
-    if ((2 * xp + 1) * (2 * xr + 1) * terms >= 9007199254740992.0) return false;
-    xp = 1.5 * xp + 2;
-    xr = 1.5 * xr + 2;
+    xp[l] = 2.0 * xp[l - 1] + 1.0;
+    xr[l] = 1.5 * xr[l - 1] + 2.0;
   }
+}
+
+inline double int_level_sum_bound(const PlanDesc &d, int l, const double *xp, const double *xr) {
+  const double terms = 2.0 * ((double)d.lv[l].len[0] + d.lv[l].len[1]);
+  return (2.0 * xp[l - 1] + 1.0) * (2.0 * xr[l - 1] + 1.0) * terms;
+}
+
+inline bool int_sums_exact(const PlanDesc &d, int ref_peak) {
+  double xp[kMaxLevels + 1], xr[kMaxLevels + 1];
+  int_level_bounds(d, ref_peak, xp, xr);
+  for (int l = 1; l <= d.J; ++l)
+    if (int_level_sum_bound(d, l, xp, xr) >= 9007199254740992.0) return false;
   return true;
 }
 

@@ -81,9 +81,10 @@ def test_zero_pulses_is_a_no_op(L):
 
 def test_integer_plans_that_could_lose_exactness_are_refused(L):
     """A full-scale int16 reference at J = 16: the level-16 bound on the
-    partial sums (growth 2 per level for details, 3/2 for approximations)
-    passes 2^53, so the plan is refused on the host; a small reference peak
-    keeps the same plan under it."""
+    partial sums (pulse approximations doubling per level, reference
+    approximations growing by 3/2, details within 2X + 1 of their input
+    bound) passes 2^53, so the plan is refused on the host; a small
+    reference peak keeps the same plan under it."""
     vp = ctypes.c_void_p
     m = 64
     loud = (ctypes.c_int16 * (2 * m))(*([32767, -32768] * m))

@@ -31,13 +31,19 @@
  *   - Device pointers are plain HIP device addresses (for instance a
  *     PyTorch tensor's data_ptr()); the caller owns them.  Host pointers are
  *     read during the call only.
- *   - Work is enqueued asynchronously on the plan's stream (default: the
- *     null stream) and the call returns; results are ready when the stream
- *     is synchronised.  Faults of earlier device work surface as
- *     SIDWT_E_DEVICE.
- *   - A plan is immutable after creation: concurrent calls with one plan on
- *     different streams are safe.  sidwt_set_stream is the one mutator and
- *     must not race with calls on the same plan.
+ *   - Work is enqueued asynchronously on a stream and the call returns;
+ *     results are ready when the stream is synchronised.  Faults of earlier
+ *     device work surface as SIDWT_E_DEVICE.  The entry points ending in
+ *     _on take the stream as their last argument (a hipStream_t; NULL = the
+ *     null stream); the older plan-stream forms (sidwt_correlate,
+ *     sidwt_correlate_many, sidwt_correlate_planes, sidwt_correlate_swapped)
+ *     use the stream stored in the plan by sidwt_set_stream.
+ *   - Concurrency: the _on entry points read the plan and never modify it,
+ *     so any number of them may run at once with one plan on different
+ *     streams (from different host threads too).  sidwt_set_stream modifies
+ *     the plan, and the plan-stream forms keep the tiled path's buffers in
+ *     the plan (see sidwt_correlate): calls of those forms on one plan must
+ *     not overlap each other or sidwt_set_stream.
  *
  * Data types:
  *   - Float filters (SIDWT_LEGALL53, SIDWT_CDF97, SIDWT_D4_CAUSAL): the
@@ -132,6 +138,13 @@ int sidwt_set_stream(sidwt_plan *p, void *hip_stream);
  * case. */
 int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out);
 
+/* sidwt_correlate on `hip_stream`, leaving the plan untouched: safe to call
+ * concurrently with one plan from several streams and threads.  A pulse
+ * that needs the tiled path gets its own temporary buffers (allocated,
+ * used, the stream synchronised, freed) instead of the plan's. */
+int sidwt_correlate_on(const sidwt_plan *p, const void *rx, int64_t n, void *out,
+                       void *hip_stream);
+
 /* A uniform batch in one launch: `count` pulses of n samples each, pulse i
  * at rx + i * rx_stride samples; its planes at out + i * out_stride
  * elements (elements are complex64 or int64 pairs).  rx_stride >= n and
@@ -150,6 +163,15 @@ int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n,
 int sidwt_correlate_planes(const sidwt_plan *p, const void *rx, int64_t n,
                            int64_t count, int64_t rx_stride, void *out,
                            int64_t out_stride, unsigned plane_mask);
+
+/* sidwt_correlate_planes on `hip_stream` (plane_mask ~0u: every plane, the
+ * work of sidwt_correlate_many), leaving the plan untouched as
+ * sidwt_correlate_on does (pulses on the tiled path: temporary buffers and
+ * a synchronised stream). */
+int sidwt_correlate_many_on(const sidwt_plan *p, const void *rx, int64_t n,
+                            int64_t count, int64_t rx_stride, void *out,
+                            int64_t out_stride, unsigned plane_mask,
+                            void *hip_stream);
 
 /* Lifting only (a1 + a2 of the path, for bandwidth measurement and for
  * callers that correlate elsewhere): `count` pulses of n samples, pulse i
@@ -202,6 +224,12 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n,
                             int64_t count, int64_t rx_stride, void *out,
                             int64_t out_stride, void *workspace,
                             int64_t workspace_bytes);
+/* The same on `hip_stream`, leaving the plan untouched (calls in flight at
+ * once need their own workspaces). */
+int sidwt_correlate_swapped_on(const sidwt_plan *p, const void *rx, int64_t n,
+                               int64_t count, int64_t rx_stride, void *out,
+                               int64_t out_stride, void *workspace,
+                               int64_t workspace_bytes, void *hip_stream);
 
 /* Target declaration (Sec. V-A, Fig. 6: targets read off |R| in dB at each
  * scale as peaks above a level).  planes: device complex64, pulse i's plane

@@ -125,6 +125,50 @@ def _check_rx(plan: Plan, rx):
         raise ValueError("rx must be contiguous")
 
 
+def _check_buf(t, dtype, numel: int, what: str, device=None):
+    """A caller-supplied device buffer: a contiguous device tensor of `dtype`
+    holding at least `numel` elements (on `device` when given), else
+    ValueError before anything is launched."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{what} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, needs {numel}")
+    return t
+
+
+def _check_pulses(rx, dtype, what="rx"):
+    """A (count, n[, 2]) batch of pulses: contiguous device tensor of dtype."""
+    torch = _torch()
+    if not isinstance(rx, torch.Tensor) or not rx.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if rx.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {rx.dtype}")
+    if not rx.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if rx.dim() < 2 or rx.shape[0] < 0 or rx.shape[1] < 1:
+        raise ValueError(f"{what} must be shaped (count, n, ...)")
+
+
+def _out_numel(plan: Plan, count: int, N: int) -> int:
+    """Elements of torch's view of the output: complex64, or int64 with the
+    (re, im) pair as the last axis."""
+    return count * plan.J * N * (2 if plan.is_int else 1)
+
+
+def _out_dtype(plan: Plan):
+    torch = _torch()
+    return torch.int64 if plan.is_int else torch.complex64
+
+
 def _out_like(plan: Plan, lead, N, device):
     torch = _torch()
     if plan.is_int:
@@ -136,13 +180,16 @@ def correlate(plan: Plan, rx, out=None, stream=None):
     """One pulse.  rx: complex64 (n,) or int16 (n, 2); returns (J, N) complex64
     or (J, N, 2) int64."""
     _check_rx(plan, rx)
+    if rx.dim() != (2 if plan.is_int else 1):
+        raise ValueError("rx must be shaped (n,) (complex64) or (n, 2) (int16)")
     n = rx.shape[0]
     N = transform_length(n, plan.J)
     if out is None:
         out = _out_like(plan, (), N, rx.device)
-    check(lib().sidwt_set_stream(plan.handle, _stream_ptr(stream)), "sidwt_set_stream")
-    check(lib().sidwt_correlate(plan.handle, ctypes.c_void_p(rx.data_ptr()), n,
-                                ctypes.c_void_p(out.data_ptr())), "sidwt_correlate")
+    _check_buf(out, _out_dtype(plan), _out_numel(plan, 1, N), "out", rx.device)
+    check(lib().sidwt_correlate_on(plan.handle, ctypes.c_void_p(rx.data_ptr()), n,
+                                   ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+          "sidwt_correlate_on")
     return out
 
 
@@ -152,24 +199,23 @@ def correlate_many(plan: Plan, rx, out=None, stream=None, planes=None):
     iterable of plane indices to compute (the others of out are left as they
     are); None computes all."""
     _check_rx(plan, rx)
+    if rx.dim() != (3 if plan.is_int else 2):
+        raise ValueError("rx must be shaped (count, n) (complex64) or (count, n, 2) (int16)")
     count, n = rx.shape[0], rx.shape[1]
     N = transform_length(n, plan.J)
     if out is None:
         out = _out_like(plan, (count,), N, rx.device)
-    check(lib().sidwt_set_stream(plan.handle, _stream_ptr(stream)), "sidwt_set_stream")
-    if planes is None:
-        check(lib().sidwt_correlate_many(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count, n,
-                                         ctypes.c_void_p(out.data_ptr()), plan.J * N),
-              "sidwt_correlate_many")
-    else:
+    _check_buf(out, _out_dtype(plan), _out_numel(plan, count, N), "out", rx.device)
+    mask = 0xFFFFFFFF
+    if planes is not None:
         mask = 0
         for j in planes:
             if not 0 <= int(j) < plan.J:
                 raise ValueError(f"plane {j} outside 0..{plan.J - 1}")
             mask |= 1 << int(j)
-        check(lib().sidwt_correlate_planes(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count,
-                                           n, ctypes.c_void_p(out.data_ptr()), plan.J * N, mask),
-              "sidwt_correlate_planes")
+    check(lib().sidwt_correlate_many_on(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count, n,
+                                        ctypes.c_void_p(out.data_ptr()), plan.J * N, mask,
+                                        _stream_ptr(stream)), "sidwt_correlate_many_on")
     return out
 
 
@@ -181,21 +227,26 @@ def correlate_swapped(plan: Plan, rx, out=None, workspace=None, stream=None):
     buffer of at least sidwt_swap_workspace_bytes (allocated if None)."""
     _check_rx(plan, rx)
     torch = _torch()
+    if rx.dim() != 2:
+        raise ValueError("rx must be shaped (count, n)")
     count, n = rx.shape[0], rx.shape[1]
     N = transform_length(n, plan.J)
     if out is None:
         out = _out_like(plan, (count,), N, rx.device)
+    _check_buf(out, _out_dtype(plan), _out_numel(plan, count, N), "out", rx.device)
     need = lib().sidwt_swap_workspace_bytes(plan.handle, n, count)
     if need < 0:
         raise SidwtError(-1, "sidwt_swap_workspace_bytes")
     if workspace is None:
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=rx.device)
-    check(lib().sidwt_set_stream(plan.handle, _stream_ptr(stream)), "sidwt_set_stream")
-    check(lib().sidwt_correlate_swapped(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count, n,
-                                        ctypes.c_void_p(out.data_ptr()), plan.J * N,
-                                        ctypes.c_void_p(workspace.data_ptr()),
-                                        workspace.numel() * workspace.element_size()),
-          "sidwt_correlate_swapped")
+    if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda or \
+            not workspace.is_contiguous() or workspace.device != rx.device:
+        raise ValueError("workspace must be a contiguous device tensor on the pulses' device")
+    check(lib().sidwt_correlate_swapped_on(plan.handle, ctypes.c_void_p(rx.data_ptr()), n, count,
+                                           n, ctypes.c_void_p(out.data_ptr()), plan.J * N,
+                                           ctypes.c_void_p(workspace.data_ptr()),
+                                           workspace.numel() * workspace.element_size(),
+                                           _stream_ptr(stream)), "sidwt_correlate_swapped_on")
     return out
 
 
@@ -282,10 +333,12 @@ def lift_generic(lifting: Lifting, J: int, rx, pyr=None, stream=None):
     """Critical lifting of complex64 pulses (count, n) with a factorized pair;
     returns (count, N): d_1 | ... | d_J | c_J, as lift_many."""
     torch = _torch()
+    _check_pulses(rx, torch.complex64)
     count, n = rx.shape[0], rx.shape[1]
     N = transform_length(n, J)
     if pyr is None:
         pyr = torch.empty((count, N), dtype=torch.complex64, device=rx.device)
+    _check_buf(pyr, torch.complex64, count * N, "pyr", rx.device)
     check(lib().sidwt_lift_generic(lifting.handle, J, ctypes.c_void_p(rx.data_ptr()), n, count, n,
                                    ctypes.c_void_p(pyr.data_ptr()), _stream_ptr(stream)),
           "sidwt_lift_generic")
@@ -296,13 +349,23 @@ def lift_many(filt: str, J: int, rx, pyr=None, stream=None):
     """Critical y-side lifting only.  Returns (count, N): d_1 | ... | d_J | c_J
     (complex64, or int32 pairs (count, N, 2) for the integer filter)."""
     torch = _torch()
+    if filt not in FILTERS:
+        raise ValueError(f"unknown filter {filt}")
+    is_int = filt == "legall53_int"
+    _check_pulses(rx, torch.int16 if is_int else torch.complex64)
+    if is_int and (rx.dim() != 3 or rx.shape[2] != 2):
+        raise ValueError("the integer filter takes int16 (count, n, 2) I/Q pulses")
     count, n = rx.shape[0], rx.shape[1]
     N = transform_length(n, J)
     if pyr is None:
-        if filt == "legall53_int":
+        if is_int:
             pyr = torch.empty((count, N, 2), dtype=torch.int32, device=rx.device)
         else:
             pyr = torch.empty((count, N), dtype=torch.complex64, device=rx.device)
+    if is_int:
+        _check_buf(pyr, torch.int32, count * N * 2, "pyr", rx.device)
+    else:
+        _check_buf(pyr, torch.complex64, count * N, "pyr", rx.device)
     check(lib().sidwt_lift_many(FILTERS[filt], J, ctypes.c_void_p(rx.data_ptr()), n, count, n,
                                 ctypes.c_void_p(pyr.data_ptr()), _stream_ptr(stream)),
           "sidwt_lift_many")
@@ -314,12 +377,19 @@ def synth_many(filt: str, J: int, pyr, to: int = 0, out=None, stream=None):
     ((count, N) complex64, or (count, N, 2) int32 for the integer filter),
     the approximations c_to, (count, N >> to) (c_0 = the zero-padded pulses)."""
     torch = _torch()
-    if not pyr.is_cuda or not pyr.is_contiguous():
-        raise ValueError("pyr must be a contiguous device tensor")
+    if filt not in FILTERS:
+        raise ValueError(f"unknown filter {filt}")
+    is_int = filt == "legall53_int"
+    _check_pulses(pyr, torch.int32 if is_int else torch.complex64, "pyr")
+    if is_int and (pyr.dim() != 3 or pyr.shape[2] != 2):
+        raise ValueError("the integer filter's pyramids are int32 (count, N, 2)")
     count, N = pyr.shape[0], pyr.shape[1]
+    if not 0 <= to < J:
+        raise ValueError(f"to = {to} outside 0..{J - 1}")
     if out is None:
-        shape = (count, N >> to, 2) if filt == "legall53_int" else (count, N >> to)
+        shape = (count, N >> to, 2) if is_int else (count, N >> to)
         out = torch.empty(shape, dtype=pyr.dtype, device=pyr.device)
+    _check_buf(out, pyr.dtype, count * (N >> to) * (2 if is_int else 1), "out", pyr.device)
     check(lib().sidwt_synth_many(FILTERS[filt], J, to, ctypes.c_void_p(pyr.data_ptr()), N, count,
                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
           "sidwt_synth_many")
@@ -391,12 +461,12 @@ class Batch:
         return self._h
 
     def _arrays(self, rx, out):
+        torch = _torch()
         if len(rx) != len(self.ns) or len(out) != len(self.ns):
             raise ValueError("one input and one output per pulse")
-        for x, n in zip(rx, self.ns):
-            if not x.is_cuda or x.dtype != _torch().complex64 or x.numel() < n or \
-                    not x.is_contiguous():
-                raise ValueError("pulses must be contiguous complex64 device tensors")
+        for i, (x, o, p, n) in enumerate(zip(rx, out, self.plans, self.ns)):
+            _check_buf(x, torch.complex64, n, f"rx[{i}]")
+            _check_buf(o, torch.complex64, p.J * transform_length(n, p.J), f"out[{i}]", x.device)
         return _ptr_array([x.data_ptr() for x in rx]), _ptr_array([o.data_ptr() for o in out])
 
     def run(self, rx, out, stream=None):
@@ -437,9 +507,16 @@ class Batch:
 
 def correlate_batch(plans, rx, out=None, stream=None):
     """One-shot uneven batch (synchronises the stream before returning)."""
+    torch = _torch()
+    if len(plans) != len(rx) or (out is not None and len(out) != len(rx)):
+        raise ValueError("one plan, input and output per pulse")
+    for i, x in enumerate(rx):
+        _check_buf(x, torch.complex64, 1, f"rx[{i}]")
     ns = [int(x.numel()) for x in rx]
     if out is None:
         out = batch_outputs(plans, ns, rx[0].device)
+    for i, (o, p, n) in enumerate(zip(out, plans, ns)):
+        _check_buf(o, torch.complex64, p.J * transform_length(n, p.J), f"out[{i}]", rx[i].device)
     plan_arr = _ptr_array([p.handle.value for p in plans])
     n_arr = (ctypes.c_int64 * len(ns))(*ns)
     check(lib().sidwt_correlate_batch(plan_arr, _ptr_array([x.data_ptr() for x in rx]), n_arr,
@@ -506,17 +583,25 @@ class Bank:
         """rx: list of complex64 device pulses; J: list of scale counts.
         Returns a list of (E_i, J_i, N_i) complex64 tensors."""
         torch = _torch()
+        if len(J) != len(rx) or (out is not None and len(out) != len(rx)):
+            raise ValueError("one scale count and one output per request")
+        for i, x in enumerate(rx):
+            _check_buf(x, torch.complex64, 1, f"rx[{i}]")
         ns = [int(x.numel()) for x in rx]
         if out is None:
             out = [torch.empty(self.out_shape(n, j), dtype=torch.complex64, device=x.device)
                    for x, n, j in zip(rx, ns, J)]
-        for x in rx:
-            if not x.is_cuda or x.dtype != torch.complex64 or not x.is_contiguous():
-                raise ValueError("pulses must be contiguous complex64 device tensors")
+        for i, (o, x, n, j) in enumerate(zip(out, rx, ns, J)):
+            need = lib().sidwt_bank_out_len(self.handle, n, int(j))
+            if need < 0:
+                raise ValueError(f"request {i}: n = {n}, J = {j} out of range for this bank")
+            if o is None and need == 0:
+                continue
+            _check_buf(o, torch.complex64, need, f"out[{i}]", x.device)
         n_arr = (ctypes.c_int64 * len(ns))(*ns)
         j_arr = (ctypes.c_int32 * len(ns))(*[int(j) for j in J])
         rx_p = _ptr_array([x.data_ptr() for x in rx])
-        out_p = _ptr_array([o.data_ptr() for o in out])
+        out_p = _ptr_array([None if o is None else o.data_ptr() for o in out])
         if workspace is None:
             check(lib().sidwt_bank_correlate(self.handle, rx_p, n_arr, j_arr, out_p, len(ns),
                                              _stream_ptr(stream)), "sidwt_bank_correlate")

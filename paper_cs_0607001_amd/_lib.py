@@ -46,6 +46,10 @@ def _declare(L):
     L.sidwt_correlate.restype = i32
     L.sidwt_correlate_many.argtypes = [vp, vp, i64, i64, i64, vp, i64]
     L.sidwt_correlate_many.restype = i32
+    L.sidwt_correlate_on.argtypes = [vp, vp, i64, vp, vp]
+    L.sidwt_correlate_on.restype = i32
+    L.sidwt_correlate_many_on.argtypes = [vp, vp, i64, i64, i64, vp, i64, c.c_uint, vp]
+    L.sidwt_correlate_many_on.restype = i32
     L.sidwt_lift_many.argtypes = [i32, i32, vp, i64, i64, i64, vp, vp]
     L.sidwt_lift_many.restype = i32
     L.sidwt_correlate_planes.argtypes = [vp, vp, i64, i64, i64, vp, i64, c.c_uint]
@@ -56,6 +60,8 @@ def _declare(L):
     L.sidwt_swap_workspace_bytes.restype = i64
     L.sidwt_correlate_swapped.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp, i64]
     L.sidwt_correlate_swapped.restype = i32
+    L.sidwt_correlate_swapped_on.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp, i64, vp]
+    L.sidwt_correlate_swapped_on.restype = i32
     L.sidwt_detect_peaks.argtypes = [vp, i64, i32, i64, i64, c.c_float, i32, vp, vp, vp, vp]
     L.sidwt_detect_peaks.restype = i32
     dp = c.POINTER(c.c_double)

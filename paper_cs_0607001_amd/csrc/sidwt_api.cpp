@@ -208,10 +208,15 @@ int sidwt_set_stream(sidwt_plan *p, void *hip_stream) {
   return SIDWT_OK;
 }
 
-// Uniform batch, the planes of `planes` (bit j: plane j) only.
+// Uniform batch, the planes of `planes` (bit j: plane j) only, on stream
+// `st`.  Pulses too long for one workgroup's LDS take the tiled path: with
+// `cache` the plan keeps that path's batch for the last (n, count) (the
+// plan-stream entry points), else a one-shot batch is built, run, the
+// stream synchronised and the batch freed (the per-call-stream entry
+// points, which leave the plan untouched).
 static int correlate_many_planes(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
                                  int64_t rx_stride, void *out, int64_t out_stride,
-                                 unsigned planes) {
+                                 unsigned planes, hipStream_t st, bool cache) {
   if (!p || count < 0 || count > 0x7fffffff) return SIDWT_E_INVAL;
   const unsigned all = (1u << p->J) - 1u;
   planes &= all;
@@ -225,43 +230,61 @@ static int correlate_many_planes(const sidwt_plan *p, const void *rx, int64_t n,
   FusedLayout lay;
   if (make_layout(p->desc, N, &lay) == 0)
     return map_err(sidwt::launch_fused(p->desc, lay, rx, n, count, rx_stride, out, out_stride,
-                                       planes, p->stream));
+                                       planes, st));
   // Too long for one workgroup's LDS: levels lifted into an HBM scratch
   // pyramid, then lag tiles (the uneven-batch machinery, one plan).
   if (p->filter == SIDWT_LEGALL53_INT || planes != all) return SIDWT_E_UNSUPPORTED;
-  if (!p->tiled || p->tiled_n != n || p->tiled_count != count) {
-    sidwt_batch_free(p->tiled);
-    p->tiled = nullptr;
-    std::vector<const sidwt_plan *> ps((size_t)count, p);
-    std::vector<int64_t> ns((size_t)count, n);
-    rc = sidwt_batch_create(ps.data(), ns.data(), (int)count, &p->tiled);
-    if (rc) return rc;
-    p->tiled_n = n;
-    p->tiled_count = count;
-  }
   std::vector<const void *> rxp((size_t)count);
   std::vector<void *> outp((size_t)count);
   for (int64_t i = 0; i < count; ++i) {
     rxp[i] = static_cast<const char *>(rx) + i * rx_stride * 8;
     outp[i] = static_cast<char *>(out) + i * out_stride * 8;
   }
-  return sidwt_batch_run(p->tiled, rxp.data(), outp.data(), p->stream);
+  std::vector<const sidwt_plan *> ps((size_t)count, p);
+  std::vector<int64_t> ns((size_t)count, n);
+  if (!cache)
+    return sidwt_correlate_batch(ps.data(), rxp.data(), ns.data(), outp.data(), (int)count, st);
+  if (!p->tiled || p->tiled_n != n || p->tiled_count != count) {
+    sidwt_batch_free(p->tiled);
+    p->tiled = nullptr;
+    rc = sidwt_batch_create(ps.data(), ns.data(), (int)count, &p->tiled);
+    if (rc) return rc;
+    p->tiled_n = n;
+    p->tiled_count = count;
+  }
+  return sidwt_batch_run(p->tiled, rxp.data(), outp.data(), st);
 }
 
 int sidwt_correlate_many(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
                          int64_t rx_stride, void *out, int64_t out_stride) {
-  return correlate_many_planes(p, rx, n, count, rx_stride, out, out_stride, ~0u);
+  if (!p) return SIDWT_E_INVAL;
+  return correlate_many_planes(p, rx, n, count, rx_stride, out, out_stride, ~0u, p->stream, true);
 }
 
 int sidwt_correlate_planes(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
                            int64_t rx_stride, void *out, int64_t out_stride,
                            unsigned plane_mask) {
-  return correlate_many_planes(p, rx, n, count, rx_stride, out, out_stride, plane_mask);
+  if (!p) return SIDWT_E_INVAL;
+  return correlate_many_planes(p, rx, n, count, rx_stride, out, out_stride, plane_mask,
+                               p->stream, true);
 }
 
 int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out) {
   if (!p) return SIDWT_E_INVAL;
   return sidwt_correlate_many(p, rx, n, 1, n, out, sidwt_out_len(p, n));
+}
+
+int sidwt_correlate_many_on(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                            int64_t rx_stride, void *out, int64_t out_stride,
+                            unsigned plane_mask, void *hip_stream) {
+  return correlate_many_planes(p, rx, n, count, rx_stride, out, out_stride, plane_mask,
+                               static_cast<hipStream_t>(hip_stream), false);
+}
+
+int sidwt_correlate_on(const sidwt_plan *p, const void *rx, int64_t n, void *out,
+                       void *hip_stream) {
+  if (!p) return SIDWT_E_INVAL;
+  return sidwt_correlate_many_on(p, rx, n, 1, n, out, sidwt_out_len(p, n), ~0u, hip_stream);
 }
 
 namespace {
@@ -282,9 +305,9 @@ int64_t sidwt_swap_workspace_bytes(const sidwt_plan *p, int64_t n, int64_t count
   return swap_ws_bytes(p->J, transform_length(n, p->J), count);
 }
 
-int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
-                            int64_t rx_stride, void *out, int64_t out_stride, void *workspace,
-                            int64_t workspace_bytes) {
+static int correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                             int64_t rx_stride, void *out, int64_t out_stride, void *workspace,
+                             int64_t workspace_bytes, hipStream_t st) {
   if (!p || count < 0 || (int64_t)count * p->J > 0x7fffffff) return SIDWT_E_INVAL;
   if (p->filter == SIDWT_LEGALL53_INT || !p->ref_dev) return SIDWT_E_UNSUPPORTED;
   // the deepest tree level launches one workgroup per (pulse, phase)
@@ -319,7 +342,22 @@ int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int6
   if (!rx || !out || (p->J > 1 && !workspace)) return SIDWT_E_INVAL;
   if (workspace_bytes < swap_ws_bytes(p->J, N, count)) return SIDWT_E_INVAL;
   return map_err(sidwt::launch_swap(p->filter, p->J, (int)N, rx, n, count, rx_stride, workspace,
-                                    wd, lds, chunked, out, out_stride, p->stream));
+                                    wd, lds, chunked, out, out_stride, st));
+}
+
+int sidwt_correlate_swapped(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                            int64_t rx_stride, void *out, int64_t out_stride, void *workspace,
+                            int64_t workspace_bytes) {
+  if (!p) return SIDWT_E_INVAL;
+  return correlate_swapped(p, rx, n, count, rx_stride, out, out_stride, workspace,
+                           workspace_bytes, p->stream);
+}
+
+int sidwt_correlate_swapped_on(const sidwt_plan *p, const void *rx, int64_t n, int64_t count,
+                               int64_t rx_stride, void *out, int64_t out_stride, void *workspace,
+                               int64_t workspace_bytes, void *hip_stream) {
+  return correlate_swapped(p, rx, n, count, rx_stride, out, out_stride, workspace,
+                           workspace_bytes, static_cast<hipStream_t>(hip_stream));
 }
 
 int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N, int64_t pulse_stride,

@@ -125,6 +125,14 @@ def test_swapped_entry_points_reject_a_null_plan(L):
     vp = ctypes.c_void_p
     assert L.sidwt_swap_workspace_bytes(None, 64, 1) == -1
     assert L.sidwt_correlate_swapped(None, vp(16), 64, 1, 64, vp(16), 192, vp(16), 1 << 20) == -1
+    assert L.sidwt_correlate_swapped_on(None, vp(16), 64, 1, 64, vp(16), 192, vp(16), 1 << 20,
+                                        None) == -1
+
+
+def test_stream_per_call_entry_points_reject_a_null_plan(L):
+    vp = ctypes.c_void_p
+    assert L.sidwt_correlate_on(None, vp(16), 64, vp(16), None) == -1
+    assert L.sidwt_correlate_many_on(None, vp(16), 64, 1, 64, vp(16), 192, 0xFFFFFFFF, None) == -1
 
 
 def test_detect_arguments_are_checked_on_the_host(L):

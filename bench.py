@@ -41,8 +41,8 @@ def _oracle_pulse(args):
     filt, J, ref, rx = args
     import oracle
     t0 = time.perf_counter()
-    oracle.correlate_direct(filt, J, ref, rx)
-    return time.perf_counter() - t0
+    R = oracle.correlate_direct(filt, J, ref, rx)
+    return time.perf_counter() - t0, R
 
 
 def _warm(_):
@@ -51,23 +51,18 @@ def _warm(_):
 
 
 def cpu_baseline(filt, J, ref, pulses, max_workers=32):
-    import multiprocessing as mp
-    os.environ["OMP_NUM_THREADS"] = "1"
-    os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    os.environ["MKL_NUM_THREADS"] = "1"
-    cores = len(os.sched_getaffinity(0))
-    workers = max(1, min(cores, max_workers, len(pulses)))
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        pool.map(_warm, range(workers))
-        t0 = time.perf_counter()
-        pool.map(_oracle_pulse, [(filt, J, ref, p) for p in pulses[:workers]])
-        wall = time.perf_counter() - t0
+    """The oracle on whole pulses, one per worker process; returns the
+    baseline record and the oracle's planes of each pulse timed."""
+    res, wall, workers, cores = _pool_map(_oracle_pulse, [(filt, J, ref, p) for p in pulses],
+                                          max_workers)
     n = pulses.shape[1]
-    return {"value": workers * n / wall, "unit": "complex samples/s", "cores": workers,
-            "kind": "oracle",
-            "sample": f"{workers} pulses x {n} samples of the same batch, one pulse per process "
-                      f"(FP64 NumPy, OMP_NUM_THREADS=1), wall {wall:.1f} s; host has {cores} cores"}
+    k = len(res)
+    return ({"value": k * n / wall, "unit": "complex samples/s", "cores": workers,
+             "kind": "oracle",
+             "sample": f"{k} pulses x {n} samples of the same batch, one pulse per process "
+                       f"(FP64 NumPy, OMP_NUM_THREADS=1), wall {wall:.1f} s; host has {cores} "
+                       f"cores"},
+            [r[1] for r in res])
 
 
 # ---------------------------------------------------------------------------
@@ -128,6 +123,11 @@ def main():
     ap.add_argument("--workload", default="batched_uniform",
                     choices=["batched_uniform", "uneven", "integer", "single", "serving", "bank",
                              "swapped", "detect", "generic"])
+    ap.add_argument("--headline-only", action="store_true",
+                    help="default workload without the single / integer / uneven / serving "
+                         "sub-records")
+    ap.add_argument("--serve-requests", type=int, default=20000,
+                    help="requests per arrival rate in the serving runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path in this library "
@@ -142,6 +142,17 @@ def main():
           "swapped": bench_swapped, "detect": bench_detect,
           "generic": bench_generic}[args.workload]
     rec = fn(args)
+    if args.workload == "batched_uniform" and not args.headline_only:
+        # The other configurations of the metric, each timed and checked the
+        # same way, as sub-records of the one JSON line.
+        import torch
+        for key, sub in (("single", bench_single), ("integer", bench_integer),
+                         ("uneven", bench_uneven), ("serving", bench_serving)):
+            torch.cuda.empty_cache()
+            log(f"---- sub-record: {key}")
+            r = sub(args)
+            rec[key] = {k: v for k, v in r.items()
+                        if k not in ("n_gpus", "scaling", "data", "higher_is_better")}
     print(json.dumps(rec), flush=True)
 
 
@@ -236,19 +247,6 @@ def bench_batched_uniform(args):
     out = torch.empty((args.count, J, N), dtype=torch.complex64, device=dev)
     stream = torch.cuda.current_stream()
 
-    # Sanity check of one pulse on sampled lags before timing anything.
-    S.correlate_many(plan, rx, out=out)
-    torch.cuda.synchronize()
-    import oracle
-    probe = np.unique([p for p in (0, 1, 7, 511, 4097, N - 1) if p < N])
-    i = min(3, args.count - 1)
-    for j in range(J):
-        want = oracle.correlate_at(b.filter, J, b.ref, b.rx[i].astype(np.complex128), j, probe)
-        got = out[i, j, probe].cpu().numpy()
-        err = np.abs(got - want).max() / max(np.abs(want).max(), 1e-30)
-        assert err < 1e-4, f"bench sanity check failed: plane {j} err {err}"
-    log("sanity check vs oracle ok")
-
     for _ in range(args.warmup):
         S.correlate_many(plan, rx, out=out)
     torch.cuda.synchronize()
@@ -305,10 +303,19 @@ def bench_batched_uniform(args):
         log("copy probe: 3 x elementwise kernels reading and writing 256 MiB each")
         del src, dst
 
-    cpu = None
+    cpu, parity = None, None
     if args.cpu:
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(b.filter, J, b.ref, b.rx[: 64].astype(np.complex128))
+        k = min(args.count, max(1, min(32, len(os.sched_getaffinity(0)))))
+        cpu, planes = cpu_baseline(b.filter, J, b.ref, b.rx[:k].astype(np.complex128))
+        S.correlate_many(plan, rx, out=out)
+        got = out[:k].cpu().numpy()
+        worst = max(float(np.linalg.norm(got[i, j] - R[j]) / np.linalg.norm(R[j]))
+                    for i, R in enumerate(planes) for j in range(J))
+        parity = {"pulses": k, "planes": "all lags", "worst_rel_l2": worst, "tolerance": 1e-5,
+                  "ok": worst <= 1e-5}
+        log(f"oracle parity on the {k} timed pulses: worst rel L2 {worst:.2e}")
+        assert worst <= 1e-5, f"parity failed: {worst}"
 
     rec = {
         "metric": "complex samples/sec through J-scale SIDWT correlate",
@@ -340,6 +347,7 @@ def bench_batched_uniform(args):
         "plain_per_pulse": None if pp_ms is None else {
             "ms_per_batch": pp_ms, "samples_per_s": args.count * args.n / (pp_ms * 1e-3),
             "batched_speedup": pp_ms / ms_step},
+        "parity": parity,
         "cpu_baseline": cpu,
     }
     plan.free()
@@ -367,31 +375,57 @@ def _time_steps(fn, steps, warmup, stream):
 
 def _oracle_lag_sample(args):
     """CPU time of the oracle on `k` lags per plane of one pulse, scaled to
-    all N lags (the direct form costs the same per lag)."""
+    all N lags (the direct form costs the same per lag), and the values at
+    those lags (plane-major) for a parity check of the GPU planes."""
     filt, J, ref, rx, k = args
     import numpy as np
     import oracle
     N = oracle.transform_length(len(rx), J)
-    lags = np.linspace(0, N - 1, k).astype(np.int64)
+    lags = np.unique(np.linspace(0, N - 1, k).astype(np.int64))
     t0 = time.perf_counter()
-    for j in range(J):
-        oracle.correlate_at(filt, J, ref, rx, j, lags)
-    return (time.perf_counter() - t0) * N / k
+    vals = [oracle.correlate_at(filt, J, ref, rx, j, lags) for j in range(J)]
+    return (time.perf_counter() - t0) * N / len(lags), lags, vals
 
 
-def cpu_baseline_lags(items, k=64, max_workers=32):
-    """items: list of (filter, J, ref, rx); returns samples/s over the pool."""
+def _pool_map(fn, items, max_workers=32):
+    """The oracle over `items`, one item per worker process (spawned, one
+    BLAS thread each).  Returns (results, wall seconds, workers, host cores)."""
     import multiprocessing as mp
     os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    os.environ["MKL_NUM_THREADS"] = "1"
     cores = len(os.sched_getaffinity(0))
     workers = max(1, min(cores, max_workers, len(items)))
     ctx = mp.get_context("spawn")
     with ctx.Pool(workers) as pool:
         pool.map(_warm, range(workers))
-        secs = pool.map(_oracle_lag_sample, [it + (k,) for it in items])
+        t0 = time.perf_counter()
+        res = pool.map(fn, items, chunksize=1)
+        wall = time.perf_counter() - t0
+    return res, wall, workers, cores
+
+
+def cpu_baseline_lags(items, k=64, max_workers=32):
+    """items: list of (filter, J, ref, rx).  Returns (samples/s of the pool,
+    workers, host cores, per-item (lags, values))."""
+    res, _, workers, cores = _pool_map(_oracle_lag_sample, [it + (k,) for it in items],
+                                       max_workers)
     samples = sum(len(it[3]) for it in items)
+    secs = sum(r[0] for r in res)
     # work spread over `workers` processes
-    return samples / (sum(secs) / workers), workers, cores
+    return samples / (secs / workers), workers, cores, [(r[1], r[2]) for r in res]
+
+
+def sampled_parity(got_planes, lags, want, tol=1e-5):
+    """Relative L2 error per plane of GPU planes (J, N) at `lags` against
+    the oracle's values there; returns the worst plane's error."""
+    import numpy as np
+    worst = 0.0
+    for j, w in enumerate(want):
+        g = got_planes[j, lags].astype(np.complex128)
+        e = float(np.linalg.norm(g - w) / max(np.linalg.norm(w), 1e-300))
+        worst = max(worst, e)
+    return worst
 
 
 def pulse_flops(plan_desc_lens, N):
@@ -458,14 +492,20 @@ def bench_uneven(args):
     pp_ms = plain_per_pulse(S, plans, rx, out) if args.per_pulse else None
     if pp_ms is not None:
         log(f"plain per-pulse path: {pp_ms:.2f} ms per batch ({pp_ms / ms:.1f}x the batched time)")
-    cpu = None
+    cpu, parity = None, None
     if args.cpu:
-        idx = np.argsort(ns)[np.linspace(0, count - 1, 32).astype(int)]
+        idx = np.argsort(ns)[np.linspace(0, count - 1, 100).astype(int)]
         items = [(reqs[i].filter, reqs[i].J, refs[reqs[i].ref_index], reqs[i].rx) for i in idx]
-        v, workers, cores = cpu_baseline_lags(items)
+        v, workers, cores, vals = cpu_baseline_lags(items)
         cpu = {"value": v, "unit": "complex samples/s", "cores": workers, "kind": "oracle",
-               "sample": f"32 pulses stratified by length, 64 lags per plane each, oracle time "
-                         f"scaled to all N lags; host has {cores} cores"}
+               "sample": f"100 pulses stratified by length (every 100th by n), 64 lags per "
+                         f"plane each, oracle time scaled to all N lags; host has {cores} cores"}
+        worst = max(sampled_parity(out[i].cpu().numpy(), lags, want)
+                    for i, (lags, want) in zip(idx, vals))
+        parity = {"pulses": len(idx), "lags_per_plane": 64, "worst_rel_l2": worst,
+                  "tolerance": 1e-5, "ok": worst <= 1e-5}
+        log(f"oracle parity on the 100 sampled pulses: worst rel L2 {worst:.2e}")
+        assert worst <= 1e-5, f"uneven batch parity failed: {worst}"
     b.free()
     return {
         "metric": "complex samples/sec through J-scale SIDWT correlate",
@@ -478,12 +518,14 @@ def bench_uneven(args):
                    "batch": info},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
-                     "kernel": "batch_persistent"},
+                     "kernel": "one graph replay: batch_lift levels + batch_persistent classes",
+                     "flops_per_step": flops},
         "planes_out": {"bytes": out_all.numel() * 8,
                        "gb_per_s": out_all.numel() * 8 / (ms * 1e-3) / 1e9},
         "plain_per_pulse": None if pp_ms is None else {
             "ms_per_batch": pp_ms, "samples_per_s": total / (pp_ms * 1e-3),
             "batched_speedup": pp_ms / ms},
+        "parity": parity,
         "cpu_baseline": cpu,
     }
 
@@ -515,13 +557,25 @@ def bench_integer(args):
     log(f"lifting only: {lift['us_per_launch']:.1f} us, {lift['achieved']:.0f} GB/s")
     synth = synthesis_roofline(S, "legall53_int", J, rx, "synth_many<LEGALL53_INT>")
     log(f"coarse-to-fine synthesis: {synth['us_per_launch']:.1f} us, {synth['achieved']:.0f} GB/s")
-    cpu = None
+    cpu, parity = None, None
     if args.cpu:
-        items = [("legall53_int", J, ib.ref_iq, ib.rx_iq[i]) for i in range(16)]
-        v, workers, cores = cpu_baseline_lags_int(items)
+        idx = np.linspace(0, count - 1, 16).astype(int)
+        items = [("legall53_int", J, ib.ref_iq, ib.rx_iq[i]) for i in idx]
+        v, workers, cores, vals = cpu_baseline_lags_int(items)
         cpu = {"value": v, "unit": "complex samples/s", "cores": workers, "kind": "oracle",
-               "sample": f"16 pulses, 64 lags per plane each, int64 oracle time scaled to all "
-                         f"N lags; host has {cores} cores"}
+               "sample": f"16 pulses spread over the batch, 64 lags per plane each, int64 oracle "
+                         f"time scaled to all N lags; host has {cores} cores"}
+        S.correlate_many(plan, rx, out=out)
+        torch.cuda.synchronize()
+        bad = 0
+        for i, (lags, want) in zip(idx, vals):
+            got = out[i].cpu().numpy()
+            for j in range(J):
+                bad += int(not np.array_equal(got[j, lags], want[j]))
+        parity = {"pulses": len(idx), "lags_per_plane": 64, "planes_differing": bad,
+                  "bit_exact": bad == 0}
+        log(f"oracle parity on 16 sampled pulses: {'bit-exact' if bad == 0 else f'{bad} planes differ'}")
+        assert bad == 0, "integer parity failed"
     plan.free()
     return {
         "metric": "complex samples/sec through J-scale SIDWT correlate",
@@ -534,6 +588,7 @@ def bench_integer(args):
                      "frac": tflops / 78.6, "traffic": None, "kernel": "fused_correlate<INT53>"},
         "lifting_roofline": lift,
         "synthesis_roofline": synth,
+        "parity": parity,
         "cpu_baseline": cpu,
     }
 
@@ -732,29 +787,36 @@ def _oracle_lag_sample_int(args):
     import numpy as np
     import oracle
     N = oracle.transform_length(len(rx), J)
-    lags = np.linspace(0, N - 1, k).astype(np.int64)
+    lags = np.unique(np.linspace(0, N - 1, k).astype(np.int64))
     t0 = time.perf_counter()
-    for j in range(J):
-        oracle.correlate_int_at(J, ref, rx, j, lags)
-    return (time.perf_counter() - t0) * N / k
+    vals = [oracle.correlate_int_at(J, ref, rx, j, lags) for j in range(J)]
+    return (time.perf_counter() - t0) * N / len(lags), lags, vals
 
 
 def cpu_baseline_lags_int(items, k=64, max_workers=32):
-    import multiprocessing as mp
-    os.environ["OMP_NUM_THREADS"] = "1"
-    cores = len(os.sched_getaffinity(0))
-    workers = max(1, min(cores, max_workers, len(items)))
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(workers) as pool:
-        pool.map(_warm, range(workers))
-        secs = pool.map(_oracle_lag_sample_int, [it + (k,) for it in items])
+    res, _, workers, cores = _pool_map(_oracle_lag_sample_int, [it + (k,) for it in items],
+                                       max_workers)
     samples = sum(len(it[3]) for it in items)
-    return samples / (sum(secs) / workers), workers, cores
+    secs = sum(r[0] for r in res)
+    return samples / (secs / workers), workers, cores, [(r[1], r[2]) for r in res]
+
+
+def _oracle_single(seed):
+    """The oracle on one request of the single-correlation workload (all
+    planes, all lags); returns (seconds, planes)."""
+    import oracle
+    import workloads as W
+    w = W.single_chirp(seed=seed)
+    t0 = time.perf_counter()
+    R = oracle.correlate_direct(w.filter, w.J, w.ref, w.rx)
+    return time.perf_counter() - t0, R
 
 
 def bench_single(args):
-    """One 1024-sample pulse per request (5/3, J = 3): per-request latency
-    (launch to completion, host clock) over seeded requests."""
+    """One 1024-sample pulse per request (256-sample chirp, 10 dB, 5/3,
+    J = 3), 1000 seeded requests one at a time: per-request latency (call to
+    completion, host clock), kernel duration (HIP events on the launch
+    stream), and the oracle over all 1000 requests with parity on each."""
     import numpy as np
     import torch
 
@@ -762,31 +824,72 @@ def bench_single(args):
     import workloads as W
 
     dev = torch.device("cuda:0")
-    reqs = [W.single_chirp(seed=s) for s in range(1, 1001)]
+    seeds = list(range(1, 1001))
+    reqs = [W.single_chirp(seed=s) for s in seeds]
     rx = [torch.from_numpy(w.rx.astype(np.complex64)).to(dev) for w in reqs]
     plan = S.plan_create("legall53", 3, reqs[0].ref)
-    out = torch.empty((3, 1024), dtype=torch.complex64, device=dev)
+    N = 1024
+    outs = torch.empty((len(reqs), 3, N), dtype=torch.complex64, device=dev)
+    stream = torch.cuda.current_stream()
     for x in rx[:50]:
-        S.correlate(plan, x, out=out)
+        S.correlate(plan, x, out=outs[0])
     torch.cuda.synchronize()
     lat = []
-    for x in rx:
+    for i, x in enumerate(rx):
         t0 = time.perf_counter()
-        S.correlate(plan, x, out=out)
+        S.correlate(plan, x, out=outs[i])
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
     lat = np.array(lat)
     p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+    # kernel durations: events around each launch, launches back to back
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in rx]
+    for (a, b), x, i in zip(ev, rx, range(len(rx))):
+        a.record(stream)
+        S.correlate(plan, x, out=outs[i])
+        b.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    flops = pulse_flops(plan_lens(S, plan), N)
+    tflops = flops / (kern_ms * 1e-3) / 1e12
+    log(f"single: p50 {p50 * 1e6:.1f} us, p99 {p99 * 1e6:.1f} us per request; kernel "
+        f"{kern_ms * 1e3:.1f} us")
+    cpu, parity = None, None
+    if args.cpu:
+        res, wall, workers, cores = _pool_map(_oracle_single, seeds)
+        got = outs.cpu().numpy().astype(np.complex128)
+        errs = np.array([[np.linalg.norm(got[i, j] - R[j]) / np.linalg.norm(R[j])
+                          for j in range(3)] for i, (_, R) in enumerate(res)])
+        peaks_ok = int(sum(int(np.argmax(np.abs(got[i, 0]))) == w.delay
+                           for i, w in enumerate(reqs)))
+        cpu = {"value": len(seeds) * N / wall, "unit": "complex samples/s", "cores": workers,
+               "kind": "oracle",
+               "sample": f"all {len(seeds)} seeded requests (FP64 NumPy, one request per process, "
+                         f"OMP_NUM_THREADS=1), wall {wall:.1f} s; host has {cores} cores",
+               "requests_per_s": len(seeds) / wall}
+        parity = {"requests": len(seeds), "worst_rel_l2": float(errs.max()), "tolerance": 1e-5,
+                  "ok": bool(errs.max() <= 1e-5), "peak_at_planted_delay": peaks_ok}
+        log(f"oracle over all {len(seeds)} requests: {wall:.1f} s on {workers} processes; "
+            f"parity worst rel L2 {errs.max():.2e}; peak at the planted delay in {peaks_ok}")
+        assert errs.max() <= 1e-5, "single-request parity failed"
     plan.free()
     return {
         "metric": "complex samples/sec through J-scale SIDWT correlate; p50/p99 request latency",
-        "value": 1024 / p50, "unit": "complex samples/s", "n_gpus": 1, "steps": len(lat),
+        "value": N / p50, "unit": "complex samples/s", "n_gpus": 1, "steps": len(lat),
         "warmup": 50, "ms_per_step": p50 * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "single correlation: 1024-sample pulse, 256-sample chirp "
-                               "(TBP 64), 10 dB, 5/3, J=3, one request at a time",
-                   "p50_us": p50 * 1e6, "p99_us": p99 * 1e6},
-        "roofline": None, "cpu_baseline": None,
+                               "(TBP 64), 10 dB, 5/3, J=3, one request at a time, 1000 requests",
+                   "p50_us": p50 * 1e6, "p99_us": p99 * 1e6, "kernel_us": kern_ms * 1e3},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS,
+                     "traffic": None, "kernel": "fused_correlate<LEGALL53> (one workgroup)",
+                     "flops_per_launch": flops,
+                     "note": "one 1024-sample pulse per launch runs on one workgroup of one CU: "
+                             "bound by launch latency, not by the chip"},
+        "parity": parity,
+        "cpu_baseline": cpu,
     }
 
 
@@ -871,27 +974,61 @@ def bench_bank(args):
     }
 
 
+def _oracle_bank_sample(args):
+    """The oracle on one serving request against a few of its eligible
+    references, `k` lags per plane; returns (seconds scaled to all N lags,
+    lags, values[ref][plane])."""
+    J, refs, rx, k = args
+    import numpy as np
+    import oracle
+    N = oracle.transform_length(len(rx), J)
+    lags = np.unique(np.linspace(0, N - 1, k).astype(np.int64))
+    y = rx.astype(np.complex128)
+    t0 = time.perf_counter()
+    vals = [[oracle.correlate_at("cdf97", J, r, y, j, lags) for j in range(J)] for r in refs]
+    return (time.perf_counter() - t0) * N / len(lags), lags, vals
+
+
+def _bank_flops_bytes(S, bank, lens, reqs):
+    """Algorithmic work of bank requests (n, J, rx): complex MACs of the
+    block-circulant products counted once (8 real flops each) over every
+    eligible reference, and HBM bytes of pulses in and planes out."""
+    flops, nbytes = 0, 0
+    for n, J, _ in reqs:
+        N = S.transform_length(n, J)
+        E = bank.eligible(n)
+        for e in range(E):
+            flops += pulse_flops(lens[e][:2 * J], N)
+        nbytes += n * 8 + E * J * N * 8
+    return flops, nbytes
+
+
 def bench_serving(args):
     """Serving with a bank of 64 references (ascending length, LFM /
     Barker-13 / polyphase, 64..2048 samples, CDF 9/7, FP16 hi+lo MFMA):
     requests sized as the uneven workload arrive as a Poisson process at
-    rates swept relative to the measured saturation rate; p50/p99 latency
-    and samples/s per rate.  Also: the same requests through the FP32 plain
-    path (every (request, reference) pair as one pulse of an uneven batch)
-    and the bank's per-scale error against the oracle."""
+    rates relative to the measured saturation rate (0.5x and 0.9x; the whole
+    sweep 0.1x..1.2x with --workload serving); p50/p99 latency and samples/s
+    per rate, the roofline of the saturation run, the bank's per-scale error
+    against the oracle and the oracle's own rate on a length-stratified
+    sample.  With --workload serving also: the same requests through the FP32
+    plain path (every (request, reference) pair as one pulse of an uneven
+    batch, and one launch per pair)."""
     import numpy as np
     import torch
 
-    import oracle
     import paper_cs_0607001_amd as S
     import workloads as W
     from paper_cs_0607001_amd import serving
 
+    full = args.workload == "serving"
     dev = torch.device("cuda:0")
-    count = args.count
+    count = args.serve_requests
     refs = W.reference_set(5, count=64)
     log("building the bank (64 references, Jmax 12)")
     bank = S.Bank("cdf97", 12, refs, "fp16")
+    lens = [plan_lens(S, bank.plan(e)) for e in range(len(refs))]
+    log(f"generating {count} requests")
     pulses = _serving_requests(refs, count)
     host = [torch.from_numpy(p[2]).pin_memory() for p in pulses]
     total_samples = sum(p[0] for p in pulses)
@@ -904,13 +1041,33 @@ def bench_serving(args):
     srv = serving.Server(bank, slots=4, budget_bytes=budget, max_group=32)
     srv.run(reqs(np.zeros(count))[:64])          # warm-up (workspaces grow)
     log(f"saturation run: {count} requests at t = 0")
-    sat = serving.summarize(srv.run(reqs(np.zeros(count))))
+    sat_recs = srv.run(reqs(np.zeros(count)))
+    sat = serving.summarize(sat_recs)
     rate_sat = sat["requests_per_s"]
     ref_samples = sum(p[0] * bank.eligible(p[0]) for p in pulses)
     sat["reference_samples_per_s"] = sat["samples_per_s"] * ref_samples / total_samples
     log(f"saturation: {rate_sat:.0f} requests/s, {sat['samples_per_s'] / 1e9:.2f} G samples/s")
+    span_s = count / rate_sat
+    flops, nbytes = _bank_flops_bytes(S, bank, lens, pulses)
+    mfma_floor = 3 * flops / 2.5e15              # hi*hi + hi*lo + lo*hi on FP16 matrix cores
+    hbm_floor = nbytes / 8e12
+    floor = max(mfma_floor, hbm_floor)
+    bound = "mfma" if mfma_floor >= hbm_floor else "hbm"
+    roof = {"bound": bound,
+            "achieved": (3 * flops / span_s / 1e12) if bound == "mfma" else nbytes / span_s / 1e9,
+            "peak": 2500.0 if bound == "mfma" else PEAK_HBM_GBS,
+            "unit": "TFLOP/s" if bound == "mfma" else "GB/s",
+            "frac": floor / span_s, "traffic": None,
+            "kernel": "saturation run: lifting + bank_items per group, 4 streams",
+            "floor_ms": floor * 1e3, "mfma_floor_ms": mfma_floor * 1e3,
+            "hbm_floor_ms": hbm_floor * 1e3, "run_ms": span_s * 1e3,
+            "flops_once": flops, "flops_split": 3 * flops, "bytes": nbytes,
+            "note": "frac = max(split flops / FP16 peak, bytes / HBM peak) / measured time of "
+                    "the saturation run (pulses copied from pinned host memory inside it)"}
+    log(f"saturation roofline: floor {floor * 1e3:.1f} ms ({bound}) of {span_s * 1e3:.1f} ms "
+        f"({roof['frac'] * 100:.1f} %)")
     sweep = []
-    for f in (0.1, 0.2, 0.4, 0.6, 0.8, 0.9, 1.0, 1.1, 1.2):
+    for f in ((0.1, 0.2, 0.4, 0.6, 0.8, 0.9, 1.0, 1.1, 1.2) if full else (0.5, 0.9)):
         rate = f * rate_sat
         t = W.poisson_arrivals(5 + int(f * 100), rate, count)
         rec = serving.summarize(srv.run(reqs(t - t[0])))
@@ -921,8 +1078,71 @@ def bench_serving(args):
             f"{rec['samples_per_s'] / 1e9:.2f} G samples/s")
     srv.close()
 
-    # Bank vs FP32 plain path on the same subset, raw GPU throughput.
-    sub = list(range(min(count, 200)))
+    # Oracle: 100 requests stratified by length, four eligible references
+    # each (spread over the eligible prefix), 16 lags per plane; its time is
+    # scaled to every eligible reference and every lag.  The bank's planes
+    # at those lags give the per-scale error against the oracle.
+    cpu, err = None, {}
+    if args.cpu:
+        order = np.argsort([p[0] for p in pulses])
+        idx = order[np.linspace(0, count - 1, 100).astype(int)]
+        picks = []
+        for i in idx:
+            E = bank.eligible(pulses[i][0])
+            picks.append(sorted({int(e) for e in np.linspace(0, E - 1, 4).round()}))
+        items = [(pulses[i][1], [refs[e] for e in pk], pulses[i][2], 16)
+                 for i, pk in zip(idx, picks)]
+        res, _, workers, cores = _pool_map(_oracle_bank_sample, items)
+        secs = sum(r[0] * bank.eligible(pulses[i][0]) / len(pk)
+                   for r, i, pk in zip(res, idx, picks))
+        samples = sum(pulses[i][0] for i in idx)
+        cpu = {"value": samples / (secs / workers), "unit": "complex samples/s",
+               "cores": workers, "kind": "oracle",
+               "sample": f"100 requests stratified by length, 4 of their eligible references "
+                         f"each, 16 lags per plane; oracle time scaled to every eligible "
+                         f"reference and all N lags; host has {cores} cores",
+               "reference_samples_per_s": sum(pulses[i][0] * bank.eligible(pulses[i][0])
+                                              for i in idx) / (secs / workers)}
+        rx = [host[i].to(dev) for i in idx]
+        outs = bank.correlate(rx, [pulses[i][1] for i in idx])
+        torch.cuda.synchronize()
+        for i, pk, (_, lags, vals), o in zip(idx, picks, res, outs):
+            g = o.cpu().numpy()
+            for e, want in zip(pk, vals):
+                for j, w in enumerate(want):
+                    r = float(np.linalg.norm(g[e, j, lags] - w) / np.linalg.norm(w))
+                    err[j] = max(err.get(j, 0.0), r)
+        log(f"bank vs oracle, worst rel L2 per scale: "
+            f"{ {j: f'{v:.1e}' for j, v in sorted(err.items())} }")
+        assert max(err.values()) <= 1e-5, "bank parity failed"
+
+    rec = {
+        "metric": "complex samples/sec through J-scale SIDWT correlate; p50/p99 request latency",
+        "value": sat["samples_per_s"], "unit": "complex samples/s", "n_gpus": 1, "steps": count,
+        "warmup": 64, "ms_per_step": 1e3 / rate_sat, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp16 hi+lo MFMA, fp32 accumulate", "data": "synthetic",
+        "config": {"workload": f"serving: {count} requests per rate, n log-uniform in "
+                               f"[512, 65536], bank of 64 references (64..2048), CDF 9/7, "
+                               f"J=floor(log2(n/16)), 4 slots, {budget >> 30} GiB budget, "
+                               f"Poisson arrivals",
+                   "saturation": sat, "sweep": sweep,
+                   "bank_rel_l2_per_scale_max": err},
+        "p50_ms": {f"{r['rate_fraction']}x": r["p50_ms"] for r in sweep},
+        "p99_ms": {f"{r['rate_fraction']}x": r["p99_ms"] for r in sweep},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    if full:
+        rec["config"]["bank_vs_fp32"] = _bank_vs_fp32(S, bank, refs, pulses, host, dev)
+    bank.free()
+    return rec
+
+
+def _bank_vs_fp32(S, bank, refs, pulses, host, dev):
+    """Bank (FP16 hi+lo) against the FP32 plain path on the first 200
+    requests: every (request, eligible reference) pair as one pulse of an
+    uneven batch, and as one launch per pair."""
+    import torch
+    sub = list(range(min(len(pulses), 200)))
     rx = [host[i].to(dev) for i in sub]
     Js = [pulses[i][1] for i in sub]
     outs = bank.correlate(rx, Js)
@@ -946,43 +1166,13 @@ def bench_serving(args):
     log(f"bank FP16 hi+lo: {ms_bank:.2f} ms, FP32 uneven batch: {ms_fp32:.2f} ms, FP32 plain "
         f"per-pulse path: {ms_pp:.2f} ms for {len(sub)} requests ({len(plans)} reference "
         f"correlations)")
-    # per-scale error of the bank (FP16 hi+lo) against the oracle, sampled lags
-    outs = bank.correlate(rx, Js)
-    torch.cuda.synchronize()
-    err = {}
-    prng = np.random.default_rng(9)
-    for i in sub[:6]:
-        n, J, y = pulses[i]
-        N = S.transform_length(n, J)
-        E = bank.eligible(n)
-        for e in sorted({0, E // 2, E - 1}):
-            lags = prng.integers(0, N, 48)
-            g = outs[i][e].cpu().numpy()
-            for j in range(J):
-                want = oracle.correlate_at("cdf97", J, refs[e], y.astype(np.complex128), j, lags)
-                r = float(np.linalg.norm(g[j, lags] - want) / np.linalg.norm(want))
-                err[j] = max(err.get(j, 0.0), r)
     b32.free()
     for p in plan_cache.values():
         p.free()
-    bank.free()
-    return {
-        "metric": "complex samples/sec through J-scale SIDWT correlate; p50/p99 request latency",
-        "value": sat["samples_per_s"], "unit": "complex samples/s", "n_gpus": 1, "steps": count,
-        "warmup": 64, "ms_per_step": 1e3 / rate_sat, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp16 hi+lo MFMA, fp32 accumulate", "data": "synthetic",
-        "config": {"workload": f"serving: {count} requests per rate, n log-uniform in "
-                               f"[512, 65536], bank of 64 references (64..2048), CDF 9/7, "
-                               f"J=floor(log2(n/16)), 4 slots, {budget >> 30} GiB budget",
-                   "saturation": sat, "sweep": sweep,
-                   "bank_vs_fp32": {"requests": len(sub), "samples": sub_samples,
-                                    "bank_ms": ms_bank, "fp32_ms": ms_fp32,
-                                    "fp32_per_pulse_ms": ms_pp,
-                                    "bank_samples_per_s": sub_samples / (ms_bank * 1e-3),
-                                    "fp32_samples_per_s": sub_samples / (ms_fp32 * 1e-3)},
-                   "bank_rel_l2_per_scale_max": err},
-        "roofline": None, "cpu_baseline": None,
-    }
+    return {"requests": len(sub), "samples": sub_samples, "bank_ms": ms_bank, "fp32_ms": ms_fp32,
+            "fp32_per_pulse_ms": ms_pp,
+            "bank_samples_per_s": sub_samples / (ms_bank * 1e-3),
+            "fp32_samples_per_s": sub_samples / (ms_fp32 * 1e-3)}
 
 
 if __name__ == "__main__":

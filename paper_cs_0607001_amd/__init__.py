@@ -593,10 +593,8 @@ class Bank:
                    for x, n, j in zip(rx, ns, J)]
         for i, (o, x, n, j) in enumerate(zip(out, rx, ns, J)):
             need = lib().sidwt_bank_out_len(self.handle, n, int(j))
-            if need < 0:
-                raise ValueError(f"request {i}: n = {n}, J = {j} out of range for this bank")
-            if o is None and need == 0:
-                continue
+            if need < 0 or (o is None and need == 0):
+                continue   # the library refuses bad sizes itself, before any launch
             _check_buf(o, torch.complex64, need, f"out[{i}]", x.device)
         n_arr = (ctypes.c_int64 * len(ns))(*ns)
         j_arr = (ctypes.c_int32 * len(ns))(*[int(j) for j in J])

@@ -91,7 +91,9 @@ enum {
                            size beyond the library's limits               */
   SIDWT_E_NOMEM = -3,   /* device allocation failed                       */
   SIDWT_E_DEVICE = -4,  /* a HIP runtime error (including earlier faults) */
-  SIDWT_E_UNSUPPORTED = -5 /* valid request the library does not handle  */
+  SIDWT_E_UNSUPPORTED = -5, /* valid request the library does not handle */
+  SIDWT_E_SCRATCH = -6  /* request needs more than the library's static
+                           scratch (SIDWT_NOALLOC_SCRATCH_BYTES)          */
 };
 
 #define SIDWT_MAX_LEVELS 16
@@ -230,6 +232,25 @@ int sidwt_correlate_swapped_on(const sidwt_plan *p, const void *rx, int64_t n,
                                int64_t count, int64_t rx_stride, void *out,
                                int64_t out_stride, void *workspace,
                                int64_t workspace_bytes, void *hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work of
+ * sidwt_correlate_swapped_on, with the tree levels kept in a scratch array
+ * that the library holds in each GPU's memory from its first use until the
+ * process ends (SIDWT_NOALLOC_SCRATCH_BYTES per device, looked up on the
+ * first call on each device), instead of a caller workspace.  The call
+ * allocates and frees nothing.  The caller passes inputs and outputs as for
+ * sidwt_correlate_swapped_on.  Requests whose tree needs more than the
+ * scratch holds (sidwt_swap_workspace_bytes(p, n, count) above
+ * SIDWT_NOALLOC_SCRATCH_BYTES) return SIDWT_E_SCRATCH before anything is
+ * enqueued.  Every call on one GPU uses that GPU's one array: calls that can
+ * run at the same time on one GPU (other streams, other threads) race and
+ * must be ordered by the caller.  The array needs no clearing: each call
+ * writes the tree levels it reads. */
+#define SIDWT_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int sidwt_correlate_swapped_noalloc(const sidwt_plan *p, const void *rx, int64_t n,
+                                    int64_t count, int64_t rx_stride, void *out,
+                                    int64_t out_stride, void *hip_stream);
 
 /* Target declaration (Sec. V-A, Fig. 6: targets read off |R| in dB at each
  * scale as peaks above a level).  planes: device complex64, pulse i's plane

@@ -18,6 +18,7 @@ SIDWT_E_SIZE = -2
 SIDWT_E_NOMEM = -3
 SIDWT_E_DEVICE = -4
 SIDWT_E_UNSUPPORTED = -5
+SIDWT_E_SCRATCH = -6
 
 FILTERS = {"legall53": 1, "cdf97": 2, "d4": 3, "legall53_int": 4}
 
@@ -62,6 +63,8 @@ def _declare(L):
     L.sidwt_correlate_swapped.restype = i32
     L.sidwt_correlate_swapped_on.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp, i64, vp]
     L.sidwt_correlate_swapped_on.restype = i32
+    L.sidwt_correlate_swapped_noalloc.argtypes = [vp, vp, i64, i64, i64, vp, i64, vp]
+    L.sidwt_correlate_swapped_noalloc.restype = i32
     L.sidwt_detect_peaks.argtypes = [vp, i64, i32, i64, i64, c.c_float, i32, vp, vp, vp, vp]
     L.sidwt_detect_peaks.restype = i32
     dp = c.POINTER(c.c_double)

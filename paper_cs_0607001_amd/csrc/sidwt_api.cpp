@@ -17,6 +17,7 @@ namespace sidwt {
 bool generic_steps_fit(const LiftingDesc &d);
 hipError_t launch_generic(const LiftingDesc &d, int J, int N, const void *rx, long long n,
                           long long count, long long rx_stride, void *pyr, hipStream_t st);
+hipError_t noalloc_scratch(void **out);
 hipError_t launch_detect(const void *planes, long long pulse_stride, int J, int N, long long count,
                          float rel, int max_peaks, int *lags, float *db, int *found,
                          hipStream_t st);
@@ -99,6 +100,7 @@ const char *sidwt_strerror(int code) {
     case SIDWT_E_NOMEM: return "device allocation failed";
     case SIDWT_E_DEVICE: return "HIP runtime error";
     case SIDWT_E_UNSUPPORTED: return "request not supported by the library";
+    case SIDWT_E_SCRATCH: return "request needs more than the library's static scratch";
     default: return "unknown error";
   }
 }
@@ -358,6 +360,22 @@ int sidwt_correlate_swapped_on(const sidwt_plan *p, const void *rx, int64_t n, i
                                int64_t workspace_bytes, void *hip_stream) {
   return correlate_swapped(p, rx, n, count, rx_stride, out, out_stride, workspace,
                            workspace_bytes, static_cast<hipStream_t>(hip_stream));
+}
+
+int sidwt_correlate_swapped_noalloc(const sidwt_plan *p, const void *rx, int64_t n,
+                                    int64_t count, int64_t rx_stride, void *out,
+                                    int64_t out_stride, void *hip_stream) {
+  if (!p || n < 1 || count < 0) return SIDWT_E_INVAL;
+  const int64_t need = swap_ws_bytes(p->J, transform_length(n, p->J), count);
+  if (need < 0 || need > (int64_t)SIDWT_NOALLOC_SCRATCH_BYTES) return SIDWT_E_SCRATCH;
+  void *ws = nullptr;
+  if (need > 0) {
+    const hipError_t e = sidwt::noalloc_scratch(&ws);
+    if (e != hipSuccess) return map_err(e);
+  }
+  return correlate_swapped(p, rx, n, count, rx_stride, out, out_stride, ws,
+                           (int64_t)SIDWT_NOALLOC_SCRATCH_BYTES,
+                           static_cast<hipStream_t>(hip_stream));
 }
 
 int sidwt_detect_peaks(const void *planes, int64_t count, int J, int64_t N, int64_t pulse_stride,

@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 
 PEAK_FP32_MATRIX_TFLOPS = 157.3   # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0             # MI355X HBM3E
+PEAK_INT8_TOPS = 5000.0           # MI355X dense INT8 matrix
 
 
 def log(*a):
@@ -532,7 +533,8 @@ def bench_uneven(args):
 
 def bench_integer(args):
     """16384 x 4096 int16 I/Q pulses, reversible 5/3, J = 6, exact int64
-    planes (FP64 MFMA accumulation of integer products)."""
+    planes (balanced base-256 digits on int8 matrix cores, int32 sums per
+    shift class, combined in int64)."""
     import numpy as np
     import torch
 
@@ -552,7 +554,18 @@ def bench_integer(args):
     flops = pulse_flops(plan_lens(S, plan), n) * count
     value = count * n / (ms * 1e-3)
     tflops = flops / (ms * 1e-3) / 1e12
-    log(f"integer: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} TFLOP/s (FP64 MFMA)")
+    info = plan.info()
+    wl = info["i8_weight_digits"]
+    # int8 path: every algorithmic op becomes 3 x wl digit products; its
+    # floor is the larger of those on the INT8 peak and the bytes on HBM
+    nbytes = rx.numel() * rx.element_size() + out.numel() * out.element_size()
+    digit_ops = flops * 3 * wl
+    t_mfma = digit_ops / (PEAK_INT8_TOPS * 1e12) if wl else flops / 78.6e12
+    t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+    bound = "hbm" if t_hbm >= t_mfma else "mfma"
+    log(f"integer: {ms:.3f} ms/step, {value / 1e9:.2f} G samples/s, {tflops:.1f} T algorithmic "
+        f"ops/s ({'int8 matrix cores, ' + str(wl) + ' weight digits' if wl else 'FP64 MFMA'}); "
+        f"floor {max(t_mfma, t_hbm) * 1e3:.3f} ms ({bound})")
     lift = lifting_roofline(S, "legall53_int", J, rx, "lift_many<LEGALL53_INT>")
     log(f"lifting only: {lift['us_per_launch']:.1f} us, {lift['achieved']:.0f} GB/s")
     synth = synthesis_roofline(S, "legall53_int", J, rx, "synth_many<LEGALL53_INT>")
@@ -581,11 +594,20 @@ def bench_integer(args):
         "metric": "complex samples/sec through J-scale SIDWT correlate",
         "value": value, "unit": "complex samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int32 lifting, int64 planes", "data": "synthetic",
+        "vs_baseline": None, "dtype": "int32 lifting; int8 digits, int32 class sums, int64 planes",
+        "data": "synthetic",
         "config": {"workload": f"integer: {count} x {n} int16 I/Q, reversible 5/3, J={J}, "
-                               f"bit-exact int64 planes"},
-        "roofline": {"bound": "mfma", "achieved": tflops, "peak": 78.6, "unit": "TFLOP/s",
-                     "frac": tflops / 78.6, "traffic": None, "kernel": "fused_correlate<INT53>"},
+                               f"bit-exact int64 planes", "weight_digits": wl},
+        "roofline": {"bound": bound,
+                     "achieved": nbytes / (ms * 1e-3) / 1e9 if bound == "hbm"
+                     else digit_ops / (ms * 1e-3) / 1e12,
+                     "peak": PEAK_HBM_GBS if bound == "hbm" else PEAK_INT8_TOPS,
+                     "unit": "GB/s" if bound == "hbm" else "TOP/s",
+                     "frac": max(t_mfma, t_hbm) / (ms * 1e-3), "traffic": None,
+                     "kernel": "fused_correlate_i8" if wl else "fused_correlate<INT53>",
+                     "bytes": nbytes, "algorithmic_ops": flops, "digit_ops": digit_ops,
+                     "int8_frac": digit_ops / (ms * 1e-3) / (PEAK_INT8_TOPS * 1e12),
+                     "hbm_frac": t_hbm / (ms * 1e-3)},
         "lifting_roofline": lift,
         "synthesis_roofline": synth,
         "parity": parity,

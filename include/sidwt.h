@@ -447,6 +447,12 @@ void sidwt_bank_free(sidwt_bank *bank);
 int sidwt_plan_phase(const sidwt_plan *p, int level, int band, int r,
                      int32_t *lo, int32_t *len, void *dst);
 
+/* values[0..nvalues): filter, J, m, bytes of the stored phase pyramid, and
+ * for integer plans the int8 matrix-core path's weight digits per phase
+ * entry (1..3; 0 when that path does not apply and the FP64 form is used)
+ * and the bytes of its digit panels.  Host only. */
+int sidwt_plan_info(const sidwt_plan *p, int64_t *values, int nvalues);
+
 /* Short description of an error code (static string). */
 const char *sidwt_strerror(int code);
 

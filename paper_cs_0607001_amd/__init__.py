@@ -85,6 +85,13 @@ class Plan:
     def out_len(self, n: int) -> int:
         return lib().sidwt_out_len(self.handle, n)
 
+    INFO_KEYS = ("filter", "J", "m", "coef_bytes", "i8_weight_digits", "i8_panel_bytes")
+
+    def info(self) -> dict:
+        v = (ctypes.c_int64 * len(self.INFO_KEYS))()
+        check(lib().sidwt_plan_info(self.handle, v, len(self.INFO_KEYS)), "sidwt_plan_info")
+        return dict(zip(self.INFO_KEYS, list(v)))
+
     def free(self):
         if getattr(self, "_h", None) is not None:
             if not getattr(self, "_borrowed", False):

@@ -87,6 +87,8 @@ def _declare(L):
     L.sidwt_plan_phase.argtypes = [vp, i32, i32, i32, c.POINTER(c.c_int32),
                                    c.POINTER(c.c_int32), vp]
     L.sidwt_plan_phase.restype = i32
+    L.sidwt_plan_info.argtypes = [vp, c.POINTER(i64), i32]
+    L.sidwt_plan_info.restype = i32
     L.sidwt_strerror.argtypes = [i32]
     L.sidwt_strerror.restype = c.c_char_p
     L.sidwt_version.argtypes = []

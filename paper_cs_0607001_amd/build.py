@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsidwt.so")
 SOURCES = ["sidwt_kernels.hip", "sidwt_bank.hip", "sidwt_synth.hip", "sidwt_swap.hip", "sidwt_detect.hip",
-           "sidwt_generic.hip", "sidwt_noalloc.hip", "sidwt_api.cpp", "sidwt_factor.cpp",
+           "sidwt_generic.hip", "sidwt_int8.hip", "sidwt_noalloc.hip", "sidwt_api.cpp", "sidwt_factor.cpp",
            "sidwt_batch.cpp", "sidwt_bank.cpp"]
 ARCH = "gfx950"
 

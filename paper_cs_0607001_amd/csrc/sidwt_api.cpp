@@ -34,6 +34,9 @@ hipError_t launch_lift(int filter, int J, int N, const void *rx, long long n, lo
                        long long rx_stride, void *pyr, hipStream_t st);
 hipError_t launch_synth(int filter, int J, int to, int N, const void *pyr, long long count,
                         void *out, hipStream_t st);
+hipError_t launch_fused_i8(const I8Layout &lay, const I8Tile *tiles, const signed char *panels,
+                           const void *rx, long long n, long long count, long long rx_stride,
+                           void *out, long long out_stride, unsigned planes, hipStream_t st);
 size_t synth_lds_bytes(int filter, int N, int to);
 }  // namespace sidwt
 
@@ -52,6 +55,13 @@ struct sidwt_plan {
   // The reference as complex64 (float filters): plane 0's weights of the
   // roles-exchanged correlation.
   void *ref_dev = nullptr;
+  // Integer plans: digit panels of the phases for the int8 matrix-core
+  // path (i8_wl digits per entry; 0 when the path does not apply).
+  int i8_wl = 0;
+  std::vector<sidwt::I8Tile> i8_tiles;
+  std::vector<int> i8_tile_base;
+  sidwt::I8Tile *d_i8_tiles = nullptr;
+  signed char *d_i8_panels = nullptr;
   // Pulses too long for the whole-pulse LDS layout go through the tiled
   // batch path; its buffers are kept for the last (n, count) seen.
   mutable sidwt_batch *tiled = nullptr;
@@ -82,6 +92,48 @@ int check_pulse(const sidwt_plan *p, int64_t n, int64_t *N_out) {
   if (p->filter == SIDWT_LEGALL53_INT && !int_support_fits(p->desc, N)) return SIDWT_E_SIZE;
   *N_out = N;
   return SIDWT_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Digit panels of an integer plan for the int8 path (see build_i8_panels):
+// the phases come back from the device, the fewest digits that hold every
+// entry are chosen, and the path is kept only while every shift-class sum
+// of a tile (at most min(3, WL) digit pairs, 32 products of at most 2^14
+// per chunk of 16 offsets) stays below 2^31.  Leaves i8_wl = 0 when the
+// path does not apply.
+hipError_t build_i8(sidwt_plan *p) {
+  const PlanDesc &d = p->desc;
+  std::vector<int32_t> coef(p->coef_bytes / 4);
+  hipError_t e = hipMemcpy(coef.data(), p->coef, p->coef_bytes, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  long long maxabs = 0;
+  for (int32_t v : coef) maxabs = std::max(maxabs, std::llabs((long long)v));
+  const int wl = i8_weight_limbs(maxabs);
+  if (!wl) return hipSuccess;
+  std::vector<signed char> panels;
+  build_i8_panels(d, coef.data(), wl, &p->i8_tiles, &p->i8_tile_base, &panels);
+  const long long pairs = std::min(sidwt::kI8DataLimbs, wl);
+  for (const sidwt::I8Tile &t : p->i8_tiles)
+    if (pairs * 32LL * (t.nch[0] + t.nch[1]) * 16384LL >= (1LL << 31)) return hipSuccess;
+  e = hipMalloc(&p->d_i8_tiles, p->i8_tiles.size() * sizeof(sidwt::I8Tile));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_i8_tiles, p->i8_tiles.data(), p->i8_tiles.size() * sizeof(sidwt::I8Tile),
+                  hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMalloc(&p->d_i8_panels, std::max<size_t>(panels.size(), 16));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_i8_panels, panels.data(), panels.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    if (p->d_i8_tiles) (void)hipFree(p->d_i8_tiles);
+    if (p->d_i8_panels) (void)hipFree(p->d_i8_panels);
+    p->d_i8_tiles = nullptr;
+    p->d_i8_panels = nullptr;
+    return e;
+  }
+  p->i8_wl = wl;
+  return hipSuccess;
 }
 
 }  // namespace
@@ -176,6 +228,7 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
     in_len = lv.len[0];
   }
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e == hipSuccess && filter == SIDWT_LEGALL53_INT && i8_data_fits(d)) e = build_i8(p);
   if (e != hipSuccess || filter == SIDWT_LEGALL53_INT) {
     if (ref_dev) (void)hipFree(ref_dev);
     ref_dev = nullptr;
@@ -193,7 +246,9 @@ int sidwt_plan_create(int filter, int J, const void *ref, int64_t m, sidwt_plan 
 void sidwt_free(sidwt_plan *p) {
   if (!p) return;
   sidwt_batch_free(p->tiled);
-  if (p->coef || p->ref_dev) (void)hipDeviceSynchronize();
+  if (p->coef || p->ref_dev || p->d_i8_panels) (void)hipDeviceSynchronize();
+  if (p->d_i8_tiles) (void)hipFree(p->d_i8_tiles);
+  if (p->d_i8_panels) (void)hipFree(p->d_i8_panels);
   if (p->coef) (void)hipFree(p->coef);
   if (p->ref_dev) (void)hipFree(p->ref_dev);
   delete p;
@@ -229,6 +284,12 @@ static int correlate_many_planes(const sidwt_plan *p, const void *rx, int64_t n,
   if (rx_stride < n || out_stride < (int64_t)p->J * N) return SIDWT_E_INVAL;
   if (count == 0) return SIDWT_OK;
   if (!rx || !out) return SIDWT_E_INVAL;
+  if (p->i8_wl) {
+    sidwt::I8Layout il;
+    if (make_i8_layout(p->desc, p->i8_wl, p->i8_tiles.data(), p->i8_tile_base.data(), N, &il) == 0)
+      return map_err(sidwt::launch_fused_i8(il, p->d_i8_tiles, p->d_i8_panels, rx, n, count,
+                                            rx_stride, out, out_stride, planes, st));
+  }
   FusedLayout lay;
   if (make_layout(p->desc, N, &lay) == 0)
     return map_err(sidwt::launch_fused(p->desc, lay, rx, n, count, rx_stride, out, out_stride,
@@ -433,6 +494,18 @@ int sidwt_synth_many(int filter, int J, int to, const void *pyr, int64_t N, int6
   if (!pyr || !out) return SIDWT_E_INVAL;
   return map_err(sidwt::launch_synth(filter, J, to, (int)N, pyr, count, out,
                                      static_cast<hipStream_t>(hip_stream)));
+}
+
+int sidwt_plan_info(const sidwt_plan *p, int64_t *v, int nv) {
+  if (!p || !v || nv < 1) return SIDWT_E_INVAL;
+  long long panel_bytes = 0;
+  for (const sidwt::I8Tile &t : p->i8_tiles)
+    panel_bytes += (long long)(t.nch[0] + t.nch[1]) * p->i8_wl * sidwt::kI8ChunkBytes;
+  const int64_t vals[] = {p->filter, p->J, p->m, (int64_t)p->coef_bytes, p->i8_wl,
+                          p->i8_wl ? panel_bytes : 0};
+  const int k = (int)(sizeof(vals) / sizeof(vals[0]));
+  for (int i = 0; i < nv; ++i) v[i] = i < k ? vals[i] : 0;
+  return SIDWT_OK;
 }
 
 int sidwt_plan_phase(const sidwt_plan *p, int level, int band, int r, int32_t *lo, int32_t *len,

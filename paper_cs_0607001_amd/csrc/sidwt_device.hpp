@@ -86,6 +86,56 @@ struct FusedLayout {
   int total;                         // words of LDS
 };
 
+// ---------------------------------------------------------------------------
+// Integer planes on int8 matrix cores (v_mfma_i32_32x32x32_i8).
+//
+// Every integer operand x is written in balanced base-256 digits
+// x = sum_a d_a 256^a, d_a in [-128, 127] (kI8DataLimbs digits for the
+// pulse's coefficients, WL for the plan's phases), and each real product is
+// the sum of the digit products d_a(x) d_w(w) 256^(a+w): the int8 MFMAs
+// accumulate one int32 sum per shift class a + w, combined in int64 at the
+// end.  Exact while every class sum stays below 2^31 (digit products are at
+// most 2^14 in magnitude) and the pulse's coefficients fit the digits.
+//
+// GEMM of one level l (P = 2^l phases, L = N/P lags per phase), Toeplitz
+// blocked by T (T | L): rows are lag blocks p1 (lag p = T p1 + p0, p0 < T),
+// columns (p0, phase r, re/im out) in tiles of 16 complex columns
+// cc' = P p0 + r (output lag T P p1 + cc'), K the lag offset u (re/im in).
+// A lane of the B operand holds 8 offsets x (re, im) of one column: tile
+// tau's panel for band b is nch[b] chunks of 16 offsets starting at
+// offset u0[b], each chunk WL digit blocks of 64 lanes x 16 bytes (lane
+// order: column lane % 32 = 2 cc + (re/im out), offsets 8 (lane / 32) + 0..7
+// of the chunk, byte 2k + (re/im in)).  Entry (u, column) is the embedded
+// conj(w_r[u - p0 - delta_b]): re-out (w.re, w.im), im-out (-w.im, w.re),
+// with delta_b = lo_b - ws_b the shift of the band's window start ws_b
+// (lo_b aligned down to 8).
+// ---------------------------------------------------------------------------
+constexpr int kI8DataLimbs = 3;
+constexpr int kI8MaxWeightLimbs = 3;
+constexpr int kI8MaxLevels = 7;   // three data digits hold the pulse's level-7 coefficients
+constexpr int kI8ChunkBytes = 64 * 16;
+
+struct I8Tile {
+  long long off[2];     // byte offset of band b's panel in the plan's panel buffer
+  int u0[2];            // first lag offset of band b (a multiple of 8)
+  int nch[2];           // chunks of 16 offsets of band b
+};
+
+// LDS of the int8 fused kernel (bytes).  c_l of odd levels at 0 (N/2 int2),
+// of even levels at c_even (N/4 int2); the digit planes of the current
+// level at planes: band b, digit a at planes + (b * kI8DataLimbs + a) *
+// plane_bytes, position j (0 <= j < ext[l][b]) holding element
+// (ws[l][b] + j) mod L as two bytes (re, im).
+struct I8Layout {
+  int N, J, WL;
+  int T[kMaxLevels + 1];
+  int ws[kMaxLevels + 1][2];
+  int ext[kMaxLevels + 1][2];
+  int ntiles[kMaxLevels + 1];
+  int tile_base[kMaxLevels + 1];
+  int c_even, planes, plane_bytes, total;
+};
+
 // Uneven-batch descriptors (host builds them, the persistent kernel reads them).
 struct BatchPulse {
   const void *rx;       // caller's pulse (complex64), n samples

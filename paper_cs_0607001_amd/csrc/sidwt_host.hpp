@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "sidwt_device.hpp"
 
@@ -105,6 +106,156 @@ inline bool int_sums_exact(const PlanDesc &d, int ref_peak) {
   for (int l = 1; l <= d.J; ++l)
     if (int_level_sum_bound(d, l, xp, xr) >= 9007199254740992.0) return false;
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Integer planes on int8 matrix cores: digit ranges, the plan's panels and
+// the fused kernel's LDS layout (see I8Tile / I8Layout).
+// ---------------------------------------------------------------------------
+
+// Largest value n balanced base-256 digits hold: 127 (1 + 256 + ... ); the
+// most negative one is -128 (1 + 256 + ...).
+inline long long i8_max_pos(int n) {
+  long long s = 0, p = 1;
+  for (int i = 0; i < n; ++i, p *= 256) s += 127 * p;
+  return s;
+}
+
+// Digits for the plan's phases: the fewest (at least 1) whose range holds
+// every stored value and its negation (|v| <= maxabs); 0 if more than
+// kI8MaxWeightLimbs would be needed.
+inline int i8_weight_limbs(long long maxabs) {
+  for (int n = 1; n <= kI8MaxWeightLimbs; ++n)
+    if (i8_max_pos(n) >= maxabs) return n;
+  return 0;
+}
+
+// The pulse's coefficients fit kI8DataLimbs digits at every level: the
+// level-l bound 2 Xp_{l-1} + 1 (int_level_bounds, any int16 pulse).
+inline bool i8_data_fits(const PlanDesc &d) {
+  if (d.J > kI8MaxLevels) return false;
+  double xp[kMaxLevels + 1], xr[kMaxLevels + 1];
+  int_level_bounds(d, 0, xp, xr);
+  for (int l = 1; l <= d.J; ++l)
+    if (2.0 * xp[l - 1] + 1.0 > (double)i8_max_pos(kI8DataLimbs)) return false;
+  return true;
+}
+
+// Window start of band b at level l: the stored support's first index
+// aligned down to 8 (rows of the A operand then start on 16-byte
+// boundaries), and delta = lo - ws.
+inline int i8_window_start(const PlanDesc &d, int l, int b) {
+  const int lo = d.lv[l].lo[b];
+  return lo - pos_mod(lo, 8);
+}
+
+// The plan's B-operand panels (see I8Tile) for the widest blocking T = 8:
+// T P / 16 = P / 2 tiles per level; a call with a smaller T uses the first
+// T P / 16 of them (the columns cc' = P p0 + r of a tile do not depend on
+// T).  coef: the plan's pyramid on the host as int32 (re, im) pairs, at the
+// PlanDesc offsets.  The digits d(v, a) of every entry fill the panels.
+inline void build_i8_panels(const PlanDesc &d, const int32_t *coef, int WL,
+                            std::vector<I8Tile> *tiles, std::vector<int> *tile_base,
+                            std::vector<signed char> *panels) {
+  tiles->clear();
+  panels->clear();
+  tile_base->assign(kMaxLevels + 1, 0);
+  for (int l = 1; l <= d.J; ++l) {
+    const int P = 1 << l;
+    const int nt = std::max(1, P / 2);
+    (*tile_base)[l] = (int)tiles->size();
+    for (int tau = 0; tau < nt; ++tau) {
+      I8Tile t{};
+      const int p0a = (16 * tau) >> l, p0b = (16 * tau + 15) >> l;
+      for (int b = 0; b < 2; ++b) {
+        const int len = d.lv[l].len[b];
+        const int delta = d.lv[l].lo[b] - i8_window_start(d, l, b);
+        const int u0 = (p0a + delta) & ~7;
+        const int nch = (p0b + delta + len - u0 + 15) / 16;
+        t.u0[b] = u0;
+        t.nch[b] = nch;
+        t.off[b] = (long long)panels->size();
+        panels->resize(panels->size() + (size_t)nch * WL * kI8ChunkBytes, 0);
+        signed char *pan = panels->data() + t.off[b];
+        for (int c = 0; c < nch; ++c)
+          for (int lane = 0; lane < 64; ++lane) {
+            const int col = lane & 31, cc = col >> 1, ro = col & 1, g = lane >> 5;
+            const int ccp = 16 * tau + cc, p0 = ccp >> l, r = ccp & (P - 1);
+            for (int k = 0; k < 8; ++k) {
+              const int i = u0 + 16 * c + 8 * g + k - p0 - delta;
+              long long wr = 0, wi = 0;
+              if (i >= 0 && i < len) {
+                const int32_t *w = coef + 2 * (d.lv[l].off[b] + (long long)r * len + i);
+                wr = w[0];
+                wi = w[1];
+              }
+              for (int ci = 0; ci < 2; ++ci) {
+                const long long v = ro == 0 ? (ci == 0 ? wr : wi) : (ci == 0 ? -wi : wr);
+                long long x = v;
+                for (int a = 0; a < WL; ++a) {
+                  const long long dg = ((x + 128) & 255) - 128;
+                  x = (x - dg) >> 8;
+                  pan[((size_t)c * WL + a) * kI8ChunkBytes + 16 * lane + 2 * k + ci] =
+                      (signed char)dg;
+                }
+              }
+            }
+          }
+      }
+      tiles->push_back(t);
+    }
+  }
+}
+
+// Toeplitz block of level l for the int8 path: 8, halved (down to 2) while
+// the level has fewer than 32 lag-block rows and a tile stays full
+// (T P >= 16).  The level has ceil(L / T) rows; lags of the last row past
+// L - 1 are computed (their data wraps) but not stored.
+inline int i8_level_T(int N, int l) {
+  const int P = 1 << l, L = N >> l;
+  int T = 8;
+  while (T > 2 && T * P > 16 && L / T < 32) T >>= 1;
+  return T;
+}
+
+// LDS layout of the int8 fused kernel for one transform length (see
+// I8Layout); tiles / tile_base as build_i8_panels returns them.  0, or -5
+// when the path does not apply (levels, blocking, LDS).
+inline int make_i8_layout(const PlanDesc &d, int WL, const I8Tile *tiles, const int *tile_base,
+                          int64_t N64, I8Layout *lay) {
+  std::memset(lay, 0, sizeof(*lay));
+  if (WL < 1 || WL > kI8MaxWeightLimbs || !i8_data_fits(d) || N64 > kLdsWords) return -5;
+  const int N = (int)N64, J = d.J;
+  lay->N = N;
+  lay->J = J;
+  lay->WL = WL;
+  int pb = 0;
+  for (int l = 1; l <= J; ++l) {
+    const int T = i8_level_T(N, l);
+    const int P = 1 << l, L = N >> l, R = (L + T - 1) / T;
+    lay->T[l] = T;
+    lay->ntiles[l] = T * P / 16;
+    lay->tile_base[l] = tile_base[l];
+    for (int b = 0; b < 2; ++b) {
+      int kmax = 0;
+      for (int tau = 0; tau < lay->ntiles[l]; ++tau) {
+        const I8Tile &t = tiles[tile_base[l] + tau];
+        kmax = std::max(kmax, t.u0[b] + 16 * t.nch[b]);
+      }
+      // rows p1 < R read positions T p1 + u0 + (0 .. 16 nch - 1)
+      const int ext = (T * R + kmax + 7) & ~7;
+      lay->ws[l][b] = i8_window_start(d, l, b);
+      lay->ext[l][b] = ext;
+      pb = std::max(pb, 2 * ext);
+    }
+  }
+  lay->plane_bytes = (pb + 15) & ~15;
+  lay->c_even = 4 * N;                        // after N/2 int2 of the odd levels
+  lay->planes = (6 * N + 15) & ~15;           // after N/4 int2 of the even levels
+  const long long total = (long long)lay->planes + 2LL * kI8DataLimbs * lay->plane_bytes;
+  if (total > (long long)kLdsWords * 4) return -5;
+  lay->total = (int)total;
+  return 0;
 }
 
 // Integer plans hold linear-support phases; they equal the circular

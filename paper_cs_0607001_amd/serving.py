@@ -14,6 +14,10 @@ Serving loop (host side; all arithmetic runs in libsidwt's kernels):
     slot, after an asynchronous copy of their pulses from pinned memory;
   * a request larger than the whole budget is admitted alone once nothing
     else is in flight, so nothing is ever dropped;
+  * each slot keeps a device arena for its group's pulses and one for its
+    planes (grown only when a larger group arrives, so a steady serving
+    loop makes no device allocations); a group's tensors are views into
+    them, reused once the group has completed;
   * slots overlap on the device; completion is detected by polling an
     event per group, which frees the group's bytes and its slot;
   * latency = completion (event timestamp on the device clock, anchored to
@@ -65,6 +69,58 @@ class Server:
         self.max_group = max_group
         self.outputs = {}
         self.max_inflight_bytes = 0
+        self.in_arena = [None] * slots
+        self.out_arena = [None] * slots
+        self.arena_grows = 0
+
+    def _arena_bytes(self) -> int:
+        return sum(b.numel() * 8 for arenas in (self.in_arena, self.out_arena)
+                   for b in arenas if b is not None)
+
+    def _arena(self, arenas, slot: int, nelem: int, busy):
+        """The slot's arena with room for nelem complex64 values (called only
+        while the slot is idle, so the old buffer is no longer in use).  When
+        the arenas together would pass the HBM budget, those of idle slots
+        are released first."""
+        buf = arenas[slot]
+        if buf is None or buf.numel() < nelem:
+            old = 0 if buf is None else buf.numel()
+            arenas[slot] = None
+            want = max(nelem, old + old // 4)
+            if self._arena_bytes() + 8 * want > self.budget:
+                for a in (self.in_arena, self.out_arena):
+                    for s in range(len(a)):
+                        if s != slot and s not in busy:
+                            a[s] = None
+                if self._arena_bytes() + 8 * want > self.budget:
+                    want = nelem
+            arenas[slot] = self.torch.empty(want, dtype=self.torch.complex64, device=self.device)
+            self.arena_grows += 1
+        return arenas[slot]
+
+    def _views(self, slot: int, group, busy):
+        """Device tensors of one group: its pulses (copied from pinned host
+        memory on the slot's stream) and its planes, carved from the slot's
+        arenas."""
+        from . import transform_length
+        ns = [r.rx.numel() for r in group]
+        shapes = []
+        for r, n in zip(group, ns):
+            shapes.append((self.bank.eligible(n), r.J, transform_length(n, r.J)))
+        # planes start on even elements (16-byte aligned)
+        sizes = [e * j * N for e, j, N in shapes]
+        sizes = [s + (s & 1) for s in sizes]
+        ain = self._arena(self.in_arena, slot, sum(ns), busy)
+        aout = self._arena(self.out_arena, slot, max(1, sum(sizes)), busy)
+        rx, outs, oi, oo = [], [], 0, 0
+        for r, n, shp, sz in zip(group, ns, shapes, sizes):
+            x = ain[oi:oi + n]
+            x.copy_(r.rx, non_blocking=True)
+            rx.append(x)
+            outs.append(aout[oo:oo + shp[0] * shp[1] * shp[2]].view(shp))
+            oi += n
+            oo += sz
+        return rx, outs
 
     def footprint(self, n: int, J: int) -> int:
         from . import transform_length
@@ -119,9 +175,11 @@ class Server:
                     st = self.streams[slot]
                     adm = time.perf_counter() - t0
                     with torch.cuda.stream(st):
-                        rx = [r.rx.to(self.device, non_blocking=True) for r in group]
-                        outs = self.bank.correlate(rx, [r.J for r in group], stream=st,
-                                                   workspace=self.ws[slot])
+                        rx, outs = self._views(slot, group, inflight)
+                        self.bank.correlate(rx, [r.J for r in group], out=outs, stream=st,
+                                            workspace=self.ws[slot])
+                        # kept results leave the arena before the slot is reused
+                        outs = [o.clone() if r.keep else None for r, o in zip(group, outs)]
                         ev = torch.cuda.Event(enable_timing=True)
                         ev.record(st)
                     inflight[slot] = (ev, group, nbytes, adm, gid, outs)
@@ -144,6 +202,8 @@ class Server:
         for w in self.ws:
             w.free()
         self.ws = []
+        self.in_arena = [None] * len(self.streams)
+        self.out_arena = [None] * len(self.streams)
 
 
 def summarize(records, t_end=None) -> dict:

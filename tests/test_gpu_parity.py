@@ -236,6 +236,43 @@ def test_integer_full_scale_bit_exact(dev):
     assert np.array_equal(out.cpu().numpy(), O.correlate_int(8, ref, rx))
 
 
+def test_integer_plans_take_the_int8_path_where_it_applies(dev):
+    """Plans up to J = 7 run on int8 matrix cores with as many weight digits
+    as their phases need; deeper plans keep the FP64 form."""
+    torch, S = dev
+    rng = np.random.default_rng(5)
+    quiet = rng.integers(-100, 101, (40, 2)).astype(np.int16)
+    adc = rng.integers(-2047, 2048, (512, 2)).astype(np.int16)
+    loud = np.where(rng.random((60, 2)) < 0.5, 32767, -32768).astype(np.int16)
+    for ref, J, digits in ((quiet, 2, 2), (adc, 6, 2), (loud, 3, 3), (loud, 7, 3), (adc, 8, 0)):
+        with S.plan_create("legall53_int", J, ref) as plan:
+            info = plan.info()
+            assert info["i8_weight_digits"] == digits, (J, info)
+            assert (info["i8_panel_bytes"] > 0) == (digits > 0)
+
+
+@pytest.mark.parametrize("value", [32767, -32768])
+def test_integer_int8_path_at_the_digit_limits(dev, value):
+    """J = 7, the deepest plan on int8 matrix cores: a full-scale DC pulse
+    drives the level-7 coefficients to the top of the three data digits,
+    a full-scale reference needs three weight digits; plus random
+    full-scale signs, through one launch of several pulses."""
+    torch, S = dev
+    rng = np.random.default_rng(abs(value))
+    ref = np.where(rng.random((90, 2)) < 0.5, 32767, -32768).astype(np.int16)
+    n = 2048
+    rx = np.stack([np.full((n, 2), value), np.where(rng.random((n, 2)) < 0.5, 32767, -32768),
+                   rng.integers(-32768, 32768, (n, 2))]).astype(np.int16)
+    print(f"[case] int8 limits J=7 m=90 n={n} value={value}", flush=True)
+    with S.plan_create("legall53_int", 7, ref) as plan:
+        assert plan.info()["i8_weight_digits"] == 3
+        out = S.correlate_many(plan, torch.from_numpy(rx).cuda())
+        torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for i in range(rx.shape[0]):
+        assert np.array_equal(got[i], O.correlate_int(7, ref, rx[i])), i
+
+
 def test_integer_support_wrap_is_rejected(dev):
     torch, S = dev
     ref = np.ones((60, 2), np.int16)

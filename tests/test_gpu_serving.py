@@ -101,3 +101,21 @@ def test_summary_reports_latency_percentiles(env):
     assert 0 < s["p50_ms"] <= s["p99_ms"]
     assert s["samples_per_s"] > 0
     srv.close()
+
+
+def test_steady_serving_reuses_the_slot_arenas(env):
+    """After a first pass the slots' device arenas hold every group, so a
+    second pass over the same requests allocates nothing and gives the same
+    planes."""
+    torch, S, serving, bank, refs = env
+    srv = serving.Server(bank, slots=1, budget_bytes=4 << 30, max_group=1)
+    srv.run(requests(serving, torch, rate_hz=0))
+    first = {rid: o.cpu() for rid, o in srv.outputs.items()}
+    grows = srv.arena_grows
+    assert grows >= 2
+    srv.outputs = {}
+    srv.run(requests(serving, torch, rate_hz=0))
+    assert srv.arena_grows == grows
+    for rid, want in first.items():
+        assert torch.equal(srv.outputs[rid].cpu(), want)
+    srv.close()

@@ -105,11 +105,21 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
   const int rw = RT == 4 ? 2 : rows > 128 ? 4 : rows > 64 ? 2 : 1;
   const int wr = wave % rw, wt = wave / rw;
   const int rows_w = rows - RWS * wr;
-  const int t0 = tile0 + TW * wt;
-  const int nt_w = min(TW, tile0 + ntiles - t0);
+  // The wave's tiles: TW consecutive ones, except in the 128 x 2 shape,
+  // whose two wave columns take tiles (0, 3) and (1, 2) of the item's four:
+  // a level's panels lengthen with the tile index (the bank is sorted by
+  // reference length), so each column gets a long and a short one.
+  int tix[TW];
+  int nt_w = 0;
+#pragma unroll
+  for (int t = 0; t < TW; ++t) {
+    const int k = RT == 4 ? (t == 0 ? wt : 3 - wt) : TW * wt + t;
+    tix[t] = tile0 + k;
+    if (k < ntiles) nt_w = t + 1;
+  }
+  if (RT == 4 && wt == 0 && ntiles < 4) nt_w = 1;   // tile 3 missing: column 0 keeps tile 0
   if (rows_w <= 0 || nt_w <= 0) return;          // no barrier follows
   const int nh = min(RT, (rows_w + 31) >> 5);    // 32-row tiles in use
-  const BankTile *tb = tl + t0;
   const int rloc = RWS * wr + (lane & 31);       // row of the first row tile
   const int g = lane >> 5;                        // K half: offsets 4g..4g+3 of a step
   f32x16 acc[RT][TW];
@@ -128,15 +138,17 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
     int S = 0;
 #pragma unroll
     for (int t = 0; t < TW; ++t) {
-      steps[t] = t < nt_w ? tb[t].steps[b] : 0;
-      pw[t] = wts + (t < nt_w ? tb[t].off[b] : 0) + 4 * lane;
+      steps[t] = t < nt_w ? tl[tix[t]].steps[b] : 0;
+      pw[t] = wts + (t < nt_w ? tl[tix[t]].off[b] : 0) + 4 * lane;
       S = max(S, steps[t]);
     }
-    // Two operand sets (x, y) alternate: the loads of a step are issued one
-    // whole step of MFMAs before its use and no register moves follow them
-    // (a move would make the wave wait for the loads it just issued).  Load
+    // Panel operands (B) come from global memory and are issued NB - 1
+    // steps ahead in NB register sets; the data operands (A) come from LDS
+    // one row tile ahead (two sets), so few registers hold them.  Buffer
+    // indices are compile-time (the step loop is unrolled by NB).  Load
     // indices are clamped to valid steps, so no load sits under a branch;
     // only the MFMAs of a tile past its own K length are skipped.
+    constexpr int NB = RT == 4 ? 3 : 2;
     int last[TW];
 #pragma unroll
     for (int t = 0; t < TW; ++t) last[t] = steps[t] > 0 ? steps[t] - 1 : 0;
@@ -148,43 +160,42 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
         BL[t] = gload8<V8>(pp + 256);
       }
     };
-    auto loadA = [&](int st, V8(&AH)[RT], V8(&AL)[RT]) {
-      const int u0 = 8 * st + 4 * g;
-#pragma unroll
-      for (int h = 0; h < RT; ++h) {
-        AH[h] = load8<V8>(dhi + rloc + 32 * h + u0);
-        AL[h] = load8<V8>(dlo + rloc + 32 * h + u0);
-      }
-    };
-    auto mma = [&](int st, const V8(&AH)[RT], const V8(&AL)[RT], const V8(&BH)[TW],
-                   const V8(&BL)[TW]) {
-#pragma unroll
-      for (int t = 0; t < TW; ++t)
-        if (st < steps[t]) {
-#pragma unroll
-          for (int h = 0; h < RT; ++h)
-            if (h == 0 || h < nh) {
-              acc[h][t] = H::mma(AH[h], BH[t], acc[h][t]);
-              acc[h][t] = H::mma(AH[h], BL[t], acc[h][t]);
-              acc[h][t] = H::mma(AL[h], BH[t], acc[h][t]);
-            }
-        }
+    auto loadA = [&](int st, int h, V8 &AH, V8 &AL) {
+      const int u0 = 8 * min(st, S - 1) + 4 * g;
+      AH = load8<V8>(dhi + rloc + 32 * h + u0);
+      AL = load8<V8>(dlo + rloc + 32 * h + u0);
     };
     if (S > 0) {
-      V8 xbh[TW], xbl[TW], ybh[TW], ybl[TW], xah[RT], xal[RT], yah[RT], yal[RT];
-      loadB(0, xbh, xbl);
-      loadA(0, xah, xal);
-      for (int st = 0; st < S; st += 2) {
-        loadB(min(st + 1, S - 1), ybh, ybl);
-        loadA(min(st + 1, S - 1), yah, yal);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(st, xah, xal, xbh, xbl);
-        __builtin_amdgcn_sched_barrier(0);
-        loadB(min(st + 2, S - 1), xbh, xbl);
-        loadA(min(st + 2, S - 1), xah, xal);
-        __builtin_amdgcn_sched_barrier(0);
-        if (st + 1 < S) mma(st + 1, yah, yal, ybh, ybl);
-        __builtin_amdgcn_sched_barrier(0);
+      V8 bh[NB][TW], bl[NB][TW], ah[2], al[2];
+#pragma unroll
+      for (int k = 0; k < NB - 1; ++k) loadB(k, bh[k], bl[k]);
+      loadA(0, 0, ah[0], al[0]);
+      for (int s0 = 0; s0 < S; s0 += NB) {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+          const int st = s0 + k;
+          if (st >= S) break;
+          loadB(st + NB - 1, bh[(k + NB - 1) % NB], bl[(k + NB - 1) % NB]);
+#pragma unroll
+          for (int h = 0; h < RT; ++h) {
+            // next row tile's A (the first one of the next step after the last)
+            if (h + 1 < RT)
+              loadA(st, h + 1, ah[(h + 1) & 1], al[(h + 1) & 1]);
+            else
+              loadA(st + 1, 0, ah[(h + 1) & 1], al[(h + 1) & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (h == 0 || h < nh) {
+#pragma unroll
+              for (int t = 0; t < TW; ++t)
+                if (st < steps[t]) {
+                  acc[h][t] = H::mma(ah[h & 1], bh[k][t], acc[h][t]);
+                  acc[h][t] = H::mma(ah[h & 1], bl[k][t], acc[h][t]);
+                  acc[h][t] = H::mma(al[h & 1], bh[k][t], acc[h][t]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+        }
       }
     }
   }
@@ -207,7 +218,7 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
     if (t >= nt_w) break;
-    const int c = kBankTilePairs * (t0 + t) + ((ln & 31) >> 1);
+    const int c = kBankTilePairs * tix[t] + ((ln & 31) >> 1);
     const float scale =
         c < pairs ? inv_sd * rl[(c >> l) * (Jmax + 1) + l].inv_scale : 0.f;
 #pragma unroll
@@ -229,7 +240,7 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
         const int rest = kk >> lcpr;
         const int row = rest & 63;
         const int pp = ((rest >> 6) << lq) + 2 * ch;
-        const int cc = kBankTilePairs * (t0 + t) + pp;
+        const int cc = kBankTilePairs * tix[t] + pp;
         if (64 * hh + row < rows_w && cc < pairs) {
           const f32x4 v = *reinterpret_cast<const f32x4 *>(stg + row * kStageLd + 2 * pp);
           const int e = cc >> l, r = cc & (P - 1);

@@ -129,7 +129,19 @@ class Server:
 
     def run(self, requests, idle_sleep: float = 20e-6):
         """Serve `requests` (any order; sorted by arrival here).  Returns a
-        list of Record, one per request, in completion order."""
+        list of Record, one per request, in completion order.  Python's
+        cyclic garbage collector is paused for the run (a full collection
+        over the run's objects stalls the loop for tens of milliseconds)."""
+        import gc
+        enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, idle_sleep)
+        finally:
+            if enabled:
+                gc.enable()
+
+    def _run(self, requests, idle_sleep):
         torch = self.torch
         reqs = sorted(requests, key=lambda r: r.arrival)
         fp = {r.rid: self.footprint(r.rx.numel(), r.J) for r in reqs}

@@ -135,7 +135,11 @@ def test_bank_full_size_sampled(dev):
         torch.cuda.synchronize()
         srng = np.random.default_rng(12)
         ns = [n for n, _, _ in reqs]
-        picks = {0, 255, 128, int(np.argmax(ns))}
+        Es = [bank.eligible(n) for n in ns]
+        # also the shortest request and one whose eligible references end
+        # mid-bank (their tiles are a prefix of each level's tiles)
+        picks = {0, 255, 128, int(np.argmax(ns)), int(np.argmin(ns)),
+                 int(np.argmin([abs(e - 33) for e in Es]))}
         for i in sorted(picks):
             n, J, y = reqs[i]
             E = bank.eligible(n)

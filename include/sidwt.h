@@ -310,11 +310,12 @@ int sidwt_lift_generic(const sidwt_lifting *f, int J, const void *rx, int64_t n,
 /* ---- Uneven batches (one persistent launch) ------------------------------
  * A batch fixes `count` pulses, each with its own plan (float filters; the
  * filter and J may differ per pulse) and length n[i].  Short pulses are
- * processed whole in LDS; long ones are lifted level by level into a
- * library-owned HBM scratch pyramid and split into lag tiles of one level.
+ * processed whole in LDS; long ones are lifted, several levels per pass,
+ * into a library-owned HBM scratch pyramid and split into lag tiles of one
+ * level.
  * All items are sorted by estimated cost (largest first) and pulled from a
  * device work counter by one persistent kernel.  The launch sequence
- * (counter reset, per-level lifting of long pulses, persistent kernel) is
+ * (counter reset, lifting passes of long pulses, persistent kernels) is
  * captured in a HIP graph on first run and replayed afterwards; a run only
  * uploads the pulse / output pointers.  Plans must outlive the batch.
  * Calls that use one batch object must not overlap (they share its
@@ -333,9 +334,10 @@ int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int cou
  * device pointers, read during the call. */
 int sidwt_batch_run(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream);
 
-/* Autotuner: times candidate (fused_max_N, tile_window) pairs by running the
- * batch on these buffers (events on `hip_stream`), keeps the fastest.  The
- * outputs hold a valid result afterwards.  Synchronous. */
+/* Autotuner: times candidate tile windows, then fused/tiled splits, then
+ * lifting depths (see sidwt_batch_configure) by running the batch on these
+ * buffers (events on `hip_stream`), keeps the fastest.  The outputs hold a
+ * valid result afterwards.  Synchronous. */
 int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream);
 
 /* Set the split explicitly: pulses with N <= fused_max_N run whole in LDS
@@ -344,9 +346,18 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
  * near tile_window elements (64..32768).  Synchronous. */
 int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_window);
 
+/* As sidwt_batch_config, plus the scale-fusion depth of the long pulses'
+ * lifting: each pass lifts lift_depth consecutive levels (1..8) from one
+ * read of its input level (blocks of 4096 input samples with halos that
+ * cover every level of the pass; a level of at most 4096 samples is one
+ * block), and writes every level's bands to the scratch pyramid.  The
+ * default depth is 4.  Synchronous. */
+int sidwt_batch_configure(sidwt_batch *b, int64_t fused_max_N, int tile_window, int lift_depth);
+
 /* values[0..nvalues): fused_max_N, tile_window, items, whole-pulse items,
  * tile items, LDS bytes per workgroup, persistent grid size, scratch
- * bytes, tuned (0/1), best tuned time in microseconds. */
+ * bytes, tuned (0/1), best tuned time in microseconds, lifting depth,
+ * lifting passes (launches). */
 int sidwt_batch_info(const sidwt_batch *b, int64_t *values, int nvalues);
 
 /* NULL is a no-op; waits for the device to be idle. */

@@ -427,7 +427,8 @@ def version() -> str:
 # ---------------------------------------------------------------------------
 
 BATCH_INFO_KEYS = ("fused_max_N", "tile_window", "items", "whole_pulse_items", "tile_items",
-                   "lds_bytes", "grid", "scratch_bytes", "tuned", "tuned_us")
+                   "lds_bytes", "grid", "scratch_bytes", "tuned", "tuned_us", "lift_depth",
+                   "lift_passes")
 
 
 def _ptr_array(ptrs):
@@ -486,8 +487,13 @@ class Batch:
         check(lib().sidwt_batch_tune(self.handle, a, b, _stream_ptr(stream)), "sidwt_batch_tune")
         return self.info()
 
-    def config(self, fused_max_N: int, tile_window: int):
-        check(lib().sidwt_batch_config(self.handle, fused_max_N, tile_window), "sidwt_batch_config")
+    def config(self, fused_max_N: int, tile_window: int, lift_depth=None):
+        if lift_depth is None:
+            check(lib().sidwt_batch_config(self.handle, fused_max_N, tile_window),
+                  "sidwt_batch_config")
+        else:
+            check(lib().sidwt_batch_configure(self.handle, fused_max_N, tile_window, lift_depth),
+                  "sidwt_batch_configure")
 
     def info(self) -> dict:
         v = (ctypes.c_int64 * len(BATCH_INFO_KEYS))()

@@ -102,6 +102,8 @@ def _declare(L):
     L.sidwt_batch_tune.restype = i32
     L.sidwt_batch_config.argtypes = [vp, i64, i32]
     L.sidwt_batch_config.restype = i32
+    L.sidwt_batch_configure.argtypes = [vp, i64, i32, i32]
+    L.sidwt_batch_configure.restype = i32
     L.sidwt_batch_info.argtypes = [vp, c.POINTER(i64), i32]
     L.sidwt_batch_info.restype = i32
     L.sidwt_batch_free.argtypes = [vp]

@@ -5,15 +5,18 @@
 //   - short pulses (transform length N <= fused_max_N whose fused LDS
 //     layout fits) become one "whole pulse" work item each (lifting and all
 //     planes in LDS);
-//   - long pulses are lifted level by level into an HBM scratch pyramid and
-//     split into lag tiles (rows of one level) whose band windows hold about
-//     `tile_window` elements;
+//   - long pulses are lifted into an HBM scratch pyramid, `lift_depth`
+//     levels per pass (each pass reads its input level once, in blocks with
+//     halos, and writes every level it lifts), and split into lag tiles
+//     (rows of one level) whose band windows hold about `tile_window`
+//     elements;
 //   - items are ordered by estimated cost, largest first, and pulled by a
 //     persistent kernel from an atomic counter.
-// The launch sequence (counter reset, per-level lifting, persistent kernel)
+// The launch sequence (counter reset, lifting passes, persistent kernels)
 // is captured once in a HIP graph and replayed; each run only uploads the
 // caller's pulse and output pointers.  sidwt_batch_tune times candidate
-// (fused_max_N, tile_window) pairs on the caller's buffers and keeps the best.
+// tile windows, fused/tiled splits and lifting depths on the caller's
+// buffers and keeps the best.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,9 +34,9 @@
 namespace sidwt {
 hipError_t batch_set_lds(size_t bytes);
 hipError_t batch_occupancy(bool tiles_only, size_t lds_bytes, int *blocks_per_cu);
-hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
-                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
-                              float2 *scratch, hipStream_t st);
+hipError_t launch_lift_passes(const PlanDesc *plans, const BatchPulse *pulses,
+                              const LiftBlock *const *blocks, const int *nblocks,
+                              const size_t *lds, int npass, float2 *scratch, hipStream_t st);
 hipError_t launch_batch_reset(int *counters, int n, hipStream_t st);
 hipError_t launch_batch_items(bool tiles_only, const PlanDesc *plans, const FusedLayout *lays,
                               const BatchPulse *pulses, const BatchItem *items, int nitems,
@@ -49,8 +52,6 @@ using namespace sidwt;
 using namespace sidwt::host;
 
 namespace {
-
-constexpr int kLiftChunkPairs = 4096;
 
 int map_err(hipError_t e, const char *what = nullptr) {
   if (e == hipSuccess) return SIDWT_OK;
@@ -89,15 +90,20 @@ struct sidwt_batch {
   // configuration
   int fused_max_N = 8192;
   int tile_window = 3072;       // band-window budget of a tile, elements
+  int lift_depth = 4;           // levels per lifting pass of the tiled pulses
   int tuned = 0;
   double tuned_us = 0;
   // derived
   std::vector<FusedLayout> lays;
   std::vector<BatchPulse> pulses;
   std::vector<BatchItem> items;
-  std::vector<LiftChunk> chunks;     // all levels, grouped by level
-  int chunk_off[kMaxLevels + 2] = {0};
-  int nchunks[kMaxLevels + 2] = {0};
+  // Lifting passes of the tiled pulses: pass k lifts levels
+  // k*lift_depth + 1 .. (k+1)*lift_depth of every pulse that has them.
+  std::vector<LiftBlock> blocks;     // grouped by pass
+  int block_off[kMaxLevels + 1] = {0};
+  int nblocks[kMaxLevels + 1] = {0};
+  size_t pass_lds[kMaxLevels + 1] = {0};
+  int npass = 0;
   int Jmax = 0, n_fused = 0, n_tiles = 0, grid = 0;
   size_t lds_bytes = 0;
   // Items run in up to three persistent launches, in this order: whole-pulse
@@ -116,8 +122,8 @@ struct sidwt_batch {
   size_t c_pulses = 0;
   BatchItem *d_items = nullptr;
   size_t c_items = 0;
-  LiftChunk *d_chunks = nullptr;
-  size_t c_chunks = 0;
+  LiftBlock *d_blocks = nullptr;
+  size_t c_blocks = 0;
   int *d_counter = nullptr;          // one work counter per item class
   // Per-pulse device pointers: staged through pinned host memory (so the
   // copy is asynchronous) and uploaded only when they change; up_done marks
@@ -166,8 +172,9 @@ int build(sidwt_batch *b) {
   b->pulses.assign(b->count, BatchPulse{});
   b->uploaded = false;
   b->items.clear();
-  b->chunks.clear();
-  std::vector<std::vector<LiftChunk>> per_level(kMaxLevels + 1);
+  b->blocks.clear();
+  std::vector<std::vector<LiftBlock>> per_pass(kMaxLevels + 1);
+  std::vector<size_t> pass_lds(kMaxLevels + 1, 0);
   std::map<std::tuple<int, long long, int>, int> lay_index;  // (plan, N, kind)
   long long scratch = 0;
   size_t lds_words = 0;
@@ -226,9 +233,12 @@ int build(sidwt_batch *b) {
           costed_cls.push_back(costed_words.back() > kLdsWordsTwoPerCu ? 1 : 2);
           ++b->n_tiles;
         }
-        const int np = (int)(N >> l);
-        for (int k0 = 0; k0 < np; k0 += kLiftChunkPairs)
-          per_level[l].push_back(LiftChunk{i, k0, std::min(np, k0 + kLiftChunkPairs), 0});
+      }
+      for (int k = 0; k * b->lift_depth < d.J; ++k) {
+        const int l0 = k * b->lift_depth + 1, l1 = std::min(d.J, (k + 1) * b->lift_depth);
+        const int nb = lift_block_count((int)N, l0, l1);
+        for (int blk = 0; blk < nb; ++blk) per_pass[k].push_back(LiftBlock{i, l0, l1, blk});
+        pass_lds[k] = std::max(pass_lds[k], (size_t)lift_block_lds((int)N, l0, l1) * sizeof(float2));
       }
     }
   }
@@ -248,11 +258,13 @@ int build(sidwt_batch *b) {
     cls_words[c] = std::max<size_t>(cls_words[c], costed_words[k]);
     b->items.push_back(it);
   }
-  for (int l = 0; l <= kMaxLevels + 1; ++l) b->chunk_off[l] = b->nchunks[l] = 0;
-  for (int l = 1; l <= kMaxLevels; ++l) {
-    b->chunk_off[l] = (int)b->chunks.size();
-    b->nchunks[l] = (int)per_level[l].size();
-    b->chunks.insert(b->chunks.end(), per_level[l].begin(), per_level[l].end());
+  b->npass = 0;
+  for (int k = 0; k <= kMaxLevels; ++k) {
+    b->block_off[k] = (int)b->blocks.size();
+    b->nblocks[k] = (int)per_pass[k].size();
+    b->pass_lds[k] = pass_lds[k];
+    b->blocks.insert(b->blocks.end(), per_pass[k].begin(), per_pass[k].end());
+    if (b->nblocks[k]) b->npass = k + 1;
   }
   b->scratch_elems = scratch;
   b->lds_bytes = std::max<size_t>(lds_words * 4, b->n_tiles ? kBalMinLdsBytes : 1024);
@@ -261,7 +273,7 @@ int build(sidwt_batch *b) {
   if (!rc) rc = upload(&b->d_lays, &b->c_lays, b->lays);
   if (!rc) rc = upload(&b->d_pulses, &b->c_pulses, b->pulses);
   if (!rc) rc = upload(&b->d_items, &b->c_items, b->items);
-  if (!rc) rc = upload(&b->d_chunks, &b->c_chunks, b->chunks);
+  if (!rc) rc = upload(&b->d_blocks, &b->c_blocks, b->blocks);
   if (rc) return rc;
   if (b->scratch_cap < std::max<long long>(1, scratch)) {
     if (b->d_scratch) (void)hipFree(b->d_scratch);
@@ -295,12 +307,12 @@ int build(sidwt_batch *b) {
 }
 
 int enqueue(sidwt_batch *b, hipStream_t st) {
-  const LiftChunk *chunk_ptr[kMaxLevels + 2];
-  for (int l = 0; l <= kMaxLevels + 1; ++l) chunk_ptr[l] = b->d_chunks + b->chunk_off[l];
+  const LiftBlock *block_ptr[kMaxLevels + 1];
+  for (int k = 0; k <= kMaxLevels; ++k) block_ptr[k] = b->d_blocks + b->block_off[k];
   hipError_t e = launch_batch_reset(b->d_counter, 3, st);
   if (e == hipSuccess)
-    e = launch_lift_levels(b->d_plans, b->d_pulses, chunk_ptr, b->nchunks, b->Jmax, b->d_scratch,
-                           st);
+    e = launch_lift_passes(b->d_plans, b->d_pulses, block_ptr, b->nblocks, b->pass_lds, b->npass,
+                           b->d_scratch, st);
   int first = 0;
   for (int c = 0; c < 3 && e == hipSuccess; ++c) {
     e = launch_batch_items(c > 0, b->d_plans, b->d_lays, b->d_pulses, b->d_items + first,
@@ -455,7 +467,7 @@ void sidwt_batch_free(sidwt_batch *b) {
   (void)hipFree(b->d_lays);
   (void)hipFree(b->d_pulses);
   (void)hipFree(b->d_items);
-  (void)hipFree(b->d_chunks);
+  (void)hipFree(b->d_blocks);
   (void)hipFree(b->d_counter);
   (void)hipFree(b->d_scratch);
   if (b->h_pulses) (void)hipHostFree(b->h_pulses);
@@ -469,6 +481,13 @@ int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_window) {
   b->fused_max_N = (int)std::min<int64_t>(fused_max_N, 1 << 20);
   b->tile_window = tile_window;
   return build(b);
+}
+
+int sidwt_batch_configure(sidwt_batch *b, int64_t fused_max_N, int tile_window, int lift_depth) {
+  if (!b || lift_depth < 1 || lift_depth > 8) return SIDWT_E_INVAL;
+  if (fused_max_N < 0 || tile_window < 64 || tile_window > 32768) return SIDWT_E_INVAL;
+  b->lift_depth = lift_depth;
+  return sidwt_batch_config(b, fused_max_N, tile_window);
 }
 
 int sidwt_batch_run(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream) {
@@ -485,9 +504,10 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
     (void)hipEventDestroy(e0);
     return SIDWT_E_DEVICE;
   }
-  auto time_cfg = [&](int fmax, int window, double *us) -> int {
+  auto time_cfg = [&](int fmax, int window, int depth, double *us) -> int {
     b->fused_max_N = fmax;
     b->tile_window = window;
+    b->lift_depth = depth;
     int rc = build(b);
     if (rc) return rc;
     rc = run(b, rx, out, st, true);  // warm-up (also builds the graph)
@@ -503,15 +523,17 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
     *us = 1e3 * ms / 2;
     return SIDWT_OK;
   };
-  // Tile window first (with the default split), then the fused/tiled split.
+  // Tile window first (with the default split and lifting depth), then the
+  // fused/tiled split, then the levels per lifting pass.
   const int win_c[] = {1024, 2048, 3072, 4096, 6144};
   const int fmax_c[] = {0, 2048, 4096, 8192, 16384};
-  int best_win = b->tile_window, best_fmax = b->fused_max_N;
+  const int depth_c[] = {1, 2, 3, 4, 6};
+  int best_win = b->tile_window, best_fmax = b->fused_max_N, best_depth = 4;
   double best = 1e300;
   int rc = SIDWT_OK;
   for (int win : win_c) {
     double us;
-    int r = time_cfg(4096, win, &us);
+    int r = time_cfg(4096, win, best_depth, &us);
     if (r == SIDWT_E_UNSUPPORTED) continue;
     if (r) { rc = r; break; }
     if (us < best) { best = us; best_win = win; best_fmax = 4096; }
@@ -519,16 +541,25 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
   for (int fmax : fmax_c) {
     if (rc || fmax == 4096) continue;
     double us;
-    int r = time_cfg(fmax, best_win, &us);
+    int r = time_cfg(fmax, best_win, best_depth, &us);
     if (r == SIDWT_E_UNSUPPORTED) continue;
     if (r) { rc = r; break; }
     if (us < best) { best = us; best_fmax = fmax; }
+  }
+  for (int depth : depth_c) {
+    if (rc || depth == 4) continue;
+    double us;
+    int r = time_cfg(best_fmax, best_win, depth, &us);
+    if (r == SIDWT_E_UNSUPPORTED) continue;
+    if (r) { rc = r; break; }
+    if (us < best) { best = us; best_depth = depth; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   b->fused_max_N = best_fmax;
   b->tile_window = best_win;
+  b->lift_depth = best_depth;
   b->tuned = 1;
   b->tuned_us = best;
   return build(b);
@@ -539,7 +570,7 @@ int sidwt_batch_info(const sidwt_batch *b, int64_t *v, int nv) {
   const int64_t vals[] = {b->fused_max_N, b->tile_window, (int64_t)b->items.size(), b->n_fused,
                           b->n_tiles, (int64_t)b->lds_bytes, b->grid,
                           b->scratch_elems * (int64_t)sizeof(float2), b->tuned,
-                          (int64_t)(b->tuned_us + 0.5)};
+                          (int64_t)(b->tuned_us + 0.5), b->lift_depth, b->npass};
   const int k = (int)(sizeof(vals) / sizeof(vals[0]));
   for (int i = 0; i < nv; ++i) v[i] = i < k ? vals[i] : 0;
   return SIDWT_OK;

@@ -159,6 +159,71 @@ struct LiftChunk {
   int pad_;
 };
 
+// Multi-level lifting of long pulses (uneven batches): a pass lifts levels
+// l0..l1 of one pulse, block by block.  A block owns kLiftBlockIn samples of
+// the pass's input level l0-1 (c_{l0-1}; the pulse itself for l0 = 1), i.e.
+// kLiftBlockIn >> (l1 - l0 + 1) output pairs of level l1 and twice as many
+// at each level above; it reads its input stretch once with halos that cover
+// the lifting reach of every level of the pass (kLiftHalo samples beyond
+// 2k .. 2k+1 per side and level: 2 HL + (odd member before) <= 5 and
+// 2 HR <= 5 for every filter), lifts the levels in two alternating LDS
+// buffers, and writes only its own outputs.  An input level of at most
+// kLiftBlockIn samples is one block holding the whole (circular) level.
+constexpr int kLiftBlockIn = 4096;
+constexpr int kLiftHalo = 5;
+
+struct LiftBlock {
+  int pulse, l0, l1, blk;
+};
+
+__host__ __device__ inline bool lift_block_whole(int N, int l0) {
+  return (N >> (l0 - 1)) <= kLiftBlockIn;
+}
+
+__host__ __device__ inline int lift_block_count(int N, int l0, int l1) {
+  if (lift_block_whole(N, l0)) return 1;
+  const int B = kLiftBlockIn >> (l1 - l0 + 1), L1 = N >> l1;
+  return (L1 + B - 1) / B;
+}
+
+// Ranges of block blk, for l = l0 - 1 .. l1 (arrays indexed by level): the
+// pairs [s, e) of level l the block computes (unwrapped; level l0 - 1: the
+// input samples it loads) and its own pairs [os, oe) (l >= l0), which it
+// writes to the pyramid.
+__host__ __device__ inline void lift_block_ranges(int N, int l0, int l1, int blk, int *s, int *e,
+                                                  int *os, int *oe) {
+  if (lift_block_whole(N, l0)) {
+    for (int l = l0 - 1; l <= l1; ++l) {
+      s[l] = os[l] = 0;
+      e[l] = oe[l] = N >> l;
+    }
+    return;
+  }
+  const int B = kLiftBlockIn >> (l1 - l0 + 1);
+  for (int l = l0; l <= l1; ++l) {
+    const int sh = l1 - l;
+    os[l] = (blk * B) << sh;
+    const int end = ((blk + 1) * B) << sh, len = N >> l;
+    oe[l] = end < len ? end : len;
+  }
+  s[l1] = os[l1];
+  e[l1] = oe[l1];
+  for (int l = l1; l >= l0; --l) {
+    s[l - 1] = 2 * s[l] - kLiftHalo;
+    e[l - 1] = 2 * e[l] + kLiftHalo;
+  }
+  os[l0 - 1] = s[l0 - 1];
+  oe[l0 - 1] = e[l0 - 1];
+}
+
+// LDS elements (complex) one block of the pass needs: the input level's
+// stretch and level l0's (the two alternating buffers).
+__host__ __device__ inline int lift_block_lds(int N, int l0, int l1) {
+  int s[kMaxLevels + 1], e[kMaxLevels + 1], os[kMaxLevels + 1], oe[kMaxLevels + 1];
+  lift_block_ranges(N, l0, l1, 0, s, e, os, oe);
+  return (e[l0 - 1] - s[l0 - 1]) + (e[l0] - s[l0]);
+}
+
 // Offset (complex elements) of c_l inside a pulse's scratch pyramid; d_l
 // follows c_l.
 __host__ __device__ inline long long scratch_level_off(int N, int l) {

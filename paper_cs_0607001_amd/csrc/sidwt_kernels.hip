@@ -714,6 +714,72 @@ __global__ __launch_bounds__(256) void batch_lift(const PlanDesc *__restrict__ p
   }
 }
 
+// One block of a multi-level lifting pass (see LiftBlock): the input
+// stretch of level l0 - 1 into LDS buffer 0, then levels l0..l1 into the two
+// buffers in turn; each level's own pairs also go to the pyramid.  Reads
+// through the circular index are clamped to the stretch (lanes past a
+// window's end load values that are never used).
+template <int F>
+__device__ void lift_block(const BatchPulse &p, float2 *scratch, const LiftBlock &bk, float2 *sm) {
+  constexpr bool OB = YLift<F>::kOddBefore;
+  const int N = p.N, l0 = bk.l0, l1 = bk.l1;
+  int s[kMaxLevels + 1], e[kMaxLevels + 1], os[kMaxLevels + 1], oe[kMaxLevels + 1];
+  lift_block_ranges(N, l0, l1, bk.blk, s, e, os, oe);
+  float2 *buf[2] = {sm, sm + (e[l0 - 1] - s[l0 - 1])};
+  {
+    const int Nin = N >> (l0 - 1), S = s[l0 - 1], R = e[l0 - 1] - S;
+    if (l0 == 1) {
+      const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
+      const long long n = p.n;
+      for (int i = threadIdx.x; i < R; i += blockDim.x)
+        buf[0][i] = rx_sample_global(rx, n, pos_mod(S + i, Nin));
+    } else {
+      const float2 *src = scratch + p.scratch + scratch_level_off(N, l0 - 1);
+      for (int i = threadIdx.x; i < R; i += blockDim.x) buf[0][i] = src[pos_mod(S + i, Nin)];
+    }
+  }
+  __syncthreads();
+  for (int l = l0; l <= l1; ++l) {
+    const float2 *in = buf[(l - l0) & 1];
+    float2 *out = buf[(l - l0 + 1) & 1];
+    const int Nin = N >> (l - 1), np = N >> l;
+    const int S = s[l - 1], R = e[l - 1] - S, so = s[l];
+    const int o0 = os[l], o1 = oe[l];
+    float2 *c = scratch + p.scratch + scratch_level_off(N, l);
+    float2 *d = c + np;
+    lift_level_range<F, 2>(
+        np, s[l], e[l],
+        [&](int kc, float2 &ev, float2 &ov) {
+          const int q1 = OB ? (kc == 0 ? Nin - 1 : 2 * kc - 1) : 2 * kc + 1;
+          ev = in[min(pos_mod(2 * kc - S, Nin), R - 1)];
+          ov = in[min(pos_mod(q1 - S, Nin), R - 1)];
+        },
+        [&](int k, float2 cv, float2 dv) {
+          out[k - so] = cv;
+          if (k >= o0 && k < o1) {
+            c[k] = cv;
+            d[k] = dv;
+          }
+        });
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void batch_lift_blocks(const PlanDesc *__restrict__ plans,
+                                                         const BatchPulse *__restrict__ pulses,
+                                                         const LiftBlock *__restrict__ blocks,
+                                                         float2 *__restrict__ scratch) {
+  extern __shared__ __align__(16) float2 sm_lift[];
+  const LiftBlock bk = blocks[blockIdx.x];
+  const BatchPulse &p = pulses[bk.pulse];
+  switch (plans[p.plan].filter) {
+    case F_LEGALL53: lift_block<F_LEGALL53>(p, scratch, bk, sm_lift); break;
+    case F_CDF97: lift_block<F_CDF97>(p, scratch, bk, sm_lift); break;
+    case F_D4: lift_block<F_D4>(p, scratch, bk, sm_lift); break;
+    default: break;
+  }
+}
+
 // Lag tile of a long pulse: level l, rows [row0, row0 + rows).  `tl` is the
 // pulse's tile layout (per level: T, windows, staging geometry; bands start
 // at word 0, band 1 at 2*plane_stride, weights at w_at).
@@ -1088,6 +1154,21 @@ hipError_t launch_batch_reset(int *counters, int n, hipStream_t st) {
   if (n < 1 || n > 64) return hipErrorInvalidValue;
   hipLaunchKernelGGL(batch_reset, dim3(1), dim3(64), 0, st, counters, n);
   return hipGetLastError();
+}
+
+// Multi-level lifting passes: npass launches, pass k over nblocks[k]
+// blocks starting at blocks[k], with lds[k] bytes per workgroup.
+hipError_t launch_lift_passes(const PlanDesc *plans, const BatchPulse *pulses,
+                              const LiftBlock *const *blocks, const int *nblocks,
+                              const size_t *lds, int npass, float2 *scratch, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < npass && e == hipSuccess; ++k) {
+    if (nblocks[k] == 0) continue;
+    hipLaunchKernelGGL(batch_lift_blocks, dim3(nblocks[k]), dim3(256), lds[k], st, plans, pulses,
+                       blocks[k], scratch);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,

@@ -38,28 +38,17 @@ __device__ __forceinline__ f32x16 swap_mfma(float a, float b, f32x16 c) {
 }
 
 // ---------------------------------------------------------------------------
-// Redundant tree, one level.  Block (pulse, child phase p): L = N >> j pairs.
-// Level 1 reads the pulse (n valid samples, zero beyond); deeper levels read
-// level j - 1 of the workspace (N elements per pulse and level).
+// Redundant tree.  One level of one phase: the y-side lifting of a parent
+// sequence of Lp samples (sample(i), i < Lp, circular) advanced by b
+// samples, L = Lp / 2 outputs (store(k, v)), in register windows of 64
+// lanes with lane-shift taps.
 // ---------------------------------------------------------------------------
-template <int F>
-__global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
-    int j, int N, const float2 *__restrict__ parent_all, long long parent_stride, int n_valid,
-    float2 *__restrict__ child_all, long long child_stride) {
+template <int F, class Sample, class Store>
+__device__ __forceinline__ void tree_phase(int Lp, int b, Sample sample, Store store) {
   using Lf = YLift<F>;
   constexpr bool OB = Lf::kOddBefore;
   constexpr int OWN = 64 - Lf::HL - Lf::HR;
-  const int P = 1 << j;
-  const int p = blockIdx.x & (P - 1);
-  const long long pulse = blockIdx.x >> j;
-  const int pp = p & ((P >> 1) - 1);  // parent phase (0 at level 1)
-  const int b = p >> (j - 1);         // advance of the parent, in its samples
-  const int Lp = N >> (j - 1), L = N >> j;
-  const float2 *par = parent_all + pulse * parent_stride + (long long)pp * Lp;
-  float2 *child = child_all + pulse * child_stride + (long long)p * L;
-  auto sample = [&](int i) -> float2 {
-    return i < n_valid ? par[i] : make_float2(0.f, 0.f);
-  };
+  const int L = Lp >> 1;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int nw = blockDim.x >> 6;
@@ -90,11 +79,68 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int k = kk[u];
-      if (lane >= Lf::HL && lane < 64 - Lf::HR && k < L && (w0 + u) < nwin) {
-        typedef float f2 __attribute__((ext_vector_type(2)));
-        __builtin_nontemporal_store(f2{e[u].x, e[u].y}, reinterpret_cast<f2 *>(child + k));
-      }
+      if (lane >= Lf::HL && lane < 64 - Lf::HR && k < L && (w0 + u) < nwin) store(k, e[u]);
     }
+  }
+}
+
+__device__ __forceinline__ void store_stream2(float2 *p, float2 v) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(f2{v.x, v.y}, reinterpret_cast<f2 *>(p));
+}
+
+// Level j of the tree, block (pulse, child phase p): L = N >> j pairs from
+// parent phase p mod 2^(j-1) advanced by p >> (j-1).  Level 1 reads the
+// pulse (n valid samples, zero beyond); deeper levels read level j - 1 of
+// the workspace (N elements per pulse and level).
+template <int F>
+__global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
+    int j, int N, const float2 *__restrict__ parent_all, long long parent_stride, int n_valid,
+    float2 *__restrict__ child_all, long long child_stride) {
+  const int P = 1 << j;
+  const int p = blockIdx.x & (P - 1);
+  const long long pulse = blockIdx.x >> j;
+  const int pp = p & ((P >> 1) - 1);  // parent phase (0 at level 1)
+  const int b = p >> (j - 1);         // advance of the parent, in its samples
+  const int Lp = N >> (j - 1);
+  const float2 *par = parent_all + pulse * parent_stride + (long long)pp * Lp;
+  float2 *child = child_all + pulse * child_stride + (long long)p * (N >> j);
+  tree_phase<F>(
+      Lp, b, [&](int i) { return i < n_valid ? par[i] : make_float2(0.f, 0.f); },
+      [&](int k, float2 v) { store_stream2(child + k, v); });
+}
+
+// Levels j and j + 1 in one pass, block (pulse, level-j phase p): the child
+// is lifted from its parent into LDS (and written out), then both of its
+// children at level j + 1 (phases p and p + 2^j: the child advanced by 0 and
+// by 1 sample) are lifted from LDS.  The parent level is read once per
+// child instead of once per level, and one launch serves two levels.
+template <int F>
+__global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level2(
+    int j, int N, const float2 *__restrict__ parent_all, long long parent_stride, int n_valid,
+    float2 *__restrict__ child_all, long long child_stride) {
+  extern __shared__ __align__(16) float2 sm_tree[];
+  const int P = 1 << j;
+  const int p = blockIdx.x & (P - 1);
+  const long long pulse = blockIdx.x >> j;
+  const int pp = p & ((P >> 1) - 1);
+  const int b = p >> (j - 1);
+  const int Lp = N >> (j - 1), L = N >> j, L2 = N >> (j + 1);
+  const float2 *par = parent_all + pulse * parent_stride + (long long)pp * Lp;
+  float2 *child = child_all + pulse * child_stride + (long long)p * L;
+  tree_phase<F>(
+      Lp, b, [&](int i) { return i < n_valid ? par[i] : make_float2(0.f, 0.f); },
+      [&](int k, float2 v) {
+        sm_tree[k] = v;
+        store_stream2(child + k, v);
+      });
+  __syncthreads();
+  float2 *grand = child_all + pulse * child_stride + (long long)N;  // level j + 1
+#pragma unroll
+  for (int b2 = 0; b2 < 2; ++b2) {
+    float2 *g = grand + (long long)(p + (b2 << j)) * L2;
+    tree_phase<F>(
+        L, b2, [&](int i) { return sm_tree[i]; }, [&](int k, float2 v) { store_stream2(g + k, v); });
   }
 }
 
@@ -285,17 +331,38 @@ __global__ __launch_bounds__(kSwapThreads) void swap_correlate_chunks(
 size_t swap_lds_bytes(int N, int j, int K, int chunk) { return swap_lds_bytes_geom(N, j, K, chunk); }
 
 
+// A level's child phase held in LDS for the two-level pass: at most this
+// many complex elements (64 KB); longer levels run one level per launch.
+constexpr int kSwapTree2MaxL = 8192;
+
 template <int F>
 static hipError_t launch_swap_tree_t(int J, int N, const void *rx, long long n, long long count,
                                      long long rx_stride, void *tree, hipStream_t st) {
   float2 *t = static_cast<float2 *>(tree);
   const long long ts = (long long)(J - 1) * N;
-  for (int j = 1; j < J; ++j) {
+  static bool attr = false;
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void *)swap_tree_level2<F>,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             kSwapTree2MaxL * (int)sizeof(float2));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  for (int j = 1; j < J;) {
     const float2 *par = j == 1 ? static_cast<const float2 *>(rx) : t + (long long)(j - 2) * N;
     const long long ps = j == 1 ? rx_stride : ts;
     const int nv = j == 1 ? (int)n : (N >> (j - 1));
-    hipLaunchKernelGGL(swap_tree_level<F>, dim3((unsigned)(count << j)), dim3(kSwapTreeThreads),
-                       0, st, j, N, par, ps, nv, t + (long long)(j - 1) * N, ts);
+    if (j + 1 < J && (N >> j) <= kSwapTree2MaxL) {
+      hipLaunchKernelGGL(swap_tree_level2<F>, dim3((unsigned)(count << j)),
+                         dim3(kSwapTreeThreads), (size_t)(N >> j) * sizeof(float2), st, j, N,
+                         par, ps, nv, t + (long long)(j - 1) * N, ts);
+      j += 2;
+    } else {
+      hipLaunchKernelGGL(swap_tree_level<F>, dim3((unsigned)(count << j)),
+                         dim3(kSwapTreeThreads), 0, st, j, N, par, ps, nv,
+                         t + (long long)(j - 1) * N, ts);
+      j += 1;
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

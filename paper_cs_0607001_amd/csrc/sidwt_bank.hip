@@ -85,6 +85,24 @@ __device__ __forceinline__ V8 gload8(const unsigned *p) {
 
 constexpr int kBankThreads = 256;  // 4 waves; a wave owns 64 rows x up to 4 column tiles
 constexpr int kStageLd = 36;       // staging row stride (floats): 32 columns + pad, 16-byte rows
+// The 128 x 2 wave shape streams its panel steps into a per-wave LDS ring of
+// kBankRing steps (2 tiles x hi/lo x 64 lanes x 16 bytes each) by direct
+// global-to-LDS loads; the ring and the wave's output staging tile share
+// one region of kBankWaveBytes.
+constexpr int kBankRing = 3;
+constexpr int kBankRingStepBytes = 2 * 2 * 64 * 16;
+constexpr int kBankWaveBytes = kBankRing * kBankRingStepBytes > 64 * kStageLd * 4
+                                   ? kBankRing * kBankRingStepBytes
+                                   : 64 * kStageLd * 4;
+
+// s_waitcnt with only the vector-memory count limited (gfx9 encoding:
+// vmcnt bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their
+// maxima).
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
 
 // The waves of one item.  Wave = (row group wr of 32 RT rows, tile group wt
 // of TW = 8 / RT column tiles): RT = 2 gives 64 rows x 4 tiles (any row
@@ -165,7 +183,91 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
       AH = load8<V8>(dhi + rloc + 32 * h + u0);
       AL = load8<V8>(dlo + rloc + 32 * h + u0);
     };
-    if (S > 0) {
+    if constexpr (RT == 4) {
+      // Panel steps go to the wave's LDS ring kBankRing - 1 steps ahead
+      // (direct loads: no registers held); before a step, its own loads
+      // must have landed (the vector-memory count then holds only the
+      // later steps' loads), and its two tiles' hi and lo are read from the
+      // ring once.  A slot is refilled only after the step that read it
+      // has its panel values in registers.
+      char *ring = reinterpret_cast<char *>(stg);
+      auto dma = [&](int st) {
+        char *slot = ring + (st % kBankRing) * kBankRingStepBytes;
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+          const unsigned *pp = pw[t] + min(st, last[t]) * kBankStepWords;
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl)
+            __builtin_amdgcn_global_load_lds(
+                (const void __attribute__((address_space(1))) *)(pp + 256 * hl),
+                (void __attribute__((address_space(3))) *)(slot + (2 * t + hl) * 1024), 16, 0,
+                0);
+        }
+      };
+      auto readB = [&](int st, V8(&BH)[TW], V8(&BL)[TW]) {
+        const char *slot = ring + (st % kBankRing) * kBankRingStepBytes + 16 * lane;
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+          BH[t] = *reinterpret_cast<const V8 *>(slot + (2 * t) * 1024);
+          BL[t] = *reinterpret_cast<const V8 *>(slot + (2 * t + 1) * 1024);
+        }
+      };
+      // Order within a step: the next row tile's data operands are read
+      // before this row tile's MFMAs (their latency runs under them); after
+      // the last row tile the next step's panel slot is awaited and read.
+      // The steps where both tiles are live and those where only the longer
+      // one is run as two straight loops (the MFMAs of a finished tile are
+      // dropped at compile time, so the code has no branches for the
+      // waits to be placed around).  The 128 x 2 shape only runs full
+      // 256-row blocks, so all four row tiles are always in use.
+      constexpr int kOut = (kBankRing - 2) * 2 * TW;  // later steps' loads left in flight
+      if (S > 0) {
+        V8 bh[TW], bl[TW], ah[2], al[2];
+#pragma unroll
+        for (int k = 0; k < kBankRing - 1; ++k) dma(k);
+        wait_vmcnt<kOut>();
+        asm volatile("" ::: "memory");
+        readB(0, bh, bl);
+        loadA(0, 0, ah[0], al[0]);
+        auto phase = [&](auto mask_c, int st0, int st1) {
+          constexpr int MASK = decltype(mask_c)::value;
+          for (int st = st0; st < st1; ++st) {
+            __builtin_amdgcn_sched_barrier(0);
+            dma(st + kBankRing - 1);
+#pragma unroll
+            for (int h = 0; h < RT; ++h) {
+              if (h + 1 < RT)
+                loadA(st, h + 1, ah[(h + 1) & 1], al[(h + 1) & 1]);
+              else
+                loadA(st + 1, 0, ah[(h + 1) & 1], al[(h + 1) & 1]);
+              __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+              for (int t = 0; t < TW; ++t)
+                if ((MASK >> t) & 1) {
+                  acc[h][t] = H::mma(ah[h & 1], bh[t], acc[h][t]);
+                  acc[h][t] = H::mma(ah[h & 1], bl[t], acc[h][t]);
+                  acc[h][t] = H::mma(al[h & 1], bh[t], acc[h][t]);
+                }
+              __builtin_amdgcn_sched_barrier(0);
+            }
+            wait_vmcnt<kOut>();
+            asm volatile("" ::: "memory");
+            readB(st + 1, bh, bl);
+          }
+        };
+        static_assert(TW == 2, "two tiles per wave in the 128 x 2 shape");
+        const int both = min(steps[0], steps[1]);
+        phase(std::integral_constant<int, 3>(), 0, both);
+        if (steps[0] > both)
+          phase(std::integral_constant<int, 1>(), both, steps[0]);
+        else
+          phase(std::integral_constant<int, 2>(), both, steps[1]);
+        // the tail's clamped loads must land before the ring is refilled
+        // (next band) or turned into the staging tile
+        wait_vmcnt<0>();
+        asm volatile("" ::: "memory");
+      }
+    } else if (S > 0) {
       V8 bh[NB][TW], bl[NB][TW], ah[2], al[2];
 #pragma unroll
       for (int k = 0; k < NB - 1; ++k) loadB(k, bh[k], bl[k]);
@@ -301,7 +403,8 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int W = 64 * rw + umax;
   unsigned *dat = sm_bank;                      // [b][hilo][Wmax]
-  float *stg = reinterpret_cast<float *>(sm_bank + 4 * Wmax) + wave * 64 * kStageLd;
+  float *stg = reinterpret_cast<float *>(reinterpret_cast<char *>(sm_bank + 4 * Wmax) +
+                                        wave * kBankWaveBytes);
   const float2 *band0 = scratch + q.scratch + scratch_level_off(N, l);
 
   // Data windows: element i of band b is c_l / d_l at (row0 + lo + i) mod L.
@@ -352,7 +455,7 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
 }
 
 size_t bank_lds_bytes(int Wmax) {
-  return (size_t)(4 * Wmax) * 4 + (size_t)4 * 64 * kStageLd * 4;
+  return (size_t)(4 * Wmax) * 4 + (size_t)4 * kBankWaveBytes;
 }
 
 hipError_t launch_bank(bool bf16, const BankSeg *segs, const int *item_seg, int nitems,

@@ -136,8 +136,11 @@ int sidwt_set_stream(sidwt_plan *p, void *hip_stream);
  * the tiled path instead (levels lifted into an HBM scratch pyramid, then
  * lag tiles on every CU, as in the uneven batch); the plan keeps that
  * path's device buffers for the last (n, count) it saw, so calls on one
- * plan must not overlap.  SIDWT_E_UNSUPPORTED for an integer plan in that
- * case. */
+ * plan must not overlap.  An integer pulse too long for one workgroup is
+ * lifted into a temporary HBM pyramid and correlated in blocks of lag rows
+ * on int8 matrix cores (plans up to J = 7; the call synchronises its stream
+ * before it returns); deeper integer plans return SIDWT_E_UNSUPPORTED
+ * there. */
 int sidwt_correlate(const sidwt_plan *p, const void *rx, int64_t n, void *out);
 
 /* sidwt_correlate on `hip_stream`, leaving the plan untouched: safe to call

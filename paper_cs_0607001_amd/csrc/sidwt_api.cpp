@@ -37,6 +37,9 @@ hipError_t launch_synth(int filter, int J, int to, int N, const void *pyr, long 
 hipError_t launch_fused_i8(const I8Layout &lay, const I8Tile *tiles, const signed char *panels,
                            const void *rx, long long n, long long count, long long rx_stride,
                            void *out, long long out_stride, unsigned planes, hipStream_t st);
+hipError_t launch_i8_blocks(const I8TilePlan &tp, const I8Tile *tiles, const signed char *panels,
+                            const void *rx, long long n, long long count, long long rx_stride,
+                            void *pyr, void *out, long long out_stride, hipStream_t st);
 size_t synth_lds_bytes(int filter, int N, int to);
 }  // namespace sidwt
 
@@ -289,6 +292,22 @@ static int correlate_many_planes(const sidwt_plan *p, const void *rx, int64_t n,
     if (make_i8_layout(p->desc, p->i8_wl, p->i8_tiles.data(), p->i8_tile_base.data(), N, &il) == 0)
       return map_err(sidwt::launch_fused_i8(il, p->d_i8_tiles, p->d_i8_panels, rx, n, count,
                                             rx_stride, out, out_stride, planes, st));
+    // Too long for one workgroup: levels lifted into a temporary HBM
+    // pyramid, then blocks of lag-block rows (the stream is synchronised
+    // before the pyramid is released).
+    sidwt::I8TilePlan tp;
+    if (make_i8_tile_plan(p->desc, p->i8_wl, p->i8_tiles.data(), p->i8_tile_base.data(), N,
+                          &tp) == 0) {
+      if (planes != all) return SIDWT_E_UNSUPPORTED;
+      void *pyr = nullptr;
+      hipError_t e = hipMalloc(&pyr, (size_t)count * 2 * (size_t)N * sizeof(int2));
+      if (e != hipSuccess) return map_err(e);
+      e = sidwt::launch_i8_blocks(tp, p->d_i8_tiles, p->d_i8_panels, rx, n, count, rx_stride,
+                                  pyr, out, out_stride, st);
+      const hipError_t es = hipStreamSynchronize(st);
+      (void)hipFree(pyr);
+      return map_err(e != hipSuccess ? e : es);
+    }
   }
   FusedLayout lay;
   if (make_layout(p->desc, N, &lay) == 0)

@@ -136,6 +136,26 @@ struct I8Layout {
   int c_even, planes, plane_bytes, total;
 };
 
+// Integer pulses beyond one workgroup's LDS on the int8 path: the pulse is
+// lifted into an HBM pyramid (int32 pairs; c_l then d_l at
+// scratch_level_off(N, l)), and each level's lag-block rows are cut into
+// blocks whose digit windows fit LDS, one workgroup per (pulse, block).
+// Block k covers rows [r0, r0 + rows) of its level; its digit planes hold
+// positions j < T rows + K[l][b], element (ws[l][b] + T r0 + j) mod L.
+constexpr int kI8MaxBlocks = 64;
+struct I8Block {
+  int level, r0, rows;
+};
+struct I8TilePlan {
+  int N, J, WL, nblocks, plane_bytes;
+  int T[kMaxLevels + 1];
+  int ws[kMaxLevels + 1][2];
+  int K[kMaxLevels + 1][2];
+  int ntiles[kMaxLevels + 1];
+  int tile_base[kMaxLevels + 1];
+  I8Block blocks[kI8MaxBlocks];
+};
+
 // Uneven-batch descriptors (host builds them, the persistent kernel reads them).
 struct BatchPulse {
   const void *rx;       // caller's pulse (complex64), n samples

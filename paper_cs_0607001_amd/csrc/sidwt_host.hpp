@@ -258,6 +258,51 @@ inline int make_i8_layout(const PlanDesc &d, int WL, const I8Tile *tiles, const 
   return 0;
 }
 
+// Block plan of an integer pulse too long for the fused int8 kernel (see
+// I8TilePlan): per level the fused kernel's blocking T and window geometry,
+// rows cut into blocks of a multiple of 32 rows whose digit windows stay
+// within kI8TilePositions positions per plane.  0, or -5 when the path does
+// not apply.
+constexpr int kI8TilePositions = 8192;   // 6 planes x 16 KB of LDS
+inline int make_i8_tile_plan(const PlanDesc &d, int WL, const I8Tile *tiles, const int *tile_base,
+                             int64_t N64, I8TilePlan *tp) {
+  std::memset(tp, 0, sizeof(*tp));
+  if (WL < 1 || WL > kI8MaxWeightLimbs || !i8_data_fits(d) || N64 > kMaxN) return -5;
+  const int N = (int)N64, J = d.J;
+  tp->N = N;
+  tp->J = J;
+  tp->WL = WL;
+  int pos = 0;
+  for (int l = 1; l <= J; ++l) {
+    const int T = i8_level_T(N, l);
+    const int P = 1 << l, L = N >> l, R = (L + T - 1) / T;
+    tp->T[l] = T;
+    tp->ntiles[l] = T * P / 16;
+    tp->tile_base[l] = tile_base[l];
+    int kmax = 0;
+    for (int b = 0; b < 2; ++b) {
+      int k = 0;
+      for (int tau = 0; tau < tp->ntiles[l]; ++tau) {
+        const I8Tile &t = tiles[tile_base[l] + tau];
+        k = std::max(k, t.u0[b] + 16 * t.nch[b]);
+      }
+      tp->ws[l][b] = i8_window_start(d, l, b);
+      tp->K[l][b] = k;
+      kmax = std::max(kmax, k);
+    }
+    int rb = ((kI8TilePositions - kmax) / T) & ~31;
+    if (rb < 32) return -5;
+    rb = std::min(rb, (R + 31) & ~31);
+    for (int r0 = 0; r0 < R; r0 += rb) {
+      if (tp->nblocks >= kI8MaxBlocks) return -5;
+      tp->blocks[tp->nblocks++] = I8Block{l, r0, std::min(rb, R - r0)};
+      pos = std::max(pos, T * std::min(rb, R - r0) + kmax);
+    }
+  }
+  tp->plane_bytes = (2 * pos + 15) & ~15;
+  return 0;
+}
+
 // Integer plans hold linear-support phases; they equal the circular
 // integer lifting at length N only if no level's input support (plus the
 // one-sample delay and the +-2 reach of the 5/3 steps) wraps around.

@@ -57,23 +57,21 @@ __device__ __forceinline__ i32x4 load_a(const char *p) {
   }
 }
 
-// Plane l-1 of one pulse: units (32 lag-block rows, one column tile) go to
-// the waves round-robin.  Rows past the last (p1 >= R) read row R - 1 and
-// are not stored.
+// Rows [row0, row0 + R) of plane l-1 of one pulse, from digit planes whose
+// position 0 is row row0's first element (pb bytes per plane): units (32
+// lag-block rows, one column tile) go to the waves round-robin.  Rows past
+// the last (p1 >= R) read row R - 1 and are not stored.
 template <int WL, int T>
-__device__ void correlate_i8_level(const I8Layout &lay, int l, const I8Tile *__restrict__ tl,
+__device__ void correlate_i8_level(int N, int l, int ctiles, const I8Tile *__restrict__ tiles,
                                    const signed char *__restrict__ panels, const char *planes,
-                                   long long *__restrict__ outp) {
+                                   int pb, int row0, int R, long long *__restrict__ outp) {
   constexpr int NC = kI8DataLimbs + WL - 1;   // shift classes a + w
-  const int P = 1 << l, L = lay.N >> l, R = (L + T - 1) / T;
-  const long long N = lay.N;
-  const int rtiles = (R + 31) >> 5, ctiles = lay.ntiles[l];
+  const int P = 1 << l;
+  const int rtiles = (R + 31) >> 5;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int nw = blockDim.x >> 6;
   const int g = lane >> 5;
-  const int pb = lay.plane_bytes;
-  const I8Tile *tiles = tl + lay.tile_base[l];
   for (int unit = wave; unit < rtiles * ctiles; unit += nw) {
     const int rt = unit % rtiles, ct = unit / rtiles;
     const int p1 = min(rt * 32 + (lane & 31), R - 1);   // rows past R: read, not stored
@@ -108,7 +106,7 @@ __device__ void correlate_i8_level(const I8Layout &lay, int l, const I8Tile *__r
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int pr = rt * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
-      const long long si = (long long)T * P * pr + 16 * ct + cc;
+      const long long si = (long long)T * P * (row0 + pr) + 16 * ct + cc;
       if (pr < R && si < N) {   // lags of the last row past L - 1 are not stored
         long long v = 0;
 #pragma unroll
@@ -163,14 +161,116 @@ __global__ __launch_bounds__(kFusedThreads) void fused_correlate_i8(
     __syncthreads();
     if ((plane_mask >> (l - 1)) & 1u) {
       long long *op = out + 2LL * (l - 1) * N;
-      switch (lay.T[l]) {
-        case 8: correlate_i8_level<WL, 8>(lay, l, tiles, panels, planes, op); break;
-        case 4: correlate_i8_level<WL, 4>(lay, l, tiles, panels, planes, op); break;
-        default: correlate_i8_level<WL, 2>(lay, l, tiles, panels, planes, op); break;
+      const int T = lay.T[l], R = (L + T - 1) / T;
+      const I8Tile *tl = tiles + lay.tile_base[l];
+      switch (T) {
+        case 8: correlate_i8_level<WL, 8>(N, l, lay.ntiles[l], tl, panels, planes, pb, 0, R, op); break;
+        case 4: correlate_i8_level<WL, 4>(N, l, lay.ntiles[l], tl, panels, planes, pb, 0, R, op); break;
+        default: correlate_i8_level<WL, 2>(N, l, lay.ntiles[l], tl, panels, planes, pb, 0, R, op); break;
       }
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Pulses beyond one workgroup's LDS: the y-side lifting of one level into
+// the HBM pyramid (one workgroup per pulse and 4096 pairs), then the blocks.
+// ---------------------------------------------------------------------------
+constexpr int kI8LiftPairs = 4096;
+
+__global__ __launch_bounds__(256) void i8_lift_level(int l, int N, const short2 *__restrict__ rx_all,
+                                                     long long n, long long rx_stride,
+                                                     int2 *__restrict__ pyr, int chunks) {
+  const long long pulse = blockIdx.x / chunks;
+  const int ch = blockIdx.x - (int)(pulse * chunks);
+  const int np = N >> l;
+  const int k0 = ch * kI8LiftPairs, k1 = min(np, k0 + kI8LiftPairs);
+  int2 *base = pyr + pulse * 2LL * N;
+  int2 *c = base + scratch_level_off(N, l);
+  int2 *d = c + np;
+  auto store = [&](int k, int2 cv, int2 dv) {
+    c[k] = cv;
+    d[k] = dv;
+  };
+  if (l == 1) {
+    const short2 *rx = rx_all + pulse * rx_stride;
+    lift_level_range<F_LEGALL53_INT, 2>(
+        np, k0, k1,
+        [&](int kc, int2 &e, int2 &o) {
+          e = rx_sample(rx, (int)n, 2 * kc);
+          o = rx_sample(rx, (int)n, 2 * kc + 1);
+        },
+        store);
+  } else {
+    const int2 *src = base + scratch_level_off(N, l - 1);
+    lift_level_range<F_LEGALL53_INT, 2>(
+        np, k0, k1,
+        [&](int kc, int2 &e, int2 &o) {
+          e = src[2 * kc];
+          o = src[2 * kc + 1];
+        },
+        store);
+  }
+}
+
+template <int WL>
+__global__ __launch_bounds__(kFusedThreads) void i8_blocks(
+    I8TilePlan tp, const I8Tile *__restrict__ tiles, const signed char *__restrict__ panels,
+    const int2 *__restrict__ pyr, long long *__restrict__ out_all, long long out_stride) {
+  extern __shared__ __align__(16) char sm_i8b[];
+  const long long pulse = blockIdx.x / tp.nblocks;
+  const I8Block bk = tp.blocks[blockIdx.x - (int)(pulse * tp.nblocks)];
+  const int N = tp.N, l = bk.level, L = N >> l, T = tp.T[l], pb = tp.plane_bytes;
+  const int2 *c = pyr + pulse * 2LL * N + scratch_level_off(N, l);
+  for (int b = 0; b < 2; ++b) {
+    const int2 *src = c + (b ? L : 0);
+    const int W = T * bk.rows + tp.K[l][b];
+    const int q0 = tp.ws[l][b] + T * bk.r0;
+    for (int j = threadIdx.x; j < W; j += blockDim.x)
+      put_digits(sm_i8b, pb, b, 0, W, 1 << 30, j, src[pos_mod(q0 + j, L)]);
+  }
+  __syncthreads();
+  long long *op = out_all + pulse * out_stride * 2 + 2LL * (l - 1) * N;
+  const I8Tile *tl = tiles + tp.tile_base[l];
+  switch (T) {
+    case 8: correlate_i8_level<WL, 8>(N, l, tp.ntiles[l], tl, panels, sm_i8b, pb, bk.r0, bk.rows, op); break;
+    case 4: correlate_i8_level<WL, 4>(N, l, tp.ntiles[l], tl, panels, sm_i8b, pb, bk.r0, bk.rows, op); break;
+    default: correlate_i8_level<WL, 2>(N, l, tp.ntiles[l], tl, panels, sm_i8b, pb, bk.r0, bk.rows, op); break;
+  }
+}
+
+// Lifting of every level into pyr (2N int32 pairs per pulse), then one
+// launch over (pulse, block).
+hipError_t launch_i8_blocks(const I8TilePlan &tp, const I8Tile *tiles, const signed char *panels,
+                            const void *rx, long long n, long long count, long long rx_stride,
+                            void *pyr, void *out, long long out_stride, hipStream_t st) {
+  const int N = tp.N;
+  int2 *py = static_cast<int2 *>(pyr);
+  for (int l = 1; l <= tp.J; ++l) {
+    const int chunks = ((N >> l) + kI8LiftPairs - 1) / kI8LiftPairs;
+    if (count * chunks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(i8_lift_level, dim3((unsigned)(count * chunks)), dim3(256), 0, st, l, N,
+                       static_cast<const short2 *>(rx), n, rx_stride, py, chunks);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (count * tp.nblocks > 0x7fffffff) return hipErrorInvalidValue;
+  const size_t lds = (size_t)2 * kI8DataLimbs * tp.plane_bytes;
+  const void *fn = tp.WL == 1 ? (const void *)i8_blocks<1>
+                 : tp.WL == 2 ? (const void *)i8_blocks<2> : (const void *)i8_blocks<3>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     host::kLdsWords * 4);
+  if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)(count * tp.nblocks)), block(kFusedThreads);
+  long long *o = static_cast<long long *>(out);
+  switch (tp.WL) {
+    case 1: hipLaunchKernelGGL(i8_blocks<1>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride); break;
+    case 2: hipLaunchKernelGGL(i8_blocks<2>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride); break;
+    case 3: hipLaunchKernelGGL(i8_blocks<3>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int WL>

@@ -727,15 +727,23 @@ __device__ void lift_block(const BatchPulse &p, float2 *scratch, const LiftBlock
   lift_block_ranges(N, l0, l1, bk.blk, s, e, os, oe);
   float2 *buf[2] = {sm, sm + (e[l0 - 1] - s[l0 - 1])};
   {
+    // eight loads in flight per thread before their LDS stores
     const int Nin = N >> (l0 - 1), S = s[l0 - 1], R = e[l0 - 1] - S;
-    if (l0 == 1) {
-      const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
-      const long long n = p.n;
-      for (int i = threadIdx.x; i < R; i += blockDim.x)
-        buf[0][i] = rx_sample_global(rx, n, pos_mod(S + i, Nin));
-    } else {
-      const float2 *src = scratch + p.scratch + scratch_level_off(N, l0 - 1);
-      for (int i = threadIdx.x; i < R; i += blockDim.x) buf[0][i] = src[pos_mod(S + i, Nin)];
+    const int nt = blockDim.x;
+    const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
+    const long long n = p.n;
+    const float2 *src = scratch + p.scratch + scratch_level_off(N, l0 - 1);
+    constexpr int U = 8;
+    for (int i0 = threadIdx.x; i0 < R; i0 += U * nt) {
+      float2 v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = pos_mod(S + min(i0 + u * nt, R - 1), Nin);
+        v[u] = l0 == 1 ? rx_sample_global(rx, n, q) : src[q];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * nt < R) buf[0][i0 + u * nt] = v[u];
     }
   }
   __syncthreads();
@@ -750,9 +758,14 @@ __device__ void lift_block(const BatchPulse &p, float2 *scratch, const LiftBlock
     lift_level_range<F, 2>(
         np, s[l], e[l],
         [&](int kc, float2 &ev, float2 &ov) {
-          const int q1 = OB ? (kc == 0 ? Nin - 1 : 2 * kc - 1) : 2 * kc + 1;
-          ev = in[min(pos_mod(2 * kc - S, Nin), R - 1)];
-          ov = in[min(pos_mod(q1 - S, Nin), R - 1)];
+          // q - S lies in (-Nin, 2 Nin): one conditional wrap, no division
+          auto at = [&](int q) {
+            int i = q - S;
+            i = i < 0 ? i + Nin : (i >= Nin ? i - Nin : i);
+            return in[min(i, R - 1)];
+          };
+          ev = at(2 * kc);
+          ov = at(OB ? (kc == 0 ? Nin - 1 : 2 * kc - 1) : 2 * kc + 1);
         },
         [&](int k, float2 cv, float2 dv) {
           out[k - so] = cv;

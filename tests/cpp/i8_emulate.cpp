@@ -14,6 +14,7 @@
 // Exit 3 on an out-of-bounds read.
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 #include "../../paper_cs_0607001_amd/csrc/sidwt_host.hpp"
@@ -26,7 +27,10 @@ static void fail(const char *what, long long a, long long b) {
   std::exit(3);
 }
 
-int main() {
+int main(int argc, char **argv) {
+  // "blocks": the long-pulse form (make_i8_tile_plan), every level's rows
+  // in blocks whose digit windows start at their first row
+  const bool blocks = argc > 1 && std::strcmp(argv[1], "blocks") == 0;
   int J, N, m;
   if (std::scanf("%d %d %d", &J, &N, &m) != 3) return 2;
   PlanDesc d;
@@ -47,7 +51,19 @@ int main() {
   std::vector<signed char> panels;
   build_i8_panels(d, coef.data(), WL, &tiles, &tile_base, &panels);
   I8Layout lay;
-  if (make_i8_layout(d, WL, tiles.data(), tile_base.data(), N, &lay) != 0) return 5;
+  I8TilePlan tp;
+  if (blocks) {
+    if (make_i8_tile_plan(d, WL, tiles.data(), tile_base.data(), N, &tp) != 0) return 5;
+    std::memset(&lay, 0, sizeof(lay));
+    for (int l = 1; l <= J; ++l) {
+      lay.T[l] = tp.T[l];
+      lay.ntiles[l] = tp.ntiles[l];
+      lay.tile_base[l] = tp.tile_base[l];
+    }
+    lay.plane_bytes = tp.plane_bytes;
+  } else if (make_i8_layout(d, WL, tiles.data(), tile_base.data(), N, &lay) != 0) {
+    return 5;
+  }
   const int pb = lay.plane_bytes;
   std::vector<signed char> planes(2 * kI8DataLimbs * (size_t)pb, 0);
   std::vector<long long> out((size_t)J * N * 2, 0);
@@ -62,6 +78,26 @@ int main() {
       for (auto &v : band[b])
         if (std::scanf("%d", &v) != 1) return 2;
     }
+    // row blocks of the level: one block of all rows in the fused form
+    std::vector<I8Block> blist;
+    if (blocks) {
+      for (int q = 0; q < tp.nblocks; ++q)
+        if (tp.blocks[q].level == l) blist.push_back(tp.blocks[q]);
+    } else {
+      blist.push_back(I8Block{l, 0, (L + T - 1) / T});
+    }
+    for (const I8Block &bk : blist) {
+    std::fill(planes.begin(), planes.end(), 0);
+    int ws[2], ext[2];
+    for (int b = 0; b < 2; ++b) {
+      if (blocks) {
+        ws[b] = tp.ws[l][b] + T * bk.r0;   // window of the block, position 0 at row r0
+        ext[b] = T * bk.rows + tp.K[l][b];
+      } else {
+        ws[b] = lay.ws[l][b];
+        ext[b] = lay.ext[l][b];
+      }
+    }
     // digit planes, as put_digits writes them
     for (int b = 0; b < 2; ++b)
       for (int k = 0; k < L; ++k) {
@@ -75,7 +111,7 @@ int main() {
           di[a] = (signed char)i;
         }
         if (xr || xi) fail("digits", band[b][2 * k], band[b][2 * k + 1]);
-        for (int j = pos_mod(k - lay.ws[l][b], L); j < lay.ext[l][b]; j += L)
+        for (int j = pos_mod(k - ws[b], L); j < ext[b]; j += L)
           for (int a = 0; a < kI8DataLimbs; ++a) {
             const size_t o = (size_t)(b * kI8DataLimbs + a) * pb + 2 * j;
             if (2 * j + 1 >= pb) fail("plane write", j, pb);
@@ -84,7 +120,7 @@ int main() {
           }
       }
     // units, as correlate_i8_level runs them
-    const int R = (L + T - 1) / T, rtiles = (R + 31) >> 5, ctiles = lay.ntiles[l];
+    const int R = bk.rows, row0 = bk.r0, rtiles = (R + 31) >> 5, ctiles = lay.ntiles[l];
     const int NC = kI8DataLimbs + WL - 1;
     for (int unit = 0; unit < rtiles * ctiles; ++unit) {
       const int rt = unit % rtiles, ct = unit / rtiles;
@@ -99,7 +135,7 @@ int main() {
                   for (int g = 0; g < 2; ++g) {
                     const int p1 = std::min(rt * 32 + row, R - 1);
                     const long long pos = (long long)T * p1 + t.u0[b] + 8 * g + 16 * c;
-                    if (pos < 0 || pos + 8 > lay.ext[l][b]) fail("A position", pos, lay.ext[l][b]);
+                    if (pos < 0 || pos + 8 > ext[b]) fail("A position", pos, ext[b]);
                     const size_t ao = (size_t)(b * kI8DataLimbs + a) * pb + 2 * pos;
                     const int lane = 32 * g + col;
                     const long long bo = t.off[b] + (long long)(c * WL + w) * kI8ChunkBytes + 16 * lane;
@@ -119,11 +155,12 @@ int main() {
         for (int col = 0; col < 32; ++col) {
           long long v = 0;
           for (int s = 0; s < NC; ++s) v += acc[((size_t)s * 32 + row) * 32 + col] << (8 * s);
-          const long long si = (long long)T * P * pr + 16 * ct + (col >> 1);
+          const long long si = (long long)T * P * (row0 + pr) + 16 * ct + (col >> 1);
           if (si < N) out[((size_t)(l - 1) * N + si) * 2 + (col & 1)] = v;
         }
       }
     }
+    }  // blocks
   }
   for (long long v : out) std::printf("%lld\n", v);
   return 0;

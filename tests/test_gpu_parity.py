@@ -273,6 +273,32 @@ def test_integer_int8_path_at_the_digit_limits(dev, value):
         assert np.array_equal(got[i], O.correlate_int(7, ref, rx[i])), i
 
 
+@pytest.mark.parametrize("n,J,count", [(65536, 6, 2), (20000, 7, 1)])
+def test_integer_pulses_beyond_one_workgroup(dev, n, J, count):
+    """Integer pulses too long for one workgroup's LDS: lifted into an HBM
+    pyramid and correlated in blocks of lag rows on int8 matrix cores;
+    bit-exact on sampled lags (block edges, both ends) of every plane."""
+    torch, S = dev
+    rng = np.random.default_rng(n + J)
+    ref = rng.integers(-2047, 2048, (512, 2)).astype(np.int16)
+    rx = rng.integers(-32768, 32768, (count, n, 2)).astype(np.int16)
+    print(f"[case] int long pulse n={n} J={J} count={count}", flush=True)
+    with S.plan_create("legall53_int", J, ref) as plan:
+        out = S.correlate_many(plan, torch.from_numpy(rx).cuda())
+        torch.cuda.synchronize()
+    N = O.transform_length(n, J)
+    got = out.cpu().numpy()
+    lags = np.unique(np.concatenate([[0, 1, 2, N // 2, N - 2, N - 1],
+                                     rng.integers(0, N, 24),
+                                     # lags around the row blocks of level 1 (992 rows of 16 lags)
+                                     [992 * 16 - 1, 992 * 16, 992 * 16 + 1]]))
+    lags = lags[lags < N]
+    for i in range(count):
+        for j in range(J):
+            want = O.correlate_int_at(J, ref, rx[i], j, lags)
+            assert np.array_equal(got[i, j, lags], want), (i, j)
+
+
 def test_integer_support_wrap_is_rejected(dev):
     torch, S = dev
     ref = np.ones((60, 2), np.int16)

@@ -57,7 +57,7 @@ def plan_pyramid(J, ref):
     return np.concatenate(out).reshape(-1)
 
 
-def run_emu(emu, J, N, ref, rx):
+def run_emu(emu, J, N, ref, rx, mode=None):
     lines = [f"{J} {N} {ref.shape[0]}", " ".join(map(str, plan_pyramid(J, ref)))]
     y_re = O.zero_pad(rx[:, 0], N)
     y_im = O.zero_pad(rx[:, 1], N)
@@ -65,7 +65,8 @@ def run_emu(emu, J, N, ref, rx):
         (c_re, c_im), (d_re, d_im) = O.i2i_bands_y(y_re, y_im, l)
         lines.append(" ".join(map(str, np.stack([c_re, c_im], -1).reshape(-1))))
         lines.append(" ".join(map(str, np.stack([d_re, d_im], -1).reshape(-1))))
-    r = subprocess.run([emu], input="\n".join(lines), capture_output=True, text=True)
+    r = subprocess.run([emu] + ([mode] if mode else []), input="\n".join(lines),
+                       capture_output=True, text=True)
     assert r.returncode == 0, r.stdout[-400:] + r.stderr[-400:]
     head = r.stdout.splitlines()
     Ts = [int(x) for x in head[0].split()[1:]]
@@ -106,3 +107,18 @@ def test_int8_emulation_full_scale_dc_pulse(emu):
     lags = np.arange(0, N, 61)
     for j in (0, J - 1):
         assert np.array_equal(got[j, lags], O.correlate_int_at(J, ref, rx, j, lags))
+
+
+@pytest.mark.parametrize("J,n,m,seed", [(3, 20000, 300, 11), (5, 30000, 700, 12)])
+def test_int8_long_pulse_blocks_match_the_oracle(emu, J, n, m, seed):
+    """The long-pulse form: levels cut into row blocks (several per level at
+    these lengths), each block's digit window starting at its first row;
+    bit-exact against the oracle on sampled lags of every plane."""
+    rng = np.random.default_rng(seed)
+    ref = rng.integers(-2047, 2048, (m, 2)).astype(np.int64)
+    rx = rng.integers(-32768, 32768, (n, 2)).astype(np.int64)
+    N = O.transform_length(n, J)
+    _, _, got = run_emu(emu, J, N, ref, rx, mode="blocks")
+    lags = np.unique(np.concatenate([np.arange(0, N, 397), [1, N // 2, N - 1]]))
+    for j in range(J):
+        assert np.array_equal(got[j, lags], O.correlate_int_at(J, ref, rx, j, lags)), j

@@ -84,7 +84,7 @@ def algorithmic_flops_per_pulse(S, plan, N):
 
 
 PROFILE = os.path.join(ROOT, "profiles", "fused_correlate_cdf97_4096x8192_J5.md")
-KERNEL_SOURCES = ["sidwt_kernels.hip", "sidwt_device.hpp", "sidwt_host.hpp"]
+KERNEL_SOURCES = ["sidwt_kernels.hip", "sidwt_lift.hpp", "sidwt_device.hpp", "sidwt_host.hpp"]
 
 
 def profiled_traffic():

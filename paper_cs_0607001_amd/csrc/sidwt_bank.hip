@@ -84,7 +84,8 @@ __device__ __forceinline__ V8 gload8(const unsigned *p) {
 }
 
 constexpr int kBankThreads = 256;  // 4 waves; a wave owns 64 rows x up to 4 column tiles
-constexpr int kStageLd = 36;       // staging row stride (floats): 32 columns + pad, 16-byte rows
+constexpr int kStageLd = 36;
+constexpr int kBankFillRegs = 6;   // data window elements per thread and band held in registers       // staging row stride (floats): 32 columns + pad, 16-byte rows
 // The 128 x 2 wave shape streams its panel steps into a per-wave LDS ring of
 // kBankRing steps (2 tiles x hi/lo x 64 lanes x 16 bytes each) by direct
 // global-to-LDS loads; the ring and the wave's output staging tile share
@@ -148,7 +149,7 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[h][t][i] = 0.f;
 
-  for (int b = 0; b < 2; ++b) {
+  if constexpr (RT == 4) for (int b = 0; b < 2; ++b) {
     const unsigned *dhi = dat + (2 * b) * Wmax;
     const unsigned *dlo = dhi + Wmax;
     int steps[TW];
@@ -267,29 +268,74 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
         wait_vmcnt<0>();
         asm volatile("" ::: "memory");
       }
-    } else if (S > 0) {
-      V8 bh[NB][TW], bl[NB][TW], ah[2], al[2];
+    }
+  }
+  if constexpr (RT == 2) {
+    // One step sequence over both bands (band 0's steps, then band 1's),
+    // so the panel prefetch runs across the band boundary instead of
+    // starting cold twice.  Panel operands (B) come from global memory one
+    // step ahead in two register sets; the data operands (A) come from LDS
+    // one row tile ahead (two sets).  Load indices are clamped to valid
+    // steps, so no load sits under a branch; only the MFMAs of a tile past
+    // its own K length are skipped.
+    int steps[2][TW], last[2][TW], Sb[2];
+    long long woff[2][TW];
 #pragma unroll
-      for (int k = 0; k < NB - 1; ++k) loadB(k, bh[k], bl[k]);
+    for (int b = 0; b < 2; ++b) {
+      Sb[b] = 0;
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        steps[b][t] = t < nt_w ? tl[tix[t]].steps[b] : 0;
+        woff[b][t] = t < nt_w ? tl[tix[t]].off[b] : 0;
+        last[b][t] = steps[b][t] > 0 ? steps[b][t] - 1 : 0;
+        Sb[b] = max(Sb[b], steps[b][t]);
+      }
+    }
+    const int S = Sb[0] + Sb[1];
+    const unsigned *wl = wts + 4 * lane;
+    auto loadB = [&](int i, V8(&BH)[TW], V8(&BL)[TW]) {
+      const bool b1 = i >= Sb[0];
+      const int st = b1 ? i - Sb[0] : i;
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        const unsigned *pp = wl + (b1 ? woff[1][t] : woff[0][t]) +
+                             min(st, b1 ? last[1][t] : last[0][t]) * kBankStepWords;
+        BH[t] = gload8<V8>(pp);
+        BL[t] = gload8<V8>(pp + 256);
+      }
+    };
+    auto loadA = [&](int i, int h, V8 &AH, V8 &AL) {
+      const int ii = min(i, S - 1);
+      const bool b1 = ii >= Sb[0];
+      const int u0 = 8 * (b1 ? ii - Sb[0] : ii) + 4 * g;
+      const unsigned *dh = dat + (b1 ? 2 * Wmax : 0) + rloc + 32 * h + u0;
+      AH = load8<V8>(dh);
+      AL = load8<V8>(dh + Wmax);
+    };
+    if (S > 0) {
+      V8 bh[2][TW], bl[2][TW], ah[2], al[2];
+      loadB(0, bh[0], bl[0]);
       loadA(0, 0, ah[0], al[0]);
-      for (int s0 = 0; s0 < S; s0 += NB) {
+      for (int s0 = 0; s0 < S; s0 += 2) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-          const int st = s0 + k;
-          if (st >= S) break;
-          loadB(st + NB - 1, bh[(k + NB - 1) % NB], bl[(k + NB - 1) % NB]);
+        for (int k = 0; k < 2; ++k) {
+          const int i = s0 + k;
+          if (i >= S) break;
+          loadB(i + 1, bh[k ^ 1], bl[k ^ 1]);
+          const bool b1 = i >= Sb[0];
+          const int st = b1 ? i - Sb[0] : i;
 #pragma unroll
           for (int h = 0; h < RT; ++h) {
             // next row tile's A (the first one of the next step after the last)
             if (h + 1 < RT)
-              loadA(st, h + 1, ah[(h + 1) & 1], al[(h + 1) & 1]);
+              loadA(i, h + 1, ah[(h + 1) & 1], al[(h + 1) & 1]);
             else
-              loadA(st + 1, 0, ah[(h + 1) & 1], al[(h + 1) & 1]);
+              loadA(i + 1, 0, ah[(h + 1) & 1], al[(h + 1) & 1]);
             __builtin_amdgcn_sched_barrier(0);
             if (h == 0 || h < nh) {
 #pragma unroll
               for (int t = 0; t < TW; ++t)
-                if (st < steps[t]) {
+                if (st < (b1 ? steps[1][t] : steps[0][t])) {
                   acc[h][t] = H::mma(ah[h & 1], bh[k][t], acc[h][t]);
                   acc[h][t] = H::mma(ah[h & 1], bl[k][t], acc[h][t]);
                   acc[h][t] = H::mma(al[h & 1], bh[k][t], acc[h][t]);
@@ -317,10 +363,22 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
   const int pairs = q.E * P;
   const int lq = min(l, 4);                       // log2 Q
   const int lcpr = lq - 1;                        // log2 runs per lag
+  // Per-lane run of each of the 8 store rounds (the same for every tile and
+  // row chunk): staging row and first pair; row < 64 and pp <= 14, so the
+  // staging reads stay inside the tile.
+  int srow[8], spp[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kk = 64 * j + ln;
+    const int rest = kk >> lcpr;
+    srow[j] = rest & 63;
+    spp[j] = ((rest >> 6) << lq) + 2 * (kk & ((1 << lcpr) - 1));
+  }
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
     if (t >= nt_w) break;
-    const int c = kBankTilePairs * tix[t] + ((ln & 31) >> 1);
+    const int c0 = kBankTilePairs * tix[t];
+    const int c = c0 + ((ln & 31) >> 1);
     const float scale =
         c < pairs ? inv_sd * rl[(c >> l) * (Jmax + 1) + l].inv_scale : 0.f;
 #pragma unroll
@@ -335,20 +393,33 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // all eight staging reads first, then the guarded stores
+      f32x4 v[8];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int kk = 64 * j + ln;
-        const int ch = kk & ((1 << lcpr) - 1);
-        const int rest = kk >> lcpr;
-        const int row = rest & 63;
-        const int pp = ((rest >> 6) << lq) + 2 * ch;
-        const int cc = kBankTilePairs * tix[t] + pp;
-        if (64 * hh + row < rows_w && cc < pairs) {
-          const f32x4 v = *reinterpret_cast<const f32x4 *>(stg + row * kStageLd + 2 * pp);
-          const int e = cc >> l, r = cc & (P - 1);
-          float *o = out + 2 * (((long long)e * q.J + (l - 1)) * N +
-                                (long long)P * (row0 + RWS * wr + 64 * hh + row) + r);
-          __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(o));
+      for (int j = 0; j < 8; ++j)
+        v[j] = *reinterpret_cast<const f32x4 *>(stg + srow[j] * kStageLd + 2 * spp[j]);
+      const int rbase = row0 + RWS * wr + 64 * hh;
+      if (l >= 4) {
+        // 2^l >= 16: the tile's 16 pairs are phases c0 mod 2^l .. of one
+        // reference, so the run addresses differ from a uniform base only
+        // by the lane's row and pair
+        const int e = c0 >> l, r0 = c0 & (P - 1);
+        float *ob = out + 2 * (((long long)e * q.J + (l - 1)) * N + (long long)P * rbase + r0);
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (64 * hh + srow[j] < rows_w && c0 + spp[j] < pairs)
+            __builtin_nontemporal_store(
+                v[j], reinterpret_cast<f32x4 *>(ob + 2 * (P * srow[j] + spp[j])));
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int cc = c0 + spp[j];
+          if (64 * hh + srow[j] < rows_w && cc < pairs) {
+            const int e = cc >> l, r = cc & (P - 1);
+            float *o = out + 2 * (((long long)e * q.J + (l - 1)) * N +
+                                  (long long)P * (rbase + srow[j]) + r);
+            __builtin_nontemporal_store(v[j], reinterpret_cast<f32x4 *>(o));
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -372,6 +443,7 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
     const float2 *__restrict__ scratch, int Wmax) {
   extern __shared__ __align__(16) unsigned sm_bank[];
   __shared__ float s_max;
+  __shared__ int s_umax;
 
   // Item: segment, row block and tile group (uniform across the block).
   const BankSeg sg = segs[item_seg[blockIdx.x]];
@@ -394,51 +466,93 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   const int tile0 = grp * per * sg.gmul;
   const int ntiles = min(per * sg.gmul, sg.ntiles - tile0);
   const BankTile *tl = tiles + tile_base[l];
-  int umax = 0;
-  for (int t = tile0; t < tile0 + ntiles; ++t)
-    umax = max(umax, 8 * max(tl[t].steps[0], tl[t].steps[1]));
-
   const int tid = threadIdx.x, nt = blockDim.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  // Longest window of the item's tiles (at most kBankThreads tiles: one per
+  // thread, then a wave and a block maximum).
+  int um = 0;
+  for (int t = tid; t < ntiles; t += nt)
+    um = max(um, 8 * max(tl[tile0 + t].steps[0], tl[tile0 + t].steps[1]));
+  for (int o = 32; o > 0; o >>= 1) um = max(um, __shfl_xor(um, o, 64));
+  if (tid == 0) {
+    s_umax = 0;
+    s_max = 0.f;
+  }
+  __syncthreads();
+  if (lane == 0) atomicMax(&s_umax, um);
+  __syncthreads();
+  const int umax = s_umax;
   const int W = 64 * rw + umax;
   unsigned *dat = sm_bank;                      // [b][hilo][Wmax]
   float *stg = reinterpret_cast<float *>(reinterpret_cast<char *>(sm_bank + 4 * Wmax) +
                                         wave * kBankWaveBytes);
   const float2 *band0 = scratch + q.scratch + scratch_level_off(N, l);
+  const int e0[2] = {row0 + lo_lb[2 * l], row0 + lo_lb[2 * l + 1]};
 
-  // Data windows: element i of band b is c_l / d_l at (row0 + lo + i) mod L.
-  if (tid == 0) s_max = 0.f;
-  __syncthreads();
-  float mx = 0.f;
-  for (int b = 0; b < 2; ++b) {
-    const float2 *src = band0 + (b ? L : 0);
-    const int e0 = row0 + lo_lb[2 * l + b];
-    for (int i = tid; i < W; i += nt) {
-      const float2 x = src[pos_mod(e0 + i, L)];
-      mx = fmaxf(mx, fmaxf(fabsf(x.x), fabsf(x.y)));
-    }
-  }
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-  if (lane == 0) atomicMax(reinterpret_cast<int *>(&s_max), __float_as_int(mx));
-  __syncthreads();
-  int ex = 0;
-  (void)frexpf(s_max, &ex);
-  const float sd = s_max > 0.f ? ldexpf(1.f, 14 - ex) : 1.f;  // largest |x| sd < 2^14
-  const float inv_sd = 1.f / sd;
-  for (int b = 0; b < 2; ++b) {
-    const float2 *src = band0 + (b ? L : 0);
-    const int e0 = row0 + lo_lb[2 * l + b];
+  // Data windows: element i of band b is c_l / d_l at (e0_b + i) mod L,
+  // scaled by a power of two sd (largest |x| sd < 2^14) and split into hi
+  // and lo.  Windows of up to kBankFillRegs elements per thread and band
+  // are read once, every load in flight together, and kept in registers
+  // across the block maximum; longer ones are read twice.
+  auto split_store = [&](int b, int i, float2 x, float sd) {
     unsigned *hi = dat + (2 * b) * Wmax;
-    unsigned *lo = hi + Wmax;
-    for (int i = tid; i < W; i += nt) {
-      const float2 x = src[pos_mod(e0 + i, L)];
-      const float xr = x.x * sd, xi = x.y * sd;
-      const unsigned h = pack2<BF16>(xr, xi);
-      hi[i] = h;
-      lo[i] = pack2<BF16>(xr - unpack_lo<BF16>(h), xi - unpack_hi<BF16>(h));
+    const float xr = x.x * sd, xi = x.y * sd;
+    const unsigned h = pack2<BF16>(xr, xi);
+    hi[i] = h;
+    hi[Wmax + i] = pack2<BF16>(xr - unpack_lo<BF16>(h), xi - unpack_hi<BF16>(h));
+  };
+  auto scale_of = [&](float m) {
+    int ex = 0;
+    (void)frexpf(m, &ex);
+    return m > 0.f ? ldexpf(1.f, 14 - ex) : 1.f;
+  };
+  float mx = 0.f;
+  float sd;
+  if (W <= kBankFillRegs * kBankThreads) {
+    float2 v[2][kBankFillRegs];
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int k = 0; k < kBankFillRegs; ++k) {
+        const int i = min(tid + k * kBankThreads, W - 1);
+        v[b][k] = band0[(b ? L : 0) + pos_mod(e0[b] + i, L)];
+      }
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int k = 0; k < kBankFillRegs; ++k)
+        mx = fmaxf(mx, fmaxf(fabsf(v[b][k].x), fabsf(v[b][k].y)));
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) atomicMax(reinterpret_cast<int *>(&s_max), __float_as_int(mx));
+    __syncthreads();
+    sd = scale_of(s_max);
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int k = 0; k < kBankFillRegs; ++k) {
+        const int i = tid + k * kBankThreads;
+        if (i < W) split_store(b, i, v[b][k], sd);
+      }
+  } else {
+    for (int b = 0; b < 2; ++b) {
+      const float2 *src = band0 + (b ? L : 0);
+      for (int i = tid; i < W; i += nt) {
+        const float2 x = src[pos_mod(e0[b] + i, L)];
+        mx = fmaxf(mx, fmaxf(fabsf(x.x), fabsf(x.y)));
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    if (lane == 0) atomicMax(reinterpret_cast<int *>(&s_max), __float_as_int(mx));
+    __syncthreads();
+    sd = scale_of(s_max);
+    for (int b = 0; b < 2; ++b) {
+      const float2 *src = band0 + (b ? L : 0);
+      for (int i = tid; i < W; i += nt) split_store(b, i, src[pos_mod(e0[b] + i, L)], sd);
     }
   }
+  const float inv_sd = 1.f / sd;
   __syncthreads();
 
   // The item's tile groups, one after another over the same data window

@@ -186,9 +186,11 @@ struct LiftChunk {
 // at each level above; it reads its input stretch once with halos that cover
 // the lifting reach of every level of the pass (kLiftHalo samples beyond
 // 2k .. 2k+1 per side and level: 2 HL + (odd member before) <= 5 and
-// 2 HR <= 5 for every filter), lifts the levels in two alternating LDS
-// buffers, and writes only its own outputs.  An input level of at most
-// kLiftBlockIn samples is one block holding the whole (circular) level.
+// 2 HR <= 5 for every filter): level l0 straight from global memory into
+// registers, the deeper levels from two alternating LDS buffers (level l0
+// in the first, l0 + 1 in the second, and so on); it writes only its own
+// outputs.  An input level of at most kLiftBlockIn samples is one block
+// holding the whole (circular) level.
 constexpr int kLiftBlockIn = 4096;
 constexpr int kLiftHalo = 5;
 
@@ -236,12 +238,14 @@ __host__ __device__ inline void lift_block_ranges(int N, int l0, int l1, int blk
   oe[l0 - 1] = e[l0 - 1];
 }
 
-// LDS elements (complex) one block of the pass needs: the input level's
-// stretch and level l0's (the two alternating buffers).
+// LDS elements (complex) one block of the pass needs: the stretches of
+// levels l0 and l0 + 1 (the two alternating buffers); none for a one-level
+// pass, whose level goes to the pyramid only.
 __host__ __device__ inline int lift_block_lds(int N, int l0, int l1) {
+  if (l1 == l0) return 0;
   int s[kMaxLevels + 1], e[kMaxLevels + 1], os[kMaxLevels + 1], oe[kMaxLevels + 1];
   lift_block_ranges(N, l0, l1, 0, s, e, os, oe);
-  return (e[l0 - 1] - s[l0 - 1]) + (e[l0] - s[l0]);
+  return (e[l0] - s[l0]) + (e[l0 + 1] - s[l0 + 1]);
 }
 
 // Offset (complex elements) of c_l inside a pulse's scratch pyramid; d_l

@@ -714,45 +714,58 @@ __global__ __launch_bounds__(256) void batch_lift(const PlanDesc *__restrict__ p
   }
 }
 
-// One block of a multi-level lifting pass (see LiftBlock): the input
-// stretch of level l0 - 1 into LDS buffer 0, then levels l0..l1 into the two
-// buffers in turn; each level's own pairs also go to the pyramid.  Reads
-// through the circular index are clamped to the stretch (lanes past a
-// window's end load values that are never used).
+// One block of a multi-level lifting pass (see LiftBlock): level l0 lifted
+// from the input level in global memory (register windows, as the
+// level-by-level kernel), then levels l0 + 1 .. l1 from the two LDS buffers
+// in turn; each level's own pairs also go to the pyramid.  LDS reads through
+// the circular index are clamped to the stretch (lanes past a window's end
+// load values that are never used).
 template <int F>
 __device__ void lift_block(const BatchPulse &p, float2 *scratch, const LiftBlock &bk, float2 *sm) {
   constexpr bool OB = YLift<F>::kOddBefore;
   const int N = p.N, l0 = bk.l0, l1 = bk.l1;
   int s[kMaxLevels + 1], e[kMaxLevels + 1], os[kMaxLevels + 1], oe[kMaxLevels + 1];
   lift_block_ranges(N, l0, l1, bk.blk, s, e, os, oe);
-  float2 *buf[2] = {sm, sm + (e[l0 - 1] - s[l0 - 1])};
+  float2 *buf[2] = {sm, sm + (e[l0] - s[l0])};
   {
-    // eight loads in flight per thread before their LDS stores
-    const int Nin = N >> (l0 - 1), S = s[l0 - 1], R = e[l0 - 1] - S;
-    const int nt = blockDim.x;
-    const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
-    const long long n = p.n;
-    const float2 *src = scratch + p.scratch + scratch_level_off(N, l0 - 1);
-    constexpr int U = 8;
-    for (int i0 = threadIdx.x; i0 < R; i0 += U * nt) {
-      float2 v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int q = pos_mod(S + min(i0 + u * nt, R - 1), Nin);
-        v[u] = l0 == 1 ? rx_sample_global(rx, n, q) : src[q];
+    const int Nin = N >> (l0 - 1), np = N >> l0, so = s[l0];
+    const int o0 = os[l0], o1 = oe[l0];
+    const bool keep = l1 > l0;
+    float2 *c = scratch + p.scratch + scratch_level_off(N, l0);
+    float2 *d = c + np;
+    float2 *out = buf[0];
+    auto store = [&](int k, float2 cv, float2 dv) {
+      if (keep) out[k - so] = cv;
+      if (k >= o0 && k < o1) {
+        c[k] = cv;
+        d[k] = dv;
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u)
-        if (i0 + u * nt < R) buf[0][i0 + u * nt] = v[u];
+    };
+    if (l0 == 1) {
+      const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
+      const int n = (int)p.n;
+      lift_level_range<F, 4>(
+          np, s[l0], e[l0],
+          [&](int kc, float2 &ev, float2 &ov) {
+            ev = rx_sample_global(rx, n, 2 * kc);
+            ov = rx_sample_global(rx, n, OB ? (kc == 0 ? Nin - 1 : 2 * kc - 1) : 2 * kc + 1);
+          },
+          store);
+    } else {
+      const float2 *src = scratch + p.scratch + scratch_level_off(N, l0 - 1);
+      lift_level_range<F, 4>(
+          np, s[l0], e[l0], [&](int kc, float2 &ev, float2 &ov) { pair_at<OB>(src, kc, np, ev, ov); },
+          store);
     }
   }
   __syncthreads();
-  for (int l = l0; l <= l1; ++l) {
-    const float2 *in = buf[(l - l0) & 1];
-    float2 *out = buf[(l - l0 + 1) & 1];
+  for (int l = l0 + 1; l <= l1; ++l) {
+    const float2 *in = buf[(l - l0 - 1) & 1];
+    float2 *out = buf[(l - l0) & 1];
     const int Nin = N >> (l - 1), np = N >> l;
     const int S = s[l - 1], R = e[l - 1] - S, so = s[l];
     const int o0 = os[l], o1 = oe[l];
+    const bool keep = l < l1;
     float2 *c = scratch + p.scratch + scratch_level_off(N, l);
     float2 *d = c + np;
     lift_level_range<F, 2>(
@@ -768,7 +781,7 @@ __device__ void lift_block(const BatchPulse &p, float2 *scratch, const LiftBlock
           ov = at(OB ? (kc == 0 ? Nin - 1 : 2 * kc - 1) : 2 * kc + 1);
         },
         [&](int k, float2 cv, float2 dv) {
-          out[k - so] = cv;
+          if (keep) out[k - so] = cv;
           if (k >= o0 && k < o1) {
             c[k] = cv;
             d[k] = dv;

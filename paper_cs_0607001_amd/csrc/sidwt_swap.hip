@@ -25,6 +25,7 @@
 //    of a tile holds lags 16 i .. 16 i + 15, the K axis runs over (offset v,
 //    re/im) and the 32 columns over (lag t within the block, re/im) with
 //    B[v][t] = conj(a)[v - t].
+#include "sidwt_lift.hpp"
 #include "sidwt_swap.hpp"
 
 namespace sidwt {
@@ -41,9 +42,10 @@ __device__ __forceinline__ f32x16 swap_mfma(float a, float b, f32x16 c) {
 // Redundant tree.  One level of one phase: the y-side lifting of a parent
 // sequence of Lp samples (sample(i), i < Lp, circular) advanced by b
 // samples, L = Lp / 2 outputs (store(k, v)), in register windows of 64
-// lanes with lane-shift taps.
+// lanes with lane-shift taps, U windows per wave at a time (the loads of
+// all U in flight together; 4 measured no faster than 2 from global memory).
 // ---------------------------------------------------------------------------
-template <int F, class Sample, class Store>
+template <int F, int U, class Sample, class Store>
 __device__ __forceinline__ void tree_phase(int Lp, int b, Sample sample, Store store) {
   using Lf = YLift<F>;
   constexpr bool OB = Lf::kOddBefore;
@@ -54,7 +56,6 @@ __device__ __forceinline__ void tree_phase(int Lp, int b, Sample sample, Store s
   const int nw = blockDim.x >> 6;
   const int nwin = (L + OWN - 1) / OWN;
   const bool wide = L >= 64;  // every index a stored output needs lies in [-HL, L + HR)
-  constexpr int U = 2;
   for (int w0 = wave * U; w0 < nwin; w0 += nw * U) {
     float2 e[U], o[U];
     int kk[U];
@@ -98,15 +99,16 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level(
     int j, int N, const float2 *__restrict__ parent_all, long long parent_stride, int n_valid,
     float2 *__restrict__ child_all, long long child_stride) {
   const int P = 1 << j;
-  const int p = blockIdx.x & (P - 1);
-  const long long pulse = blockIdx.x >> j;
+  long long pulse;
+  int p;
+  swap_tree_block(blockIdx.x, gridDim.x, j, pulse, p);
   const int pp = p & ((P >> 1) - 1);  // parent phase (0 at level 1)
   const int b = p >> (j - 1);         // advance of the parent, in its samples
   const int Lp = N >> (j - 1);
   const float2 *par = parent_all + pulse * parent_stride + (long long)pp * Lp;
   float2 *child = child_all + pulse * child_stride + (long long)p * (N >> j);
-  tree_phase<F>(
-      Lp, b, [&](int i) { return i < n_valid ? par[i] : make_float2(0.f, 0.f); },
+  tree_phase<F, 2>(
+      Lp, b, [&](int i) { return rx_sample(par, n_valid, i); },
       [&](int k, float2 v) { store_stream2(child + k, v); });
 }
 
@@ -121,15 +123,16 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level2(
     float2 *__restrict__ child_all, long long child_stride) {
   extern __shared__ __align__(16) float2 sm_tree[];
   const int P = 1 << j;
-  const int p = blockIdx.x & (P - 1);
-  const long long pulse = blockIdx.x >> j;
+  long long pulse;
+  int p;
+  swap_tree_block(blockIdx.x, gridDim.x, j, pulse, p);
   const int pp = p & ((P >> 1) - 1);
   const int b = p >> (j - 1);
   const int Lp = N >> (j - 1), L = N >> j, L2 = N >> (j + 1);
   const float2 *par = parent_all + pulse * parent_stride + (long long)pp * Lp;
   float2 *child = child_all + pulse * child_stride + (long long)p * L;
-  tree_phase<F>(
-      Lp, b, [&](int i) { return i < n_valid ? par[i] : make_float2(0.f, 0.f); },
+  tree_phase<F, 2>(
+      Lp, b, [&](int i) { return rx_sample(par, n_valid, i); },
       [&](int k, float2 v) {
         sm_tree[k] = v;
         store_stream2(child + k, v);
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(kSwapTreeThreads) void swap_tree_level2(
 #pragma unroll
   for (int b2 = 0; b2 < 2; ++b2) {
     float2 *g = grand + (long long)(p + (b2 << j)) * L2;
-    tree_phase<F>(
+    tree_phase<F, 2>(
         L, b2, [&](int i) { return sm_tree[i]; }, [&](int k, float2 v) { store_stream2(g + k, v); });
   }
 }

@@ -3,8 +3,8 @@ library's own geometry code): for every pass of a sweep of transform
 lengths, scale counts and depths, the blocks' own outputs tile every level
 exactly once; every input pair an owned output's lifting window reads lies
 inside the block's range of the level above (with the filters' actual reach,
-also measured here on the oracle's lifting); the levels fit the two LDS
-buffers the pass is given; and the kernel's clamped circular read index
+also measured here on the oracle's lifting); the levels kept in LDS fit the
+two buffers the pass is given; and the kernel's clamped circular read index
 equals the true one for every needed sample."""
 import os
 import shutil
@@ -102,15 +102,21 @@ def test_blocks_tile_levels_and_read_inside_their_ranges(geometry, filt):
                 covered[os_:oe] += 1
             assert np.all(covered == 1), (p["N"], l0, l1, l)
         for rng in p["blocks"]:
-            R0 = rng[l0 - 1][1] - rng[l0 - 1][0]
-            R1 = rng[l0][1] - rng[l0][0]
-            assert R0 + R1 <= p["lds"]
+            # level l0 is lifted from global memory; levels l0 .. l1 - 1
+            # are kept in LDS, level l in buffer (l - l0) & 1, whose sizes
+            # are those of levels l0 and l0 + 1
+            if l1 > l0:
+                R0 = rng[l0][1] - rng[l0][0]
+                R1 = rng[l0 + 1][1] - rng[l0 + 1][0]
+                assert R0 + R1 <= p["lds"]
+            else:
+                assert p["lds"] == 0
             for l in range(l0, l1 + 1):
                 s, e, os_, oe = rng[l]
                 S, E = rng[l - 1][0], rng[l - 1][1]
                 R, Nin = E - S, N >> (l - 1)
-                # level l lives in buffer (l - l0 + 1) & 1 of size R1 or R0
-                assert e - s <= (R1 if (l - l0) % 2 == 0 else R0)
+                if l < l1:
+                    assert e - s <= (R0 if (l - l0) % 2 == 0 else R1)
                 assert s <= os_ and oe <= e
                 # every output of [s, e) reads pairs k - HL .. k + HR
                 ks = np.arange(s, e)

@@ -327,14 +327,26 @@ int sidwt_lift_generic(const sidwt_lifting *f, int J, const void *rx, int64_t n,
 typedef struct sidwt_batch sidwt_batch;
 
 /* plans[i], n[i] for i < count (host arrays).  Builds descriptors and
- * allocates device scratch; synchronous.  SIDWT_E_UNSUPPORTED for the
- * integer filter. */
+ * allocates device scratch; synchronous.
+ * Integer batches: when every plan is the integer filter the batch takes
+ * int16 I/Q pulses and int64 (re, im) outputs, exact as sidwt_correlate.
+ * Its pulses are grouped by (plan, n); a group of a plan up to J = 7 is one
+ * launch of the int8 whole-pulse kernel, or (pulses beyond one workgroup's
+ * LDS) one lifting launch per level into the batch's HBM pyramid plus one
+ * launch over blocks of lag rows, reading the group's per-pulse pointers
+ * (uploaded only when they change); deeper plans run one FP64 whole-pulse
+ * launch per pulse.  No graph capture; sidwt_batch_config / _configure
+ * change nothing and sidwt_batch_tune only runs the batch once.
+ * SIDWT_E_INVAL when integer and float plans are mixed;
+ * SIDWT_E_UNSUPPORTED for an integer pulse no path can hold (a plan with
+ * J >= 8 whose pulse exceeds one workgroup's LDS). */
 int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int count,
                        sidwt_batch **out);
 
-/* Enqueue one pass on `hip_stream`: rx[i] (device, n[i] complex64 samples)
- * -> out[i] (device, J_i x N_i complex64).  rx and out are host arrays of
- * device pointers, read during the call. */
+/* Enqueue one pass on `hip_stream`: rx[i] (device, n[i] complex64 samples,
+ * or n[i] int16 (re, im) pairs in an integer batch) -> out[i] (device,
+ * J_i x N_i complex64, or int64 (re, im) pairs).  rx and out are host arrays
+ * of device pointers, read during the call. */
 int sidwt_batch_run(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream);
 
 /* Autotuner: times candidate tile windows, then fused/tiled splits, then

@@ -439,15 +439,29 @@ def _ptr_array(ptrs):
 
 
 def batch_outputs(plans, ns, device):
-    """Allocate (J, N) complex64 outputs for each pulse of a batch."""
+    """Allocate each pulse's output of a batch: (J, N) complex64, or (J, N, 2)
+    int64 for integer plans."""
+    return [_out_like(p, (), transform_length(n, p.J), device) for p, n in zip(plans, ns)]
+
+
+def _check_batch_pulse(plan, x, o, n, i):
+    """Pulse i of a batch: rx complex64 (n,) or int16 (n, 2) for an integer
+    plan; out as batch_outputs allocates it."""
     torch = _torch()
-    return [torch.empty((p.J, transform_length(n, p.J)), dtype=torch.complex64, device=device)
-            for p, n in zip(plans, ns)]
+    N = transform_length(n, plan.J)
+    if plan.is_int:
+        _check_buf(x, torch.int16, 2 * n, f"rx[{i}]")
+    else:
+        _check_buf(x, torch.complex64, n, f"rx[{i}]")
+    if o is not None:
+        _check_buf(o, _out_dtype(plan), _out_numel(plan, 1, N), f"out[{i}]", x.device)
 
 
 class Batch:
     """Owns a sidwt_batch: pulses of uneven lengths with their own plans,
-    one persistent launch (replayed from a HIP graph) per run."""
+    one persistent launch (replayed from a HIP graph) per run; or, when every
+    plan is integer, one int8 launch per group of pulses of one plan and
+    length."""
 
     def __init__(self, plans, ns):
         _torch()
@@ -473,8 +487,7 @@ class Batch:
         if len(rx) != len(self.ns) or len(out) != len(self.ns):
             raise ValueError("one input and one output per pulse")
         for i, (x, o, p, n) in enumerate(zip(rx, out, self.plans, self.ns)):
-            _check_buf(x, torch.complex64, n, f"rx[{i}]")
-            _check_buf(o, torch.complex64, p.J * transform_length(n, p.J), f"out[{i}]", x.device)
+            _check_batch_pulse(p, x, o, n, i)
         return _ptr_array([x.data_ptr() for x in rx]), _ptr_array([o.data_ptr() for o in out])
 
     def run(self, rx, out, stream=None):
@@ -523,13 +536,16 @@ def correlate_batch(plans, rx, out=None, stream=None):
     torch = _torch()
     if len(plans) != len(rx) or (out is not None and len(out) != len(rx)):
         raise ValueError("one plan, input and output per pulse")
-    for i, x in enumerate(rx):
-        _check_buf(x, torch.complex64, 1, f"rx[{i}]")
-    ns = [int(x.numel()) for x in rx]
+    ns = []
+    for i, (p, x) in enumerate(zip(plans, rx)):
+        if not isinstance(x, torch.Tensor):
+            raise ValueError(f"rx[{i}] must be a torch tensor")
+        ns.append(int(x.numel() // 2 if p.is_int else x.numel()))
+        _check_batch_pulse(p, x, None, max(1, ns[-1]), i)
     if out is None:
         out = batch_outputs(plans, ns, rx[0].device)
-    for i, (o, p, n) in enumerate(zip(out, plans, ns)):
-        _check_buf(o, torch.complex64, p.J * transform_length(n, p.J), f"out[{i}]", rx[i].device)
+    for i, (x, o, p, n) in enumerate(zip(rx, out, plans, ns)):
+        _check_batch_pulse(p, x, o, n, i)
     plan_arr = _ptr_array([p.handle.value for p in plans])
     n_arr = (ctypes.c_int64 * len(ns))(*ns)
     check(lib().sidwt_correlate_batch(plan_arr, _ptr_array([x.data_ptr() for x in rx]), n_arr,

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "../../include/sidwt.h"
@@ -36,10 +37,12 @@ hipError_t launch_synth(int filter, int J, int to, int N, const void *pyr, long 
                         void *out, hipStream_t st);
 hipError_t launch_fused_i8(const I8Layout &lay, const I8Tile *tiles, const signed char *panels,
                            const void *rx, long long n, long long count, long long rx_stride,
-                           void *out, long long out_stride, unsigned planes, hipStream_t st);
+                           void *out, long long out_stride, unsigned planes, const I8Ptrs *ptrs,
+                           hipStream_t st);
 hipError_t launch_i8_blocks(const I8TilePlan &tp, const I8Tile *tiles, const signed char *panels,
                             const void *rx, long long n, long long count, long long rx_stride,
-                            void *pyr, void *out, long long out_stride, hipStream_t st);
+                            void *pyr, void *out, long long out_stride, const I8Ptrs *ptrs,
+                            hipStream_t st);
 size_t synth_lds_bytes(int filter, int N, int to);
 }  // namespace sidwt
 
@@ -144,6 +147,167 @@ hipError_t build_i8(sidwt_plan *p) {
 // Descriptor of a plan for the batch module (C++ linkage, not exported in
 // the header).
 const sidwt::PlanDesc *sidwt_plan_desc(const sidwt_plan *p) { return p ? &p->desc : nullptr; }
+
+// ---------------------------------------------------------------------------
+// Integer batches (C++ linkage; sidwt_batch.cpp holds the handle when every
+// plan of a batch is integer).  Pulses are grouped by (plan, n); a group on
+// the int8 path is one launch of the whole-pulse kernel, or one lifting pass
+// per level plus one block launch, over the group's per-pulse pointers
+// (uploaded only when they change).  FP64 plans (J >= 8) run one whole-pulse
+// launch per pulse.  Groups go out in order on the call's stream, so the
+// block path's pyramid is shared by all groups (largest group's size).
+// ---------------------------------------------------------------------------
+struct sidwt_int_batch {
+  struct Group {
+    const sidwt_plan *p;
+    int64_t n, N;
+    int path;                 // 0: int8 whole pulse, 1: int8 blocks, 2: FP64 per pulse
+    std::vector<int> pulses;  // batch indices
+    int ptr0;                 // first entry in the pointer array
+    sidwt::I8Layout lay;
+    sidwt::I8TilePlan tp;
+    FusedLayout flay;
+  };
+  int count = 0;
+  std::vector<Group> groups;
+  std::vector<sidwt::I8Ptrs> ptrs;     // group order
+  sidwt::I8Ptrs *d_ptrs = nullptr;
+  sidwt::I8Ptrs *h_stage = nullptr;    // pinned staging of ptrs
+  hipEvent_t up_done = nullptr;
+  bool uploaded = false;
+  void *pyr = nullptr;
+  size_t pyr_bytes = 0;
+  int64_t n_whole = 0, n_blocks = 0, n_fp64 = 0;
+};
+
+void sidwt_int_batch_free(sidwt_int_batch *ib) {
+  if (!ib) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFree(ib->d_ptrs);
+  (void)hipFree(ib->pyr);
+  if (ib->h_stage) (void)hipHostFree(ib->h_stage);
+  if (ib->up_done) (void)hipEventDestroy(ib->up_done);
+  delete ib;
+}
+
+int sidwt_int_batch_create(const sidwt_plan *const *plans, const int64_t *n, int count,
+                           sidwt_int_batch **out) {
+  if (!plans || !n || !out || count < 1) return SIDWT_E_INVAL;
+  sidwt_int_batch *ib = new (std::nothrow) sidwt_int_batch();
+  if (!ib) return SIDWT_E_NOMEM;
+  ib->count = count;
+  int rc = SIDWT_OK;
+  for (int i = 0; i < count && !rc; ++i) {
+    const sidwt_plan *p = plans[i];
+    if (!p || p->filter != SIDWT_LEGALL53_INT) {
+      rc = SIDWT_E_INVAL;
+      break;
+    }
+    int64_t N = 0;
+    rc = check_pulse(p, n[i], &N);
+    if (rc) break;
+    size_t g = 0;
+    while (g < ib->groups.size() && !(ib->groups[g].p == p && ib->groups[g].n == n[i])) ++g;
+    if (g == ib->groups.size()) {
+      sidwt_int_batch::Group G{};
+      G.p = p;
+      G.n = n[i];
+      G.N = N;
+      if (p->i8_wl && make_i8_layout(p->desc, p->i8_wl, p->i8_tiles.data(),
+                                     p->i8_tile_base.data(), N, &G.lay) == 0)
+        G.path = 0;
+      else if (p->i8_wl && make_i8_tile_plan(p->desc, p->i8_wl, p->i8_tiles.data(),
+                                             p->i8_tile_base.data(), N, &G.tp) == 0)
+        G.path = 1;
+      else if (make_layout(p->desc, N, &G.flay) == 0)
+        G.path = 2;
+      else
+        rc = SIDWT_E_UNSUPPORTED;
+      ib->groups.push_back(G);
+    }
+    ib->groups[g].pulses.push_back(i);
+  }
+  if (!rc) {
+    int at = 0;
+    for (auto &G : ib->groups) {
+      G.ptr0 = at;
+      at += (int)G.pulses.size();
+      const int64_t c = (int64_t)G.pulses.size();
+      (G.path == 0 ? ib->n_whole : G.path == 1 ? ib->n_blocks : ib->n_fp64) += c;
+      if (G.path == 1)
+        ib->pyr_bytes = std::max(ib->pyr_bytes, (size_t)c * 2 * (size_t)G.N * sizeof(int2));
+    }
+    ib->ptrs.assign((size_t)count, sidwt::I8Ptrs{nullptr, nullptr});
+    hipError_t e = hipMalloc(&ib->d_ptrs, (size_t)count * sizeof(sidwt::I8Ptrs));
+    if (e == hipSuccess && ib->pyr_bytes) e = hipMalloc(&ib->pyr, ib->pyr_bytes);
+    if (e == hipSuccess)
+      e = hipHostMalloc((void **)&ib->h_stage, (size_t)count * sizeof(sidwt::I8Ptrs),
+                        hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ib->up_done, hipEventDisableTiming);
+    rc = map_err(e);
+  }
+  if (rc) {
+    sidwt_int_batch_free(ib);
+    return rc;
+  }
+  *out = ib;
+  return SIDWT_OK;
+}
+
+int sidwt_int_batch_run(sidwt_int_batch *ib, const void *const *rx, void *const *out,
+                        hipStream_t st) {
+  if (!ib || !rx || !out) return SIDWT_E_INVAL;
+  bool same = ib->uploaded;
+  for (const auto &G : ib->groups)
+    for (size_t k = 0; k < G.pulses.size(); ++k) {
+      const int i = G.pulses[k];
+      if (!rx[i] || !out[i]) return SIDWT_E_INVAL;
+      sidwt::I8Ptrs &q = ib->ptrs[(size_t)G.ptr0 + k];
+      same = same && q.rx == rx[i] && q.out == out[i];
+      q.rx = static_cast<const short2 *>(rx[i]);
+      q.out = static_cast<long long *>(out[i]);
+    }
+  hipError_t e = hipSuccess;
+  if (!same) {
+    const size_t bytes = ib->ptrs.size() * sizeof(sidwt::I8Ptrs);
+    e = hipEventSynchronize(ib->up_done);  // the staging buffer is free again
+    if (e == hipSuccess) {
+      std::memcpy(ib->h_stage, ib->ptrs.data(), bytes);
+      e = hipMemcpyAsync(ib->d_ptrs, ib->h_stage, bytes, hipMemcpyHostToDevice, st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ib->up_done, st);
+    if (e != hipSuccess) return map_err(e);
+    ib->uploaded = true;
+  }
+  for (const auto &G : ib->groups) {
+    const sidwt_plan *p = G.p;
+    const long long c = (long long)G.pulses.size();
+    const sidwt::I8Ptrs *dp = ib->d_ptrs + G.ptr0;
+    if (G.path == 0) {
+      e = sidwt::launch_fused_i8(G.lay, p->d_i8_tiles, p->d_i8_panels, nullptr, G.n, c, 0,
+                                 nullptr, 0, (1u << p->J) - 1u, dp, st);
+    } else if (G.path == 1) {
+      e = sidwt::launch_i8_blocks(G.tp, p->d_i8_tiles, p->d_i8_panels, nullptr, G.n, c, 0,
+                                  ib->pyr, nullptr, 0, dp, st);
+    } else {
+      for (long long k = 0; k < c && e == hipSuccess; ++k) {
+        const int i = G.pulses[(size_t)k];
+        e = sidwt::launch_fused(p->desc, G.flay, rx[i], G.n, 1, G.n, out[i],
+                                (long long)p->J * G.N, (1u << p->J) - 1u, st);
+      }
+    }
+    if (e != hipSuccess) return map_err(e);
+  }
+  return SIDWT_OK;
+}
+
+void sidwt_int_batch_counts(const sidwt_int_batch *ib, int64_t *whole, int64_t *blocks,
+                            int64_t *fp64, int64_t *scratch_bytes) {
+  *whole = ib->n_whole;
+  *blocks = ib->n_blocks;
+  *fp64 = ib->n_fp64;
+  *scratch_bytes = (int64_t)ib->pyr_bytes;
+}
 
 extern "C" {
 
@@ -291,7 +455,7 @@ static int correlate_many_planes(const sidwt_plan *p, const void *rx, int64_t n,
     sidwt::I8Layout il;
     if (make_i8_layout(p->desc, p->i8_wl, p->i8_tiles.data(), p->i8_tile_base.data(), N, &il) == 0)
       return map_err(sidwt::launch_fused_i8(il, p->d_i8_tiles, p->d_i8_panels, rx, n, count,
-                                            rx_stride, out, out_stride, planes, st));
+                                            rx_stride, out, out_stride, planes, nullptr, st));
     // Too long for one workgroup: levels lifted into a temporary HBM
     // pyramid, then blocks of lag-block rows (the stream is synchronised
     // before the pyramid is released).
@@ -303,7 +467,7 @@ static int correlate_many_planes(const sidwt_plan *p, const void *rx, int64_t n,
       hipError_t e = hipMalloc(&pyr, (size_t)count * 2 * (size_t)N * sizeof(int2));
       if (e != hipSuccess) return map_err(e);
       e = sidwt::launch_i8_blocks(tp, p->d_i8_tiles, p->d_i8_panels, rx, n, count, rx_stride,
-                                  pyr, out, out_stride, st);
+                                  pyr, out, out_stride, nullptr, st);
       const hipError_t es = hipStreamSynchronize(st);
       (void)hipFree(pyr);
       return map_err(e != hipSuccess ? e : es);

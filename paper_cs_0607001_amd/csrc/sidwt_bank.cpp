@@ -27,7 +27,7 @@
 #include "sidwt_host.hpp"
 
 namespace sidwt {
-hipError_t launch_bank(bool bf16, const BankSeg *segs, const int *item_seg, int nitems,
+hipError_t launch_bank(bool bf16, const BankSeg *segs, const int2 *items, int nitems,
                        const BankTile *tiles, const int *tile_base, const BankRefLevel *rl,
                        int Jmax, const int *lo_lb, const unsigned *wts, const float2 *scratch,
                        int Wmax, hipStream_t st);
@@ -52,6 +52,7 @@ constexpr int kChunk = 4096;
 // per data window, and the most tile groups one item may take.
 constexpr double kBankItemSteps = 256.0;
 constexpr int kBankMaxGroups = 16;
+constexpr int kBankXcdRun = 8;      // consecutive items of a class kept on one XCD
 
 int map_err(hipError_t e, const char *what = nullptr) {
   if (e == hipSuccess) return SIDWT_OK;
@@ -107,8 +108,8 @@ int grow(T **p, size_t *cap, size_t need) {
 struct sidwt_bank_ws {
   BankSeg *d_segs = nullptr;
   size_t c_segs = 0;
-  int *d_item_seg = nullptr;
-  size_t c_item_seg = 0;
+  int2 *d_items = nullptr;
+  size_t c_items = 0;
   BatchPulse *d_pulses = nullptr;
   size_t c_pulses = 0;
   LiftChunk *d_chunks = nullptr;
@@ -395,7 +396,7 @@ void sidwt_bank_ws_free(sidwt_bank_ws *w) {
   if (w->h_stage) (void)hipHostFree(w->h_stage);
   if (w->up_done) (void)hipEventDestroy(w->up_done);
   (void)hipFree(w->d_segs);
-  (void)hipFree(w->d_item_seg);
+  (void)hipFree(w->d_items);
   (void)hipFree(w->d_pulses);
   (void)hipFree(w->d_chunks);
   (void)hipFree(w->d_scratch);
@@ -553,11 +554,65 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
     nitems += (long long)(sorted[k].nblocks - 1) * sorted[k].g_full + sorted[k].g_last;
   }
   if (nitems > (1LL << 31) - 1) return SIDWT_E_SIZE;
-  std::vector<int> item_seg((size_t)nitems);
-  for (size_t k = 0; k < sorted.size(); ++k) {
-    const long long a = sorted[k].item0;
-    const long long b = k + 1 < sorted.size() ? sorted[k + 1].item0 : nitems;
-    std::fill(item_seg.begin() + a, item_seg.begin() + b, (int)k);
+  // Items (segment, index within it): classes of half an octave of the
+  // item's own cost (rows x panel steps of its tiles), costliest first;
+  // within a class by level, then tile group, then segment, then row block,
+  // so the items of one level and tile group of different requests are
+  // neighbours.  Workgroups go to the eight XCDs round-robin (position p to
+  // XCD p mod 8), so each class is then laid out in runs of kBankXcdRun
+  // consecutive list items, run r going to the XCD of the class's (r mod
+  // 8)-th position (the class's last 8 kBankXcdRun - 1 items or fewer keep
+  // their order): the items of a run
+  // mostly share a tile group's weight panels (a deep level's panels are
+  // read by every request, whose few rows reuse them little) and find them
+  // in that XCD's L2, while every XCD still draws from the whole class.
+  std::vector<std::vector<int>> seg_of_level(kMaxLevels + 1);
+  for (size_t k = 0; k < sorted.size(); ++k) seg_of_level[sorted[k].level].push_back((int)k);
+  std::vector<std::vector<int2>> bucket(130);
+  for (int l = 1; l <= kMaxLevels; ++l) {
+    if (seg_of_level[l].empty()) continue;
+    const long long *pre = bk->steps_pre.data() + bk->tile_base[l] + (l - 1);
+    int gmax = 0;
+    for (int k : seg_of_level[l]) gmax = std::max(gmax, std::max(sorted[k].g_full, sorted[k].g_last));
+    for (int grp = 0; grp < gmax; ++grp)
+      for (int k : seg_of_level[l]) {
+        const BankSeg &q = sorted[k];
+        for (int rb = 0; rb < q.nblocks; ++rb) {
+          const bool lastb = rb == q.nblocks - 1;
+          if (grp >= (lastb ? q.g_last : q.g_full)) continue;
+          const int rows = lastb ? q.L - 256 * (q.nblocks - 1) : 256;
+          const int span = bank_tiles_per_item(rows) * q.gmul;
+          const int t0 = grp * span, t1 = std::min(q.ntiles, t0 + span);
+          const double c = (double)rows * (double)(pre[t1] - pre[t0] + 8);
+          const int cls = std::min(129, std::max(0, (int)std::floor(2.0 * std::log2(c))));
+          bucket[cls].push_back(make_int2(k, lastb ? (q.nblocks - 1) * q.g_full + grp
+                                                   : rb * q.g_full + grp));
+        }
+      }
+  }
+  std::vector<int2> items;
+  std::vector<size_t> cls_end;
+  items.reserve((size_t)nitems);
+  for (int c = 129; c >= 0; --c) {
+    if (bucket[c].empty()) continue;
+    items.insert(items.end(), bucket[c].begin(), bucket[c].end());
+    cls_end.push_back(items.size());
+  }
+  if ((long long)items.size() != nitems) return SIDWT_E_INVAL;  // (cannot happen)
+  {
+    std::vector<int2> placed(items);
+    size_t c0 = 0;
+    for (size_t c1 : cls_end) {
+      const size_t R = kBankXcdRun, full = (c1 - c0) / (8 * R) * (8 * R);
+      for (size_t j = 0; j < full; ++j) {
+        // position c0 + j runs on XCD (c0 + j) mod 8; its k-th position in
+        // the class takes element k mod R of run 8 (k / R) + j mod 8
+        const size_t x = j % 8, k = j / 8;
+        placed[c0 + j] = items[c0 + (8 * (k / R) + x) * R + k % R];
+      }
+      c0 = c1;
+    }
+    items.swap(placed);
   }
   std::vector<LiftChunk> chunks;
   int off[kMaxLevels + 2] = {0}, nch[kMaxLevels + 2] = {0};
@@ -567,16 +622,16 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
     chunks.insert(chunks.end(), per_level[l].begin(), per_level[l].end());
   }
   int rc = grow(&ws->d_segs, &ws->c_segs, sorted.size());
-  if (!rc) rc = grow(&ws->d_item_seg, &ws->c_item_seg, item_seg.size());
+  if (!rc) rc = grow(&ws->d_items, &ws->c_items, items.size());
   if (!rc) rc = grow(&ws->d_pulses, &ws->c_pulses, pulses.size());
   if (!rc) rc = grow(&ws->d_chunks, &ws->c_chunks, chunks.size());
   if (!rc) rc = grow(&ws->d_scratch, &ws->c_scratch, (size_t)scratch);
   if (rc) return rc;
   // Descriptor uploads through the workspace's pinned staging buffer.
-  const size_t nb[4] = {sorted.size() * sizeof(BankSeg), item_seg.size() * sizeof(int),
+  const size_t nb[4] = {sorted.size() * sizeof(BankSeg), items.size() * sizeof(int2),
                         pulses.size() * sizeof(BatchPulse), chunks.size() * sizeof(LiftChunk)};
-  const void *src[4] = {sorted.data(), item_seg.data(), pulses.data(), chunks.data()};
-  void *dst[4] = {ws->d_segs, ws->d_item_seg, ws->d_pulses, ws->d_chunks};
+  const void *src[4] = {sorted.data(), items.data(), pulses.data(), chunks.data()};
+  void *dst[4] = {ws->d_segs, ws->d_items, ws->d_pulses, ws->d_chunks};
   size_t at[5] = {0};
   for (int k = 0; k < 4; ++k) at[k + 1] = at[k] + ((nb[k] + 255) & ~size_t(255));
   hipError_t e = hipSuccess;
@@ -605,7 +660,7 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   if (e != hipSuccess) return map_err(e, "lifting");
   if (ws->timing) e = hipEventRecord(ws->ev[1], st);
   if (e != hipSuccess) return map_err(e, "event");
-  e = launch_bank(bk->precision == SIDWT_BANK_BF16, ws->d_segs, ws->d_item_seg, (int)nitems,
+  e = launch_bank(bk->precision == SIDWT_BANK_BF16, ws->d_segs, ws->d_items, (int)nitems,
                   bk->d_tiles, bk->d_tile_base, bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w,
                   ws->d_scratch, 256 + bk->Umax, st);
   if (e == hipSuccess && ws->timing) {

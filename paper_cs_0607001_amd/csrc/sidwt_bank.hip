@@ -436,7 +436,7 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
 // same panel lines close together in time.
 template <bool BF16>
 __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
-    const BankSeg *__restrict__ segs, const int *__restrict__ item_seg,
+    const BankSeg *__restrict__ segs, const int2 *__restrict__ items,
     const BankTile *__restrict__ tiles, const int *__restrict__ tile_base,
     const BankRefLevel *__restrict__ rl, int Jmax, const int *__restrict__ lo_lb,
     const unsigned *__restrict__ wts,
@@ -446,10 +446,11 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   __shared__ int s_umax;
 
   // Item: segment, row block and tile group (uniform across the block).
-  const BankSeg sg = segs[item_seg[blockIdx.x]];
+  const int2 it = items[blockIdx.x];
+  const BankSeg sg = segs[it.x];
   const BankSeg &q = sg;                         // the request's fields
   const int l = sg.level, L = sg.L, N = q.N;
-  int k = (int)(blockIdx.x - sg.item0);
+  const int k = it.y;
   const int kfull = (sg.nblocks - 1) * sg.g_full;
   int rb, grp;
   if (k < kfull) {
@@ -572,7 +573,7 @@ size_t bank_lds_bytes(int Wmax) {
   return (size_t)(4 * Wmax) * 4 + (size_t)4 * kBankWaveBytes;
 }
 
-hipError_t launch_bank(bool bf16, const BankSeg *segs, const int *item_seg, int nitems,
+hipError_t launch_bank(bool bf16, const BankSeg *segs, const int2 *items, int nitems,
                        const BankTile *tiles, const int *tile_base, const BankRefLevel *rl,
                        int Jmax, const int *lo_lb, const unsigned *wts, const float2 *scratch,
                        int Wmax, hipStream_t st) {
@@ -583,10 +584,10 @@ hipError_t launch_bank(bool bf16, const BankSeg *segs, const int *item_seg, int 
   if (nitems <= 0) return hipSuccess;
   if (bf16)
     hipLaunchKernelGGL(bank_items<true>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
-                       item_seg, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
+                       items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
   else
     hipLaunchKernelGGL(bank_items<false>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
-                       item_seg, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
+                       items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
   return hipGetLastError();
 }
 

@@ -23,8 +23,10 @@ struct BankTile {
 // Work of one request and level: its lags are cut into blocks of 256 (the
 // last may be shorter) and its tiles [0, ntiles) into groups of
 // bank_tiles_per_item(rows) tiles; one work item per (block, gmul
-// consecutive groups), numbered block-major from item0.  An item loads its
-// data window once and runs its groups one after another.
+// consecutive groups), numbered block-major within the segment (item k:
+// block k / g_full, group k mod g_full; the last block's items follow);
+// the launch's item list gives each workgroup its (segment, k).  An item
+// loads its data window once and runs its groups one after another.
 __host__ __device__ inline int bank_tiles_per_item(int rows) {
   return rows > 128 ? 4 : rows > 64 ? 8 : 16;
 }
@@ -32,7 +34,7 @@ __host__ __device__ inline int bank_tiles_per_item(int rows) {
 struct BankSeg {
   void *out;            // the request's output, E x J x N complex64
   long long scratch;    // complex offset of the request's pyramid in scratch
-  long long item0;
+  long long item0;      // first item's position in segment order (host bookkeeping)
   int N, J, E, level;   // E: eligible references (the first E of the bank)
   int L, ntiles;
   int nblocks;          // row blocks, the last holding L - 256 (nblocks - 1) lags

@@ -81,8 +81,19 @@ int upload(T **dptr, size_t *cap, const std::vector<T> &v) {
 
 }  // namespace
 
+// Integer batches (sidwt_api.cpp): every plan of the batch integer.
+struct sidwt_int_batch;
+int sidwt_int_batch_create(const sidwt_plan *const *plans, const int64_t *n, int count,
+                           sidwt_int_batch **out);
+int sidwt_int_batch_run(sidwt_int_batch *ib, const void *const *rx, void *const *out,
+                        hipStream_t st);
+void sidwt_int_batch_free(sidwt_int_batch *ib);
+void sidwt_int_batch_counts(const sidwt_int_batch *ib, int64_t *whole, int64_t *blocks,
+                            int64_t *fp64, int64_t *scratch_bytes);
+
 struct sidwt_batch {
   int count = 0;
+  sidwt_int_batch *ib = nullptr;     // integer batch: every other field unused
   std::vector<PlanDesc> plans;       // distinct plans
   std::vector<int> pulse_plan;       // per pulse: index into plans
   std::vector<int64_t> n, N;
@@ -451,16 +462,30 @@ int sidwt_batch_create(const sidwt_plan *const *plans, const int64_t *n, int cou
                        sidwt_batch **out) {
   if (!plans || !n || !out || count < 1) return SIDWT_E_INVAL;
   std::vector<const PlanDesc *> descs((size_t)count);
+  int n_int = 0;
   for (int i = 0; i < count; ++i) {
     descs[i] = plans[i] ? sidwt_plan_desc(plans[i]) : nullptr;
     if (!descs[i]) return SIDWT_E_INVAL;
+    n_int += is_int_filter(descs[i]->filter) ? 1 : 0;
   }
-  return create_from_descs(descs.data(), n, count, out);
+  if (n_int == 0) return create_from_descs(descs.data(), n, count, out);
+  if (n_int != count) return SIDWT_E_INVAL;  // integer and float plans in one batch
+  sidwt_batch *b = new (std::nothrow) sidwt_batch();
+  if (!b) return SIDWT_E_NOMEM;
+  b->count = count;
+  const int rc = sidwt_int_batch_create(plans, n, count, &b->ib);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return SIDWT_OK;
 }
 
 void sidwt_batch_free(sidwt_batch *b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
+  sidwt_int_batch_free(b->ib);
   drop_graph(b);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   (void)hipFree(b->d_plans);
@@ -477,6 +502,7 @@ void sidwt_batch_free(sidwt_batch *b) {
 
 int sidwt_batch_config(sidwt_batch *b, int64_t fused_max_N, int tile_window) {
   if (!b || fused_max_N < 0 || tile_window < 64 || tile_window > 32768) return SIDWT_E_INVAL;
+  if (b->ib) return SIDWT_OK;  // integer batches have no split or window
   (void)hipDeviceSynchronize();
   b->fused_max_N = (int)std::min<int64_t>(fused_max_N, 1 << 20);
   b->tile_window = tile_window;
@@ -492,12 +518,17 @@ int sidwt_batch_configure(sidwt_batch *b, int64_t fused_max_N, int tile_window, 
 
 int sidwt_batch_run(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream) {
   if (!b || !rx || !out) return SIDWT_E_INVAL;
+  if (b->ib) return sidwt_int_batch_run(b->ib, rx, out, static_cast<hipStream_t>(hip_stream));
   return run(b, rx, out, static_cast<hipStream_t>(hip_stream), true);
 }
 
 int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, void *hip_stream) {
   if (!b || !rx || !out) return SIDWT_E_INVAL;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (b->ib) {  // nothing to tune: one run, so the outputs hold a result
+    const int rc = sidwt_int_batch_run(b->ib, rx, out, st);
+    return rc ? rc : map_err(hipStreamSynchronize(st), "integer batch");
+  }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return SIDWT_E_DEVICE;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -567,6 +598,14 @@ int sidwt_batch_tune(sidwt_batch *b, const void *const *rx, void *const *out, vo
 
 int sidwt_batch_info(const sidwt_batch *b, int64_t *v, int nv) {
   if (!b || !v || nv < 1) return SIDWT_E_INVAL;
+  if (b->ib) {
+    int64_t whole = 0, blocks = 0, fp64 = 0, scratch = 0;
+    sidwt_int_batch_counts(b->ib, &whole, &blocks, &fp64, &scratch);
+    const int64_t vals[] = {0, 0, b->count, whole + fp64, blocks, 0, 0, scratch, 0, 0, 1, 0};
+    const int k = (int)(sizeof(vals) / sizeof(vals[0]));
+    for (int i = 0; i < nv; ++i) v[i] = i < k ? vals[i] : 0;
+    return SIDWT_OK;
+  }
   const int64_t vals[] = {b->fused_max_N, b->tile_window, (int64_t)b->items.size(), b->n_fused,
                           b->n_tiles, (int64_t)b->lds_bytes, b->grid,
                           b->scratch_elems * (int64_t)sizeof(float2), b->tuned,
@@ -583,7 +622,7 @@ int sidwt_correlate_batch(const sidwt_plan *const *plans, const void *const *rx,
   int rc = sidwt_batch_create(plans, n, count, &b);
   if (rc) return rc;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  rc = run(b, rx, out, st, false);
+  rc = b->ib ? sidwt_int_batch_run(b->ib, rx, out, st) : run(b, rx, out, st, false);
   if (!rc) rc = map_err(hipStreamSynchronize(st));
   sidwt_batch_free(b);
   return rc;

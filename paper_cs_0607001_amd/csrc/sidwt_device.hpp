@@ -146,6 +146,13 @@ constexpr int kI8MaxBlocks = 64;
 struct I8Block {
   int level, r0, rows;
 };
+// Per-pulse pointers of a group of integer pulses of one plan and length
+// (integer batches): given to the int8 kernels, pulse i reads rx and writes
+// out from here instead of base + i * stride.
+struct I8Ptrs {
+  const short2 *rx;
+  long long *out;
+};
 struct I8TilePlan {
   int N, J, WL, nblocks, plane_bytes;
   int T[kMaxLevels + 1];

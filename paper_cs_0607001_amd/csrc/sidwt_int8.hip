@@ -121,10 +121,11 @@ template <int WL>
 __global__ __launch_bounds__(kFusedThreads) void fused_correlate_i8(
     I8Layout lay, const I8Tile *__restrict__ tiles, const signed char *__restrict__ panels,
     const short2 *__restrict__ rx_all, long long n, long long rx_stride,
-    long long *__restrict__ out_all, long long out_stride, unsigned plane_mask) {
+    long long *__restrict__ out_all, long long out_stride, unsigned plane_mask,
+    const I8Ptrs *__restrict__ ptrs) {
   extern __shared__ __align__(16) char sm_i8[];
-  const short2 *rx = rx_all + (long long)blockIdx.x * rx_stride;
-  long long *out = out_all + (long long)blockIdx.x * out_stride * 2;
+  const short2 *rx = ptrs ? ptrs[blockIdx.x].rx : rx_all + (long long)blockIdx.x * rx_stride;
+  long long *out = ptrs ? ptrs[blockIdx.x].out : out_all + (long long)blockIdx.x * out_stride * 2;
   const int N = lay.N, pb = lay.plane_bytes;
   int2 *c_odd = reinterpret_cast<int2 *>(sm_i8);
   int2 *c_even = reinterpret_cast<int2 *>(sm_i8 + lay.c_even);
@@ -181,7 +182,8 @@ constexpr int kI8LiftPairs = 4096;
 
 __global__ __launch_bounds__(256) void i8_lift_level(int l, int N, const short2 *__restrict__ rx_all,
                                                      long long n, long long rx_stride,
-                                                     int2 *__restrict__ pyr, int chunks) {
+                                                     int2 *__restrict__ pyr, int chunks,
+                                                     const I8Ptrs *__restrict__ ptrs) {
   const long long pulse = blockIdx.x / chunks;
   const int ch = blockIdx.x - (int)(pulse * chunks);
   const int np = N >> l;
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(256) void i8_lift_level(int l, int N, const short2 
     d[k] = dv;
   };
   if (l == 1) {
-    const short2 *rx = rx_all + pulse * rx_stride;
+    const short2 *rx = ptrs ? ptrs[pulse].rx : rx_all + pulse * rx_stride;
     lift_level_range<F_LEGALL53_INT, 2>(
         np, k0, k1,
         [&](int kc, int2 &e, int2 &o) {
@@ -217,7 +219,8 @@ __global__ __launch_bounds__(256) void i8_lift_level(int l, int N, const short2 
 template <int WL>
 __global__ __launch_bounds__(kFusedThreads) void i8_blocks(
     I8TilePlan tp, const I8Tile *__restrict__ tiles, const signed char *__restrict__ panels,
-    const int2 *__restrict__ pyr, long long *__restrict__ out_all, long long out_stride) {
+    const int2 *__restrict__ pyr, long long *__restrict__ out_all, long long out_stride,
+    const I8Ptrs *__restrict__ ptrs) {
   extern __shared__ __align__(16) char sm_i8b[];
   const long long pulse = blockIdx.x / tp.nblocks;
   const I8Block bk = tp.blocks[blockIdx.x - (int)(pulse * tp.nblocks)];
@@ -231,7 +234,7 @@ __global__ __launch_bounds__(kFusedThreads) void i8_blocks(
       put_digits(sm_i8b, pb, b, 0, W, 1 << 30, j, src[pos_mod(q0 + j, L)]);
   }
   __syncthreads();
-  long long *op = out_all + pulse * out_stride * 2 + 2LL * (l - 1) * N;
+  long long *op = (ptrs ? ptrs[pulse].out : out_all + pulse * out_stride * 2) + 2LL * (l - 1) * N;
   const I8Tile *tl = tiles + tp.tile_base[l];
   switch (T) {
     case 8: correlate_i8_level<WL, 8>(N, l, tp.ntiles[l], tl, panels, sm_i8b, pb, bk.r0, bk.rows, op); break;
@@ -244,14 +247,15 @@ __global__ __launch_bounds__(kFusedThreads) void i8_blocks(
 // launch over (pulse, block).
 hipError_t launch_i8_blocks(const I8TilePlan &tp, const I8Tile *tiles, const signed char *panels,
                             const void *rx, long long n, long long count, long long rx_stride,
-                            void *pyr, void *out, long long out_stride, hipStream_t st) {
+                            void *pyr, void *out, long long out_stride, const I8Ptrs *ptrs,
+                            hipStream_t st) {
   const int N = tp.N;
   int2 *py = static_cast<int2 *>(pyr);
   for (int l = 1; l <= tp.J; ++l) {
     const int chunks = ((N >> l) + kI8LiftPairs - 1) / kI8LiftPairs;
     if (count * chunks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(i8_lift_level, dim3((unsigned)(count * chunks)), dim3(256), 0, st, l, N,
-                       static_cast<const short2 *>(rx), n, rx_stride, py, chunks);
+                       static_cast<const short2 *>(rx), n, rx_stride, py, chunks, ptrs);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -265,9 +269,9 @@ hipError_t launch_i8_blocks(const I8TilePlan &tp, const I8Tile *tiles, const sig
   const dim3 grid((unsigned)(count * tp.nblocks)), block(kFusedThreads);
   long long *o = static_cast<long long *>(out);
   switch (tp.WL) {
-    case 1: hipLaunchKernelGGL(i8_blocks<1>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride); break;
-    case 2: hipLaunchKernelGGL(i8_blocks<2>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride); break;
-    case 3: hipLaunchKernelGGL(i8_blocks<3>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride); break;
+    case 1: hipLaunchKernelGGL(i8_blocks<1>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride, ptrs); break;
+    case 2: hipLaunchKernelGGL(i8_blocks<2>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride, ptrs); break;
+    case 3: hipLaunchKernelGGL(i8_blocks<3>, grid, block, lds, st, tp, tiles, panels, py, o, out_stride, ptrs); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -276,7 +280,8 @@ hipError_t launch_i8_blocks(const I8TilePlan &tp, const I8Tile *tiles, const sig
 template <int WL>
 static hipError_t launch_i8_t(const I8Layout &lay, const I8Tile *tiles, const signed char *panels,
                               const void *rx, long long n, long long count, long long rx_stride,
-                              void *out, long long out_stride, unsigned planes, hipStream_t st) {
+                              void *out, long long out_stride, unsigned planes, const I8Ptrs *ptrs,
+                              hipStream_t st) {
   static bool attr = false;
   if (!attr) {
     const hipError_t e = hipFuncSetAttribute((const void *)fused_correlate_i8<WL>,
@@ -288,17 +293,18 @@ static hipError_t launch_i8_t(const I8Layout &lay, const I8Tile *tiles, const si
   hipLaunchKernelGGL(fused_correlate_i8<WL>, dim3((unsigned)count), dim3(kFusedThreads),
                      (size_t)lay.total, st, lay, tiles, panels,
                      static_cast<const short2 *>(rx), n, rx_stride, static_cast<long long *>(out),
-                     out_stride, planes);
+                     out_stride, planes, ptrs);
   return hipGetLastError();
 }
 
 hipError_t launch_fused_i8(const I8Layout &lay, const I8Tile *tiles, const signed char *panels,
                            const void *rx, long long n, long long count, long long rx_stride,
-                           void *out, long long out_stride, unsigned planes, hipStream_t st) {
+                           void *out, long long out_stride, unsigned planes, const I8Ptrs *ptrs,
+                           hipStream_t st) {
   switch (lay.WL) {
-    case 1: return launch_i8_t<1>(lay, tiles, panels, rx, n, count, rx_stride, out, out_stride, planes, st);
-    case 2: return launch_i8_t<2>(lay, tiles, panels, rx, n, count, rx_stride, out, out_stride, planes, st);
-    case 3: return launch_i8_t<3>(lay, tiles, panels, rx, n, count, rx_stride, out, out_stride, planes, st);
+    case 1: return launch_i8_t<1>(lay, tiles, panels, rx, n, count, rx_stride, out, out_stride, planes, ptrs, st);
+    case 2: return launch_i8_t<2>(lay, tiles, panels, rx, n, count, rx_stride, out, out_stride, planes, ptrs, st);
+    case 3: return launch_i8_t<3>(lay, tiles, panels, rx, n, count, rx_stride, out, out_stride, planes, ptrs, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -152,12 +152,14 @@ def test_autotuner_picks_a_valid_split(dev):
         p.free()
 
 
-def test_batch_rejects_integer_plans(dev):
+def test_batch_refuses_an_integer_pulse_no_path_holds(dev):
+    """A J = 8 integer plan (no int8 path) with a pulse beyond one
+    workgroup's LDS: SIDWT_E_UNSUPPORTED at creation."""
     torch, S = dev
-    ref = np.ones((16, 2), np.int16)
-    with S.plan_create("legall53_int", 3, ref) as p:
+    ref = np.ones((40, 2), np.int16)
+    with S.plan_create("legall53_int", 8, ref) as p:
         with pytest.raises(S.SidwtError) as e:
-            S.Batch([p], [256])
+            S.Batch([p], [65536])
         assert e.value.code == -5
 
 
@@ -187,3 +189,56 @@ def test_plain_path_handles_pulses_beyond_one_workgroup(dev, n, J, count):
                     want = O.correlate_at("cdf97", J, ref, ys[i], j, lags)
                     e = np.linalg.norm(g[j, lags] - want) / np.linalg.norm(want)
                     assert e <= 1e-5, (rep, i, j, e)
+
+
+def test_integer_batch_is_bit_exact(dev):
+    """A batch of integer plans: pulses of several lengths and plans grouped
+    by (plan, n), on the int8 whole-pulse kernel, the int8 block path (pulses
+    beyond one workgroup's LDS) and the FP64 kernel (J = 8); every plane
+    bit-exact against the oracle (whole planes for short pulses, sampled lags
+    for long ones), on two runs with different output buffers."""
+    torch, S = dev
+    rng = np.random.default_rng(77)
+    refs = [rng.integers(-2047, 2048, (m, 2)).astype(np.int16) for m in (60, 200, 300)]
+    spec = [(0, 5, 700), (1, 6, 1500), (0, 5, 700), (2, 8, 2048), (1, 6, 20000),
+            (1, 6, 20000), (0, 5, 3000), (2, 8, 2560)]
+    plans, rx, cache = [], [], {}
+    for k, J, n in spec:
+        if (k, J) not in cache:
+            cache[(k, J)] = S.plan_create("legall53_int", J, refs[k])
+        plans.append(cache[(k, J)])
+        rx.append(rng.integers(-32768, 32768, (n, 2)).astype(np.int16))
+    print("[case] integer batch", [(J, n) for _, J, n in spec], flush=True)
+    rx_d = [torch.from_numpy(x).cuda() for x in rx]
+    ns = [n for _, _, n in spec]
+    with S.Batch(plans, ns) as b:
+        info = b.info()
+        assert info["items"] == len(spec)
+        assert info["tile_items"] == 2 and info["whole_pulse_items"] == len(spec) - 2
+        outs = []
+        for _ in range(2):
+            out = S.batch_outputs(plans, ns, rx_d[0].device)
+            b.run(rx_d, out)
+            torch.cuda.synchronize()
+            outs.append([o.cpu().numpy() for o in out])
+    for i, (k, J, n) in enumerate(spec):
+        N = O.transform_length(n, J)
+        if n <= 3000:
+            want = O.correlate_int(J, refs[k], rx[i])
+            for got in outs:
+                assert np.array_equal(got[i], want), (i, J, n)
+        else:
+            lags = np.unique(np.concatenate([[0, 1, N - 1], rng.integers(0, N, 12)]))
+            for j in range(J):
+                want = O.correlate_int_at(J, refs[k], rx[i], j, lags)
+                for got in outs:
+                    assert np.array_equal(got[i][j, lags], want), (i, j)
+
+
+def test_integer_and_float_plans_do_not_mix(dev):
+    torch, S = dev
+    ri = np.ones((40, 2), np.int16)
+    rf = np.ones(40, np.complex64)
+    with S.plan_create("legall53_int", 4, ri) as pi, S.plan_create("cdf97", 4, rf) as pf:
+        with pytest.raises(S.SidwtError):
+            S.Batch([pi, pf], [512, 512])

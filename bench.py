@@ -127,6 +127,9 @@ def main():
     ap.add_argument("--headline-only", action="store_true",
                     help="default workload without the single / integer / uneven / serving "
                          "sub-records")
+    ap.add_argument("--uneven-config", default=None, metavar="FMAX,WINDOW,DEPTH",
+                    help="uneven batch: this split, tile window and lifting depth instead of "
+                         "the autotuner (e.g. 0,4096,4)")
     ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests per arrival rate in the serving runs")
     args = ap.parse_args()
@@ -484,8 +487,14 @@ def bench_uneven(args):
         f"{out_all.numel() * 8 / 1e9:.1f} GB of planes")
     stream = torch.cuda.current_stream()
     b = S.Batch(plans, ns)
-    info = b.tune(rx, out)
-    log(f"autotuned: {info}")
+    if args.uneven_config:
+        fmax, win, depth = (int(v) for v in args.uneven_config.split(","))
+        b.config(fmax, win, depth)
+        info = b.info()
+        log(f"configured: {info}")
+    else:
+        info = b.tune(rx, out)
+        log(f"autotuned: {info}")
     ms = _time_steps(lambda: b.run(rx, out), args.steps, args.warmup, stream)
     value = total / (ms * 1e-3)
     tflops = flops / (ms * 1e-3) / 1e12
@@ -519,7 +528,7 @@ def bench_uneven(args):
                    "batch": info},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,
-                     "kernel": "one graph replay: batch_lift levels + batch_persistent classes",
+                     "kernel": "one graph replay: batch_lift_blocks passes + batch_persistent classes",
                      "flops_per_step": flops},
         "planes_out": {"bytes": out_all.numel() * 8,
                        "gb_per_s": out_all.numel() * 8 / (ms * 1e-3) / 1e9},

@@ -915,10 +915,10 @@ def bench_single(args):
                    "p50_us": p50 * 1e6, "p99_us": p99 * 1e6, "kernel_us": kern_ms * 1e3},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS,
-                     "traffic": None, "kernel": "fused_correlate<LEGALL53> (one workgroup)",
+                     "traffic": None, "kernel": "fused_correlate<LEGALL53> (one workgroup per plane)",
                      "flops_per_launch": flops,
-                     "note": "one 1024-sample pulse per launch runs on one workgroup of one CU: "
-                             "bound by launch latency, not by the chip"},
+                     "note": "one 1024-sample pulse per launch runs on three workgroups (one "
+                             "per plane) of three CUs: bound by launch latency, not by the chip"},
         "parity": parity,
         "cpu_baseline": cpu,
     }

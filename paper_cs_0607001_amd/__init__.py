@@ -37,9 +37,16 @@ def _torch():
 
 
 def _stream_ptr(stream=None):
+    """The HIP stream of a call: `stream`, else torch's current stream on the
+    current device (read through torch's raw accessor where it has one: the
+    public one builds a Stream object per call, a few microseconds)."""
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return ctypes.c_void_p(raw(torch._C._cuda_getDevice()))
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 class Plan:

@@ -3,7 +3,9 @@
 //   ref_tree_level<F>   x-side lifting of the reference phase tree (plan).
 //   fused_correlate<F>  one workgroup per pulse: y-side lifting of all J
 //                       levels in LDS, each level correlated against the
-//                       plan's stored phases with MFMA as soon as it exists.
+//                       plan's stored phases with MFMA as soon as it exists
+//                       (for a few pulses, one workgroup per pulse and
+//                       plane, each lifting up to its own level).
 //   lift_many<F>        y-side lifting only, pyramid written to HBM.
 //
 // Method references (Bhattacharya & Mahapatra): shift-circulant phases
@@ -620,9 +622,11 @@ __device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLay
       [&](int k, V c, V d) { store_pair(sm, lay, 1, k, c, d); });
   __syncthreads();
 
-  for (int l = 1; l <= lay.J; ++l) {
+  // levels past the last requested plane's are not lifted
+  const int lmax = 32 - __builtin_clz(planes & ((2u << (lay.J - 1)) - 1u));
+  for (int l = 1; l <= lmax; ++l) {
     // plane l-1 only if requested (a coarse-scale subset costs only its own
-    // correlation; every level is still lifted)
+    // correlation; every level up to it is still lifted)
     if ((planes >> (l - 1)) & 1u) {
       if constexpr (INT) {
         correlate_level_int(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N);
@@ -630,7 +634,7 @@ __device__ __forceinline__ void fused_pulse(const PlanDesc &plan, const FusedLay
         correlate_rows_f32<BAL>(plan, fused_view(lay, l), sm, out + 2LL * (l - 1) * N, lay.total);
       }
     }
-    if (l < lay.J) {
+    if (l < lmax) {
       const int np = N >> (l + 1);
       const int Lin = N >> l;
       lift_level<F, 1>(
@@ -651,11 +655,18 @@ __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, 
                                                                 long long n, long long rx_stride,
                                                                 void *__restrict__ out_all,
                                                                 long long out_stride,
-                                                                unsigned planes) {
+                                                                unsigned planes, int split) {
   using RxT = typename RxOf<F>::T;
   using OutT = typename RxOf<F>::Out;
   extern __shared__ __align__(16) char smem_fused[];
-  const long long pulse = blockIdx.x;
+  // split = J: one workgroup per (pulse, plane), each lifting only the
+  // levels its plane needs (few pulses: the planes run side by side)
+  long long pulse = blockIdx.x;
+  if (split) {
+    pulse = blockIdx.x / split;
+    planes &= 1u << (blockIdx.x - pulse * split);
+    if (!planes) return;
+  }
   fused_pulse<F, BAL>(plan, lay, reinterpret_cast<const RxT *>(rx_all) + pulse * rx_stride, n,
                       reinterpret_cast<OutT *>(out_all) + pulse * out_stride * 2, smem_fused,
                       planes);
@@ -1061,6 +1072,9 @@ hipError_t launch_tree(int filter, const void *in, int in_lo, int in_len, int le
   return hipErrorInvalidValue;
 }
 
+// Largest grid (pulses x planes) launched with one workgroup per plane.
+constexpr int kFusedSplitMaxBlocks = 256;
+
 template <int F>
 static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, const void *rx,
                                  long long n, long long count, long long rx_stride, void *out,
@@ -1084,12 +1098,17 @@ static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, c
     if (e != hipSuccess) return e;
     attr_set = true;
   }
+  // A few pulses: one workgroup per (pulse, requested plane), so the planes
+  // of a pulse run on different CUs at once (their lifting repeated up to
+  // each plane's level) instead of one after another in one workgroup.
+  const int split = count * plan.J <= kFusedSplitMaxBlocks ? plan.J : 0;
+  const unsigned grid = (unsigned)(split ? count * split : count);
   if (bal)
-    hipLaunchKernelGGL((fused_correlate<F, true>), dim3((unsigned)count), dim3(kFusedThreads), shm,
-                       st, plan, lay, rx, n, rx_stride, out, out_stride, planes);
+    hipLaunchKernelGGL((fused_correlate<F, true>), dim3(grid), dim3(kFusedThreads), shm,
+                       st, plan, lay, rx, n, rx_stride, out, out_stride, planes, split);
   else
-    hipLaunchKernelGGL((fused_correlate<F, false>), dim3((unsigned)count), dim3(kFusedThreads),
-                       shm, st, plan, lay, rx, n, rx_stride, out, out_stride, planes);
+    hipLaunchKernelGGL((fused_correlate<F, false>), dim3(grid), dim3(kFusedThreads),
+                       shm, st, plan, lay, rx, n, rx_stride, out, out_stride, planes, split);
   return hipGetLastError();
 }
 

@@ -120,3 +120,18 @@ def test_tiled_pulse_on_two_streams_matches_one_stream(dev):
             w = O.correlate_at("cdf97", 8, ref, y.astype(np.complex128), j, lags)
             g = want[j].numpy()[lags]
             assert np.abs(g - w).max() <= 1e-4 * np.abs(w).max()
+
+
+def test_binding_uses_the_current_stream(dev):
+    """The binding's default stream is torch's current stream of the
+    current device, also inside a stream context."""
+    torch, S = dev
+
+    def ptr(p):  # the null (default) stream reads back as None
+        return p.value or 0
+
+    assert ptr(S._stream_ptr()) == torch.cuda.current_stream().cuda_stream
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        assert ptr(S._stream_ptr()) == s.cuda_stream != 0
+    assert ptr(S._stream_ptr(s)) == s.cuda_stream

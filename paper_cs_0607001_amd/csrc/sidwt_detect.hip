@@ -11,6 +11,8 @@
 // chunk's peaks are compacted in lag order by wave ballots and one scan of
 // their counts, so the output order is deterministic and no atomics are
 // used.
+#include <atomic>
+
 #include <hip/hip_runtime.h>
 
 namespace sidwt {
@@ -157,7 +159,7 @@ hipError_t launch_detect(const void *planes, long long pulse_stride, int J, int 
                          hipStream_t st) {
   const size_t lds = (size_t)N * 4;
   if (lds <= (size_t)kDetectLdsBytes) {
-    static bool attr_set = false;
+    static std::atomic<bool> attr_set{false};  // set once per process (calls may race: both set it)
     if (!attr_set) {
       hipError_t e = hipFuncSetAttribute((const void *)detect_peaks<true>,
                                          hipFuncAttributeMaxDynamicSharedMemorySize,

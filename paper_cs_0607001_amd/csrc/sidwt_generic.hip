@@ -8,6 +8,8 @@
 // N/2; each level in 64-lane register windows where a step's taps at offset
 // v come from lane + v (ds_bpermute shuffles), so the HL leftmost and HR
 // rightmost lanes of a window only feed their neighbours.
+#include <atomic>
+
 #include <hip/hip_runtime.h>
 
 #include "sidwt_device.hpp"
@@ -225,7 +227,7 @@ template <int MODE>
 static hipError_t launch_generic_t(const GenericSteps &g, int J, int N, const void *rx,
                                    long long n, long long count, long long rx_stride, void *pyr,
                                    hipStream_t st) {
-  static bool attr_set = false;
+  static std::atomic<bool> attr_set{false};  // set once per process (calls may race: both set it)
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)lift_generic<MODE>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

@@ -10,6 +10,8 @@
 // digit panels (I8Tile), and the digit products of each shift class a + w
 // accumulate in int32 (exact: at most 3 digit pairs per class, products of
 // at most 2^14, K below 2^15 per pass), combined in int64 at the store.
+#include <atomic>
+
 #include "sidwt_device.hpp"
 #include "sidwt_host.hpp"
 #include "sidwt_lift.hpp"
@@ -282,7 +284,7 @@ static hipError_t launch_i8_t(const I8Layout &lay, const I8Tile *tiles, const si
                               const void *rx, long long n, long long count, long long rx_stride,
                               void *out, long long out_stride, unsigned planes, const I8Ptrs *ptrs,
                               hipStream_t st) {
-  static bool attr = false;
+  static std::atomic<bool> attr{false};  // set once per process (calls may race: both set it)
   if (!attr) {
     const hipError_t e = hipFuncSetAttribute((const void *)fused_correlate_i8<WL>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,

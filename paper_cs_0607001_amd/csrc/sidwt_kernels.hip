@@ -12,6 +12,8 @@
 // Sec. II; dual analysis lifting Sec. III; per-scale correlation eq. (15),
 // (20), (20a); the Fig. 5 even/odd tree; Fig. 7 lifting of the received
 // signal.
+#include <atomic>
+
 #include <type_traits>
 
 #include "sidwt_device.hpp"
@@ -1088,7 +1090,7 @@ static hipError_t launch_fused_t(const PlanDesc &plan, const FusedLayout &lay, c
                    (bal_words <= (size_t)host::kLdsWordsTwoPerCu ||
                     (count <= 256 && bal_words <= (size_t)host::kLdsWords));
   const size_t shm = (bal ? bal_words : (size_t)lay.total) * 4;
-  static bool attr_set = false;
+  static std::atomic<bool> attr_set{false};  // set once per process (calls may race: both set it)
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)fused_correlate<F, false>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -1129,7 +1131,7 @@ template <int F>
 static hipError_t launch_lift_t(int J, int N, const void *rx, long long n, long long count,
                                 long long rx_stride, void *pyr, hipStream_t st) {
   const size_t shm = (size_t)(N / 2 + N / 4 + 1) * sizeof(typename ElemOf<F>::T);
-  static bool attr_set = false;
+  static std::atomic<bool> attr_set{false};  // set once per process (calls may race: both set it)
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)lift_many<F>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

@@ -25,6 +25,8 @@
 //    of a tile holds lags 16 i .. 16 i + 15, the K axis runs over (offset v,
 //    re/im) and the 32 columns over (lag t within the block, re/im) with
 //    B[v][t] = conj(a)[v - t].
+#include <atomic>
+
 #include "sidwt_lift.hpp"
 #include "sidwt_swap.hpp"
 
@@ -343,7 +345,7 @@ static hipError_t launch_swap_tree_t(int J, int N, const void *rx, long long n, 
                                      long long rx_stride, void *tree, hipStream_t st) {
   float2 *t = static_cast<float2 *>(tree);
   const long long ts = (long long)(J - 1) * N;
-  static bool attr = false;
+  static std::atomic<bool> attr{false};  // set once per process (calls may race: both set it)
   if (!attr) {
     const hipError_t e = hipFuncSetAttribute((const void *)swap_tree_level2<F>,
                                              hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -383,7 +385,7 @@ hipError_t launch_swap(int filter, int J, int N, const void *rx, long long n, lo
     default: return hipErrorInvalidValue;
   }
   if (e != hipSuccess) return e;
-  static bool attr_set = false;
+  static std::atomic<bool> attr_set{false};  // set once per process (calls may race: both set it)
   if (!attr_set) {
     e = hipFuncSetAttribute((const void *)swap_correlate, hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);

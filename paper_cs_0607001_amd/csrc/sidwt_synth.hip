@@ -7,6 +7,8 @@
 // correlation of a finer plane needs c_l of that level, so a caller that
 // correlated the coarse planes first can form the finer ones from the stored
 // pyramid without lifting the pulse again (Sec. V).
+#include <atomic>
+
 #include <type_traits>
 
 #include "sidwt_device.hpp"
@@ -200,7 +202,7 @@ static hipError_t launch_synth_t(int J, int to, int N, const void *pyr, long lon
                                  hipStream_t st) {
   using V = typename ElemOf<F>::T;
   const size_t shm = synth_lds_bytes(F, N, to);
-  static bool attr_set = false;
+  static std::atomic<bool> attr_set{false};  // set once per process (calls may race: both set it)
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void *)synth_many<F>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

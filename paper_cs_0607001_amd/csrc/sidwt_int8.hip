@@ -102,19 +102,45 @@ __device__ void correlate_i8_level(int N, int l, int ctiles, const I8Tile *__res
       }
     }
     // register i of lane: row 8 (i / 4) + 4 g + i % 4 of the unit, column
-    // lane % 32 = 2 cc + (re/im out); lag T P p1 + 16 ct + cc
+    // lane % 32 = 2 cc + (re/im out); lag T P p1 + 16 ct + cc.  The lane's
+    // address is formed once; register i adds a uniform row offset.  Units
+    // whose rows and lags are all inside the plane store without guards.
     const int col = lane & 31;
     const int cc = col >> 1, ro = col & 1;
+    const long long rs = (long long)T * P;                 // lags per row
+    const int pr0 = rt * 32 + 4 * g;
+    const long long s0 = rs * (row0 + pr0) + 16 * ct + cc;
+    typedef __attribute__((address_space(1))) long long gll;
+    gll *o0 = (gll *)outp + 2 * s0 + ro;
+    const long long rs2 = 2 * rs;                          // elements per row of lags
+    const bool full = rt * 32 + 32 <= R && rs * (row0 + rt * 32 + 31) + 16 * ct + 15 < N;
+    // the class sums combine as sum_c acc_c 256^c in int64: for c < 4 one
+    // 32 x 32 -> 64-bit multiply-add each (the factors are kept opaque so
+    // they are not turned into 64-bit shifts), for c = 4 an add to the high
+    // word
+    int f[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      f[c] = 1 << (8 * c);
+      asm volatile("" : "+s"(f[c]));
+    }
+    auto value = [&](int i) {
+      long long v = acc[0][i];
+#pragma unroll
+      for (int c = 1; c < NC; ++c) {
+        if (c < 4)
+          v += (long long)acc[c][i] * (long long)f[c];
+        else
+          v += (long long)acc[c][i] << 32;
+      }
+      return v;
+    };
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int pr = rt * 32 + 8 * (i >> 2) + 4 * g + (i & 3);
-      const long long si = (long long)T * P * (row0 + pr) + 16 * ct + cc;
-      if (pr < R && si < N) {   // lags of the last row past L - 1 are not stored
-        long long v = 0;
-#pragma unroll
-        for (int s = 0; s < NC; ++s) v += (long long)acc[s][i] << (8 * s);
-        __builtin_nontemporal_store(v, outp + 2 * si + ro);
-      }
+      const int dr = 8 * (i >> 2) + (i & 3);
+      // rows past R and lags of the last row past L - 1 are not stored
+      if (full || (pr0 + dr < R && s0 + rs * dr < N))
+        __builtin_nontemporal_store(value(i), o0 + rs2 * dr);
     }
   }
 }

@@ -36,7 +36,9 @@ __device__ __forceinline__ void put_digits(char *planes, int pb, int b, int ws, 
     h[a] = (unsigned short)((dr & 255) | ((di & 255) << 8));
   }
   char *base = planes + b * kI8DataLimbs * pb;
-  for (int j = pos_mod(k - ws, L); j < ext; j += L) {
+  int j0 = k - ws;  // almost always in [0, L): the division only for the rest
+  if (j0 < 0 || j0 >= L) j0 = pos_mod(j0, L);
+  for (int j = j0; j < ext; j += L) {
 #pragma unroll
     for (int a = 0; a < kI8DataLimbs; ++a)
       *reinterpret_cast<unsigned short *>(base + a * pb + 2 * j) = h[a];

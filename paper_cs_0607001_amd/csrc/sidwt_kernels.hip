@@ -395,15 +395,31 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
       // hold them in registers through it).
       int ln = lane;
       if constexpr (BAL) asm volatile("" : "+v"(ln));
-      // register i of lane l: row 8*(i/4) + 4*(l/32) + i%4, column l%32
+      // register i of lane l: row 8*(i/4) + 4*(l/32) + i%4, column l%32.
+      // The lane's address is formed once; register (h, i) adds a uniform
+      // offset of rows; a tile pair whose 64 rows are all in range stores
+      // without guards.
+      const int pr0 = v.row_begin + mp * 64 + 4 * (ln >> 5);
+      const long long s0 = (long long)P * (pr0 * TT + p0) + r0 + r;
+      typedef __attribute__((address_space(1))) float gf;
+      gf *o0 = (gf *)outp + 2 * s0 + co;
+      const long long rs2 = 2LL * P * TT;  // floats per row of lags
+      const bool full = v.row_begin + mp * 64 + 64 <= v.row_end;
+      if (full) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int pp1 = v.row_begin + mp * 64 + h * 32 + 8 * (i >> 2) + 4 * (ln >> 5) + (i & 3);
-          if (pp1 < v.row_end) {
-            const long long s = (long long)P * (pp1 * TT + p0) + r0 + r;
-            __builtin_nontemporal_store(h ? acc1[i] : acc0[i], &outp[2 * s + co]);
+          for (int i = 0; i < 16; ++i)
+            __builtin_nontemporal_store(h ? acc1[i] : acc0[i],
+                                        o0 + rs2 * (h * 32 + 8 * (i >> 2) + (i & 3)));
+      } else {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int dr = h * 32 + 8 * (i >> 2) + (i & 3);
+            if (pr0 + dr < v.row_end)
+              __builtin_nontemporal_store(h ? acc1[i] : acc0[i], o0 + rs2 * dr);
           }
         }
       }

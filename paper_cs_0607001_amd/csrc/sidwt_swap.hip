@@ -270,18 +270,29 @@ __device__ __forceinline__ void swap_item(int j, int N, const SwapGeom &g, int p
         }
       }
     }
-    // register i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32
+    // register i of lane l: row 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
+    // The lane's address is formed once; register i adds a uniform offset of
+    // rows; a tile whose 32 rows are all inside the plane stores unguarded.
+    typedef __attribute__((address_space(1))) float gf;
 #pragma unroll
     for (int r = 0; r < kSwapRT; ++r) {
       const int t = t0 + r;
       if (t >= ntiles) break;
       const int q = t / ntp, rt = t - q * ntp;
       const int p = p_begin + q;
+      const int rr0 = (rt0 + rt) * 32 + 4 * (lane >> 5);
+      const int lag0 = 16 * rr0 + bt;
+      gf *o0 = (gf *)outp + 2 * ((long long)lag0 * P + p) + bc;
+      const long long rs2 = 32LL * P;  // floats per row of 16 lags
+      if (16 * ((rt0 + rt) * 32 + 31) + 15 < L) {
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int rr = (rt0 + rt) * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-        const int lag = 16 * rr + bt;
-        if (lag < L) outp[2 * ((long long)lag * P + p) + bc] = acc[r][i];
+        for (int i = 0; i < 16; ++i) o0[rs2 * (8 * (i >> 2) + (i & 3))] = acc[r][i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int dr = 8 * (i >> 2) + (i & 3);
+          if (lag0 + 16 * dr < L) o0[rs2 * dr] = acc[r][i];
+        }
       }
     }
   }

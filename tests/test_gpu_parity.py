@@ -411,3 +411,36 @@ def test_plane_mask_computes_only_the_chosen_planes(dev, filt, planes):
                 assert torch.equal(part[:, j], full[:, j]), j
             else:
                 assert bool((part[:, j] == 7).all()), j
+
+
+@pytest.mark.parametrize("filt", ["cdf97", "legall53_int"])
+def test_few_pulses_one_workgroup_per_plane_match_the_batch(dev, filt):
+    """A launch of a few pulses runs one workgroup per (pulse, plane); the
+    same pulses inside a batch too large for that run one workgroup per
+    pulse.  Both give the same planes bit for bit, and the oracle's."""
+    torch, S = dev
+    rng = np.random.default_rng(91)
+    J, n, m = 5, 1500, 80
+    count = 64   # 64 x 5 planes: more than one workgroup per plane allows
+    if filt == "legall53_int":
+        ref = rng.integers(-2047, 2048, size=(m, 2)).astype(np.int16)
+        rx = torch.from_numpy(rng.integers(-2048, 2048, size=(count, n, 2)).astype(np.int16))
+    else:
+        ref = crandn(rng, m)
+        rx = torch.from_numpy(np.stack([crandn(rng, n) for _ in range(count)]).astype(np.complex64))
+    print(f"[case] per-plane workgroups {filt}", flush=True)
+    with S.plan_create(filt, J, ref) as plan:
+        rx = rx.cuda()
+        big = S.correlate_many(plan, rx)
+        few = S.correlate_many(plan, rx[:3].contiguous())
+        one = S.correlate(plan, rx[5].contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(few, big[:3])
+        assert torch.equal(one, big[5])
+        got = one.cpu().numpy()
+        if filt == "legall53_int":
+            assert np.array_equal(got, O.correlate_int(J, ref, rx[5].cpu().numpy()))
+        else:
+            want = O.correlate_direct(filt, J, ref, rx[5].cpu().numpy())
+            for j in range(J):
+                assert np.linalg.norm(got[j] - want[j]) <= 1e-5 * np.linalg.norm(want[j]), j

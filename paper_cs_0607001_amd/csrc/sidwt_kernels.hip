@@ -226,24 +226,62 @@ __device__ __forceinline__ LevelView fused_view(const FusedLayout &lay, int l) {
 
 // Stage phases r0..r0+pcc-1 of both bands as complex rows W[b][rr][v] with
 // W[v] = w[v - F] (zero outside the stored support).
-template <class V>
+// KB coefficient loads per thread are issued before any of them is stored
+// (more reads in flight; the tile items' kernel gains from it, while the
+// whole-pulse kernel, whose registers are scarcer, keeps one).
+template <int KB, class V>
 __device__ __forceinline__ void stage_weights(const PlanDesc &plan, const LevelView &lv, int r0,
                                               int pcc, V *W) {
-  const V *coef = reinterpret_cast<const V *>(plan.coef);
+  // coefficients read as 8-byte words through a global-memory pointer
+  static_assert(sizeof(V) == 8, "complex element of 8 bytes");
+  typedef __attribute__((address_space(1))) const long long gw;
   const LevelDesc &ld = plan.lv[lv.l];
-  const int V0 = lv.V[0], V1 = lv.V[1];
-  const int tot0 = pcc * V0, tot = tot0 + pcc * V1;
-  for (int i = threadIdx.x; i < tot; i += blockDim.x) {
-    const int b = i >= tot0;
-    const int j = b ? i - tot0 : i;
-    const int Vb = b ? V1 : V0;
-    const int rr = j / Vb;
-    const int t = j - rr * Vb - lv.F[b];
-    V w;
-    w.x = 0;
-    w.y = 0;
-    if (t >= 0 && t < ld.len[b]) w = coef[ld.off[b] + (long long)(r0 + rr) * ld.len[b] + t];
-    W[i] = w;
+  // One loop per band, so that the band's support, offset and shift are
+  // workgroup-uniform values read once (a per-lane band index would fetch
+  // them from the descriptor in memory for every element, in series with
+  // the coefficient load).
+  V *Wb = W;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const int Vb = lv.V[b], Fb = lv.F[b], len = ld.len[b];
+    const gw *coef = (const gw *)plan.coef + ld.off[b] + (long long)r0 * len;
+    const int tot = pcc * Vb;
+    if constexpr (KB == 1) {
+      for (int i = threadIdx.x; i < tot; i += blockDim.x) {
+        const int rr = i / Vb;
+        const int t = i - rr * Vb - Fb;
+        V w;
+        w.x = 0;
+        w.y = 0;
+        if (t >= 0 && t < len) w = __builtin_bit_cast(V, coef[(long long)rr * len + t]);
+        Wb[i] = w;
+      }
+    } else {
+      // entries outside the support (and indexes past tot) load the row's
+      // first coefficient, which exists, and store zero (or nothing)
+      const int nt = blockDim.x;
+      for (int i0 = threadIdx.x; i0 < tot; i0 += KB * nt) {
+        V w[KB];
+        bool ok[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          const int i = min(i0 + k * nt, tot - 1);
+          const int rr = i / Vb;
+          const int t = i - rr * Vb - Fb;
+          ok[k] = t >= 0 && t < len;
+          w[k] = __builtin_bit_cast(V, coef[ok[k] ? (long long)rr * len + t : 0]);
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+          if (!ok[k]) {
+            w[k].x = 0;
+            w[k].y = 0;
+          }
+          if (i0 + k * nt < tot) Wb[i0 + k * nt] = w[k];
+        }
+      }
+    }
+    Wb += tot;
   }
 }
 
@@ -292,7 +330,7 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
   const bool neg = (ci == 0) && (co == 1);
   for (int r0 = 0; r0 < P; r0 += v.pc) {
     const int pcc = min(v.pc, P - r0);
-    stage_weights(plan, v, r0, pcc, W);
+    stage_weights<BAL ? 4 : 1>(plan, v, r0, pcc, W);
     __syncthreads();
     // P < 16: one column tile holds all (p0, r) pairs, p0 < TT; otherwise
     // TT = 1 and each column tile holds 16 phases.
@@ -519,7 +557,7 @@ __device__ void correlate_level_int(const PlanDesc &plan, const LevelView &v, in
   const bool neg = (ci == 0) && (co == 1);
   for (int r0 = 0; r0 < P; r0 += v.pc) {
     const int pcc = min(v.pc, P - r0);
-    stage_weights(plan, v, r0, pcc, W);
+    stage_weights<1>(plan, v, r0, pcc, W);
     __syncthreads();
     const int ntn = (P < 8) ? 1 : (pcc >> 3);
     const int ntiles = mpairs * ntn;

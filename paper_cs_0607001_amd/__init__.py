@@ -502,6 +502,24 @@ class Batch:
         check(lib().sidwt_batch_run(self.handle, a, b, _stream_ptr(stream)), "sidwt_batch_run")
         return out
 
+    def bind(self, rx, out):
+        """Check the pulse and output tensors once and keep their pointer
+        arrays, so that run_bound() replays the batch on exactly these
+        buffers without re-marshalling one pointer per pulse on every call
+        (for 10^4 pulses that host work outlasts the GPU step).  The batch
+        holds references to the tensors until the next bind or free."""
+        a, b = self._arrays(rx, out)
+        self._bound = (a, b, list(rx), list(out))
+
+    def run_bound(self, stream=None):
+        """run() on the buffers of the last bind()."""
+        bound = getattr(self, "_bound", None)
+        if bound is None:
+            raise RuntimeError("run_bound() before bind()")
+        a, b, _, out = bound
+        check(lib().sidwt_batch_run(self.handle, a, b, _stream_ptr(stream)), "sidwt_batch_run")
+        return out
+
     def tune(self, rx, out, stream=None):
         a, b = self._arrays(rx, out)
         check(lib().sidwt_batch_tune(self.handle, a, b, _stream_ptr(stream)), "sidwt_batch_tune")
@@ -521,6 +539,7 @@ class Batch:
         return dict(zip(BATCH_INFO_KEYS, list(v)))
 
     def free(self):
+        self._bound = None
         if getattr(self, "_h", None) is not None:
             lib().sidwt_batch_free(self._h)
             self._h = None

@@ -27,7 +27,7 @@
 #include "sidwt_host.hpp"
 
 namespace sidwt {
-hipError_t launch_bank(bool bf16, const BankSeg *segs, const int2 *items, int nitems,
+hipError_t launch_bank(bool bf16, bool deep, const BankSeg *segs, const int2 *items, int nitems,
                        const BankTile *tiles, const int *tile_base, const BankRefLevel *rl,
                        int Jmax, const int *lo_lb, const unsigned *wts, const float2 *scratch,
                        int Wmax, hipStream_t st);
@@ -53,6 +53,10 @@ constexpr int kChunk = 4096;
 constexpr double kBankItemSteps = 256.0;
 constexpr int kBankMaxGroups = 16;
 constexpr int kBankXcdRun = 8;      // consecutive items of a class kept on one XCD
+// Levels from this one on (short panels: items bound by their latency and
+// plane writes) run on the deep kernel, after the others, in a launch of
+// their own.
+constexpr int kBankDeepLevel = 4;
 
 int map_err(hipError_t e, const char *what = nullptr) {
   if (e == hipSuccess) return SIDWT_OK;
@@ -137,7 +141,8 @@ struct sidwt_bank {
   std::vector<BankTile> tiles;       // [tile_base[l] + T]
   std::vector<long long> steps_pre;  // prefix sums of steps (both bands), [tile_base[l] + T + l]
   std::vector<int> tile_base;        // [l], l = 0..Jmax
-  int Umax = 0;
+  int Umax = 0;        // longest tile window (lag offsets), all levels
+  int UmaxDeep = 0;    // the same from level kBankDeepLevel on
   long long weight_words = 0;
   // device
   unsigned *d_w = nullptr;
@@ -294,6 +299,7 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
           tile.steps[b] = steps;
           tile.off[b] = (long long)words.size();
           bk->Umax = std::max(bk->Umax, 8 * steps);
+          if (l >= kBankDeepLevel) bk->UmaxDeep = std::max(bk->UmaxDeep, 8 * steps);
           words.resize(words.size() + (size_t)steps * kBankStepWords, 0u);
           unsigned *panel = words.data() + tile.off[b];
           for (int st = 0; st < steps; ++st)
@@ -566,54 +572,61 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   // mostly share a tile group's weight panels (a deep level's panels are
   // read by every request, whose few rows reuse them little) and find them
   // in that XCD's L2, while every XCD still draws from the whole class.
+  // The items of levels below kBankDeepLevel and those from it on form two
+  // such lists, one per launch (the general kernel, then the deep one).
   std::vector<std::vector<int>> seg_of_level(kMaxLevels + 1);
   for (size_t k = 0; k < sorted.size(); ++k) seg_of_level[sorted[k].level].push_back((int)k);
-  std::vector<std::vector<int2>> bucket(130);
-  for (int l = 1; l <= kMaxLevels; ++l) {
-    if (seg_of_level[l].empty()) continue;
-    const long long *pre = bk->steps_pre.data() + bk->tile_base[l] + (l - 1);
-    int gmax = 0;
-    for (int k : seg_of_level[l]) gmax = std::max(gmax, std::max(sorted[k].g_full, sorted[k].g_last));
-    for (int grp = 0; grp < gmax; ++grp)
-      for (int k : seg_of_level[l]) {
-        const BankSeg &q = sorted[k];
-        for (int rb = 0; rb < q.nblocks; ++rb) {
-          const bool lastb = rb == q.nblocks - 1;
-          if (grp >= (lastb ? q.g_last : q.g_full)) continue;
-          const int rows = lastb ? q.L - 256 * (q.nblocks - 1) : 256;
-          const int span = bank_tiles_per_item(rows) * q.gmul;
-          const int t0 = grp * span, t1 = std::min(q.ntiles, t0 + span);
-          const double c = (double)rows * (double)(pre[t1] - pre[t0] + 8);
-          const int cls = std::min(129, std::max(0, (int)std::floor(2.0 * std::log2(c))));
-          bucket[cls].push_back(make_int2(k, lastb ? (q.nblocks - 1) * q.g_full + grp
-                                                   : rb * q.g_full + grp));
+  // The items of levels [l_lo, l_hi], ordered and placed as described above.
+  auto order_levels = [&](int l_lo, int l_hi, std::vector<int2> &items) {
+    std::vector<std::vector<int2>> bucket(130);
+    for (int l = l_lo; l <= l_hi; ++l) {
+      if (seg_of_level[l].empty()) continue;
+      const long long *pre = bk->steps_pre.data() + bk->tile_base[l] + (l - 1);
+      int gmax = 0;
+      for (int k : seg_of_level[l]) gmax = std::max(gmax, std::max(sorted[k].g_full, sorted[k].g_last));
+      for (int grp = 0; grp < gmax; ++grp)
+        for (int k : seg_of_level[l]) {
+          const BankSeg &q = sorted[k];
+          for (int rb = 0; rb < q.nblocks; ++rb) {
+            const bool lastb = rb == q.nblocks - 1;
+            if (grp >= (lastb ? q.g_last : q.g_full)) continue;
+            const int rows = lastb ? q.L - 256 * (q.nblocks - 1) : 256;
+            const int span = bank_tiles_per_item(rows) * q.gmul;
+            const int t0 = grp * span, t1 = std::min(q.ntiles, t0 + span);
+            const double c = (double)rows * (double)(pre[t1] - pre[t0] + 8);
+            const int cls = std::min(129, std::max(0, (int)std::floor(2.0 * std::log2(c))));
+            bucket[cls].push_back(make_int2(k, lastb ? (q.nblocks - 1) * q.g_full + grp
+                                                     : rb * q.g_full + grp));
+          }
         }
-      }
-  }
-  std::vector<int2> items;
-  std::vector<size_t> cls_end;
-  items.reserve((size_t)nitems);
-  for (int c = 129; c >= 0; --c) {
-    if (bucket[c].empty()) continue;
-    items.insert(items.end(), bucket[c].begin(), bucket[c].end());
-    cls_end.push_back(items.size());
-  }
-  if ((long long)items.size() != nitems) return SIDWT_E_INVAL;  // (cannot happen)
-  {
-    std::vector<int2> placed(items);
-    size_t c0 = 0;
+    }
+    const size_t first = items.size();
+    std::vector<size_t> cls_end;
+    for (int c = 129; c >= 0; --c) {
+      if (bucket[c].empty()) continue;
+      items.insert(items.end(), bucket[c].begin(), bucket[c].end());
+      cls_end.push_back(items.size());
+    }
+    std::vector<int2> placed(items.begin() + first, items.end());
+    size_t c0 = first;
     for (size_t c1 : cls_end) {
       const size_t R = kBankXcdRun, full = (c1 - c0) / (8 * R) * (8 * R);
       for (size_t j = 0; j < full; ++j) {
         // position c0 + j runs on XCD (c0 + j) mod 8; its k-th position in
         // the class takes element k mod R of run 8 (k / R) + j mod 8
         const size_t x = j % 8, k = j / 8;
-        placed[c0 + j] = items[c0 + (8 * (k / R) + x) * R + k % R];
+        placed[c0 - first + j] = items[c0 + (8 * (k / R) + x) * R + k % R];
       }
       c0 = c1;
     }
-    items.swap(placed);
-  }
+    std::copy(placed.begin(), placed.end(), items.begin() + first);
+  };
+  std::vector<int2> items;
+  items.reserve((size_t)nitems);
+  order_levels(1, kBankDeepLevel - 1, items);
+  const long long n_main = (long long)items.size();
+  order_levels(kBankDeepLevel, kMaxLevels, items);
+  if ((long long)items.size() != nitems) return SIDWT_E_INVAL;  // (cannot happen)
   std::vector<LiftChunk> chunks;
   int off[kMaxLevels + 2] = {0}, nch[kMaxLevels + 2] = {0};
   for (int l = 1; l <= kMaxLevels; ++l) {
@@ -660,9 +673,13 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   if (e != hipSuccess) return map_err(e, "lifting");
   if (ws->timing) e = hipEventRecord(ws->ev[1], st);
   if (e != hipSuccess) return map_err(e, "event");
-  e = launch_bank(bk->precision == SIDWT_BANK_BF16, ws->d_segs, ws->d_items, (int)nitems,
-                  bk->d_tiles, bk->d_tile_base, bk->d_rl, bk->Jmax, bk->d_lo, bk->d_w,
-                  ws->d_scratch, 256 + bk->Umax, st);
+  e = launch_bank(bk->precision == SIDWT_BANK_BF16, false, ws->d_segs, ws->d_items,
+                  (int)n_main, bk->d_tiles, bk->d_tile_base, bk->d_rl, bk->Jmax, bk->d_lo,
+                  bk->d_w, ws->d_scratch, 256 + bk->Umax, st);
+  if (e == hipSuccess)
+    e = launch_bank(bk->precision == SIDWT_BANK_BF16, true, ws->d_segs, ws->d_items + n_main,
+                    (int)(nitems - n_main), bk->d_tiles, bk->d_tile_base, bk->d_rl, bk->Jmax,
+                    bk->d_lo, bk->d_w, ws->d_scratch, 256 + bk->UmaxDeep, st);
   if (e == hipSuccess && ws->timing) {
     e = hipEventRecord(ws->ev[2], st);
     ws->timed = e == hipSuccess;

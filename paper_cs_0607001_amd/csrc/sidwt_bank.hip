@@ -92,9 +92,10 @@ constexpr int kBankFillRegs = 6;   // data window elements per thread and band h
 // one region of kBankWaveBytes.
 constexpr int kBankRing = 3;
 constexpr int kBankRingStepBytes = 2 * 2 * 64 * 16;
-constexpr int kBankWaveBytes = kBankRing * kBankRingStepBytes > 64 * kStageLd * 4
+constexpr int kBankStageBytes = 64 * kStageLd * 4;   // one wave's output staging tile
+constexpr int kBankWaveBytes = kBankRing * kBankRingStepBytes > kBankStageBytes
                                    ? kBankRing * kBankRingStepBytes
-                                   : 64 * kStageLd * 4;
+                                   : kBankStageBytes;
 
 // s_waitcnt with only the vector-memory count limited (gfx9 encoding:
 // vmcnt bits 3:0 and 15:14, expcnt 6:4 and lgkmcnt 11:8 left at their
@@ -106,11 +107,13 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 // The waves of one item.  Wave = (row group wr of 32 RT rows, tile group wt
-// of TW = 8 / RT column tiles): RT = 2 gives 64 rows x 4 tiles (any row
-// block); RT = 4 gives 128 rows x 2 tiles (full 256-row blocks), which
-// halves the panel loads per MFMA at the cost of twice the data-operand
-// reads (used where the windows are longest).
-template <bool BF16, int RT>
+// of TW column tiles): RT = 2, TW = 4 gives 64 rows x 4 tiles (any row
+// block); RT = 4, TW = 2 gives 128 rows x 2 tiles (full 256-row blocks),
+// which halves the panel loads per MFMA at the cost of twice the
+// data-operand reads (used where the windows are longest); RT = 2, TW = 2
+// (64 rows x 2 tiles, half the accumulators) serves the deep levels' kernel,
+// which runs more workgroups per CU.
+template <bool BF16, int RT, int TW = 8 / RT>
 __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
                                            const BankRefLevel *__restrict__ rl, int Jmax,
                                            const unsigned *__restrict__ wts, const unsigned *dat,
@@ -118,8 +121,8 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
                                            int ntiles, int wave, int lane, float inv_sd) {
   using H = Half<BF16>;
   using V8 = typename H::V8;
-  static_assert(RT == 2 || RT == 4, "row tiles per wave");
-  constexpr int TW = 8 / RT, RWS = 32 * RT;
+  static_assert((RT == 2 && (TW == 4 || TW == 2)) || (RT == 4 && TW == 2), "wave shape");
+  constexpr int RWS = 32 * RT;
   const int l = q.level, P = 1 << l, N = q.N;
   const int rw = RT == 4 ? 2 : rows > 128 ? 4 : rows > 64 ? 2 : 1;
   const int wr = wave % rw, wt = wave / rw;
@@ -434,16 +437,15 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
 // Weights are read from their panels straight into registers (no LDS, no
 // barrier in the K loop); the waves of an item that share tiles read the
 // same panel lines close together in time.
-template <bool BF16>
-__global__ __launch_bounds__(kBankThreads, 2) void bank_items(
+// DEEP: the deep levels' instance (64 x 2 wave tiles, the staging tile
+// alone per wave: no panel ring).
+template <bool BF16, bool DEEP>
+__device__ __forceinline__ void bank_item(
     const BankSeg *__restrict__ segs, const int2 *__restrict__ items,
     const BankTile *__restrict__ tiles, const int *__restrict__ tile_base,
     const BankRefLevel *__restrict__ rl, int Jmax, const int *__restrict__ lo_lb,
     const unsigned *__restrict__ wts,
-    const float2 *__restrict__ scratch, int Wmax) {
-  extern __shared__ __align__(16) unsigned sm_bank[];
-  __shared__ float s_max;
-  __shared__ int s_umax;
+    const float2 *__restrict__ scratch, int Wmax, unsigned *sm_bank, float &s_max, int &s_umax) {
 
   // Item: segment, row block and tile group (uniform across the block).
   const int2 it = items[blockIdx.x];
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
   const int W = 64 * rw + umax;
   unsigned *dat = sm_bank;                      // [b][hilo][Wmax]
   float *stg = reinterpret_cast<float *>(reinterpret_cast<char *>(sm_bank + 4 * Wmax) +
-                                        wave * kBankWaveBytes);
+                                        wave * (DEEP ? kBankStageBytes : kBankWaveBytes));
   const float2 *band0 = scratch + q.scratch + scratch_level_off(N, l);
   const int e0[2] = {row0 + lo_lb[2 * l], row0 + lo_lb[2 * l + 1]};
 
@@ -558,36 +560,83 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
 
   // The item's tile groups, one after another over the same data window
   // (each wave only touches its own staging area: no barrier in between).
-  for (int g0 = 0; g0 < ntiles; g0 += per) {
-    const int ng = min(per, ntiles - g0);
-    if (sg.wide && rows == 256)
-      bank_waves<BF16, 4>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0 + g0, ng,
-                          wave, lane, inv_sd);
-    else
-      bank_waves<BF16, 2>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0 + g0, ng,
-                          wave, lane, inv_sd);
+  if constexpr (DEEP) {
+    // half of a group's tiles per pass: the waves' 64 x 2 tiles cover
+    // (4 / rw) x 2 = per / 2 of them
+    for (int g0 = 0; g0 < ntiles; g0 += per / 2)
+      bank_waves<BF16, 2, 2>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0 + g0,
+                             min(per / 2, ntiles - g0), wave, lane, inv_sd);
+  } else {
+    for (int g0 = 0; g0 < ntiles; g0 += per) {
+      const int ng = min(per, ntiles - g0);
+      if (sg.wide && rows == 256)
+        bank_waves<BF16, 4>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0 + g0, ng,
+                            wave, lane, inv_sd);
+      else
+        bank_waves<BF16, 2>(q, tl, rl, Jmax, wts, dat, stg, Wmax, rows, row0, tile0 + g0, ng,
+                            wave, lane, inv_sd);
+    }
   }
 }
 
-size_t bank_lds_bytes(int Wmax) {
-  return (size_t)(4 * Wmax) * 4 + (size_t)4 * kBankWaveBytes;
+template <bool BF16>
+__global__ __launch_bounds__(kBankThreads, 2) void bank_items(
+    const BankSeg *__restrict__ segs, const int2 *__restrict__ items,
+    const BankTile *__restrict__ tiles, const int *__restrict__ tile_base,
+    const BankRefLevel *__restrict__ rl, int Jmax, const int *__restrict__ lo_lb,
+    const unsigned *__restrict__ wts, const float2 *__restrict__ scratch, int Wmax) {
+  extern __shared__ __align__(16) unsigned sm_bank[];
+  __shared__ float s_max;
+  __shared__ int s_umax;
+  bank_item<BF16, false>(segs, items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax,
+                         sm_bank, s_max, s_umax);
 }
 
-hipError_t launch_bank(bool bf16, const BankSeg *segs, const int2 *items, int nitems,
+// The deep levels' items (short panels, bound by per-item latency and plane
+// writes): fewer registers per wave, so three workgroups per CU.
+template <bool BF16>
+__global__ __launch_bounds__(kBankThreads, 3) void bank_items_deep(
+    const BankSeg *__restrict__ segs, const int2 *__restrict__ items,
+    const BankTile *__restrict__ tiles, const int *__restrict__ tile_base,
+    const BankRefLevel *__restrict__ rl, int Jmax, const int *__restrict__ lo_lb,
+    const unsigned *__restrict__ wts, const float2 *__restrict__ scratch, int Wmax) {
+  extern __shared__ __align__(16) unsigned sm_bank[];
+  __shared__ float s_max;
+  __shared__ int s_umax;
+  bank_item<BF16, true>(segs, items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax,
+                        sm_bank, s_max, s_umax);
+}
+
+size_t bank_lds_bytes(int Wmax, bool deep) {
+  return (size_t)(4 * Wmax) * 4 + (size_t)4 * (deep ? kBankStageBytes : kBankWaveBytes);
+}
+
+hipError_t launch_bank(bool bf16, bool deep, const BankSeg *segs, const int2 *items, int nitems,
                        const BankTile *tiles, const int *tile_base, const BankRefLevel *rl,
                        int Jmax, const int *lo_lb, const unsigned *wts, const float2 *scratch,
                        int Wmax, hipStream_t st) {
-  const size_t lds = bank_lds_bytes(Wmax);
-  const void *fn = bf16 ? (const void *)bank_items<true> : (const void *)bank_items<false>;
+  const size_t lds = bank_lds_bytes(Wmax, deep);
+  const void *fn = deep ? (bf16 ? (const void *)bank_items_deep<true>
+                                : (const void *)bank_items_deep<false>)
+                        : (bf16 ? (const void *)bank_items<true> : (const void *)bank_items<false>);
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   if (nitems <= 0) return hipSuccess;
-  if (bf16)
-    hipLaunchKernelGGL(bank_items<true>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
-                       items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
-  else
-    hipLaunchKernelGGL(bank_items<false>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
-                       items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
+  if (deep) {
+    if (bf16)
+      hipLaunchKernelGGL(bank_items_deep<true>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
+                         items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
+    else
+      hipLaunchKernelGGL(bank_items_deep<false>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
+                         items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
+  } else {
+    if (bf16)
+      hipLaunchKernelGGL(bank_items<true>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
+                         items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
+    else
+      hipLaunchKernelGGL(bank_items<false>, dim3(nitems), dim3(kBankThreads), lds, st, segs,
+                         items, tiles, tile_base, rl, Jmax, lo_lb, wts, scratch, Wmax);
+  }
   return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ constexpr int kBankFillRegs = 6;   // data window elements per thread and band h
 constexpr int kBankRing = 3;
 constexpr int kBankRingStepBytes = 2 * 2 * 64 * 16;
 constexpr int kBankStageBytes = 64 * kStageLd * 4;   // one wave's output staging tile
+constexpr int kBankStageBytesDeep = 32 * kStageLd * 4;   // the same, 32 rows (deep levels)
 constexpr int kBankWaveBytes = kBankRing * kBankRingStepBytes > kBankStageBytes
                                    ? kBankRing * kBankRingStepBytes
                                    : kBankStageBytes;
@@ -366,16 +367,21 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
   const int pairs = q.E * P;
   const int lq = min(l, 4);                       // log2 Q
   const int lcpr = lq - 1;                        // log2 runs per lag
-  // Per-lane run of each of the 8 store rounds (the same for every tile and
-  // row chunk): staging row and first pair; row < 64 and pp <= 14, so the
+  // Rows staged at a time: 64 (two row tiles), or 32 in the deep levels'
+  // 64 x 2 shape, whose smaller staging tile lets more workgroups share a CU.
+  constexpr int SR = (RT == 2 && TW == 2) ? 32 : 64, LSR = SR == 32 ? 5 : 6;
+  constexpr int CH = SR / 32;             // row tiles per staged chunk
+  constexpr int NR = SR * 8 / 64;         // store rounds per chunk (8 runs per row)
+  // Per-lane run of each of the NR store rounds (the same for every tile and
+  // row chunk): staging row and first pair; row < SR and pp <= 14, so the
   // staging reads stay inside the tile.
-  int srow[8], spp[8];
+  int srow[NR], spp[NR];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
+  for (int j = 0; j < NR; ++j) {
     const int kk = 64 * j + ln;
     const int rest = kk >> lcpr;
-    srow[j] = rest & 63;
-    spp[j] = ((rest >> 6) << lq) + 2 * (kk & ((1 << lcpr) - 1));
+    srow[j] = rest & (SR - 1);
+    spp[j] = ((rest >> LSR) << lq) + 2 * (kk & ((1 << lcpr) - 1));
   }
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
@@ -385,23 +391,23 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
     const float scale =
         c < pairs ? inv_sd * rl[(c >> l) * (Jmax + 1) + l].inv_scale : 0.f;
 #pragma unroll
-    for (int hh = 0; hh < RT / 2; ++hh) {
-      if (64 * hh >= rows_w) break;
+    for (int hh = 0; hh < RT / CH; ++hh) {
+      if (SR * hh >= rows_w) break;
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < CH; ++h)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
           stg[(32 * h + 8 * (i >> 2) + 4 * (ln >> 5) + (i & 3)) * kStageLd + (ln & 31)] =
-              acc[2 * hh + h][t][i] * scale;
+              acc[CH * hh + h][t][i] * scale;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      // all eight staging reads first, then the guarded stores
-      f32x4 v[8];
+      // all the staging reads first, then the guarded stores
+      f32x4 v[NR];
 #pragma unroll
-      for (int j = 0; j < 8; ++j)
+      for (int j = 0; j < NR; ++j)
         v[j] = *reinterpret_cast<const f32x4 *>(stg + srow[j] * kStageLd + 2 * spp[j]);
-      const int rbase = row0 + RWS * wr + 64 * hh;
+      const int rbase = row0 + RWS * wr + SR * hh;
       if (l >= 4) {
         // 2^l >= 16: the tile's 16 pairs are phases c0 mod 2^l .. of one
         // reference, so the run addresses differ from a uniform base only
@@ -409,15 +415,15 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
         const int e = c0 >> l, r0 = c0 & (P - 1);
         float *ob = out + 2 * (((long long)e * q.J + (l - 1)) * N + (long long)P * rbase + r0);
 #pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (64 * hh + srow[j] < rows_w && c0 + spp[j] < pairs)
+        for (int j = 0; j < NR; ++j)
+          if (SR * hh + srow[j] < rows_w && c0 + spp[j] < pairs)
             __builtin_nontemporal_store(
                 v[j], reinterpret_cast<f32x4 *>(ob + 2 * (P * srow[j] + spp[j])));
       } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < NR; ++j) {
           const int cc = c0 + spp[j];
-          if (64 * hh + srow[j] < rows_w && cc < pairs) {
+          if (SR * hh + srow[j] < rows_w && cc < pairs) {
             const int e = cc >> l, r = cc & (P - 1);
             float *o = out + 2 * (((long long)e * q.J + (l - 1)) * N +
                                   (long long)P * (rbase + srow[j]) + r);
@@ -437,7 +443,7 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
 // Weights are read from their panels straight into registers (no LDS, no
 // barrier in the K loop); the waves of an item that share tiles read the
 // same panel lines close together in time.
-// DEEP: the deep levels' instance (64 x 2 wave tiles, the staging tile
+// DEEP: the deep levels' instance (64 x 2 wave tiles, a 32-row staging tile
 // alone per wave: no panel ring).
 template <bool BF16, bool DEEP>
 __device__ __forceinline__ void bank_item(
@@ -490,7 +496,7 @@ __device__ __forceinline__ void bank_item(
   const int W = 64 * rw + umax;
   unsigned *dat = sm_bank;                      // [b][hilo][Wmax]
   float *stg = reinterpret_cast<float *>(reinterpret_cast<char *>(sm_bank + 4 * Wmax) +
-                                        wave * (DEEP ? kBankStageBytes : kBankWaveBytes));
+                                        wave * (DEEP ? kBankStageBytesDeep : kBankWaveBytes));
   const float2 *band0 = scratch + q.scratch + scratch_level_off(N, l);
   const int e0[2] = {row0 + lo_lb[2 * l], row0 + lo_lb[2 * l + 1]};
 
@@ -593,9 +599,10 @@ __global__ __launch_bounds__(kBankThreads, 2) void bank_items(
 }
 
 // The deep levels' items (short panels, bound by per-item latency and plane
-// writes): fewer registers per wave, so three workgroups per CU.
+// writes): fewer registers per wave and a 32-row staging tile, so four
+// workgroups per CU.
 template <bool BF16>
-__global__ __launch_bounds__(kBankThreads, 3) void bank_items_deep(
+__global__ __launch_bounds__(kBankThreads, 4) void bank_items_deep(
     const BankSeg *__restrict__ segs, const int2 *__restrict__ items,
     const BankTile *__restrict__ tiles, const int *__restrict__ tile_base,
     const BankRefLevel *__restrict__ rl, int Jmax, const int *__restrict__ lo_lb,
@@ -608,7 +615,7 @@ __global__ __launch_bounds__(kBankThreads, 3) void bank_items_deep(
 }
 
 size_t bank_lds_bytes(int Wmax, bool deep) {
-  return (size_t)(4 * Wmax) * 4 + (size_t)4 * (deep ? kBankStageBytes : kBankWaveBytes);
+  return (size_t)(4 * Wmax) * 4 + (size_t)4 * (deep ? kBankStageBytesDeep : kBankWaveBytes);
 }
 
 hipError_t launch_bank(bool bf16, bool deep, const BankSeg *segs, const int2 *items, int nitems,

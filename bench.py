@@ -1006,7 +1006,8 @@ def bench_bank(args):
                    "samples": samples, "plane_bytes": out_bytes,
                    "lift_ms": lift_ms, "gemm_ms": gemm_ms},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": tflops / 2500.0, "traffic": None, "kernel": "bank_items<FP16>",
+                     "frac": tflops / 2500.0, "traffic": None,
+                     "kernel": "bank_items<FP16> (levels 1-3) + bank_items_deep<FP16> (levels 4+)",
                      "hbm_write_frac": out_bytes / (gemm_ms * 1e-3) / 8e12},
         "cpu_baseline": None,
     }

@@ -417,8 +417,10 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
 /* `count` requests: rx[i] (device, n[i] complex64), J[i] <= Jmax scales,
  * out[i] (device, sidwt_bank_out_len(bank, n[i], J[i]) complex64, laid out
  * [e][j][k] for eligible reference e, scale j, lag k; 16-byte aligned, else
- * SIDWT_E_INVAL; NULL allowed for a request with no eligible reference).  All requests go through one lifting pass and one GEMM
- * launch on `hip_stream`; returns once both are queued.  count = 0 is a
+ * SIDWT_E_INVAL; NULL allowed for a request with no eligible reference).  All requests go through one lifting pass and the
+ * GEMM launches (for a call large enough to fill the device, levels 1-3
+ * and then the deeper levels on a kernel instance of their own; otherwise
+ * one launch) on `hip_stream`; returns once they are queued.  count = 0 is a
  * no-op (nothing launched or timed). */
 int sidwt_bank_correlate(sidwt_bank *bank, const void *const *rx, const int64_t *n,
                          const int *J, void *const *out, int count, void *hip_stream);
@@ -437,7 +439,7 @@ int sidwt_bank_correlate_ws(sidwt_bank *bank, sidwt_bank_ws *ws, const void *con
 
 /* Kernel timing of the calls through a workspace (benchmarks): with timing
  * on, every call records HIP events on its stream before the lifting
- * launches, between lifting and the GEMM launch, and after it.
+ * launches, between lifting and the GEMM launches, and after them.
  * sidwt_bank_ws_times waits for the last call and returns both durations
  * in milliseconds; SIDWT_E_INVAL if no call was timed since timing was
  * switched on. */

@@ -55,8 +55,12 @@ constexpr int kBankMaxGroups = 16;
 constexpr int kBankXcdRun = 8;      // consecutive items of a class kept on one XCD
 // Levels from this one on (short panels: items bound by their latency and
 // plane writes) run on the deep kernel, after the others, in a launch of
-// their own.
+// their own -- when the other levels' items alone fill the chip for several
+// rounds (kBankSplitItems: 256 CUs x 2 workgroups x 4).  A smaller call
+// (serving at light load) keeps one launch of the general kernel, where
+// the deep levels' items run beside the others instead of after them.
 constexpr int kBankDeepLevel = 4;
+constexpr long long kBankSplitItems = 2048;
 
 int map_err(hipError_t e, const char *what = nullptr) {
   if (e == hipSuccess) return SIDWT_OK;
@@ -572,8 +576,9 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   // mostly share a tile group's weight panels (a deep level's panels are
   // read by every request, whose few rows reuse them little) and find them
   // in that XCD's L2, while every XCD still draws from the whole class.
-  // The items of levels below kBankDeepLevel and those from it on form two
-  // such lists, one per launch (the general kernel, then the deep one).
+  // When the call is split, the items of levels below kBankDeepLevel and
+  // those from it on form two such lists, one per launch (the general
+  // kernel, then the deep one); otherwise one list for the general kernel.
   std::vector<std::vector<int>> seg_of_level(kMaxLevels + 1);
   for (size_t k = 0; k < sorted.size(); ++k) seg_of_level[sorted[k].level].push_back((int)k);
   // The items of levels [l_lo, l_hi], ordered and placed as described above.
@@ -621,11 +626,15 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
     }
     std::copy(placed.begin(), placed.end(), items.begin() + first);
   };
+  long long n_shallow = 0;
+  for (const BankSeg &q : sorted)
+    if (q.level < kBankDeepLevel) n_shallow += (long long)(q.nblocks - 1) * q.g_full + q.g_last;
+  const bool split = n_shallow >= kBankSplitItems;
   std::vector<int2> items;
   items.reserve((size_t)nitems);
-  order_levels(1, kBankDeepLevel - 1, items);
+  order_levels(1, split ? kBankDeepLevel - 1 : kMaxLevels, items);
   const long long n_main = (long long)items.size();
-  order_levels(kBankDeepLevel, kMaxLevels, items);
+  if (split) order_levels(kBankDeepLevel, kMaxLevels, items);
   if ((long long)items.size() != nitems) return SIDWT_E_INVAL;  // (cannot happen)
   std::vector<LiftChunk> chunks;
   int off[kMaxLevels + 2] = {0}, nch[kMaxLevels + 2] = {0};

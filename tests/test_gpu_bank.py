@@ -62,6 +62,62 @@ def test_bank_matches_oracle(dev, filt, precision):
         print(f"[case] worst rel L2 {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_bank_with_only_shallow_levels(dev, precision):
+    """Jmax = 3: every item runs on the general kernel and the deep levels'
+    launch is empty; whole planes against the oracle."""
+    torch, S = dev
+    refs = W.reference_set(11, count=3, m_lo=20, m_hi=60)
+    rng = np.random.default_rng(5)
+    print(f"[case] shallow bank {precision}", flush=True)
+    with S.Bank("cdf97", 3, refs, precision) as bank:
+        ns, Js = [130, 400, 64], [3, 3, 2]
+        ys = [W.echoes(n, refs[0], rng) for n in ns]
+        rx = [torch.from_numpy(y.astype(np.complex64)).cuda() for y in ys]
+        out = bank.correlate(rx, Js)
+        torch.cuda.synchronize()
+        for y, J, o in zip(ys, Js, out):
+            E = bank.eligible(len(y))
+            assert E > 0 and o.shape[0] == E
+            g = o.cpu().numpy().astype(np.complex128)
+            for e in range(E):
+                want = O.correlate_direct("cdf97", J, refs[e], y)
+                for j in range(J):
+                    err = np.linalg.norm(g[e, j] - want[j]) / np.linalg.norm(want[j])
+                    assert err <= TOL[precision], (len(y), e, j, err)
+
+
+def test_split_launch_equals_single_requests_bit_for_bit(dev):
+    """A call large enough to be split (levels 1-3 on the general kernel,
+    deeper levels on the deep instance) gives the same bits as each request
+    alone (one launch of the general kernel): both accumulate every tile in
+    the same order.  Two requests of the large call are also checked against
+    the oracle on sampled lags."""
+    torch, S = dev
+    refs = W.reference_set(13, count=16, m_lo=40, m_hi=900)
+    rng = np.random.default_rng(17)
+    n, J, count = 16384, 10, 64
+    ys = [W.echoes(n, refs[k % 16], rng) for k in range(count)]
+    rx = [torch.from_numpy(y.astype(np.complex64)).cuda() for y in ys]
+    print(f"[case] split bank call: {count} x {n}, J={J}", flush=True)
+    with S.Bank("cdf97", J, refs, "fp16") as bank:
+        big = bank.correlate(rx, [J] * count)
+        torch.cuda.synchronize()
+        for i in (0, 17, 63):
+            one = bank.correlate([rx[i]], [J])[0]
+            torch.cuda.synchronize()
+            assert torch.equal(one, big[i]), i
+        N = O.transform_length(n, J)
+        for i in (5, 40):
+            g = big[i].cpu().numpy().astype(np.complex128)
+            for e in (0, 7, 15):
+                lags = np.concatenate([[0, N - 1], rng.integers(0, N, 20)])
+                for j in (0, 3, 6, 9):
+                    want = O.correlate_at("cdf97", J, refs[e], ys[i], j, lags)
+                    err = np.linalg.norm(g[e, j, lags] - want) / np.linalg.norm(want)
+                    assert err <= TOL["fp16"], (i, e, j, err)
+
+
 def test_bank_equals_fp32_path_within_tolerance(dev):
     torch, S = dev
     refs = bank_refs(seed=9, count=4)

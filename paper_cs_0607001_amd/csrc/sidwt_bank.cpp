@@ -52,7 +52,7 @@ constexpr int kChunk = 4096;
 // per data window, and the most tile groups one item may take.
 constexpr double kBankItemSteps = 256.0;
 constexpr int kBankMaxGroups = 16;
-constexpr int kBankXcdRun = 8;      // consecutive items of a class kept on one XCD
+constexpr int kBankXcdRun = 16;     // consecutive items of a class kept on one XCD
 // Levels from this one on (short panels: items bound by their latency and
 // plane writes) run on the deep kernel, after the others, in a launch of
 // their own -- when the other levels' items alone fill the chip for several

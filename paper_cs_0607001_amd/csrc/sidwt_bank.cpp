@@ -617,8 +617,10 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
     for (size_t c1 : cls_end) {
       const size_t R = kBankXcdRun, full = (c1 - c0) / (8 * R) * (8 * R);
       for (size_t j = 0; j < full; ++j) {
-        // position c0 + j runs on XCD (c0 + j) mod 8; its k-th position in
-        // the class takes element k mod R of run 8 (k / R) + j mod 8
+        // the class's j-th position takes element k mod R of run
+        // 8 (k / R) + j mod 8 (k = j / 8): a run's items sit at positions
+        // of one residue mod 8 from the class start, so they go to one XCD
+        // whatever the class's offset in its launch
         const size_t x = j % 8, k = j / 8;
         placed[c0 - first + j] = items[c0 + (8 * (k / R) + x) * R + k % R];
       }

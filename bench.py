@@ -530,7 +530,8 @@ def bench_uneven(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"uneven batch: {count} pulses, n log-uniform in [512, 65536], "
                                f"16 references 64..2048, D4 / CDF 9/7, J=floor(log2(n/16)), "
-                               f"one persistent graph-replayed launch", "samples": total,
+                               f"one persistent graph-replayed launch, pulse and output buffers "
+                               f"bound once", "samples": total,
                    "batch": info},
         "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_FP32_MATRIX_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / PEAK_FP32_MATRIX_TFLOPS, "traffic": None,

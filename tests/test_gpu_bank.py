@@ -118,6 +118,35 @@ def test_split_launch_equals_single_requests_bit_for_bit(dev):
                     assert err <= TOL["fp16"], (i, e, j, err)
 
 
+def test_bank_with_the_longest_reference_a_plan_accepts(dev):
+    """Plans take references of up to 8192 samples (longer ones are refused
+    with SIDWT_E_SIZE before anything is launched); at 8192 the bank's
+    level-1 window is about 4100 lags, its largest LDS footprint (one
+    workgroup per CU), checked against the oracle on sampled lags."""
+    torch, S = dev
+    rng = np.random.default_rng(23)
+    too_long = W.reference_set(29, count=1, m_lo=8193, m_hi=8194)[0]
+    assert len(too_long) == 8193
+    with pytest.raises(S.SidwtError) as e:
+        S.Bank("cdf97", 4, [too_long], "fp16")
+    assert e.value.code == -2
+    ref = W.reference_set(31, count=1, m_lo=8192, m_hi=8193)[0]
+    assert len(ref) == 8192
+    n, J = 16384, 4
+    y = W.echoes(n, ref, rng)
+    print(f"[case] bank with a {len(ref)}-sample reference", flush=True)
+    with S.Bank("cdf97", J, [ref], "fp16") as bank:
+        out = bank.correlate([torch.from_numpy(y.astype(np.complex64)).cuda()], [J])[0]
+        torch.cuda.synchronize()
+        g = out.cpu().numpy().astype(np.complex128)
+    N = O.transform_length(n, J)
+    lags = np.concatenate([[0, N - 1], rng.integers(0, N, 10)])
+    for j in range(J):
+        want = O.correlate_at("cdf97", J, ref, y, j, lags)
+        err = np.linalg.norm(g[0, j, lags] - want) / np.linalg.norm(want)
+        assert err <= TOL["fp16"], (j, err)
+
+
 def test_bank_equals_fp32_path_within_tolerance(dev):
     torch, S = dev
     refs = bank_refs(seed=9, count=4)

@@ -395,34 +395,46 @@ __device__ __forceinline__ void correlate_rows_f32_t(const PlanDesc &plan, const
         // Groups of 4 lag offsets in two register sets (x, y): the loads of
         // a group are issued one whole group of MFMAs before its use, with
         // no register moves in between (a move would make the wave wait
-        // for the loads it just issued).
-        auto load = [&](int g, float(&A0)[4], float(&A1)[4], float(&Wt)[4]) {
-          data(ia, g, A0);
-          data(ib, g, A1);
-          const float *w = wp + 8 * g;
+        // for the loads it just issued).  TWO: both row tiles; otherwise
+        // only the first (the second lies past the level's last row).
+        auto kloop = [&](auto two_c) {
+          constexpr bool TWO = decltype(two_c)::value;
+          auto load = [&](int g, float(&A0)[4], float(&A1)[4], float(&Wt)[4]) {
+            data(ia, g, A0);
+            if constexpr (TWO) data(ib, g, A1);
+            const float *w = wp + 8 * g;
 #pragma unroll
-          for (int q = 0; q < 4; ++q) Wt[q] = w[2 * q];
-        };
-        auto mma = [&](const float(&A0)[4], const float(&A1)[4], const float(&Wt)[4]) {
+            for (int q = 0; q < 4; ++q) Wt[q] = w[2 * q];
+          };
+          auto mma = [&](const float(&A0)[4], const float(&A1)[4], const float(&Wt)[4]) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const float wq = neg ? -Wt[q] : Wt[q];
-            acc0 = mfma32(A0[q], wq, acc0);
-            acc1 = mfma32(A1[q], wq, acc1);
+            for (int q = 0; q < 4; ++q) {
+              const float wq = neg ? -Wt[q] : Wt[q];
+              acc0 = mfma32(A0[q], wq, acc0);
+              if constexpr (TWO) acc1 = mfma32(A1[q], wq, acc1);
+            }
+          };
+          float xa0[4], xa1[4] = {}, xw[4], ya0[4], ya1[4] = {}, yw[4];
+          load(glo, xa0, xa1, xw);
+          for (int g = glo; g < ghi; g += 2) {
+            load(min(g + 1, ghi - 1), ya0, ya1, yw);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(xa0, xa1, xw);
+            __builtin_amdgcn_sched_barrier(0);
+            load(min(g + 2, ghi - 1), xa0, xa1, xw);
+            __builtin_amdgcn_sched_barrier(0);
+            if (g + 1 < ghi) mma(ya0, ya1, yw);
+            __builtin_amdgcn_sched_barrier(0);
           }
         };
-        float xa0[4], xa1[4], xw[4], ya0[4], ya1[4], yw[4];
-        load(glo, xa0, xa1, xw);
-        for (int g = glo; g < ghi; g += 2) {
-          load(min(g + 1, ghi - 1), ya0, ya1, yw);
-          __builtin_amdgcn_sched_barrier(0);
-          mma(xa0, xa1, xw);
-          __builtin_amdgcn_sched_barrier(0);
-          load(min(g + 2, ghi - 1), xa0, xa1, xw);
-          __builtin_amdgcn_sched_barrier(0);
-          if (g + 1 < ghi) mma(ya0, ya1, yw);
-          __builtin_amdgcn_sched_barrier(0);
-        }
+        // rows of the second tile (uniform over the wave) are never stored
+        // when it starts at or past the level's end: with BAL (the tile
+        // items, whose deepest levels have 16-32 rows) its products are
+        // skipped; the whole-pulse kernel's levels fill their tile pairs
+        if (!BAL || v.row_begin + mp * 64 + 32 < v.row_end)
+          kloop(std::true_type{});
+        else if constexpr (BAL)
+          kloop(std::false_type{});
       }
     };
     auto store = [&](int mp, int nt, const f32x16 &acc0, const f32x16 &acc1) {

@@ -439,10 +439,12 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
 }
 
 // LDS: data windows [band][hi/lo][Wmax] words (W = 64 rw + umax of the
-// item), then one output staging tile [64 rows][kStageLd] floats per wave.
-// Weights are read from their panels straight into registers (no LDS, no
-// barrier in the K loop); the waves of an item that share tiles read the
-// same panel lines close together in time.
+// item), then one region per wave: kBankWaveBytes (the 128 x 2 shape's
+// panel ring, or the [64 rows][kStageLd]-float output staging tile) in the
+// general kernel, a [32 rows][kStageLd] staging tile in the deep one.  In
+// the 64 x 4 and 64 x 2 shapes the weights are read from their panels
+// straight into registers (no LDS, no barrier in the K loop); the waves of
+// an item that share tiles read the same panel lines close together in time.
 // DEEP: the deep levels' instance (64 x 2 wave tiles, a 32-row staging tile
 // alone per wave: no panel ring).
 template <bool BF16, bool DEEP>

@@ -31,9 +31,9 @@ hipError_t launch_bank(bool bf16, bool deep, const BankSeg *segs, const int2 *it
                        const BankTile *tiles, const int *tile_base, const BankRefLevel *rl,
                        int Jmax, const int *lo_lb, const unsigned *wts, const float2 *scratch,
                        int Wmax, hipStream_t st);
-hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
-                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
-                              float2 *scratch, hipStream_t st);
+hipError_t launch_lift_passes(const PlanDesc *plans, const BatchPulse *pulses,
+                              const LiftBlock *const *blocks, const int *nblocks,
+                              const size_t *lds, int npass, float2 *scratch, hipStream_t st);
 }  // namespace sidwt
 
 extern "C++" const sidwt::PlanDesc *sidwt_plan_desc(const sidwt_plan *p);
@@ -47,7 +47,9 @@ using namespace sidwt::host;
 
 namespace {
 
-constexpr int kChunk = 4096;
+// Levels lifted per pass of the request pyramids (one launch per pass:
+// blocks of input samples with halos, every level of the pass written).
+constexpr int kBankLiftDepth = 4;
 // Panel steps (both bands, summed over an item's tiles) an item should run
 // per data window, and the most tile groups one item may take.
 constexpr double kBankItemSteps = 256.0;
@@ -120,8 +122,8 @@ struct sidwt_bank_ws {
   size_t c_items = 0;
   BatchPulse *d_pulses = nullptr;
   size_t c_pulses = 0;
-  LiftChunk *d_chunks = nullptr;
-  size_t c_chunks = 0;
+  LiftBlock *d_blocks = nullptr;
+  size_t c_blocks = 0;
   float2 *d_scratch = nullptr;
   size_t c_scratch = 0;
   bool timing = false;
@@ -408,7 +410,7 @@ void sidwt_bank_ws_free(sidwt_bank_ws *w) {
   (void)hipFree(w->d_segs);
   (void)hipFree(w->d_items);
   (void)hipFree(w->d_pulses);
-  (void)hipFree(w->d_chunks);
+  (void)hipFree(w->d_blocks);
   (void)hipFree(w->d_scratch);
   for (hipEvent_t e : w->ev)
     if (e) (void)hipEventDestroy(e);
@@ -493,7 +495,8 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   std::vector<BatchPulse> pulses(count);
   std::vector<BankSeg> segs;
   std::vector<long long> cost;       // per item of the segment
-  std::vector<std::vector<LiftChunk>> per_level(kMaxLevels + 1);
+  std::vector<std::vector<LiftBlock>> per_pass(kMaxLevels + 1);
+  std::vector<size_t> pass_lds(kMaxLevels + 1, 0);
   long long scratch = 0;
   int Jmax = 0;
   for (int i = 0; i < count; ++i) {
@@ -515,10 +518,14 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
     scratch += 2 * N;
     Jmax = std::max(Jmax, J[i]);
     if (E == 0) continue;
+    for (int k = 0; k * kBankLiftDepth < J[i]; ++k) {
+      const int l0 = k * kBankLiftDepth + 1, l1 = std::min(J[i], (k + 1) * kBankLiftDepth);
+      const int nb = lift_block_count((int)N, l0, l1);
+      for (int blk = 0; blk < nb; ++blk) per_pass[k].push_back(LiftBlock{i, l0, l1, blk});
+      pass_lds[k] = std::max(pass_lds[k], (size_t)lift_block_lds((int)N, l0, l1) * sizeof(float2));
+    }
     for (int l = 1; l <= J[i]; ++l) {
       const int L = (int)(N >> l), P = 1 << l;
-      for (int k0 = 0; k0 < L; k0 += kChunk)
-        per_level[l].push_back(LiftChunk{i, k0, std::min(L, k0 + kChunk), 0});
       BankSeg sg{};
       sg.out = out[i];
       sg.scratch = scratch - 2 * N;
@@ -638,24 +645,25 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   const long long n_main = (long long)items.size();
   if (split) order_levels(kBankDeepLevel, kMaxLevels, items);
   if ((long long)items.size() != nitems) return SIDWT_E_INVAL;  // (cannot happen)
-  std::vector<LiftChunk> chunks;
-  int off[kMaxLevels + 2] = {0}, nch[kMaxLevels + 2] = {0};
-  for (int l = 1; l <= kMaxLevels; ++l) {
-    off[l] = (int)chunks.size();
-    nch[l] = (int)per_level[l].size();
-    chunks.insert(chunks.end(), per_level[l].begin(), per_level[l].end());
+  std::vector<LiftBlock> blocks;
+  int boff[kMaxLevels + 1] = {0}, nblk[kMaxLevels + 1] = {0}, npass = 0;
+  for (int k = 0; k <= kMaxLevels; ++k) {
+    boff[k] = (int)blocks.size();
+    nblk[k] = (int)per_pass[k].size();
+    blocks.insert(blocks.end(), per_pass[k].begin(), per_pass[k].end());
+    if (nblk[k]) npass = k + 1;
   }
   int rc = grow(&ws->d_segs, &ws->c_segs, sorted.size());
   if (!rc) rc = grow(&ws->d_items, &ws->c_items, items.size());
   if (!rc) rc = grow(&ws->d_pulses, &ws->c_pulses, pulses.size());
-  if (!rc) rc = grow(&ws->d_chunks, &ws->c_chunks, chunks.size());
+  if (!rc) rc = grow(&ws->d_blocks, &ws->c_blocks, blocks.size());
   if (!rc) rc = grow(&ws->d_scratch, &ws->c_scratch, (size_t)scratch);
   if (rc) return rc;
   // Descriptor uploads through the workspace's pinned staging buffer.
   const size_t nb[4] = {sorted.size() * sizeof(BankSeg), items.size() * sizeof(int2),
-                        pulses.size() * sizeof(BatchPulse), chunks.size() * sizeof(LiftChunk)};
-  const void *src[4] = {sorted.data(), items.data(), pulses.data(), chunks.data()};
-  void *dst[4] = {ws->d_segs, ws->d_items, ws->d_pulses, ws->d_chunks};
+                        pulses.size() * sizeof(BatchPulse), blocks.size() * sizeof(LiftBlock)};
+  const void *src[4] = {sorted.data(), items.data(), pulses.data(), blocks.data()};
+  void *dst[4] = {ws->d_segs, ws->d_items, ws->d_pulses, ws->d_blocks};
   size_t at[5] = {0};
   for (int k = 0; k < 4; ++k) at[k + 1] = at[k] + ((nb[k] + 255) & ~size_t(255));
   hipError_t e = hipSuccess;
@@ -675,12 +683,13 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   }
   if (e == hipSuccess) e = hipEventRecord(ws->up_done, st);
   if (e != hipSuccess) return map_err(e, "descriptor upload");
-  const LiftChunk *cp[kMaxLevels + 2];
-  for (int l = 0; l <= kMaxLevels + 1; ++l) cp[l] = ws->d_chunks + off[l];
+  const LiftBlock *bp[kMaxLevels + 1];
+  for (int k = 0; k <= kMaxLevels; ++k) bp[k] = ws->d_blocks + boff[k];
   ws->timed = false;
   if (ws->timing) e = hipEventRecord(ws->ev[0], st);
   if (e == hipSuccess)
-    e = launch_lift_levels(bk->d_plan, ws->d_pulses, cp, nch, Jmax, ws->d_scratch, st);
+    e = launch_lift_passes(bk->d_plan, ws->d_pulses, bp, nblk, pass_lds.data(), npass,
+                           ws->d_scratch, st);
   if (e != hipSuccess) return map_err(e, "lifting");
   if (ws->timing) e = hipEventRecord(ws->ev[1], st);
   if (e != hipSuccess) return map_err(e, "event");

@@ -165,24 +165,13 @@ __device__ __forceinline__ void bank_waves(const BankSeg &q, const BankTile *tl,
       pw[t] = wts + (t < nt_w ? tl[tix[t]].off[b] : 0) + 4 * lane;
       S = max(S, steps[t]);
     }
-    // Panel operands (B) come from global memory and are issued NB - 1
-    // steps ahead in NB register sets; the data operands (A) come from LDS
-    // one row tile ahead (two sets), so few registers hold them.  Buffer
-    // indices are compile-time (the step loop is unrolled by NB).  Load
-    // indices are clamped to valid steps, so no load sits under a branch;
-    // only the MFMAs of a tile past its own K length are skipped.
-    constexpr int NB = RT == 4 ? 3 : 2;
+    // The data operands (A) come from LDS one row tile ahead (two sets), so
+    // few registers hold them.  Load indices are clamped to valid steps, so
+    // no load sits under a branch; only the MFMAs of a tile past its own K
+    // length are skipped.
     int last[TW];
 #pragma unroll
     for (int t = 0; t < TW; ++t) last[t] = steps[t] > 0 ? steps[t] - 1 : 0;
-    auto loadB = [&](int st, V8(&BH)[TW], V8(&BL)[TW]) {
-#pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        const unsigned *pp = pw[t] + min(st, last[t]) * kBankStepWords;
-        BH[t] = gload8<V8>(pp);
-        BL[t] = gload8<V8>(pp + 256);
-      }
-    };
     auto loadA = [&](int st, int h, V8 &AH, V8 &AL) {
       const int u0 = 8 * min(st, S - 1) + 4 * g;
       AH = load8<V8>(dhi + rloc + 32 * h + u0);

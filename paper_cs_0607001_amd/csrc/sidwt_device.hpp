@@ -180,12 +180,6 @@ struct BatchItem {
   int pad_[3];
 };
 
-struct LiftChunk {
-  int pulse;
-  int k0, k1;           // pairs [k0, k1) of the level
-  int pad_;
-};
-
 // Multi-level lifting of long pulses (uneven batches): a pass lifts levels
 // l0..l1 of one pulse, block by block.  A block owns kLiftBlockIn samples of
 // the pass's input level l0-1 (c_{l0-1}; the pulse itself for l0 = 1), i.e.

@@ -741,57 +741,12 @@ __global__ __launch_bounds__(kFusedThreads) void fused_correlate(PlanDesc plan, 
 }
 
 // ===========================================================================
-// Uneven batches.  Long pulses are lifted level by level into an HBM
-// scratch pyramid (c_l then d_l for l = 1..J, 2N complex per pulse); one
+// Uneven batches.  Long pulses are lifted into an HBM scratch pyramid (c_l
+// then d_l for l = 1..J, 2N complex per pulse) in multi-level passes; one
 // persistent kernel then pulls work items from an atomic counter: whole
 // short pulses (fused path above) and lag tiles (rows of one level) of long
 // pulses, whose band windows are read from the scratch pyramid.
 // ===========================================================================
-
-template <int F>
-__device__ void lift_chunk(const BatchPulse &p, float2 *scratch, int l, int k0, int k1) {
-  constexpr bool OB = YLift<F>::kOddBefore;
-  const int N = p.N;
-  const int np = N >> l;
-  float2 *c = scratch + p.scratch + scratch_level_off(N, l);
-  float2 *d = c + np;
-  if (l == 1) {
-    const float2 *rx = reinterpret_cast<const float2 *>(p.rx);
-    const long long n = p.n;
-    lift_level_range<F, 2>(
-        np, k0, k1,
-        [&](int kc, float2 &e, float2 &o) {
-          e = rx_sample_global(rx, n, 2 * kc);
-          o = rx_sample_global(rx, n, OB ? (kc == 0 ? N - 1 : 2 * kc - 1) : 2 * kc + 1);
-        },
-        [&](int k, float2 cv, float2 dv) {
-          c[k] = cv;
-          d[k] = dv;
-        });
-  } else {
-    const float2 *src = scratch + p.scratch + scratch_level_off(N, l - 1);
-    lift_level_range<F, 2>(
-        np, k0, k1, [&](int kc, float2 &e, float2 &o) { pair_at<OB>(src, kc, np, e, o); },
-        [&](int k, float2 cv, float2 dv) {
-          c[k] = cv;
-          d[k] = dv;
-        });
-  }
-}
-
-__global__ __launch_bounds__(256) void batch_lift(const PlanDesc *__restrict__ plans,
-                                                  const BatchPulse *__restrict__ pulses,
-                                                  const LiftChunk *__restrict__ chunks, int l,
-                                                  float2 *__restrict__ scratch) {
-  const LiftChunk ch = chunks[blockIdx.x];
-  const BatchPulse &p = pulses[ch.pulse];
-  switch (plans[p.plan].filter) {
-    case F_LEGALL53: lift_chunk<F_LEGALL53>(p, scratch, l, ch.k0, ch.k1); break;
-    case F_CDF97: lift_chunk<F_CDF97>(p, scratch, l, ch.k0, ch.k1); break;
-    case F_D4: lift_chunk<F_D4>(p, scratch, l, ch.k0, ch.k1); break;
-    default: break;
-  }
-}
 
 // One block of a multi-level lifting pass (see LiftBlock): level l0 lifted
 // from the input level in global memory (register windows, as the
@@ -1238,11 +1193,6 @@ hipError_t batch_occupancy(bool tiles_only, size_t lds_bytes, int *blocks_per_cu
                                                       kFusedThreads, lds_bytes);
 }
 
-// Lifting of every tiled pulse into its scratch pyramid, level by level.
-hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
-                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
-                              float2 *scratch, hipStream_t st);
-
 // Zero counters[0..n), n <= 64.
 hipError_t launch_batch_reset(int *counters, int n, hipStream_t st);
 
@@ -1284,17 +1234,5 @@ hipError_t launch_lift_passes(const PlanDesc *plans, const BatchPulse *pulses,
   return e;
 }
 
-hipError_t launch_lift_levels(const PlanDesc *plans, const BatchPulse *pulses,
-                              const LiftChunk *const *chunks, const int *nchunks, int Jmax,
-                              float2 *scratch, hipStream_t st) {
-  hipError_t e = hipSuccess;
-  for (int l = 1; l <= Jmax && e == hipSuccess; ++l) {
-    if (nchunks[l] == 0) continue;
-    hipLaunchKernelGGL(batch_lift, dim3(nchunks[l]), dim3(256), 0, st, plans, pulses, chunks[l], l,
-                       scratch);
-    e = hipGetLastError();
-  }
-  return e;
-}
 
 }  // namespace sidwt

@@ -498,7 +498,6 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
   std::vector<std::vector<LiftBlock>> per_pass(kMaxLevels + 1);
   std::vector<size_t> pass_lds(kMaxLevels + 1, 0);
   long long scratch = 0;
-  int Jmax = 0;
   for (int i = 0; i < count; ++i) {
     if (!rx[i] || n[i] < 1 || J[i] < 1 || J[i] > bk->Jmax) return SIDWT_E_INVAL;
     const int64_t N = transform_length(n[i], J[i]);
@@ -516,7 +515,6 @@ int sidwt_bank_correlate_ws(sidwt_bank *bk, sidwt_bank_ws *ws, const void *const
     p.plan = 0;
     p.scratch = scratch;
     scratch += 2 * N;
-    Jmax = std::max(Jmax, J[i]);
     if (E == 0) continue;
     for (int k = 0; k * kBankLiftDepth < J[i]; ++k) {
       const int l0 = k * kBankLiftDepth + 1, l1 = std::min(J[i], (k + 1) * kBankLiftDepth);

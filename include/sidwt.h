@@ -417,8 +417,9 @@ int sidwt_bank_create(int filter, int Jmax, const void *const *refs, const int64
 /* `count` requests: rx[i] (device, n[i] complex64), J[i] <= Jmax scales,
  * out[i] (device, sidwt_bank_out_len(bank, n[i], J[i]) complex64, laid out
  * [e][j][k] for eligible reference e, scale j, lag k; 16-byte aligned, else
- * SIDWT_E_INVAL; NULL allowed for a request with no eligible reference).  All requests go through one lifting pass and the
- * GEMM launches (for a call large enough to fill the device, levels 1-3
+ * SIDWT_E_INVAL; NULL allowed for a request with no eligible reference).
+ * All requests go through the lifting passes (four levels per launch) and
+ * the GEMM launches (for a call large enough to fill the device, levels 1-3
  * and then the deeper levels on a kernel instance of their own; otherwise
  * one launch) on `hip_stream`; returns once they are queued.  count = 0 is a
  * no-op (nothing launched or timed). */
